@@ -1,0 +1,259 @@
+"""FP64 CPU oracle for the short-range MD step (ESPResSo++, arXiv 2608.14911).
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
+CPU-baseline leg of ``bench.py`` may import this package.  It shares no code
+with the HIP library in ``paper_2608_14911_amd`` and never imports it.
+
+The arithmetic lives in ``md_oracle.c`` (plain C, FP64, no fused multiply-add);
+this module only marshals numpy arrays through ctypes.  Functions and the
+passages of the paper they follow:
+
+* ``pair_eval``    -- LennardJones / LennardJonesCapped with shift='auto'
+                      (section "Example usage").
+* ``fene_eval``, ``bend_eval`` -- bonded interactions (section
+                      "Functionality"); FENE and cosine bending of the
+                      Kremer-Grest melt.
+* ``forces``       -- F_i = -grad_i U summed over pairs inside the cutoff, by
+                      brute force or the oracle's own linked cells (CellGrid,
+                      section "Software design").
+* ``neighbors``    -- Verlet-list sets { j != i : r_ij^2 < (rc+skin)^2 }
+                      (VerletList + system.skin, section "Example usage").
+* ``run``          -- VelocityVerlet with the LangevinThermostat extension
+                      (section "Example usage").
+* ``philox``, ``gauss3`` -- the counter-based noise source (Philox4x64-10,
+                      Salmon et al. 2011) that both sides implement
+                      independently.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "_md_oracle.so")
+_lib = None
+
+NOBS = 10   # e_pair, e_bond, e_angle, W, Wxx, Wyy, Wzz, Wxy, Wxz, Wyz
+NHIST = 11  # e_pair, e_bond, e_angle, e_kin, W, tensor[6]
+
+OK = 0
+ERR_ARG = -1
+ERR_NL_OVERFLOW = -4
+ERR_BOND_BROKEN = -5
+ERR_NONFINITE = -6
+
+
+class OracleError(RuntimeError):
+    def __init__(self, code, what):
+        super().__init__("%s failed with status %d" % (what, code))
+        self.code = code
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        from . import build as _b
+        _b.build()
+    lib = ctypes.CDLL(_LIB_PATH)
+    P = ctypes.c_void_p
+    i64, i32, f64, u64 = ctypes.c_int64, ctypes.c_int32, ctypes.c_double, ctypes.c_uint64
+    lib.orc_philox4x64_10.argtypes = [P, P, P]
+    lib.orc_philox4x64_10.restype = None
+    lib.orc_gauss3.argtypes = [u64, u64, u64, u64, P]
+    lib.orc_gauss3.restype = None
+    lib.orc_pair_eval.argtypes = [P, f64, P, P]
+    lib.orc_pair_eval.restype = ctypes.c_int
+    lib.orc_fene_eval.argtypes = [f64, f64, f64, P, P]
+    lib.orc_fene_eval.restype = ctypes.c_int
+    lib.orc_bend_eval.argtypes = [f64, P, P, P, P, P, P, P]
+    lib.orc_bend_eval.restype = ctypes.c_int
+    lib.orc_forces.argtypes = [i64, P, P, i32, P, P, i64, P, f64, f64, i64, P, f64, i32, i32, P, P, P]
+    lib.orc_forces.restype = ctypes.c_int
+    lib.orc_neighbors.argtypes = [i64, P, P, f64, i64, P, i32, P, P, i32]
+    lib.orc_neighbors.restype = ctypes.c_int
+    lib.orc_neighbors_cells.argtypes = [i64, P, P, f64, i32, P, P, i32]
+    lib.orc_neighbors_cells.restype = ctypes.c_int
+    lib.orc_run.argtypes = [i64, P, P, P, P, P, i32, P, P, i64, P, f64, f64, i64, P, f64,
+                            f64, i32, f64, f64, u64, P, P, i64, i32, i32, P]
+    lib.orc_run.restype = ctypes.c_int
+    lib.orc_nthreads_default.argtypes = []
+    lib.orc_nthreads_default.restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _c(a, dtype):
+    return None if a is None else np.ascontiguousarray(a, dtype=dtype)
+
+
+def nthreads_default():
+    return _load().orc_nthreads_default()
+
+
+# ---------------------------------------------------------------- RNG
+def philox(counter, key):
+    """One Philox4x64-10 block: counter (4 x u64), key (2 x u64) -> 4 x u64."""
+    c = np.asarray(counter, dtype=np.uint64).copy()
+    k = np.asarray(key, dtype=np.uint64).copy()
+    out = np.zeros(4, dtype=np.uint64)
+    _load().orc_philox4x64_10(_ptr(c), _ptr(k), _ptr(out))
+    return out
+
+
+def gauss3(seed, stream, step, tag):
+    """Three N(0,1) draws for (seed, stream, step, tag) by Box-Muller."""
+    out = np.zeros(3, dtype=np.float64)
+    _load().orc_gauss3(seed, stream, step, tag, _ptr(out))
+    return out
+
+
+# ---------------------------------------------------------------- potentials
+def pair_params(eps=1.0, sigma=1.0, rc=2.5, shift=float("nan"), caprad=0.0):
+    """One type-pair row: eps, sigma, rc, shift (NaN = auto), caprad (0 = none)."""
+    return np.array([eps, sigma, rc, shift, caprad], dtype=np.float64)
+
+
+def pair_eval(pp, r):
+    """LJ energy u(r) and radial force magnitude f(r) (positive = repulsive)."""
+    pp = _c(pp, np.float64)
+    u = ctypes.c_double()
+    f = ctypes.c_double()
+    _load().orc_pair_eval(_ptr(pp), float(r), ctypes.byref(u), ctypes.byref(f))
+    return u.value, f.value
+
+
+def fene_eval(K, R0, r):
+    u = ctypes.c_double()
+    f = ctypes.c_double()
+    st = _load().orc_fene_eval(K, R0, float(r), ctypes.byref(u), ctypes.byref(f))
+    if st != OK:
+        raise OracleError(st, "fene_eval")
+    return u.value, f.value
+
+
+def bend_eval(k, ra, rb, rc):
+    """Cosine bending energy and forces on (a, centre b, c)."""
+    ra, rb, rc = (_c(x, np.float64) for x in (ra, rb, rc))
+    u = ctypes.c_double()
+    Fa, Fb, Fc = (np.zeros(3) for _ in range(3))
+    _load().orc_bend_eval(k, _ptr(ra), _ptr(rb), _ptr(rc), ctypes.byref(u), _ptr(Fa), _ptr(Fb), _ptr(Fc))
+    return u.value, Fa, Fb, Fc
+
+
+# ---------------------------------------------------------------- system-level
+def pair_table(ntypes, rows):
+    """rows: dict (ti, tj) -> pair_params row, symmetric; returns flat table."""
+    t = np.zeros((ntypes, ntypes, 5), dtype=np.float64)
+    for (a, b), row in rows.items():
+        t[a, b] = row
+        t[b, a] = row
+    return t.reshape(-1)
+
+
+def forces(pos, box, pp, ntypes=1, type=None, bonds=None, angles=None, fene_K=30.0,
+           fene_R0=1.5, k_bend=0.0, use_cells=True, nthreads=0, want_fscale=False):
+    """Forces F [N,3] and obs dict at positions pos [N,3] (FP64)."""
+    pos = _c(pos, np.float64)
+    n = pos.shape[0]
+    box = _c(box, np.float64)
+    pp = _c(pp, np.float64)
+    type = _c(type, np.int32)
+    bonds = _c(bonds, np.int32)
+    angles = _c(angles, np.int32)
+    nb = 0 if bonds is None else bonds.shape[0]
+    na = 0 if angles is None else angles.shape[0]
+    F = np.zeros((n, 3))
+    obs = np.zeros(NOBS)
+    fscale = np.zeros(n) if want_fscale else None
+    st = _load().orc_forces(n, _ptr(pos), _ptr(type), ntypes, _ptr(pp), _ptr(box), nb, _ptr(bonds),
+                            fene_K, fene_R0, na, _ptr(angles), k_bend, int(bool(use_cells)), nthreads,
+                            _ptr(F), _ptr(obs), _ptr(fscale))
+    if st != OK:
+        raise OracleError(st, "forces")
+    out = {"e_pair": obs[0], "e_bond": obs[1], "e_angle": obs[2], "virial": obs[3],
+           "virial_tensor": obs[4:10].copy()}
+    if want_fscale:
+        out["fscale"] = fscale
+    return F, out
+
+
+def neighbors(pos, box, rv, query=None, cap=512, nthreads=0):
+    """Full Verlet-list sets by brute force: list of sorted int arrays."""
+    pos = _c(pos, np.float64)
+    box = _c(box, np.float64)
+    n = pos.shape[0]
+    q = None if query is None else _c(query, np.int64)
+    nq = n if q is None else q.shape[0]
+    count = np.zeros(nq, dtype=np.int32)
+    idx = np.zeros((nq, cap), dtype=np.int32)
+    st = _load().orc_neighbors(n, _ptr(pos), _ptr(box), float(rv), nq, _ptr(q), cap, _ptr(count),
+                               _ptr(idx), nthreads)
+    if st != OK:
+        raise OracleError(st, "neighbors")
+    return [np.sort(idx[k, :count[k]]) for k in range(nq)]
+
+
+def neighbors_cells(pos, box, rv, cap=512, nthreads=0):
+    """The same sets through the oracle's own linked cells (all particles)."""
+    pos = _c(pos, np.float64)
+    box = _c(box, np.float64)
+    n = pos.shape[0]
+    count = np.zeros(n, dtype=np.int32)
+    idx = np.zeros((n, cap), dtype=np.int32)
+    st = _load().orc_neighbors_cells(n, _ptr(pos), _ptr(box), float(rv), cap, _ptr(count), _ptr(idx),
+                                     nthreads)
+    if st != OK:
+        raise OracleError(st, "neighbors_cells")
+    return [np.sort(idx[k, :count[k]]) for k in range(n)]
+
+
+NVE = 0
+LANGEVIN = 1
+
+
+def run(state, params, nsteps, use_cells=True, nthreads=0):
+    """Advance ``state`` in place by nsteps of velocity Verlet (+ Langevin).
+
+    state: dict with pos [N,3], vel [N,3], image [N,3] int32, step (int),
+           vel_half (0/1), type [N] int32 or None.
+    params: dict with box, pp, ntypes, mass_by_type, dt, integrator,
+           temperature, gamma, seed, bonds, angles, fene_K, fene_R0, k_bend.
+    Returns the per-step history [nsteps, NHIST].
+    """
+    pos = state["pos"]
+    vel = state["vel"]
+    img = state["image"]
+    assert pos.dtype == np.float64 and pos.flags.c_contiguous
+    assert vel.dtype == np.float64 and vel.flags.c_contiguous
+    assert img.dtype == np.int32 and img.flags.c_contiguous
+    n = pos.shape[0]
+    type = _c(state.get("type"), np.int32)
+    box = _c(params["box"], np.float64)
+    pp = _c(params["pp"], np.float64)
+    mass = _c(params["mass_by_type"], np.float64)
+    bonds = _c(params.get("bonds"), np.int32)
+    angles = _c(params.get("angles"), np.int32)
+    nb = 0 if bonds is None else bonds.shape[0]
+    na = 0 if angles is None else angles.shape[0]
+    step = ctypes.c_int64(int(state["step"]))
+    vh = ctypes.c_int32(int(state["vel_half"]))
+    hist = np.zeros((nsteps, NHIST))
+    st = _load().orc_run(n, _ptr(pos), _ptr(vel), _ptr(img), _ptr(type), _ptr(mass),
+                         int(params.get("ntypes", 1)), _ptr(pp), _ptr(box), nb, _ptr(bonds),
+                         float(params.get("fene_K", 30.0)), float(params.get("fene_R0", 1.5)), na,
+                         _ptr(angles), float(params.get("k_bend", 0.0)), float(params["dt"]),
+                         int(params["integrator"]), float(params.get("temperature", 0.0)),
+                         float(params.get("gamma", 0.0)), int(params.get("seed", 0)),
+                         ctypes.byref(step), ctypes.byref(vh), nsteps, int(bool(use_cells)),
+                         nthreads, _ptr(hist))
+    state["step"] = step.value
+    state["vel_half"] = vh.value
+    if st != OK:
+        raise OracleError(st, "run")
+    return hist

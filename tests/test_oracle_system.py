@@ -1,0 +1,227 @@
+"""System-level pins of the oracle: forces, energies, virial, neighbour sets.
+
+The paper's hot path is the Verlet-list pair loop over linked cells
+(section "Software design": VerletListInteractionTemplate, CellGrid; section
+"Example usage": VerletList(cutoff), system.skin).  Its result has a plain
+definition -- F_i = -grad_i U with U summed over pairs inside the cutoff --
+so the oracle is pinned by:
+  * an independent lattice enumeration of the infinite FCC crystal (numpy);
+  * central finite differences of the total energy;
+  * the virial identity sum_i r_i.F_i = W for an isolated cluster;
+  * Newton's third law and translation invariance;
+  * numpy brute-force neighbour sets with the same FP64 operation order.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2608_14911_amd import inputs
+
+WCA = 2.0 ** (1.0 / 6.0)
+
+
+def lj_numpy(r, eps=1.0, sigma=1.0, rc=2.5):
+    """4eps[(s/r)^12-(s/r)^6] shifted to zero at rc; r*f(r) for the virial."""
+    def u0(x):
+        s6 = (sigma / x) ** 6
+        return 4 * eps * (s6 * s6 - s6)
+    s6 = (sigma / r) ** 6
+    return u0(r) - u0(rc), 24 * eps * (2 * s6 * s6 - s6)
+
+
+def fcc_lattice_sums(density, rc):
+    """Per-particle energy and virial of the infinite FCC crystal by direct
+    enumeration of lattice vectors (independent of boxes and cells)."""
+    a = (4.0 / density) ** (1.0 / 3.0)
+    m = int(np.ceil(rc / a)) + 1
+    g = np.arange(-m, m + 1)
+    cells = np.stack(np.meshgrid(g, g, g, indexing="ij"), axis=-1).reshape(-1, 3)
+    basis = np.array([[0, 0, 0], [0.5, 0.5, 0], [0.5, 0, 0.5], [0, 0.5, 0.5]])
+    R = ((cells[:, None, :] + basis[None]).reshape(-1, 3)) * a
+    r = np.linalg.norm(R, axis=1)
+    r = r[(r > 0) & (r < rc)]
+    u, rf = lj_numpy(r, rc=rc)
+    return 0.5 * u.sum(), 0.5 * rf.sum(), r
+
+
+def test_fcc_shell_counts_and_lattice_sums():
+    rho, rc, rv = 0.8442, 2.5, 2.8
+    U_per, W_per, r = fcc_lattice_sums(rho, rc)
+    assert r.size == 54          # 12 + 6 + 24 + 12 FCC shells inside 2.5
+    _, _, r2 = fcc_lattice_sums(rho, rv)
+    assert r2.size == 78         # + the 24-site fifth shell inside 2.8
+    pos, box = inputs.fcc_lattice(8, rho, jitter=0.0)
+    n = pos.shape[0]
+    F, obs = oracle.forces(pos, box, oracle.pair_params(rc=rc))
+    assert obs["e_pair"] / n == pytest.approx(U_per, rel=1e-12)
+    assert obs["virial"] / n == pytest.approx(W_per, rel=1e-12)
+    assert np.abs(F).max() < 1e-10
+    # the two values quoted for this lattice in the workload notes
+    assert U_per == pytest.approx(-6.332811992580958, rel=1e-12)
+    assert W_per == pytest.approx(-22.158199254035495, rel=1e-12)
+    nl = oracle.neighbors_cells(pos, box, rv)
+    assert all(len(x) == 78 for x in nl)
+    nl_c = oracle.neighbors_cells(pos, box, rc)
+    assert all(len(x) == 54 for x in nl_c)
+
+
+def numpy_neighbors(pos, box, rv):
+    """O(N^2) Verlet sets with compare-based minimum image and
+    r^2 = (dx*dx + dy*dy) + dz*dz, elementwise FP64 (no fused ops)."""
+    L = np.asarray(box)
+    H = 0.5 * L
+    d = pos[None, :, :] - pos[:, None, :]          # x_j - x_i
+    d = np.where(d > H, d - L, np.where(d < -H, d + L, d))
+    r2 = (d[..., 0] * d[..., 0] + d[..., 1] * d[..., 1]) + d[..., 2] * d[..., 2]
+    np.fill_diagonal(r2, np.inf)
+    return [np.nonzero(row < rv * rv)[0] for row in r2]
+
+
+def tricky_positions(seed, n, L, rv):
+    g = np.random.default_rng(seed)
+    pos = g.uniform(0, L, size=(n, 3))
+    pos[0] = [0.0, 0.0, 0.0]
+    pos[1] = [np.nextafter(L, 0), 0.5, 0.5]
+    pos[2] = [L / 2, np.nextafter(L, 0), 0.0]
+    # pairs placed exactly at and one ulp around the list radius
+    base = np.array([L / 3, L / 3, L / 3])
+    for k, r in enumerate([rv, np.nextafter(rv, 0), np.nextafter(rv, 10)]):
+        pos[3 + 2 * k] = base + [0, 0, 1.3 * k]
+        pos[4 + 2 * k] = base + [r, 0, 1.3 * k]
+    return inputs.wrap_into_box(pos, [L, L, L])
+
+
+@pytest.mark.parametrize("seed,n,L", [(0, 300, 7.0), (1, 800, 9.5), (2, 60, 5.8)])
+def test_neighbor_sets_match_numpy_bruteforce(seed, n, L):
+    rv = 1.1224620483093730 + 0.3
+    pos = tricky_positions(seed, n, L, rv)
+    box = np.array([L, L, L])
+    ref = numpy_neighbors(pos, box, rv)
+    got = oracle.neighbors(pos, box, rv)
+    got_c = oracle.neighbors_cells(pos, box, rv)
+    for i in range(n):
+        assert np.array_equal(ref[i], got[i]), i
+        assert np.array_equal(ref[i], got_c[i]), i
+    # full list is exactly symmetric
+    for i in range(n):
+        for j in got[i]:
+            assert i in got[j]
+
+
+def random_system(seed, n_chains=6, chain_len=12, density=0.5, k_bend=1.5):
+    w = inputs.random_walk_chains(n_chains, chain_len, density, seed=seed)
+    # spread beads to avoid huge overlaps: capped WCA keeps forces moderate
+    return w
+
+
+def test_cells_equal_bruteforce_with_types_bonds_angles():
+    g = np.random.default_rng(5)
+    w = inputs.random_walk_chains(10, 20, 0.6, seed=11)
+    pos, box = w["pos"], w["box"]
+    n = pos.shape[0]
+    types = g.integers(0, 2, size=n).astype(np.int32)
+    pp = oracle.pair_table(2, {(0, 0): oracle.pair_params(1.0, 1.0, 2.5, caprad=0.7),
+                               (0, 1): oracle.pair_params(0.5, 1.1, WCA * 1.1, caprad=0.7),
+                               (1, 1): oracle.pair_params(1.5, 0.9, 2.0, shift=0.0, caprad=0.7)})
+    kw = dict(ntypes=2, type=types, bonds=w["bonds"], angles=w["angles"], k_bend=1.5)
+    Fb, ob = oracle.forces(pos, box, pp, use_cells=False, **kw)
+    Fc, oc = oracle.forces(pos, box, pp, use_cells=True, **kw)
+    np.testing.assert_allclose(Fc, Fb, rtol=1e-12, atol=1e-9)
+    for k in ("e_pair", "e_bond", "e_angle", "virial"):
+        assert oc[k] == pytest.approx(ob[k], rel=1e-11), k
+    np.testing.assert_allclose(oc["virial_tensor"], ob["virial_tensor"], rtol=1e-10, atol=1e-9)
+    # Newton's third law: the net force vanishes to rounding
+    scale = np.abs(Fb).sum()
+    assert np.abs(Fb.sum(axis=0)).max() < 1e-13 * scale
+    # trace of the virial tensor is the scalar virial
+    assert ob["virial_tensor"][:3].sum() == pytest.approx(ob["virial"], rel=1e-12)
+
+
+def total_energy(pos, box, pp, **kw):
+    _, o = oracle.forces(pos, box, pp, use_cells=False, **kw)
+    return o["e_pair"] + o["e_bond"] + o["e_angle"]
+
+
+def snake_on_lattice(m=4, a=1.1, jitter=0.08, seed=0):
+    """m^3 beads on a jittered cubic lattice of spacing a (no close contacts),
+    chained along a boustrophedon path: bonds ~a, angles along the path."""
+    g = np.random.default_rng(seed)
+    order = []
+    for z in range(m):
+        ys = range(m) if z % 2 == 0 else range(m - 1, -1, -1)
+        for k, y in enumerate(ys):
+            xs = range(m) if (k + z) % 2 == 0 else range(m - 1, -1, -1)
+            order += [(x, y, z) for x in xs]
+    pos = np.array(order, dtype=np.float64) * a + 0.5 * a + g.uniform(-jitter, jitter, (m ** 3, 3))
+    n = pos.shape[0]
+    bonds = np.array([[i, i + 1] for i in range(n - 1)], dtype=np.int32)
+    angles = np.array([[i, i + 1, i + 2] for i in range(n - 2)], dtype=np.int32)
+    return pos, np.array([m * a] * 3), bonds, angles
+
+
+def test_forces_are_minus_gradient_of_total_energy():
+    pos, box, bonds, angles = snake_on_lattice(m=5, seed=2)
+    # box 5.5 >= 2 rc: minimum image is exact for rc = 2.5
+    pp = oracle.pair_params(1.0, 1.0, 2.5)
+    kw = dict(bonds=bonds, angles=angles, k_bend=1.5)
+    F, _ = oracle.forces(pos, box, pp, use_cells=False, **kw)
+    h = 1e-6
+    for i in range(0, pos.shape[0], 7):
+        for d in range(3):
+            p1 = pos.copy(); p1[i, d] += h
+            p2 = pos.copy(); p2[i, d] -= h
+            fd = -(total_energy(p1, box, pp, **kw) - total_energy(p2, box, pp, **kw)) / (2 * h)
+            assert F[i, d] == pytest.approx(fd, rel=1e-6, abs=1e-6)
+
+
+def test_virial_identity_for_isolated_cluster():
+    # a compact cluster in a huge box: no periodic image interacts, so
+    # W = sum_pairs r_ij.f_ij equals sum_i r_i.F_i computed from positions
+    w = inputs.random_walk_chains(4, 10, 0.5, seed=8)
+    pos = w["pos"] - w["pos"].min(axis=0) + 1.0
+    span = pos.max() + 4.0
+    box = np.array([span * 3, span * 3, span * 3])
+    # unwrap chains: rebuild from bonds so the cluster is compact
+    pp = oracle.pair_params(1.0, 1.0, 2.5, caprad=0.8)
+    g = np.random.default_rng(1)
+    pos = np.cumsum(g.normal(size=(40, 3)) * 0.5, axis=0) + span
+    bonds = np.array([[i, i + 1] for i in range(39) if np.linalg.norm(pos[i + 1] - pos[i]) < 1.4],
+                     dtype=np.int32)
+    angles = np.array([[i, i + 1, i + 2] for i in range(38)], dtype=np.int32)
+    F, o = oracle.forces(pos, box, pp, bonds=bonds, angles=angles, k_bend=1.5, use_cells=False)
+    assert (pos * F).sum() == pytest.approx(o["virial"], rel=1e-10)
+    T = o["virial_tensor"]
+    assert (pos[:, 0] * F[:, 0]).sum() == pytest.approx(T[0], rel=1e-9, abs=1e-9)
+    assert (0.5 * (pos[:, 0] * F[:, 1] + pos[:, 1] * F[:, 0])).sum() == pytest.approx(T[3], rel=1e-9, abs=1e-9)
+
+
+def test_translation_invariance():
+    w = inputs.random_walk_chains(5, 10, 0.7, seed=4)
+    pp = oracle.pair_params(1.0, 1.0, WCA, caprad=0.8)
+    kw = dict(bonds=w["bonds"], angles=w["angles"], k_bend=1.5)
+    F1, o1 = oracle.forces(w["pos"], w["box"], pp, **kw)
+    shifted = inputs.wrap_into_box(w["pos"] + np.array([1.234, -3.3, 0.71]), w["box"])
+    F2, o2 = oracle.forces(shifted, w["box"], pp, **kw)
+    np.testing.assert_allclose(F2, F1, rtol=1e-9, atol=1e-9)
+    assert o2["e_pair"] == pytest.approx(o1["e_pair"], rel=1e-12)
+
+
+def test_broken_bond_and_nonfinite_are_errors():
+    box = np.array([10.0, 10.0, 10.0])
+    pos = np.array([[1.0, 1, 1], [2.6, 1, 1], [5, 5, 5]])
+    pp = oracle.pair_params(rc=WCA)
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.forces(pos, box, pp, bonds=np.array([[0, 1]]))
+    assert e.value.code == oracle.ERR_BOND_BROKEN
+    pos2 = pos.copy(); pos2[2, 0] = np.nan
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.forces(pos2, box, pp, bonds=np.array([[0, 2]]))
+    # a NaN fails the bond-length test first or the finiteness test
+    assert e.value.code in (oracle.ERR_NONFINITE, oracle.ERR_BOND_BROKEN)
+
+
+def test_neighbor_overflow_is_reported():
+    pos, box = inputs.fcc_lattice(4, 0.8442)
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.neighbors(pos, box, 2.8, cap=10)
+    assert e.value.code == oracle.ERR_NL_OVERFLOW
