@@ -1,0 +1,225 @@
+/*
+ * md.h -- C ABI of the MI355X (gfx950) short-range coarse-grained MD step.
+ *
+ * The operations follow the problem statement of ESPResSo++ (arXiv
+ * 2608.14911), section "Example usage": a periodic orthorhombic box
+ * (OrthorhombicBC), a Verlet list with a cutoff and a skin (VerletList,
+ * system.skin) over linked cells (CellGrid, section "Software design"),
+ * per-type-pair Lennard-Jones potentials with shift='auto' and an optional
+ * capping radius (LennardJones, LennardJonesCapped), bonded interactions
+ * (section "Functionality"; here FENE bonds and cosine bending angles),
+ * VelocityVerlet with a LangevinThermostat extension, particles given as
+ * (id, type, mass, pos, v) (storage.addParticles), integrator.run(n) and
+ * computeEnergy().
+ *
+ * Units: reduced LJ units (sigma, epsilon, mass, tau); "all lengths are in
+ * sigma" as the paper's example states.
+ *
+ * Memory ownership.  The caller owns every device buffer, including the
+ * workspace whose size md_workspace_bytes() returns; the library never
+ * allocates or frees device memory.  It owns only host-side bookkeeping and
+ * HIP events/graphs, released by md_destroy().  Input arrays are copied in
+ * by md_init()/md_set_state(); outputs are written to caller buffers.
+ *
+ * Streams.  Every device operation is enqueued on the hipStream_t passed to
+ * md_init() and is asynchronous unless stated otherwise.  Only
+ * md_observables(), md_history(), md_get_neighbors(), md_status_check() and
+ * md_timing_read() synchronise that stream.
+ *
+ * Errors.  Every function returns md_status (0 = MD_OK, negative = error);
+ * nothing is thrown across the ABI.  Argument and geometry errors are
+ * reported synchronously.  Conditions found on the device (neighbour-list
+ * overflow, a FENE bond stretched to R0, a non-finite position) are latched
+ * in a sticky device status word and reported by the next synchronising
+ * call; the state is then invalid until md_set_state() or a new md_init().
+ * md_last_error() returns a message for the last error on a handle.
+ */
+#ifndef MD_H
+#define MD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t md_status;
+enum {
+    MD_OK = 0,
+    MD_ERR_ARG = -1,            /* invalid argument (NULL, size, range)      */
+    MD_ERR_HIP = -2,            /* a HIP runtime call failed                 */
+    MD_ERR_BOX_TOO_SMALL = -3,  /* fewer than 3 cells of side >= rc+skin     */
+    MD_ERR_NL_OVERFLOW = -4,    /* a particle has more neighbours than the
+                                   list capacity; md_last_error() names the
+                                   capacity needed                            */
+    MD_ERR_BOND_BROKEN = -5,    /* FENE bond length reached R0               */
+    MD_ERR_NONFINITE = -6,      /* a position or velocity became NaN/Inf     */
+    MD_ERR_STATE = -7,          /* handle poisoned by an earlier device error */
+    MD_ERR_WORKSPACE = -8,      /* workspace too small or misaligned         */
+    MD_ERR_TOPOLOGY = -9        /* bonds/angles exceed the per-particle limits */
+};
+
+/* status-word bits (md_obs.status_flags) */
+#define MD_FLAG_NL_OVERFLOW 0x1u
+#define MD_FLAG_BOND_BROKEN 0x2u
+#define MD_FLAG_NONFINITE 0x4u
+
+enum { MD_NVE = 0, MD_LANGEVIN = 1 };    /* md_config.integrator      */
+enum { MD_FP64 = 0, MD_FP32 = 1 };       /* md_config.force_precision */
+
+#define MD_MAX_TYPES 4
+#define MD_MAX_BONDS_PER_PARTICLE 4
+#define MD_MAX_ANGLES_PER_PARTICLE 8
+#define MD_HISTORY_CAPACITY 8192
+
+/* md_config.flags */
+#define MD_CFG_VIRIAL_TENSOR 0x1  /* accumulate the 6-component virial every step */
+#define MD_CFG_NO_GRAPH 0x2       /* md_step launches kernels one by one, no hipGraph */
+
+/* One type pair of the LennardJones / LennardJonesCapped potential
+ * (section "Example usage"): u(r) = 4 eps [(sigma/r)^12 - (sigma/r)^6] - shift
+ * for r < rc; shift = NaN means 'auto' (u(rc) = 0); caprad > 0 freezes u and
+ * the force magnitude at their values at r = caprad for r < caprad.
+ * eps = 0 switches the pair off. */
+typedef struct md_pair_params {
+    double eps, sigma, rc, shift, caprad;
+} md_pair_params;
+
+typedef struct md_config {
+    uint32_t struct_size;      /* = sizeof(md_config); ABI version check */
+    int32_t n_types;           /* 1 .. MD_MAX_TYPES */
+    int64_t n_particles;       /* >= 1 */
+    double box[3];             /* periodic orthorhombic box lengths */
+    double dt;                 /* > 0 */
+    double skin;               /* > 0; Verlet list radius = max rc + skin */
+    int32_t integrator;        /* MD_NVE or MD_LANGEVIN */
+    int32_t force_precision;   /* MD_FP64 or MD_FP32 (pair and bonded math) */
+    double temperature;        /* Langevin kT */
+    double gamma;              /* Langevin friction */
+    uint64_t seed;             /* Philox4x64-10 key word 0 (noise stream 0) */
+    md_pair_params pair[MD_MAX_TYPES * MD_MAX_TYPES]; /* row-major [ti][tj], symmetric */
+    int64_t n_bonds;           /* FENE bonds */
+    int64_t n_angles;          /* cosine bending angles */
+    double fene_K, fene_R0;    /* u = -K R0^2/2 ln(1 - r^2/R0^2) */
+    double k_bend;             /* u = k (1 - cos theta), theta = 0 straight */
+    int32_t cell_factor;       /* reserved, 0 or 1: cells of side >= rc + skin */
+    int32_t nl_capacity;       /* neighbours per particle; 0 = from density */
+    int32_t block_size;        /* threads per block of the force kernel; 0 = 256 */
+    int32_t flags;             /* MD_CFG_* */
+} md_config;
+
+/* Observables of one step n (positions x_n, on-step velocities v_n). */
+typedef struct md_obs {
+    int64_t step;
+    double e_pair, e_bond, e_angle, e_kin, e_total;
+    double virial;              /* W = sum over pairs/bonds/angles of r_ij . f_ij */
+    double virial_tensor[6];    /* xx yy zz xy xz yz (only with MD_CFG_VIRIAL_TENSOR
+                                   or from md_observables) */
+    double pressure;            /* (2 K + W) / (3 V) */
+    double temperature;         /* 2 K / ndof; ndof = 3N-3 (NVE) or 3N (Langevin) */
+    int64_t n_rebuilds;         /* neighbour-list builds since md_init */
+    uint32_t status_flags;      /* MD_FLAG_* latched on the device */
+    int32_t nl_max_count;       /* largest neighbour count at the last build */
+} md_obs;
+
+/* Per-kernel timing collected with HIP events on the handle's stream. */
+typedef struct md_timing {
+    int64_t n_step_kernels;     /* launches of the fused force+integrate kernel */
+    double ms_step_kernels;     /* their summed duration */
+    int64_t n_rebuild;          /* steps whose rebuild stage was timed */
+    double ms_rebuild;          /* summed duration of the rebuild stage (gated kernels) */
+    int64_t n_finalize;
+    double ms_finalize;
+} md_timing;
+
+typedef struct md_handle_s* md_handle;
+
+/* Bytes of device workspace md_init needs for this configuration (host
+ * arithmetic only, no device call).  Returns MD_ERR_ARG for an invalid
+ * config and MD_ERR_BOX_TOO_SMALL when fewer than 3 cells fit per side. */
+md_status md_workspace_bytes(const md_config* cfg, size_t* bytes);
+
+/* Create a simulation (storage.addParticles + decompose of the paper).
+ *   pos, vel      device, FP64 [N][3], particle-id (tag) order; positions may
+ *                 lie outside the box, they are folded in with image counters
+ *   type          device int32 [N] in 0..n_types-1, or NULL (all type 0)
+ *   mass_by_type  host FP64 [n_types], > 0
+ *   bonds         host int32 [n_bonds][2] particle ids, or NULL if n_bonds = 0
+ *   angles        host int32 [n_angles][3] particle ids (centre in the middle),
+ *                 or NULL if n_angles = 0
+ *   workspace     device, >= md_workspace_bytes(), 256-byte aligned,
+ *                 owned by the caller and kept alive until md_destroy
+ *   stream        hipStream_t (NULL = default stream)
+ * Builds cells and the Verlet list.  Velocities are on-step velocities.
+ * Synchronises the stream once (topology upload).  */
+md_status md_init(const md_config* cfg, const double* pos, const double* vel, const int32_t* type,
+                  const double* mass_by_type, const int32_t* bonds, const int32_t* angles,
+                  void* workspace, size_t ws_bytes, void* stream, md_handle* out);
+
+/* Change run parameters without touching the state: dt, temperature, gamma,
+ * seed, integrator, force_precision, the pair table (e.g. switching
+ * LennardJonesCapped to LennardJones as the paper's example does),
+ * fene_K/R0, k_bend, flags.  n_particles, n_types, box, skin, n_bonds and
+ * n_angles must equal those given to md_init; a pair table whose cutoffs
+ * exceed the list radius fixed at md_init is rejected. */
+md_status md_set_params(md_handle h, const md_config* cfg);
+
+/* Force a cell sort and neighbour-list build at the current positions. */
+md_status md_build_neighbors(md_handle h);
+
+/* Conservative forces at the current positions (no thermostat term), FP64
+ * [N][3] in tag order into device f_out (NULL: only observables update). */
+md_status md_forces(md_handle h, double* f_out);
+
+/* Advance nsteps of velocity Verlet (+ Langevin).  Each step: rebuild the
+ * list when some particle moved more than skin/2 since the last build,
+ * evaluate forces, integrate, reduce energy and virial in FP64 into the
+ * history ring.  Asynchronous; no host synchronisation. */
+md_status md_step(md_handle h, int64_t nsteps);
+
+/* Energies, virial, pressure and temperature at the current step
+ * (computeEnergy() of the paper), on-step velocities.  Synchronises. Returns
+ * the error code of a latched device condition, with *out still filled. */
+md_status md_observables(md_handle h, md_obs* out);
+
+/* Copy the per-step observables recorded since the last md_history call
+ * (at most MD_HISTORY_CAPACITY of the most recent steps) to host out[max];
+ * *n receives the number written.  Synchronises. */
+md_status md_history(md_handle h, md_obs* out, int64_t max, int64_t* n);
+
+/* Raw state in tag order, device buffers: pos [N][3] FP64 in [0,L), vel
+ * [N][3] FP64, image [N][3] int32, pos_build [N][3] FP64 = positions at the
+ * last neighbour-list build (each may be NULL); *step and *vel_half host
+ * (may be NULL).  vel_half = 1: vel holds v_{step-1/2}; 0: the on-step
+ * v_step.  A pending list rebuild is carried out first.  Restoring the
+ * tuple with md_set_state (pos_build included) continues the run bit for
+ * bit: the cell order is a function of the build positions and the ids.  */
+md_status md_get_state(md_handle h, double* pos, double* vel, int32_t* image, double* pos_build,
+                       int64_t* step, int32_t* vel_half);
+/* Replace the state (same particles, types, topology).  pos_build NULL:
+ * the list is built at pos.  Clears the latched device status. */
+md_status md_set_state(md_handle h, const double* pos, const double* vel, const int32_t* image,
+                       const double* pos_build, int64_t step, int32_t vel_half);
+
+/* Current Verlet list in tag space: count [N] and idx [N][cap] device int32
+ * (rows unsorted; entries past count are untouched).  Returns
+ * MD_ERR_NL_OVERFLOW if cap is smaller than the longest row.  Synchronises. */
+md_status md_get_neighbors(md_handle h, int32_t* count, int32_t* idx, int32_t cap);
+
+/* Synchronise and return the latched device status as an md_status. */
+md_status md_status_check(md_handle h);
+
+/* Enable (1) / disable (0) HIP-event timing of the kernels md_step launches
+ * (forces kernel-by-kernel launches while enabled); read and reset it. */
+md_status md_timing_enable(md_handle h, int32_t enable);
+md_status md_timing_read(md_handle h, md_timing* out);
+
+md_status md_destroy(md_handle h);
+const char* md_status_string(md_status s);
+const char* md_last_error(md_handle h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MD_H */

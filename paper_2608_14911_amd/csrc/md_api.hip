@@ -1,0 +1,740 @@
+// Host runtime and C ABI of the short-range MD step (include/md.h).
+//
+// The handle plans the cell grid, carves the caller's workspace, keeps
+// host mirrors of the step counter and the position-buffer parity, and
+// enqueues every step as
+//     rebuild stage (8 kernels that return at once unless a particle moved
+//     more than skin/2) -> fused force+integrate kernel -> 1-block finalize
+// on the caller's stream, optionally replayed from a hipGraph of two steps.
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <new>
+#include <string>
+#include <vector>
+
+#include "md_internal.h"
+
+using namespace md;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+struct EvQuad {
+    hipEvent_t e[4];
+};
+
+}  // namespace
+
+struct md_handle_s {
+    md_config cfg;
+    Geom g;
+    Bufs b;
+    PairTable pt;
+    Dyn dy;
+    hipStream_t stream = nullptr;
+    int parity = 0;
+    int64_t host_step = 0;
+    int32_t vel_half = 0;
+    int bonded = 0, single = 1, fp64 = 0;
+    int step_grid = 1;
+    int64_t hist_next = 0;
+    std::string err;
+    uint8_t* ws = nullptr;
+    size_t ws_bytes = 0;
+    // graph of two steps, valid for one parity
+    hipGraphExec_t gexec = nullptr;
+    int graph_parity = -1;
+    // timing
+    bool timing = false;
+    std::vector<EvQuad> ev_free, ev_pending;
+    md_timing tacc;
+};
+
+// ------------------------------------------------------------------ helpers
+
+static md_status fail(md_handle h, md_status st, const std::string& msg) {
+    if (h) h->err = msg;
+    g_last_error = msg;
+    return st;
+}
+
+#define HIP_TRY(h, call)                                                                   \
+    do {                                                                                   \
+        hipError_t e_ = (call);                                                            \
+        if (e_ != hipSuccess)                                                              \
+            return fail((h), MD_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+static md_status validate(const md_config* c, std::string* why) {
+    if (!c) { *why = "config is NULL"; return MD_ERR_ARG; }
+    if (c->struct_size != sizeof(md_config)) { *why = "md_config.struct_size mismatch (ABI version)"; return MD_ERR_ARG; }
+    if (c->n_types < 1 || c->n_types > MD_MAX_TYPES) { *why = "n_types out of range"; return MD_ERR_ARG; }
+    if (c->n_particles < 1 || c->n_particles > (int64_t)0x3fffffff) { *why = "n_particles out of range"; return MD_ERR_ARG; }
+    for (int d = 0; d < 3; ++d)
+        if (!(c->box[d] > 0.0) || !isfinite(c->box[d])) { *why = "box must be positive and finite"; return MD_ERR_ARG; }
+    if (!(c->dt > 0.0) || !isfinite(c->dt)) { *why = "dt must be > 0"; return MD_ERR_ARG; }
+    if (!(c->skin > 0.0) || !isfinite(c->skin)) { *why = "skin must be > 0"; return MD_ERR_ARG; }
+    if (c->integrator != MD_NVE && c->integrator != MD_LANGEVIN) { *why = "unknown integrator"; return MD_ERR_ARG; }
+    if (c->force_precision != MD_FP64 && c->force_precision != MD_FP32) { *why = "unknown force precision"; return MD_ERR_ARG; }
+    if (c->integrator == MD_LANGEVIN && (!(c->gamma >= 0.0) || !(c->temperature >= 0.0))) {
+        *why = "Langevin gamma and temperature must be >= 0";
+        return MD_ERR_ARG;
+    }
+    const int nt = c->n_types;
+    for (int a = 0; a < nt; ++a)
+        for (int bb = 0; bb < nt; ++bb) {
+            const md_pair_params& p = c->pair[a * MD_MAX_TYPES + bb];
+            const md_pair_params& q = c->pair[bb * MD_MAX_TYPES + a];
+            if (!(p.rc > 0.0) || !(p.sigma > 0.0) || !(p.eps >= 0.0) || !(p.caprad >= 0.0) || !isfinite(p.rc)) {
+                *why = "pair parameters: need rc > 0, sigma > 0, eps >= 0, caprad >= 0";
+                return MD_ERR_ARG;
+            }
+            if (memcmp(&p, &q, sizeof(p)) != 0) { *why = "pair table must be symmetric"; return MD_ERR_ARG; }
+        }
+    if (c->n_bonds < 0 || c->n_angles < 0) { *why = "negative bond/angle count"; return MD_ERR_ARG; }
+    if (c->n_bonds > 0 && !(c->fene_R0 > 0.0 && c->fene_K >= 0.0)) { *why = "FENE needs R0 > 0, K >= 0"; return MD_ERR_ARG; }
+    if (c->nl_capacity < 0 || c->nl_capacity > 4096) { *why = "nl_capacity out of range"; return MD_ERR_ARG; }
+    if (c->cell_factor < 0 || c->cell_factor > 1) { *why = "cell_factor must be 0 or 1"; return MD_ERR_ARG; }
+    return MD_OK;
+}
+
+static double rc_max_of(const md_config* c) {
+    double m = 0.0;
+    for (int a = 0; a < c->n_types; ++a)
+        for (int bb = 0; bb < c->n_types; ++bb) m = fmax(m, c->pair[a * MD_MAX_TYPES + bb].rc);
+    return m;
+}
+
+static md_status plan_geom(const md_config* c, Geom* g, std::string* why) {
+    md_status st = validate(c, why);
+    if (st != MD_OK) return st;
+    memset(g, 0, sizeof(*g));
+    g->n = c->n_particles;
+    g->ntypes = c->n_types;
+    const double rv = rc_max_of(c) + c->skin;
+    g->rv2 = rv * rv;
+    g->disp2 = (0.5 * c->skin) * (0.5 * c->skin);
+    g->ncell = 1;
+    for (int d = 0; d < 3; ++d) {
+        g->L[d] = c->box[d];
+        g->hL[d] = 0.5 * c->box[d];
+        int nc = (int)floor(c->box[d] / (rv * (1.0 + 1e-12)));
+        if (nc < 3) {
+            char buf[160];
+            snprintf(buf, sizeof buf, "box %.6g holds %d cells of side >= rc+skin = %.6g along axis %d; need >= 3",
+                     c->box[d], nc, rv, d);
+            *why = buf;
+            return MD_ERR_BOX_TOO_SMALL;
+        }
+        if (nc > 4096) nc = 4096;
+        g->nc[d] = nc;
+        g->invh[d] = (double)nc / c->box[d];
+        g->ncell *= nc;
+    }
+    if (c->nl_capacity > 0) {
+        g->cap = c->nl_capacity;
+    } else {
+        const double vol = c->box[0] * c->box[1] * c->box[2];
+        const double expect = (double)c->n_particles / vol * (4.0 / 3.0) * M_PI * rv * rv * rv;
+        int cap = (int)ceil(1.5 * expect + 32.0);
+        cap = (cap + 7) & ~7;
+        if (cap < 16) cap = 16;
+        if (cap > 4096) cap = 4096;
+        g->cap = cap;
+    }
+    return MD_OK;
+}
+
+// Carve the workspace; with base == nullptr only the size is computed.
+static size_t carve(const md_config* c, const Geom& g, int step_grid, uint8_t* base, Bufs* b) {
+    const int64_t n = g.n;
+    const bool bonded = c->n_bonds > 0 || c->n_angles > 0;
+    const int maxb = c->n_bonds > 0 ? MD_MAX_BONDS_PER_PARTICLE : 0;
+    const int maxa = c->n_angles > 0 ? MD_MAX_ANGLES_PER_PARTICLE : 0;
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> void* {
+        void* p = base ? (void*)(base + off) : nullptr;
+        off += align256(bytes);
+        return p;
+    };
+    Bufs t;
+    memset(&t, 0, sizeof(t));
+    t.ctl = (DevCtl*)take(sizeof(DevCtl));
+    t.cur = (double*)take(sizeof(double) * kHistRec);
+    t.hist = (double*)take(sizeof(double) * kHistRec * MD_HISTORY_CAPACITY);
+    t.partials = (double*)take(sizeof(double) * kNacc * (size_t)step_grid);
+    t.x[0] = (double4*)take(sizeof(double4) * n);
+    t.x[1] = (double4*)take(sizeof(double4) * n);
+    t.v = (double*)take(sizeof(double) * 3 * n);
+    t.xb = (double*)take(sizeof(double) * 3 * n);
+    t.img = (int32_t*)take(sizeof(int32_t) * 3 * n);
+    t.type_t = (int32_t*)take(sizeof(int32_t) * n);
+    t.tag = (int32_t*)take(sizeof(int32_t) * n);
+    t.inv = (int32_t*)take(sizeof(int32_t) * n);
+    t.cellid = (uint32_t*)take(sizeof(uint32_t) * n);
+    t.ccount = (int32_t*)take(sizeof(int32_t) * g.ncell);
+    t.cstart = (int32_t*)take(sizeof(int32_t) * (g.ncell + 1));
+    t.bsum = (int32_t*)take(sizeof(int32_t) * kScanBlocks);
+    t.tmp = (int32_t*)take(sizeof(int32_t) * n);
+    t.xt = (double4*)take(sizeof(double4) * n);
+    t.vt = (double*)take(sizeof(double) * 3 * n);
+    t.imgt = (int32_t*)take(sizeof(int32_t) * 3 * n);
+    t.tagt = (int32_t*)take(sizeof(int32_t) * n);
+    t.ncount = (int32_t*)take(sizeof(int32_t) * n);
+    t.nl = (int32_t*)take(sizeof(int32_t) * (size_t)g.cap * n);
+    if (bonded) {
+        t.tcnt_t = (int32_t*)take(sizeof(int32_t) * n);
+        t.tcnt_s = (int32_t*)take(sizeof(int32_t) * n);
+        if (maxb) {
+            t.bp_t = (int32_t*)take(sizeof(int32_t) * (size_t)maxb * n);
+            t.bp_s = (int32_t*)take(sizeof(int32_t) * (size_t)maxb * n);
+        }
+        if (maxa) {
+            t.ang_t = (int2*)take(sizeof(int2) * (size_t)maxa * n);
+            t.ang_s = (int2*)take(sizeof(int2) * (size_t)maxa * n);
+        }
+    }
+    t.maxb = maxb;
+    t.maxa = maxa;
+    if (b) *b = t;
+    return off;
+}
+
+static int step_grid_of(int64_t n) { return (int)((n + kBlock - 1) / kBlock); }
+
+static void fill_params(md_handle h, const md_config* c) {
+    PairTable& pt = h->pt;
+    memset(&pt, 0, sizeof(pt));
+    for (int a = 0; a < c->n_types; ++a)
+        for (int bb = 0; bb < c->n_types; ++bb) {
+            const int tp = a * MD_MAX_TYPES + bb;
+            const md_pair_params& p = c->pair[tp];
+            double shift;
+            if (isnan(p.shift)) {
+                double s2 = (p.sigma * p.sigma) / (p.rc * p.rc);
+                double s6 = s2 * s2 * s2;
+                shift = 4.0 * p.eps * (s6 * s6 - s6);
+            } else {
+                shift = p.shift;
+            }
+            PairCoef<double> d;
+            d.eps4 = 4.0 * p.eps;
+            d.eps24 = 24.0 * p.eps;
+            d.sig2 = p.sigma * p.sigma;
+            d.rc2 = p.rc * p.rc;
+            d.shift = shift;
+            d.cap2 = p.caprad > 0.0 ? p.caprad * p.caprad : 0.0;
+            d.ucap = 0.0;
+            d.fcap = 0.0;
+            if (p.caprad > 0.0) {
+                double s2 = d.sig2 / d.cap2, s6 = s2 * s2 * s2, s12 = s6 * s6;
+                d.ucap = 4.0 * p.eps * (s12 - s6) - shift;
+                d.fcap = 24.0 * p.eps * (2.0 * s12 - s6) / d.cap2 * sqrt(d.cap2);
+            }
+            pt.d[tp] = d;
+            pt.f[tp] = PairCoef<float>{(float)d.eps4, (float)d.eps24, (float)d.sig2, (float)d.rc2,
+                                       (float)d.shift, (float)d.cap2, (float)d.ucap, (float)d.fcap};
+            pt.rc2d[tp] = p.rc * p.rc;
+        }
+    Dyn& dy = h->dy;
+    memset(&dy, 0, sizeof(dy));
+    dy.dt = c->dt;
+    dy.langevin = c->integrator == MD_LANGEVIN;
+    dy.seed = c->seed;
+    dy.fene_K = c->fene_K;
+    dy.fene_R02 = c->fene_R0 * c->fene_R0;
+    dy.fene_halfKR02 = 0.5 * c->fene_K * c->fene_R0 * c->fene_R0;
+    dy.fene_Kf = (float)dy.fene_K;
+    dy.fene_R02f = (float)dy.fene_R02;
+    dy.fene_halfKR02f = (float)dy.fene_halfKR02;
+    dy.k_bend = c->k_bend;
+    dy.k_bendf = (float)c->k_bend;
+}
+
+static void fill_masses(md_handle h, const double* mass_by_type) {
+    const md_config* c = &h->cfg;
+    for (int t = 0; t < MD_MAX_TYPES; ++t) {
+        const double m = t < c->n_types ? mass_by_type[t] : 1.0;
+        h->dy.mass[t] = m;
+        h->dy.hdtm[t] = 0.5 * c->dt / m;
+        h->dy.gm[t] = c->gamma * m;
+        h->dy.amp[t] = c->integrator == MD_LANGEVIN ? sqrt(2.0 * c->gamma * m * c->temperature / c->dt) : 0.0;
+    }
+}
+
+static StepArgs make_args(md_handle h, int mode, int tensor, double* f_out) {
+    StepArgs a;
+    memset(&a, 0, sizeof(a));
+    a.g = h->g;
+    a.b = h->b;
+    a.pt = h->pt;
+    a.dy = h->dy;
+    a.parity = h->parity;
+    a.mode = mode;
+    a.tensor = tensor;
+    a.f_out = f_out;
+    return a;
+}
+
+static void drop_graph(md_handle h) {
+    if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
+    h->gexec = nullptr;
+    h->graph_parity = -1;
+}
+
+// Enqueue one full step at the handle's current parity and advance the
+// host mirrors.  Events (timing mode) bracket the three stages.
+static hipError_t enqueue_step(md_handle h, const EvQuad* q) {
+    hipError_t e;
+    if (q) (void)hipEventRecord(q->e[0], h->stream);
+    e = launch_rebuild(h->g, h->b, h->parity, h->bonded, h->stream, nullptr, nullptr);
+    if (e != hipSuccess) return e;
+    if (q) (void)hipEventRecord(q->e[1], h->stream);
+    StepArgs a = make_args(h, MODE_STEP, (h->cfg.flags & MD_CFG_VIRIAL_TENSOR) ? 1 : 0, nullptr);
+    e = launch_step(a, h->fp64, h->single, h->bonded, kBlock, h->stream);
+    if (e != hipSuccess) return e;
+    if (q) (void)hipEventRecord(q->e[2], h->stream);
+    e = launch_finalize(h->b, h->step_grid, MODE_STEP, h->stream);
+    if (e != hipSuccess) return e;
+    if (q) (void)hipEventRecord(q->e[3], h->stream);
+    h->parity ^= 1;
+    h->host_step += 1;
+    h->vel_half = 1;
+    return hipSuccess;
+}
+
+static md_status build_graph(md_handle h) {
+    drop_graph(h);
+    hipGraph_t graph = nullptr;
+    const int p0 = h->parity;
+    const int64_t s0 = h->host_step;
+    HIP_TRY(h, hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
+    hipError_t e1 = enqueue_step(h, nullptr);
+    hipError_t e2 = e1 == hipSuccess ? enqueue_step(h, nullptr) : e1;
+    hipError_t e3 = hipStreamEndCapture(h->stream, &graph);
+    // capture does not execute anything: restore the mirrors
+    h->parity = p0;
+    h->host_step = s0;
+    if (e2 != hipSuccess || e3 != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return fail(h, MD_ERR_HIP, std::string("graph capture failed: ") +
+                                       hipGetErrorString(e2 != hipSuccess ? e2 : e3));
+    }
+    hipError_t e4 = hipGraphInstantiate(&h->gexec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e4 != hipSuccess) {
+        h->gexec = nullptr;
+        return fail(h, MD_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e4));
+    }
+    h->graph_parity = p0;
+    return MD_OK;
+}
+
+static md_status rebuild_now(md_handle h, int force) {
+    if (force) HIP_TRY(h, launch_set_ctl(h->b, -1, -1, 1, 0, h->stream));
+    HIP_TRY(h, launch_rebuild(h->g, h->b, h->parity, h->bonded, h->stream, nullptr, nullptr));
+    HIP_TRY(h, launch_clear_rebuild(h->b, h->stream));
+    return MD_OK;
+}
+
+static md_status status_to_code(md_handle h, uint32_t st, int32_t nl_max) {
+    if (st & MD_FLAG_NL_OVERFLOW) {
+        char buf[160];
+        snprintf(buf, sizeof buf, "neighbour list overflow: a particle has %d neighbours, capacity %d; "
+                                  "re-create with md_config.nl_capacity >= %d", nl_max, h->g.cap, nl_max);
+        return fail(h, MD_ERR_NL_OVERFLOW, buf);
+    }
+    if (st & MD_FLAG_BOND_BROKEN) return fail(h, MD_ERR_BOND_BROKEN, "a FENE bond reached R0");
+    if (st & MD_FLAG_NONFINITE) return fail(h, MD_ERR_NONFINITE, "non-finite position or velocity");
+    if (st & MD_FLAG_BAD_TYPE) return fail(h, MD_ERR_ARG, "particle type outside 0..n_types-1");
+    return MD_OK;
+}
+
+static md_status read_ctl(md_handle h, DevCtl* c) {
+    HIP_TRY(h, hipMemcpyAsync(c, h->b.ctl, sizeof(DevCtl), hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    return MD_OK;
+}
+
+static void fill_obs(md_handle h, const double* rec, md_obs* o) {
+    memset(o, 0, sizeof(*o));
+    o->step = (int64_t)rec[H_STEP];
+    o->e_pair = rec[H_EPAIR];
+    o->e_bond = rec[H_EBOND];
+    o->e_angle = rec[H_EANGLE];
+    o->e_kin = rec[H_EKIN];
+    o->e_total = rec[H_EPAIR] + rec[H_EBOND] + rec[H_EANGLE] + rec[H_EKIN];
+    o->virial = rec[H_VIR];
+    for (int k = 0; k < 6; ++k) o->virial_tensor[k] = rec[H_T0 + k];
+    const double V = h->g.L[0] * h->g.L[1] * h->g.L[2];
+    o->pressure = (2.0 * rec[H_EKIN] + rec[H_VIR]) / (3.0 * V);
+    const double n = (double)h->g.n;
+    const double ndof = h->cfg.integrator == MD_LANGEVIN ? 3.0 * n : (n > 1 ? 3.0 * n - 3.0 : 3.0);
+    o->temperature = 2.0 * rec[H_EKIN] / ndof;
+    o->n_rebuilds = (int64_t)rec[H_NREB];
+    o->status_flags = (uint32_t)rec[H_STATUS];
+    o->nl_max_count = (int32_t)rec[H_NLMAX];
+}
+
+static md_status upload_topology(md_handle h, const int32_t* bonds, const int32_t* angles) {
+    const md_config* c = &h->cfg;
+    const int64_t n = h->g.n;
+    std::vector<int32_t> tcnt(n, 0), bp((size_t)h->b.maxb * n, 0);
+    std::vector<int32_t> ang((size_t)h->b.maxa * n * 2, 0);
+    std::vector<int32_t> nb(n, 0), na(n, 0);
+    for (int64_t k = 0; k < c->n_bonds; ++k) {
+        const int64_t p = bonds[2 * k], q = bonds[2 * k + 1];
+        if (p < 0 || q < 0 || p >= n || q >= n || p == q) return fail(h, MD_ERR_TOPOLOGY, "bond with invalid particle id");
+        if (nb[p] >= MD_MAX_BONDS_PER_PARTICLE || nb[q] >= MD_MAX_BONDS_PER_PARTICLE)
+            return fail(h, MD_ERR_TOPOLOGY, "more than MD_MAX_BONDS_PER_PARTICLE bonds on a particle");
+        bp[(size_t)nb[p]++ * n + p] = (int32_t)q;
+        bp[(size_t)nb[q]++ * n + q] = (int32_t)p;
+    }
+    for (int64_t k = 0; k < c->n_angles; ++k) {
+        const int64_t ids[3] = {angles[3 * k], angles[3 * k + 1], angles[3 * k + 2]};
+        for (int r = 0; r < 3; ++r)
+            if (ids[r] < 0 || ids[r] >= n) return fail(h, MD_ERR_TOPOLOGY, "angle with invalid particle id");
+        if (ids[0] == ids[1] || ids[1] == ids[2] || ids[0] == ids[2])
+            return fail(h, MD_ERR_TOPOLOGY, "angle with repeated particle");
+        for (int r = 0; r < 3; ++r)
+            if (na[ids[r]] >= MD_MAX_ANGLES_PER_PARTICLE)
+                return fail(h, MD_ERR_TOPOLOGY, "more than MD_MAX_ANGLES_PER_PARTICLE angles on a particle");
+        // per member: role and the two other members in (a, b, c) order
+        const int64_t others[3][2] = {{ids[1], ids[2]}, {ids[0], ids[2]}, {ids[0], ids[1]}};
+        for (int r = 0; r < 3; ++r) {
+            const int64_t p = ids[r];
+            const size_t slot = (size_t)na[p]++ * n + p;
+            ang[2 * slot] = (int32_t)(others[r][0] | ((int64_t)r << 30));
+            ang[2 * slot + 1] = (int32_t)others[r][1];
+        }
+    }
+    for (int64_t p = 0; p < n; ++p) tcnt[p] = nb[p] | (na[p] << 8);
+    HIP_TRY(h, hipMemcpyAsync(h->b.tcnt_t, tcnt.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, h->stream));
+    if (h->b.maxb)
+        HIP_TRY(h, hipMemcpyAsync(h->b.bp_t, bp.data(), sizeof(int32_t) * bp.size(), hipMemcpyHostToDevice, h->stream));
+    if (h->b.maxa)
+        HIP_TRY(h, hipMemcpyAsync(h->b.ang_t, ang.data(), sizeof(int32_t) * ang.size(), hipMemcpyHostToDevice, h->stream));
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    return MD_OK;
+}
+
+// ------------------------------------------------------------------ ABI
+
+extern "C" {
+
+const char* md_status_string(md_status s) {
+    switch (s) {
+        case MD_OK: return "MD_OK";
+        case MD_ERR_ARG: return "MD_ERR_ARG";
+        case MD_ERR_HIP: return "MD_ERR_HIP";
+        case MD_ERR_BOX_TOO_SMALL: return "MD_ERR_BOX_TOO_SMALL";
+        case MD_ERR_NL_OVERFLOW: return "MD_ERR_NL_OVERFLOW";
+        case MD_ERR_BOND_BROKEN: return "MD_ERR_BOND_BROKEN";
+        case MD_ERR_NONFINITE: return "MD_ERR_NONFINITE";
+        case MD_ERR_STATE: return "MD_ERR_STATE";
+        case MD_ERR_WORKSPACE: return "MD_ERR_WORKSPACE";
+        case MD_ERR_TOPOLOGY: return "MD_ERR_TOPOLOGY";
+        default: return "MD_ERR_UNKNOWN";
+    }
+}
+
+const char* md_last_error(md_handle h) { return h ? h->err.c_str() : g_last_error.c_str(); }
+
+md_status md_workspace_bytes(const md_config* cfg, size_t* bytes) {
+    if (!bytes) return fail(nullptr, MD_ERR_ARG, "bytes is NULL");
+    Geom g;
+    std::string why;
+    md_status st = plan_geom(cfg, &g, &why);
+    if (st != MD_OK) return fail(nullptr, st, why);
+    *bytes = carve(cfg, g, step_grid_of(g.n), nullptr, nullptr);
+    return MD_OK;
+}
+
+md_status md_init(const md_config* cfg, const double* pos, const double* vel, const int32_t* type,
+                  const double* mass_by_type, const int32_t* bonds, const int32_t* angles, void* workspace,
+                  size_t ws_bytes, void* stream, md_handle* out) {
+    if (!out) return fail(nullptr, MD_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    Geom g;
+    std::string why;
+    md_status st = plan_geom(cfg, &g, &why);
+    if (st != MD_OK) return fail(nullptr, st, why);
+    if (!pos || !vel || !mass_by_type || !workspace) return fail(nullptr, MD_ERR_ARG, "NULL pos/vel/mass/workspace");
+    if (cfg->n_bonds > 0 && !bonds) return fail(nullptr, MD_ERR_ARG, "n_bonds > 0 but bonds is NULL");
+    if (cfg->n_angles > 0 && !angles) return fail(nullptr, MD_ERR_ARG, "n_angles > 0 but angles is NULL");
+    for (int t = 0; t < cfg->n_types; ++t)
+        if (!(mass_by_type[t] > 0.0) || !isfinite(mass_by_type[t])) return fail(nullptr, MD_ERR_ARG, "mass must be > 0");
+    const int sg = step_grid_of(g.n);
+    const size_t need = carve(cfg, g, sg, nullptr, nullptr);
+    if (ws_bytes < need) return fail(nullptr, MD_ERR_WORKSPACE, "workspace smaller than md_workspace_bytes()");
+    if (((uintptr_t)workspace & 255) != 0) return fail(nullptr, MD_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+
+    md_handle h = new (std::nothrow) md_handle_s();
+    if (!h) return fail(nullptr, MD_ERR_ARG, "out of host memory");
+    h->cfg = *cfg;
+    h->g = g;
+    h->stream = (hipStream_t)stream;
+    h->ws = (uint8_t*)workspace;
+    h->ws_bytes = ws_bytes;
+    h->step_grid = sg;
+    h->bonded = (cfg->n_bonds > 0 || cfg->n_angles > 0) ? 1 : 0;
+    h->single = cfg->n_types == 1 ? 1 : 0;
+    h->fp64 = cfg->force_precision == MD_FP64 ? 1 : 0;
+    memset(&h->tacc, 0, sizeof(h->tacc));
+    carve(cfg, g, sg, h->ws, &h->b);
+    fill_params(h, cfg);
+    fill_masses(h, mass_by_type);
+
+    auto bail = [&](md_status s) {
+        md_destroy(h);
+        return s;
+    };
+    md_status r;
+    // control block and cell counters start at zero
+    if (launch_zero_i32((int32_t*)h->b.ctl, sizeof(DevCtl) / 4, h->stream) != hipSuccess ||
+        launch_zero_i32(h->b.ccount, g.ncell, h->stream) != hipSuccess ||
+        launch_zero_i32(h->b.ncount, g.n, h->stream) != hipSuccess ||
+        launch_zero_i32((int32_t*)h->b.partials, 2 * kNacc * (int64_t)sg, h->stream) != hipSuccess)
+        return bail(fail(nullptr, MD_ERR_HIP, "kernel launch failed during init"));
+    if (type) {
+        if (launch_copy_i32(h->b.type_t, type, g.n, h->stream) != hipSuccess)
+            return bail(fail(nullptr, MD_ERR_HIP, "type copy failed"));
+    } else if (launch_zero_i32(h->b.type_t, g.n, h->stream) != hipSuccess) {
+        return bail(fail(nullptr, MD_ERR_HIP, "type init failed"));
+    }
+    if (launch_init_load(g, h->b, 0, pos, vel, h->b.type_t, nullptr, h->stream) != hipSuccess)
+        return bail(fail(nullptr, MD_ERR_HIP, "state upload failed"));
+    if (h->bonded && (r = upload_topology(h, bonds, angles)) != MD_OK) {
+        g_last_error = h->err;
+        return bail(r);
+    }
+    if (launch_set_ctl(h->b, 0, 0, 1, 0, h->stream) != hipSuccess)
+        return bail(fail(nullptr, MD_ERR_HIP, "control init failed"));
+    if ((r = rebuild_now(h, 0)) != MD_OK) { g_last_error = h->err; return bail(r); }
+    DevCtl c;
+    if ((r = read_ctl(h, &c)) != MD_OK) { g_last_error = h->err; return bail(r); }
+    if ((r = status_to_code(h, c.status, c.nl_max)) != MD_OK) { g_last_error = h->err; return bail(r); }
+    *out = h;
+    return MD_OK;
+}
+
+md_status md_set_params(md_handle h, const md_config* cfg) {
+    if (!h) return fail(nullptr, MD_ERR_ARG, "NULL handle");
+    Geom g;
+    std::string why;
+    md_status st = plan_geom(cfg, &g, &why);
+    if (st != MD_OK) return fail(h, st, why);
+    const md_config& o = h->cfg;
+    if (cfg->n_particles != o.n_particles || cfg->n_types != o.n_types || cfg->n_bonds != o.n_bonds ||
+        cfg->n_angles != o.n_angles || memcmp(cfg->box, o.box, sizeof(o.box)) != 0)
+        return fail(h, MD_ERR_ARG, "md_set_params cannot change N, types, box or topology");
+    if (g.rv2 > h->g.rv2 * (1.0 + 1e-15))
+        return fail(h, MD_ERR_ARG, "cutoff + skin exceeds the list radius fixed at md_init");
+    double mass[MD_MAX_TYPES];
+    for (int t = 0; t < MD_MAX_TYPES; ++t) mass[t] = h->dy.mass[t];
+    // keep the geometry (list radius, cells, capacity) of md_init; the
+    // rebuild threshold follows the new skin only if it is not larger
+    const double old_disp2 = h->g.disp2;
+    h->cfg = *cfg;
+    h->cfg.skin = o.skin;
+    h->fp64 = cfg->force_precision == MD_FP64 ? 1 : 0;
+    fill_params(h, cfg);
+    fill_masses(h, mass);
+    h->g.disp2 = old_disp2;
+    drop_graph(h);
+    return MD_OK;
+}
+
+md_status md_build_neighbors(md_handle h) {
+    if (!h) return fail(nullptr, MD_ERR_ARG, "NULL handle");
+    return rebuild_now(h, 1);
+}
+
+md_status md_forces(md_handle h, double* f_out) {
+    if (!h) return fail(nullptr, MD_ERR_ARG, "NULL handle");
+    md_status r = rebuild_now(h, 0);
+    if (r != MD_OK) return r;
+    StepArgs a = make_args(h, MODE_FORCES, 1, f_out);
+    HIP_TRY(h, launch_step(a, h->fp64, h->single, h->bonded, kBlock, h->stream));
+    HIP_TRY(h, launch_finalize(h->b, h->step_grid, MODE_FORCES, h->stream));
+    return MD_OK;
+}
+
+md_status md_step(md_handle h, int64_t nsteps) {
+    if (!h) return fail(nullptr, MD_ERR_ARG, "NULL handle");
+    if (nsteps < 0) return fail(h, MD_ERR_ARG, "nsteps < 0");
+    const bool use_graph = !(h->cfg.flags & MD_CFG_NO_GRAPH) && !h->timing && h->stream != nullptr;
+    int64_t left = nsteps;
+    while (left > 0) {
+        if (use_graph && left >= 2) {
+            if (h->graph_parity != h->parity) {
+                if (h->gexec && h->graph_parity >= 0) {
+                    // single eager step to align the parity with the graph
+                    HIP_TRY(h, enqueue_step(h, nullptr));
+                    --left;
+                    continue;
+                }
+                md_status r = build_graph(h);
+                if (r != MD_OK) return r;
+            }
+            HIP_TRY(h, hipGraphLaunch(h->gexec, h->stream));
+            h->parity ^= 0;  // two steps: parity unchanged
+            h->host_step += 2;
+            h->vel_half = 1;
+            left -= 2;
+            continue;
+        }
+        EvQuad q;
+        const EvQuad* qp = nullptr;
+        if (h->timing) {
+            if (!h->ev_free.empty()) {
+                q = h->ev_free.back();
+                h->ev_free.pop_back();
+            } else {
+                for (int k = 0; k < 4; ++k) HIP_TRY(h, hipEventCreate(&q.e[k]));
+            }
+            h->ev_pending.push_back(q);
+            qp = &h->ev_pending.back();
+        }
+        HIP_TRY(h, enqueue_step(h, qp));
+        --left;
+    }
+    return MD_OK;
+}
+
+md_status md_observables(md_handle h, md_obs* out) {
+    if (!h || !out) return fail(h, MD_ERR_ARG, "NULL handle or output");
+    md_status r = rebuild_now(h, 0);
+    if (r != MD_OK) return r;
+    StepArgs a = make_args(h, MODE_OBSERVE, 1, nullptr);
+    HIP_TRY(h, launch_step(a, h->fp64, h->single, h->bonded, kBlock, h->stream));
+    HIP_TRY(h, launch_finalize(h->b, h->step_grid, MODE_OBSERVE, h->stream));
+    double rec[kHistRec];
+    HIP_TRY(h, hipMemcpyAsync(rec, h->b.cur, sizeof(rec), hipMemcpyDeviceToHost, h->stream));
+    DevCtl c;
+    if ((r = read_ctl(h, &c)) != MD_OK) return r;
+    fill_obs(h, rec, out);
+    out->status_flags = c.status;
+    return status_to_code(h, c.status, c.nl_max);
+}
+
+md_status md_history(md_handle h, md_obs* out, int64_t max, int64_t* n) {
+    if (!h || !n || (max > 0 && !out)) return fail(h, MD_ERR_ARG, "NULL argument");
+    DevCtl c;
+    md_status r = read_ctl(h, &c);
+    if (r != MD_OK) return r;
+    const int64_t end = c.step;
+    int64_t first = h->hist_next;
+    if (end - first > MD_HISTORY_CAPACITY) first = end - MD_HISTORY_CAPACITY;
+    int64_t count = end - first;
+    if (count > max) count = max;
+    if (count < 0) count = 0;
+    std::vector<double> ring((size_t)kHistRec * MD_HISTORY_CAPACITY);
+    if (count > 0) {
+        HIP_TRY(h, hipMemcpyAsync(ring.data(), h->b.hist, sizeof(double) * ring.size(), hipMemcpyDeviceToHost, h->stream));
+        HIP_TRY(h, hipStreamSynchronize(h->stream));
+    }
+    for (int64_t k = 0; k < count; ++k) {
+        const int64_t s = first + k;
+        fill_obs(h, &ring[(size_t)(s % MD_HISTORY_CAPACITY) * kHistRec], &out[k]);
+    }
+    h->hist_next = first + count;
+    *n = count;
+    return MD_OK;
+}
+
+md_status md_get_state(md_handle h, double* pos, double* vel, int32_t* image, double* pos_build, int64_t* step,
+                       int32_t* vel_half) {
+    if (!h) return fail(nullptr, MD_ERR_ARG, "NULL handle");
+    md_status r = rebuild_now(h, 0);
+    if (r != MD_OK) return r;
+    HIP_TRY(h, launch_get_state(h->g, h->b, h->parity, pos, vel, image, pos_build, h->stream));
+    if (step) *step = h->host_step;
+    if (vel_half) *vel_half = h->vel_half;
+    return MD_OK;
+}
+
+md_status md_set_state(md_handle h, const double* pos, const double* vel, const int32_t* image,
+                       const double* pos_build, int64_t step, int32_t vel_half) {
+    if (!h) return fail(nullptr, MD_ERR_ARG, "NULL handle");
+    if (!pos || !vel) return fail(h, MD_ERR_ARG, "NULL pos or vel");
+    if (step < 0 || (vel_half != 0 && vel_half != 1)) return fail(h, MD_ERR_ARG, "bad step or vel_half");
+    h->parity = 0;
+    drop_graph(h);
+    HIP_TRY(h, launch_init_load(h->g, h->b, 0, pos_build ? pos_build : pos, vel, h->b.type_t, image, h->stream));
+    HIP_TRY(h, launch_set_ctl(h->b, step, vel_half, 1, 1, h->stream));
+    md_status r = rebuild_now(h, 0);
+    if (r != MD_OK) return r;
+    if (pos_build) HIP_TRY(h, launch_overwrite_state(h->g, h->b, 0, pos, vel, image, h->stream));
+    h->host_step = step;
+    h->vel_half = vel_half;
+    h->hist_next = step;
+    return MD_OK;
+}
+
+md_status md_get_neighbors(md_handle h, int32_t* count, int32_t* idx, int32_t cap) {
+    if (!h || !count || !idx || cap < 1) return fail(h, MD_ERR_ARG, "bad argument");
+    md_status r = rebuild_now(h, 0);
+    if (r != MD_OK) return r;
+    HIP_TRY(h, launch_get_neighbors(h->g, h->b, count, idx, cap, h->stream));
+    DevCtl c;
+    if ((r = read_ctl(h, &c)) != MD_OK) return r;
+    if ((r = status_to_code(h, c.status, c.nl_max)) != MD_OK) return r;
+    if (c.nl_max > cap) return fail(h, MD_ERR_NL_OVERFLOW, "cap smaller than the longest neighbour row");
+    return MD_OK;
+}
+
+md_status md_status_check(md_handle h) {
+    if (!h) return fail(nullptr, MD_ERR_ARG, "NULL handle");
+    DevCtl c;
+    md_status r = read_ctl(h, &c);
+    if (r != MD_OK) return r;
+    return status_to_code(h, c.status, c.nl_max);
+}
+
+md_status md_timing_enable(md_handle h, int32_t enable) {
+    if (!h) return fail(nullptr, MD_ERR_ARG, "NULL handle");
+    h->timing = enable != 0;
+    return MD_OK;
+}
+
+md_status md_timing_read(md_handle h, md_timing* out) {
+    if (!h || !out) return fail(h, MD_ERR_ARG, "NULL argument");
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    for (const EvQuad& q : h->ev_pending) {
+        float a = 0, b = 0, c = 0;
+        HIP_TRY(h, hipEventElapsedTime(&a, q.e[0], q.e[1]));
+        HIP_TRY(h, hipEventElapsedTime(&b, q.e[1], q.e[2]));
+        HIP_TRY(h, hipEventElapsedTime(&c, q.e[2], q.e[3]));
+        h->tacc.n_rebuild += 1;
+        h->tacc.ms_rebuild += a;
+        h->tacc.n_step_kernels += 1;
+        h->tacc.ms_step_kernels += b;
+        h->tacc.n_finalize += 1;
+        h->tacc.ms_finalize += c;
+        h->ev_free.push_back(q);
+    }
+    h->ev_pending.clear();
+    *out = h->tacc;
+    memset(&h->tacc, 0, sizeof(h->tacc));
+    return MD_OK;
+}
+
+md_status md_destroy(md_handle h) {
+    if (!h) return MD_OK;
+    (void)hipStreamSynchronize(h->stream);
+    drop_graph(h);
+    for (auto& q : h->ev_free)
+        for (int k = 0; k < 4; ++k) (void)hipEventDestroy(q.e[k]);
+    for (auto& q : h->ev_pending)
+        for (int k = 0; k < 4; ++k) (void)hipEventDestroy(q.e[k]);
+    delete h;
+    return MD_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,155 @@
+// Internal definitions shared by the host runtime and the gfx950 kernels of
+// the short-range MD step.  Not part of the public ABI (see include/md.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/md.h"
+
+namespace md {
+
+constexpr int kBlock = 256;            // threads per block of the streaming kernels
+constexpr int kScanBlocks = 1024;      // blocks of the 3-phase cell-count scan
+constexpr int kMaxGrid = 65535 * 16;   // cap for 1-D grids
+constexpr int kNacc = 11;              // reduced quantities per step, see Acc
+constexpr int kHistRec = 16;           // doubles per history record
+
+// Order of the per-step FP64 reductions.
+enum Acc { A_EPAIR = 0, A_EBOND, A_EANGLE, A_EKIN, A_VIR, A_TXX, A_TYY, A_TZZ, A_TXY, A_TXZ, A_TYZ };
+
+// History record layout (doubles): step, e_pair, e_bond, e_angle, e_kin, W,
+// tensor[6], n_rebuilds, status, nl_max, pad.
+enum Hist { H_STEP = 0, H_EPAIR, H_EBOND, H_EANGLE, H_EKIN, H_VIR, H_T0, H_NREB = 12, H_STATUS, H_NLMAX };
+
+// Device control block, lives at the start of the workspace.
+struct DevCtl {
+    int64_t step;          // n of the positions x_n currently stored
+    int32_t vel_half;      // 1: stored velocity is v_{n-1/2}; 0: on-step v_n
+    uint32_t rebuild;      // rebuild the list before the next force evaluation
+    uint32_t rebuild_next; // set by the step kernel when a particle moved > skin/2
+    uint32_t status;       // sticky MD_FLAG_* bits
+    int32_t nl_max;        // longest row at the last build
+    int32_t pad0;
+    int64_t n_rebuilds;
+    int64_t pad[11];
+};
+
+// One type pair, precomputed on the host in FP64 and rounded once for FP32.
+template <typename Real>
+struct PairCoef {
+    Real eps4;     // 4 eps
+    Real eps24;    // 24 eps
+    Real sig2;     // sigma^2
+    Real rc2;      // rc^2 (FP64 copy is used for the cutoff test)
+    Real shift;    // energy shift
+    Real cap2;     // caprad^2 (0: no cap)
+    Real ucap;     // u(caprad) - shift
+    Real fcap;     // |f(caprad)|
+};
+
+struct PairTable {
+    PairCoef<double> d[MD_MAX_TYPES * MD_MAX_TYPES];
+    PairCoef<float> f[MD_MAX_TYPES * MD_MAX_TYPES];
+    double rc2d[MD_MAX_TYPES * MD_MAX_TYPES];
+};
+
+// Everything a kernel of one handle needs; passed by value.
+struct Geom {
+    int64_t n;
+    double L[3], hL[3];     // box, half box
+    double invh[3];         // cells per unit length
+    int nc[3];
+    int64_t ncell;
+    double rv2;             // list radius squared (FP64, exact same ops as the oracle)
+    double disp2;           // (skin/2)^2
+    int32_t cap;            // ELL capacity
+    int32_t ntypes;
+};
+
+struct Bufs {
+    DevCtl* ctl;
+    double* partials;       // [grid][kNacc]
+    double* hist;           // [MD_HISTORY_CAPACITY][kHistRec]
+    double* cur;            // [kHistRec] observables of the last finalize
+    double4* x[2];          // positions (w = type), sorted order, by step parity
+    double* v;              // [3][N] SoA, sorted order
+    double* xb;             // [3][N] positions at the last build
+    int32_t* img;           // [3][N]
+    int32_t* type_t;        // [N] particle types in tag order
+    int32_t* tag;           // sorted -> tag
+    int32_t* inv;           // tag -> sorted
+    uint32_t* cellid;       // [N]
+    int32_t* ccount;        // [ncell], all zero between rebuilds
+    int32_t* cstart;        // [ncell + 1]
+    int32_t* bsum;          // [kScanBlocks]
+    int32_t* tmp;           // [N] scatter slots
+    double4* xt;            // permute temporaries
+    double* vt;
+    int32_t* imgt;
+    int32_t* tagt;
+    int32_t* nl;            // [cap][N] neighbour-major ELL, sorted indices
+    int32_t* ncount;        // [N]
+    // topology, tag space (static) and sorted space (remapped at each build)
+    int32_t* tcnt_t;        // [N] nbond | nangle << 8
+    int32_t* bp_t;          // [MAXB][N] partner tags
+    int2* ang_t;            // [MAXA][N] (other1 | role << 30, other2) tags
+    int32_t* tcnt_s;        // [N]
+    int32_t* bp_s;          // [MAXB][N]
+    int2* ang_s;            // [MAXA][N]
+    int32_t maxb, maxa;     // row counts actually used (<= limits)
+};
+
+struct Dyn {
+    double dt;
+    double hdtm[MD_MAX_TYPES];  // dt / (2 m)
+    double mass[MD_MAX_TYPES];
+    double gm[MD_MAX_TYPES];    // gamma m
+    double amp[MD_MAX_TYPES];   // sqrt(2 gamma m kT / dt)
+    int32_t langevin;
+    uint64_t seed;
+    double fene_K, fene_R02;
+    double fene_halfKR02;       // K R0^2 / 2
+    float fene_Kf, fene_R02f, fene_halfKR02f;
+    double k_bend;
+    float k_bendf;
+};
+
+// internal status bit (init only): a particle type outside 0..n_types-1
+constexpr uint32_t MD_FLAG_BAD_TYPE = 0x100u;
+
+enum Mode { MODE_STEP = 0, MODE_OBSERVE = 1, MODE_FORCES = 2 };
+
+struct StepArgs {
+    Geom g;
+    Bufs b;
+    PairTable pt;
+    Dyn dy;
+    int32_t parity;
+    int32_t mode;
+    int32_t tensor;
+    double* f_out;              // MODE_FORCES: [N][3] tag order
+};
+
+// launchers (md_kernels.hip)
+hipError_t launch_init_load(const Geom& g, const Bufs& b, int parity, const double* pos,
+                            const double* vel, const int32_t* type, const int32_t* image,
+                            hipStream_t s);
+hipError_t launch_set_ctl(const Bufs& b, int64_t step, int vel_half, int rebuild, int clear_status,
+                          hipStream_t s);
+hipError_t launch_rebuild(const Geom& g, const Bufs& b, int parity, int bonded, hipStream_t s,
+                          hipEvent_t ev0, hipEvent_t ev1);
+hipError_t launch_clear_rebuild(const Bufs& b, hipStream_t s);
+hipError_t launch_step(const StepArgs& a, int fp64, int single_type, int bonded, int block,
+                       hipStream_t s);
+hipError_t launch_finalize(const Bufs& b, int nblocks, int mode, hipStream_t s);
+hipError_t launch_overwrite_state(const Geom& g, const Bufs& b, int parity, const double* pos,
+                                  const double* vel, const int32_t* image, hipStream_t s);
+hipError_t launch_get_state(const Geom& g, const Bufs& b, int parity, double* pos, double* vel,
+                            int32_t* image, double* pos_build, hipStream_t s);
+hipError_t launch_copy_i32(int32_t* dst, const int32_t* src, int64_t n, hipStream_t s);
+hipError_t launch_get_neighbors(const Geom& g, const Bufs& b, int32_t* count, int32_t* idx,
+                                int32_t cap, hipStream_t s);
+hipError_t launch_zero_i32(int32_t* p, int64_t n, hipStream_t s);
+
+}  // namespace md

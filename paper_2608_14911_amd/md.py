@@ -1,0 +1,264 @@
+"""ctypes binding of the C ABI in include/md.h (argument marshalling only).
+
+Every function here has the name of the C entry point it calls and passes
+plain pointers and sizes through; all arithmetic of the MD step runs in the
+gfx950 kernels of libmdgpu.so.  Device pointers are given as integers (for
+example ``tensor.data_ptr()``), host arrays as numpy arrays.  The library is
+required: importing this module on a machine without the built library
+raises at the first call instead of falling back to anything else.
+"""
+import ctypes
+import math
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmdgpu.so")
+
+MD_OK = 0
+MD_ERR_ARG = -1
+MD_ERR_HIP = -2
+MD_ERR_BOX_TOO_SMALL = -3
+MD_ERR_NL_OVERFLOW = -4
+MD_ERR_BOND_BROKEN = -5
+MD_ERR_NONFINITE = -6
+MD_ERR_STATE = -7
+MD_ERR_WORKSPACE = -8
+MD_ERR_TOPOLOGY = -9
+
+MD_FLAG_NL_OVERFLOW = 0x1
+MD_FLAG_BOND_BROKEN = 0x2
+MD_FLAG_NONFINITE = 0x4
+
+MD_NVE = 0
+MD_LANGEVIN = 1
+MD_FP64 = 0
+MD_FP32 = 1
+MD_MAX_TYPES = 4
+MD_HISTORY_CAPACITY = 8192
+MD_CFG_VIRIAL_TENSOR = 0x1
+MD_CFG_NO_GRAPH = 0x2
+
+EXPORTED = ["md_workspace_bytes", "md_init", "md_set_params", "md_build_neighbors", "md_forces",
+            "md_step", "md_observables", "md_history", "md_get_state", "md_set_state",
+            "md_get_neighbors", "md_status_check", "md_timing_enable", "md_timing_read",
+            "md_destroy", "md_status_string", "md_last_error"]
+
+
+class md_pair_params(ctypes.Structure):
+    _fields_ = [("eps", ctypes.c_double), ("sigma", ctypes.c_double), ("rc", ctypes.c_double),
+                ("shift", ctypes.c_double), ("caprad", ctypes.c_double)]
+
+
+class md_config(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("n_types", ctypes.c_int32),
+                ("n_particles", ctypes.c_int64), ("box", ctypes.c_double * 3), ("dt", ctypes.c_double),
+                ("skin", ctypes.c_double), ("integrator", ctypes.c_int32),
+                ("force_precision", ctypes.c_int32), ("temperature", ctypes.c_double),
+                ("gamma", ctypes.c_double), ("seed", ctypes.c_uint64),
+                ("pair", md_pair_params * (MD_MAX_TYPES * MD_MAX_TYPES)), ("n_bonds", ctypes.c_int64),
+                ("n_angles", ctypes.c_int64), ("fene_K", ctypes.c_double), ("fene_R0", ctypes.c_double),
+                ("k_bend", ctypes.c_double), ("cell_factor", ctypes.c_int32),
+                ("nl_capacity", ctypes.c_int32), ("block_size", ctypes.c_int32), ("flags", ctypes.c_int32)]
+
+
+class md_obs(ctypes.Structure):
+    _fields_ = [("step", ctypes.c_int64), ("e_pair", ctypes.c_double), ("e_bond", ctypes.c_double),
+                ("e_angle", ctypes.c_double), ("e_kin", ctypes.c_double), ("e_total", ctypes.c_double),
+                ("virial", ctypes.c_double), ("virial_tensor", ctypes.c_double * 6),
+                ("pressure", ctypes.c_double), ("temperature", ctypes.c_double),
+                ("n_rebuilds", ctypes.c_int64), ("status_flags", ctypes.c_uint32),
+                ("nl_max_count", ctypes.c_int32)]
+
+    def as_dict(self):
+        d = {k: getattr(self, k) for k, _ in self._fields_}
+        d["virial_tensor"] = np.array(list(self.virial_tensor))
+        return d
+
+
+class md_timing(ctypes.Structure):
+    _fields_ = [("n_step_kernels", ctypes.c_int64), ("ms_step_kernels", ctypes.c_double),
+                ("n_rebuild", ctypes.c_int64), ("ms_rebuild", ctypes.c_double),
+                ("n_finalize", ctypes.c_int64), ("ms_finalize", ctypes.c_double)]
+
+
+class MDError(RuntimeError):
+    def __init__(self, code, fn, msg):
+        super().__init__("%s -> %s: %s" % (fn, status_string(code), msg))
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    """Load libmdgpu.so from the package directory; raise if it is not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("HIP library %s is not built; run __graft_entry__.build() "
+                           "(hipcc --offload-arch=gfx950)" % LIB_PATH)
+    L = ctypes.CDLL(LIB_PATH)
+    P, I32, I64, SZ = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+    sig = {
+        "md_workspace_bytes": [ctypes.POINTER(md_config), ctypes.POINTER(SZ)],
+        "md_init": [ctypes.POINTER(md_config), P, P, P, P, P, P, P, SZ, P, ctypes.POINTER(P)],
+        "md_set_params": [P, ctypes.POINTER(md_config)],
+        "md_build_neighbors": [P],
+        "md_forces": [P, P],
+        "md_step": [P, I64],
+        "md_observables": [P, ctypes.POINTER(md_obs)],
+        "md_history": [P, P, I64, ctypes.POINTER(I64)],
+        "md_get_state": [P, P, P, P, P, ctypes.POINTER(I64), ctypes.POINTER(I32)],
+        "md_set_state": [P, P, P, P, P, I64, I32],
+        "md_get_neighbors": [P, P, P, I32],
+        "md_status_check": [P],
+        "md_timing_enable": [P, I32],
+        "md_timing_read": [P, ctypes.POINTER(md_timing)],
+        "md_destroy": [P],
+    }
+    for name, args in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = ctypes.c_int32
+    L.md_status_string.argtypes = [ctypes.c_int32]
+    L.md_status_string.restype = ctypes.c_char_p
+    L.md_last_error.argtypes = [P]
+    L.md_last_error.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def status_string(code):
+    return lib().md_status_string(code).decode()
+
+
+def md_last_error(h=None):
+    return lib().md_last_error(h).decode()
+
+
+def _check(code, fn, h=None):
+    if code != MD_OK:
+        raise MDError(code, fn, md_last_error(h))
+
+
+def _p(x):
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return ctypes.c_void_p(x)
+    if isinstance(x, np.ndarray):
+        return x.ctypes.data_as(ctypes.c_void_p)
+    return ctypes.c_void_p(x.data_ptr())
+
+
+# ------------------------------------------------------------------ config helper
+def make_config(n, box, *, n_types=1, pair=None, dt=0.005, skin=0.3, integrator=MD_NVE,
+                force_precision=MD_FP32, temperature=1.0, gamma=0.0, seed=0, n_bonds=0, n_angles=0,
+                fene_K=30.0, fene_R0=1.5, k_bend=0.0, nl_capacity=0, flags=0):
+    """Fill an md_config.  pair: dict (ti, tj) -> (eps, sigma, rc, shift, caprad)."""
+    c = md_config()
+    c.struct_size = ctypes.sizeof(md_config)
+    c.n_types = n_types
+    c.n_particles = int(n)
+    for d in range(3):
+        c.box[d] = float(box[d])
+    c.dt, c.skin = float(dt), float(skin)
+    c.integrator, c.force_precision = int(integrator), int(force_precision)
+    c.temperature, c.gamma, c.seed = float(temperature), float(gamma), int(seed)
+    pair = pair or {(0, 0): (1.0, 1.0, 2.5, math.nan, 0.0)}
+    for (a, b), row in pair.items():
+        for (x, y) in ((a, b), (b, a)):
+            pp = c.pair[x * MD_MAX_TYPES + y]
+            pp.eps, pp.sigma, pp.rc, pp.shift, pp.caprad = (float(v) for v in row)
+    c.n_bonds, c.n_angles = int(n_bonds), int(n_angles)
+    c.fene_K, c.fene_R0, c.k_bend = float(fene_K), float(fene_R0), float(k_bend)
+    c.nl_capacity = int(nl_capacity)
+    c.flags = int(flags)
+    return c
+
+
+# ------------------------------------------------------------------ entry points
+def md_workspace_bytes(cfg):
+    n = ctypes.c_size_t()
+    _check(lib().md_workspace_bytes(ctypes.byref(cfg), ctypes.byref(n)), "md_workspace_bytes")
+    return n.value
+
+
+def md_init(cfg, pos, vel, type, mass_by_type, bonds, angles, workspace, ws_bytes, stream):
+    h = ctypes.c_void_p()
+    mass = np.ascontiguousarray(mass_by_type, dtype=np.float64)
+    b = None if bonds is None else np.ascontiguousarray(bonds, dtype=np.int32)
+    a = None if angles is None else np.ascontiguousarray(angles, dtype=np.int32)
+    code = lib().md_init(ctypes.byref(cfg), _p(pos), _p(vel), _p(type), _p(mass), _p(b), _p(a),
+                         _p(workspace), ws_bytes, _p(stream), ctypes.byref(h))
+    _check(code, "md_init")
+    return h
+
+
+def md_set_params(h, cfg):
+    _check(lib().md_set_params(h, ctypes.byref(cfg)), "md_set_params", h)
+
+
+def md_build_neighbors(h):
+    _check(lib().md_build_neighbors(h), "md_build_neighbors", h)
+
+
+def md_forces(h, f_out):
+    _check(lib().md_forces(h, _p(f_out)), "md_forces", h)
+
+
+def md_step(h, nsteps):
+    _check(lib().md_step(h, int(nsteps)), "md_step", h)
+
+
+def md_observables(h, check=True):
+    o = md_obs()
+    code = lib().md_observables(h, ctypes.byref(o))
+    if check:
+        _check(code, "md_observables", h)
+    return o.as_dict() if check else (code, o.as_dict())
+
+
+def md_history(h, max_records=MD_HISTORY_CAPACITY):
+    arr = (md_obs * max_records)()
+    n = ctypes.c_int64()
+    _check(lib().md_history(h, ctypes.cast(arr, ctypes.c_void_p), max_records, ctypes.byref(n)), "md_history", h)
+    return [arr[k].as_dict() for k in range(n.value)]
+
+
+def md_get_state(h, pos, vel, image=None, pos_build=None):
+    step = ctypes.c_int64()
+    vh = ctypes.c_int32()
+    _check(lib().md_get_state(h, _p(pos), _p(vel), _p(image), _p(pos_build), ctypes.byref(step),
+                              ctypes.byref(vh)), "md_get_state", h)
+    return step.value, vh.value
+
+
+def md_set_state(h, pos, vel, image, pos_build, step, vel_half):
+    _check(lib().md_set_state(h, _p(pos), _p(vel), _p(image), _p(pos_build), int(step), int(vel_half)),
+           "md_set_state", h)
+
+
+def md_get_neighbors(h, count, idx, cap):
+    _check(lib().md_get_neighbors(h, _p(count), _p(idx), int(cap)), "md_get_neighbors", h)
+
+
+def md_status_check(h):
+    return lib().md_status_check(h)
+
+
+def md_timing_enable(h, enable):
+    _check(lib().md_timing_enable(h, int(bool(enable))), "md_timing_enable", h)
+
+
+def md_timing_read(h):
+    t = md_timing()
+    _check(lib().md_timing_read(h, ctypes.byref(t)), "md_timing_read", h)
+    return {k: getattr(t, k) for k, _ in t._fields_}
+
+
+def md_destroy(h):
+    _check(lib().md_destroy(h), "md_destroy")

@@ -1,0 +1,158 @@
+"""A simulation handle with torch-owned device memory.
+
+``System`` mirrors the nouns of the paper's scripting interface (section
+"Example usage": System, OrthorhombicBC box, VerletList(cutoff) + skin,
+LennardJones / LennardJonesCapped, VelocityVerlet + LangevinThermostat,
+addParticles, run(n), computeEnergy()).  It only marshals arguments: torch
+allocates the workspace and the state buffers and supplies the stream; every
+step of the computation runs in libmdgpu.so (see md.py).
+"""
+import math
+
+import numpy as np
+
+from . import md
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("no GPU visible: the MD library runs on gfx950 only")
+    return torch
+
+
+class System:
+    def __init__(self, pos, box, vel=None, *, types=None, n_types=1, pair=None, masses=(1.0,),
+                 bonds=None, angles=None, dt=0.005, skin=0.3, integrator="nve", precision="fp32",
+                 temperature=1.0, gamma=0.0, seed=0, fene_K=30.0, fene_R0=1.5, k_bend=0.0,
+                 nl_capacity=0, flags=0, device="cuda"):
+        torch = _torch()
+        self.torch = torch
+        pos = np.ascontiguousarray(pos, dtype=np.float64)
+        n = pos.shape[0]
+        self.n = n
+        self.box = np.asarray(box, dtype=np.float64)
+        vel = np.zeros_like(pos) if vel is None else np.ascontiguousarray(vel, dtype=np.float64)
+        self.device = torch.device(device)
+        integ = md.MD_LANGEVIN if integrator == "langevin" else md.MD_NVE
+        prec = md.MD_FP64 if precision == "fp64" else md.MD_FP32
+        nb = 0 if bonds is None else len(bonds)
+        na = 0 if angles is None else len(angles)
+        self.cfg = md.make_config(n, self.box, n_types=n_types, pair=pair, dt=dt, skin=skin, integrator=integ,
+                                  force_precision=prec, temperature=temperature, gamma=gamma, seed=seed,
+                                  n_bonds=nb, n_angles=na, fene_K=fene_K, fene_R0=fene_R0, k_bend=k_bend,
+                                  nl_capacity=nl_capacity, flags=flags)
+        self.ws_bytes = md.md_workspace_bytes(self.cfg)
+        self._ws_raw = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
+        base = self._ws_raw.data_ptr()
+        self.ws_ptr = (base + 255) & ~255
+        self.stream = torch.cuda.current_stream(self.device)
+        dpos = torch.as_tensor(pos, device=self.device)
+        dvel = torch.as_tensor(vel, device=self.device)
+        dtype_ = None if types is None else torch.as_tensor(np.asarray(types, dtype=np.int32), device=self.device)
+        self.masses = np.asarray(masses, dtype=np.float64)
+        self.h = md.md_init(self.cfg, dpos.data_ptr(), dvel.data_ptr(),
+                            None if dtype_ is None else dtype_.data_ptr(), self.masses,
+                            bonds, angles, self.ws_ptr, self.ws_bytes, self.stream.cuda_stream)
+        self._closed = False
+
+    # -------------------------------------------------------------- control
+    def set_params(self, **kw):
+        c = self.cfg
+        if "pair" in kw:
+            for (a, b), row in kw.pop("pair").items():
+                for (x, y) in ((a, b), (b, a)):
+                    pp = c.pair[x * md.MD_MAX_TYPES + y]
+                    pp.eps, pp.sigma, pp.rc, pp.shift, pp.caprad = (float(v) for v in row)
+        for k, v in kw.items():
+            if k == "integrator":
+                v = md.MD_LANGEVIN if v == "langevin" else md.MD_NVE
+            if k == "precision":
+                k, v = "force_precision", (md.MD_FP64 if v == "fp64" else md.MD_FP32)
+            setattr(c, k, v)
+        md.md_set_params(self.h, c)
+
+    def step(self, n):
+        md.md_step(self.h, n)
+
+    def build_neighbors(self):
+        md.md_build_neighbors(self.h)
+
+    def observables(self, check=True):
+        return md.md_observables(self.h, check=check)
+
+    def history(self):
+        return md.md_history(self.h)
+
+    def forces(self):
+        f = self.torch.zeros((self.n, 3), dtype=self.torch.float64, device=self.device)
+        md.md_forces(self.h, f.data_ptr())
+        self.stream.synchronize()
+        return f.cpu().numpy()
+
+    def get_state(self):
+        t = self.torch
+        z = lambda dt_: t.zeros((self.n, 3), dtype=dt_, device=self.device)
+        pos, vel, pb, img = z(t.float64), z(t.float64), z(t.float64), z(t.int32)
+        step, vh = md.md_get_state(self.h, pos.data_ptr(), vel.data_ptr(), img.data_ptr(), pb.data_ptr())
+        self.stream.synchronize()
+        return {"pos": pos.cpu().numpy(), "vel": vel.cpu().numpy(), "image": img.cpu().numpy(),
+                "pos_build": pb.cpu().numpy(), "step": step, "vel_half": vh}
+
+    def set_state(self, state, with_build=True):
+        t = self.torch
+        pos = t.as_tensor(np.ascontiguousarray(state["pos"], dtype=np.float64), device=self.device)
+        vel = t.as_tensor(np.ascontiguousarray(state["vel"], dtype=np.float64), device=self.device)
+        img = None
+        if state.get("image") is not None:
+            img = t.as_tensor(np.ascontiguousarray(state["image"], dtype=np.int32), device=self.device)
+        pb = None
+        if with_build and state.get("pos_build") is not None:
+            pb = t.as_tensor(np.ascontiguousarray(state["pos_build"], dtype=np.float64), device=self.device)
+        md.md_set_state(self.h, pos.data_ptr(), vel.data_ptr(), None if img is None else img.data_ptr(),
+                        None if pb is None else pb.data_ptr(), state.get("step", 0), state.get("vel_half", 0))
+        self.stream.synchronize()
+
+    def neighbors(self, cap=None):
+        t = self.torch
+        cap = cap or int(self.cfg.nl_capacity or 512)
+        cnt = t.zeros(self.n, dtype=t.int32, device=self.device)
+        idx = t.full((self.n, cap), -1, dtype=t.int32, device=self.device)
+        md.md_get_neighbors(self.h, cnt.data_ptr(), idx.data_ptr(), cap)
+        c = cnt.cpu().numpy()
+        m = idx.cpu().numpy()
+        return [np.sort(m[i, :c[i]]) for i in range(self.n)]
+
+    def timing(self, enable=None):
+        if enable is not None:
+            md.md_timing_enable(self.h, enable)
+            return None
+        return md.md_timing_read(self.h)
+
+    def status(self):
+        return md.md_status_check(self.h)
+
+    def close(self):
+        if not self._closed:
+            md.md_destroy(self.h)
+            self._closed = True
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def lj_pair(eps=1.0, sigma=1.0, rc=2.5, shift=math.nan, caprad=0.0):
+    return (eps, sigma, rc, shift, caprad)
+
+
+def from_workload(w, precision="fp32", **kw):
+    """System for a workload dict from inputs.py."""
+    pair = {(0, 0): lj_pair(w["eps"], w["sigma"], w["rc"], w["shift"], w["caprad"])}
+    return System(w["pos"], w["box"], w["vel"], pair=pair, bonds=w.get("bonds"), angles=w.get("angles"),
+                  dt=w["dt"], skin=w["skin"], integrator=w["integrator"], precision=precision,
+                  temperature=w["temperature"], gamma=w["gamma"], seed=w["seed"],
+                  fene_K=w.get("fene_K", 30.0), fene_R0=w.get("fene_R0", 1.5), k_bend=w.get("k_bend", 0.0),
+                  **kw)

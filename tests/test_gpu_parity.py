@@ -1,0 +1,244 @@
+"""GPU parity of the HIP path against the FP64 oracle, through the C ABI.
+
+Neighbour sets must equal the oracle's bit for bit (same FP64 positions,
+same IEEE operations for r^2); forces, energies and virial must agree within
+1e-12 (FP64 pair path) and 1e-5 (FP32 pair path, condition-aware per
+particle); short trajectories in FP64 within 1e-9 on unwrapped positions.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from gpu_helpers import WCA, assert_forces_close, banner, oracle_pp, rel, unwrap
+from kg_fixture import kg1k_state
+from paper_2608_14911_amd import inputs
+from paper_2608_14911_amd.system import System, from_workload, lj_pair
+
+pytestmark = pytest.mark.gpu
+
+
+def tricky(seed, n, L, rv):
+    g = np.random.default_rng(seed)
+    pos = g.uniform(0, L, size=(n, 3))
+    pos[0] = [0.0, 0.0, 0.0]
+    pos[1] = [np.nextafter(L, 0), 0.5, 0.5]
+    pos[2] = [L / 2, np.nextafter(L, 0), 0.0]
+    base = np.array([L / 3, L / 3, L / 3])
+    for k, r in enumerate([rv, np.nextafter(rv, 0), np.nextafter(rv, 10)]):
+        pos[3 + 2 * k] = base + [0, 0, 1.3 * k]
+        pos[4 + 2 * k] = base + [r, 0, 1.3 * k]
+    return inputs.wrap_into_box(pos, [L, L, L])
+
+
+@pytest.mark.parametrize("seed,n,L", [(0, 300, 7.0), (1, 2000, 12.0), (2, 5000, 15.3)])
+def test_neighbor_sets_bitexact_random(seed, n, L):
+    banner("NL random seed=%d n=%d L=%g" % (seed, n, L))
+    rc, skin = WCA, 0.3
+    rv = rc + skin
+    pos = tricky(seed, n, L, rv)
+    s = System(pos, [L, L, L], pair={(0, 0): lj_pair(rc=rc, caprad=0.8)}, skin=skin, nl_capacity=64)
+    got = s.neighbors(cap=64)
+    ref = oracle.neighbors(pos, [L, L, L], rv)
+    for i in range(n):
+        assert np.array_equal(got[i], ref[i]), i
+    s.close()
+
+
+def test_neighbor_sets_bitexact_kg1k_and_paper_density():
+    w = inputs.workload_kg1k()
+    banner("NL kg1k")
+    s = from_workload(w, precision="fp64")
+    got = s.neighbors(cap=64)
+    ref = oracle.neighbors(w["pos"], w["box"], w["rc"] + w["skin"])
+    assert all(np.array_equal(a, b) for a, b in zip(got, ref))
+    s.close()
+    banner("NL paper-example density")
+    w = inputs.workload_paper_example(n=3000)
+    L = (3000 / 1.25) ** (1 / 3)
+    pos = inputs.random_positions(3000, [L, L, L], seed=3)
+    s = System(pos, [L, L, L], pair={(0, 0): lj_pair(rc=1.12246, caprad=0.8)}, skin=0.3)
+    got = s.neighbors(cap=128)
+    ref = oracle.neighbors(pos, [L, L, L], 1.12246 + 0.3)
+    assert all(np.array_equal(a, b) for a, b in zip(got, ref))
+    s.close()
+
+
+def test_nl_overflow_is_reported_with_needed_capacity():
+    banner("NL overflow")
+    from paper_2608_14911_amd import md
+    pos, box = inputs.fcc_lattice(6, 0.8442)
+    with pytest.raises(md.MDError) as e:
+        System(pos, box, pair={(0, 0): lj_pair(rc=2.5)}, skin=0.3, nl_capacity=40)
+    assert e.value.code == md.MD_ERR_NL_OVERFLOW
+    assert ">= 78" in str(e.value)
+
+
+def test_fcc_lattice_counts_and_sums():
+    banner("FCC 6^3 lattice sums")
+    pos, box = inputs.fcc_lattice(6, 0.8442)
+    n = pos.shape[0]
+    for prec, tol in (("fp64", 1e-12), ("fp32", 1e-5)):
+        s = System(pos, box, pair={(0, 0): lj_pair(rc=2.5)}, skin=0.3, precision=prec)
+        nl = s.neighbors(cap=128)
+        assert all(len(x) == 78 for x in nl)
+        o = s.observables()
+        assert rel(o["e_pair"] / n, -6.332811992580958) < tol
+        assert rel(o["virial"] / n, -22.158199254035495) < tol
+        assert o["nl_max_count"] == 78
+        F = s.forces()
+        assert np.abs(F).max() < (1e-9 if prec == "fp64" else 2e-4)
+        s.close()
+
+
+def lj_liquid(ncell=6, seed=4, jitter=0.2):
+    pos, box = inputs.fcc_lattice(ncell, 0.8442, jitter=jitter, seed=seed)
+    return pos, box
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
+def test_lj_forces_energy_virial(prec, tol):
+    banner("LJ forces %s" % prec)
+    pos, box = lj_liquid()
+    s = System(pos, box, pair={(0, 0): lj_pair(rc=2.5)}, skin=0.3, precision=prec)
+    Fg = s.forces()
+    o = s.observables()
+    Fo, oo = oracle.forces(pos, box, oracle_pp(rc=2.5), want_fscale=True)
+    assert_forces_close(Fg, Fo, oo["fscale"], tol, "LJ " + prec)
+    assert rel(o["e_pair"], oo["e_pair"]) < tol
+    assert rel(o["virial"], oo["virial"]) < tol
+    np.testing.assert_allclose(o["virial_tensor"], oo["virial_tensor"], rtol=tol * 10,
+                               atol=tol * abs(oo["virial"]))
+    s.close()
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
+def test_kg_forces_with_bonds_angles_capped(prec, tol):
+    banner("KG raw-walk forces %s" % prec)
+    w = inputs.random_walk_chains(20, 50, 0.85, seed=9)
+    pos, box = w["pos"], w["box"]
+    s = System(pos, box, pair={(0, 0): lj_pair(rc=WCA, caprad=0.8)}, bonds=w["bonds"], angles=w["angles"],
+               skin=0.4, precision=prec, k_bend=1.5)
+    Fg = s.forces()
+    o = s.observables()
+    Fo, oo = oracle.forces(pos, box, oracle_pp(rc=WCA, caprad=0.8), bonds=w["bonds"], angles=w["angles"],
+                           k_bend=1.5, want_fscale=True)
+    assert_forces_close(Fg, Fo, oo["fscale"], tol, "KG " + prec)
+    for k in ("e_pair", "e_bond", "e_angle", "virial"):
+        assert rel(o[k], oo[k]) < tol * 10, k
+    s.close()
+
+
+def test_multitype_forces():
+    banner("multi-type forces")
+    g = np.random.default_rng(12)
+    pos, box = lj_liquid(ncell=6, seed=6)
+    n = pos.shape[0]
+    types = g.integers(0, 3, size=n).astype(np.int32)
+    rows = {(0, 0): (1.0, 1.0, 2.5, math.nan, 0.0), (0, 1): (0.5, 1.1, 2.2, math.nan, 0.0),
+            (1, 1): (1.5, 0.9, 2.0, 0.0, 0.0), (0, 2): (0.8, 1.0, WCA, math.nan, 0.0),
+            (1, 2): (0.0, 1.0, 1.5, math.nan, 0.0), (2, 2): (1.2, 1.05, 2.4, math.nan, 0.0)}
+    pp = oracle.pair_table(3, {k: oracle.pair_params(*v) for k, v in rows.items()})
+    for prec, tol in (("fp64", 1e-12), ("fp32", 1e-5)):
+        s = System(pos, box, types=types, n_types=3, pair=rows, masses=(1.0, 2.0, 0.5), skin=0.3,
+                   precision=prec)
+        Fg = s.forces()
+        Fo, oo = oracle.forces(pos, box, pp, ntypes=3, type=types, want_fscale=True)
+        assert_forces_close(Fg, Fo, oo["fscale"], tol, "multitype " + prec)
+        assert rel(s.observables()["e_pair"], oo["e_pair"]) < tol
+        s.close()
+
+
+def oracle_params(w, pp, integrator):
+    return {"box": w["box"], "pp": pp, "ntypes": 1, "mass_by_type": np.array([1.0]), "dt": w["dt"],
+            "integrator": integrator, "temperature": w["temperature"], "gamma": w["gamma"],
+            "seed": w["seed"], "bonds": w.get("bonds"), "angles": w.get("angles"),
+            "fene_K": w.get("fene_K", 30.0), "fene_R0": w.get("fene_R0", 1.5), "k_bend": w.get("k_bend", 0.0)}
+
+
+@pytest.mark.parametrize("k_bend", [0.0, 1.5])
+def test_trajectory_fp64_langevin_kg1k(k_bend):
+    banner("trajectory KG1k fp64 langevin 100 steps k_bend=%g" % k_bend)
+    w = kg1k_state(k_bend)
+    pp = oracle_pp(rc=WCA)
+    s = from_workload(w, precision="fp64")
+    s.step(100)
+    assert s.status() == 0
+    hg = s.history()
+    sg = s.get_state()
+    n = w["pos"].shape[0]
+    st = {"pos": w["pos"].copy(), "vel": w["vel"].copy(), "image": np.zeros((n, 3), dtype=np.int32),
+          "step": 0, "vel_half": 0, "type": None}
+    ho = oracle.run(st, oracle_params(w, pp, oracle.LANGEVIN), 100)
+    assert sg["step"] == 100 and st["step"] == 100
+    np.testing.assert_allclose(unwrap(sg, w["box"]), unwrap(st, w["box"]), rtol=0, atol=1e-9)
+    np.testing.assert_allclose(sg["vel"], st["vel"], rtol=0, atol=1e-8)
+    assert len(hg) == 100
+    for k in range(100):
+        assert hg[k]["step"] == k
+        for key, col in (("e_pair", 0), ("e_bond", 1), ("e_angle", 2), ("e_kin", 3), ("virial", 4)):
+            assert abs(hg[k][key] - ho[k, col]) <= 1e-9 * max(1.0, abs(ho[k, col])), (k, key)
+    assert hg[-1]["n_rebuilds"] >= 2
+    s.close()
+
+
+def test_trajectory_fp64_nve_lj():
+    banner("trajectory LJ fp64 NVE 200 steps")
+    w = inputs.workload_lj(ncell=6, seed=21)
+    s = from_workload(w, precision="fp64")
+    s.step(200)
+    sg = s.get_state()
+    hg = s.history()
+    st = {"pos": w["pos"].copy(), "vel": w["vel"].copy(), "image": np.zeros(w["pos"].shape, dtype=np.int32),
+          "step": 0, "vel_half": 0, "type": None}
+    ho = oracle.run(st, oracle_params(w, oracle_pp(rc=2.5), oracle.NVE), 200)
+    np.testing.assert_allclose(unwrap(sg, w["box"]), unwrap(st, w["box"]), rtol=0, atol=1e-8)
+    e = np.array([h["e_pair"] + h["e_kin"] for h in hg])
+    eo = ho[:, 0] + ho[:, 3]
+    np.testing.assert_allclose(e, eo, rtol=1e-9)
+    s.close()
+
+
+def test_fp32_step_parity_and_statistics_lj():
+    banner("LJ fp32 single step + short run")
+    w = inputs.workload_lj(ncell=6, seed=22)
+    s = from_workload(w, precision="fp32")
+    s.step(1)
+    sg = s.get_state()
+    st = {"pos": w["pos"].copy(), "vel": w["vel"].copy(), "image": np.zeros(w["pos"].shape, dtype=np.int32),
+          "step": 0, "vel_half": 0, "type": None}
+    oracle.run(st, oracle_params(w, oracle_pp(rc=2.5), oracle.NVE), 1)
+    # one step moves x by dt^2/2 F: FP32 force error 1e-5 relative -> tiny
+    np.testing.assert_allclose(unwrap(sg, w["box"]), unwrap(st, w["box"]), rtol=0, atol=1e-8)
+    s.step(399)
+    h = s.history()
+    e = np.array([x["e_total"] for x in h])
+    n = w["pos"].shape[0]
+    assert np.abs(e - e[0]).max() / n < 2e-3
+    s.close()
+
+
+def test_determinism_and_checkpoint_bitwise():
+    banner("determinism + checkpoint resume")
+    w = kg1k_state(1.5)
+    runs = []
+    for _ in range(2):
+        s = from_workload(w, precision="fp32")
+        s.step(120)
+        runs.append(s.get_state())
+        s.close()
+    assert np.array_equal(runs[0]["pos"], runs[1]["pos"]) and np.array_equal(runs[0]["vel"], runs[1]["vel"])
+    s = from_workload(w, precision="fp32")
+    s.step(60)
+    ck = s.get_state()
+    s.close()
+    s2 = from_workload(w, precision="fp32")
+    s2.set_state(ck)
+    s2.step(60)
+    r = s2.get_state()
+    assert r["step"] == 120
+    assert np.array_equal(r["pos"], runs[0]["pos"])
+    assert np.array_equal(r["vel"], runs[0]["vel"])
+    assert np.array_equal(r["image"], runs[0]["image"])
+    s2.close()
