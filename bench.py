@@ -1,0 +1,204 @@
+"""Throughput of the short-range MD step on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload lj1m|kg2m|kg1k]
+
+Default workload: LJ fluid of 1,048,576 particles (FCC 64^3, density 0.8442,
+uniform jitter 0.05, T = 0.72), rc = 2.5 shifted, skin 0.3, NVE dt = 0.005,
+FP32 pair math, FP64 positions / velocities / reductions.  A "step" is one
+pass of the whole hot path: gated cell sort + Verlet-list rebuild, fused
+force + velocity-Verlet kernel, FP64 energy/virial reduction.  Inputs are
+resident in HBM before the timed region.
+
+Prints one JSON line with the metric, a "roofline" object for the dominant
+(fused force+integrate) kernel, timed with HIP events on the library's
+stream over the timed region, and a "cpu_baseline" object: the FP64 oracle
+timed on this host on a bounded sample of the same workload.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+# Algorithmic bytes per atom-step of the plain method (half Verlet list in
+# int32, compulsory FP64 x/v streams, FP32 force), per workload:
+#   LJ 1M:  NL 4 + 38.8*4 = 159, positions 24, force 12, integration 132 -> 327
+#   KG 2M:  NL 4 + 6.3*4 = 29, positions 24, force 12, topology 16,
+#           integration 132 -> 213
+ALG_BYTES = {"lj1m": 327.0, "kg2m": 213.0, "kg1k": 213.0}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="lj1m", choices=["lj1m", "kg2m", "kg1k"])
+    ap.add_argument("--no-events", action="store_true",
+                    help="time with a hipGraph replay and no per-kernel events")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--quiet", action="store_true")
+    ap.add_argument("--cell-factor", type=int, default=0, help="cells per list radius (1 or 2; 0 = library default)")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="after the run, copy 512 MiB three times (torch copy kernel) so that hardware "
+                         "byte counters can be scaled against a transfer of known size")
+    return ap.parse_args()
+
+
+def log(msg, quiet=False):
+    if not quiet:
+        print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def make_system(name, quiet, cell_factor=0):
+    from paper_2608_14911_amd import inputs
+    from paper_2608_14911_amd.system import from_workload
+    if name == "lj1m":
+        w = inputs.workload_lj(ncell=64, seed=1001)
+        s = from_workload(w, precision="fp32", cell_factor=cell_factor)
+        return w, s
+    if name == "kg2m":
+        w = inputs.workload_kg(2000, 1000, seed=1002)
+    else:
+        w = inputs.workload_kg1k()
+        w["k_bend"] = 1.5
+    # push-off on the GPU (capped WCA ladder, then uncapped), then the run
+    # parameters of the workload
+    w0 = dict(w)
+    w0["caprad"] = 1.0
+    w0["dt"] = 0.002
+    w0["gamma"] = 1.0
+    w0["vel"] = np.zeros_like(w["pos"])
+    s = from_workload(w0, precision="fp32", cell_factor=cell_factor)
+    t0 = time.time()
+    for cap, dt, ns in ((1.0, 0.002, 500), (0.95, 0.002, 500), (0.9, 0.002, 1000), (0.85, 0.002, 1000),
+                        (0.8, 0.002, 1000), (0.0, 0.005, 1000)):
+        s.set_params(pair={(0, 0): (1.0, 1.0, w["rc"], math.nan, cap)}, dt=dt)
+        s.step(ns)
+    st = s.status()
+    if st != 0:
+        raise RuntimeError("push-off failed with status %d" % st)
+    s.set_params(dt=w["dt"], gamma=w["gamma"])
+    s.step(200)
+    s.stream.synchronize()
+    log("push-off done in %.1f s" % (time.time() - t0), quiet)
+    return w, s
+
+
+def cpu_baseline(w, name, budget_s, quiet):
+    """The FP64 oracle (linked cells, OpenMP) on this host, on a bounded
+    number of steps of the same workload; extrapolated to atom-steps/s."""
+    import oracle
+    n = w["pos"].shape[0]
+    st = {"pos": w["pos"].copy(), "vel": w["vel"].copy(), "image": np.zeros((n, 3), dtype=np.int32),
+          "step": 0, "vel_half": 0, "type": None}
+    par = {"box": w["box"], "pp": oracle.pair_params(w["eps"], w["sigma"], w["rc"], w["shift"], 0.0),
+           "ntypes": 1, "mass_by_type": np.array([1.0]), "dt": w["dt"],
+           "integrator": oracle.LANGEVIN if w["integrator"] == "langevin" else oracle.NVE,
+           "temperature": w["temperature"], "gamma": w["gamma"], "seed": w["seed"],
+           "bonds": w.get("bonds"), "angles": w.get("angles"), "k_bend": w.get("k_bend", 0.0)}
+    threads = oracle.nthreads_default()
+    t0 = time.time()
+    oracle.run(st, par, 1)          # untimed: first touch
+    t1 = time.time()
+    oracle.run(st, par, 1)
+    one = time.time() - t1
+    k = max(1, min(50, int(budget_s / max(one, 1e-6))))
+    t2 = time.time()
+    oracle.run(st, par, k)
+    el = time.time() - t2
+    steps = k + 1
+    secs = el + one
+    log("cpu oracle: %d steps in %.2f s on %d threads (setup %.1f s)" % (steps, secs, threads, t1 - t0), quiet)
+    return {"value": n * steps / secs, "unit": "atom-steps/s", "cores": threads, "kind": "oracle",
+            "sample": "%d steps of the same %d-particle workload (FP64 linked cells, OpenMP), "
+                      "after 1 untimed step" % (steps, n)}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(--gpus %d requested)" % a.gpus, file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    w, s = make_system(a.workload, a.quiet, a.cell_factor)
+    n = s.n
+    s.step(a.warmup)
+    o0 = s.observables()
+    s.history()
+    timing = not a.no_events
+    if timing:
+        s.timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.step(a.steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    tm = s.timing() if timing else None
+    if timing:
+        s.timing(False)
+    o1 = s.observables()
+    hist = s.history()
+    value = n * a.steps / el
+    ms = 1e3 * el / a.steps
+    rec = {
+        "metric": "atom-steps/s (1M LJ, 2M KG melt)",
+        "value": value,
+        "unit": "atom-steps/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": w["name"], "n_particles": n, "rc": w["rc"], "skin": w["skin"],
+                   "dt": w["dt"], "integrator": w["integrator"],
+                   "precision": "FP32 pair/bonded math, FP64 positions, velocities and reductions",
+                   "parallelism": "single GPU", "cell_factor": s.cfg.cell_factor or 1},
+        "n_rebuilds": o1["n_rebuilds"] - o0["n_rebuilds"],
+        "energy_drift_per_particle": (o1["e_total"] - o0["e_total"]) / n,
+        "nl_max_count": o1["nl_max_count"],
+    }
+    if tm:
+        k_ms = tm["ms_step_kernels"] / max(tm["n_step_kernels"], 1)
+        alg = ALG_BYTES[a.workload] * n
+        ach = alg / (k_ms * 1e-3) / 1e9
+        rec["roofline"] = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                           "frac": ach / HBM_PEAK_GBS, "traffic": None,
+                           "kernel": "k_step (fused pair+bonded forces, velocity Verlet, reductions)",
+                           "kernel_ms": k_ms, "alg_bytes_per_launch": alg}
+        rec["kernel_breakdown_ms_per_step"] = {
+            "rebuild_stage": tm["ms_rebuild"] / max(tm["n_rebuild"], 1),
+            "step_kernel": k_ms,
+            "finalize": tm["ms_finalize"] / max(tm["n_finalize"], 1)}
+    if a.calib_copy:
+        src = torch.ones(128 * 1024 * 1024, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        rec["calib_copy_bytes"] = src.numel() * 4
+    if not a.no_cpu_baseline:
+        rec["cpu_baseline"] = cpu_baseline(w, a.workload, a.cpu_seconds, a.quiet)
+    s.close()
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -34,6 +34,8 @@ struct md_handle_s {
     Bufs b;
     PairTable pt;
     Dyn dy;
+    FastCoef fast;
+    int32_t use_fast = 0;
     hipStream_t stream = nullptr;
     int parity = 0;
     int64_t host_step = 0;
@@ -99,7 +101,7 @@ static md_status validate(const md_config* c, std::string* why) {
     if (c->n_bonds < 0 || c->n_angles < 0) { *why = "negative bond/angle count"; return MD_ERR_ARG; }
     if (c->n_bonds > 0 && !(c->fene_R0 > 0.0 && c->fene_K >= 0.0)) { *why = "FENE needs R0 > 0, K >= 0"; return MD_ERR_ARG; }
     if (c->nl_capacity < 0 || c->nl_capacity > 4096) { *why = "nl_capacity out of range"; return MD_ERR_ARG; }
-    if (c->cell_factor < 0 || c->cell_factor > 1) { *why = "cell_factor must be 0 or 1"; return MD_ERR_ARG; }
+    if (c->cell_factor < 0 || c->cell_factor > 2) { *why = "cell_factor must be 0, 1 or 2"; return MD_ERR_ARG; }
     return MD_OK;
 }
 
@@ -108,6 +110,16 @@ static double rc_max_of(const md_config* c) {
     for (int a = 0; a < c->n_types; ++a)
         for (int bb = 0; bb < c->n_types; ++bb) m = fmax(m, c->pair[a * MD_MAX_TYPES + bb].rc);
     return m;
+}
+
+// Width of the band around a squared cutoff r2 inside which a decision
+// taken on fixed-point coordinates is retaken in FP64: four times a bound on
+// |r2_fixed - r2| from the quantisation (L / 2^32 per coordinate), the
+// int->float conversion and the FP32 products.
+static double fixed_band(double r2, double Lmax) {
+    const double r = sqrt(r2);
+    const double eq = Lmax * 0x1.0p-32;
+    return 4.0 * (2.0 * sqrt(3.0) * r * 2.0 * eq + (4.0 * sqrt(3.0) + 4.0) * 0x1.0p-24 * r2);
 }
 
 static md_status plan_geom(const md_config* c, Geom* g, std::string* why) {
@@ -119,23 +131,33 @@ static md_status plan_geom(const md_config* c, Geom* g, std::string* why) {
     const double rv = rc_max_of(c) + c->skin;
     g->rv2 = rv * rv;
     g->disp2 = (0.5 * c->skin) * (0.5 * c->skin);
+    g->kc = c->cell_factor > 0 ? c->cell_factor : 1;
     g->ncell = 1;
+    double Lmax = 0.0;
     for (int d = 0; d < 3; ++d) {
         g->L[d] = c->box[d];
         g->hL[d] = 0.5 * c->box[d];
-        int nc = (int)floor(c->box[d] / (rv * (1.0 + 1e-12)));
-        if (nc < 3) {
-            char buf[160];
-            snprintf(buf, sizeof buf, "box %.6g holds %d cells of side >= rc+skin = %.6g along axis %d; need >= 3",
-                     c->box[d], nc, rv, d);
+        g->invL[d] = 1.0 / c->box[d];
+        Lmax = fmax(Lmax, c->box[d]);
+        int nc = (int)floor(c->box[d] * g->kc / (rv * (1.0 + 1e-12)));
+        if (nc < 2 * g->kc + 1) {
+            char buf[200];
+            snprintf(buf, sizeof buf, "box %.6g holds %d cells of side >= (rc+skin)/%d = %.6g along axis %d; need >= %d",
+                     c->box[d], nc, g->kc, rv / g->kc, d, 2 * g->kc + 1);
             *why = buf;
             return MD_ERR_BOX_TOO_SMALL;
         }
         if (nc > 4096) nc = 4096;
         g->nc[d] = nc;
         g->invh[d] = (double)nc / c->box[d];
+        g->h[d] = c->box[d] / (double)nc;
         g->ncell *= nc;
+        g->qs[d] = 0x1.0p32 / c->box[d];
+        g->ql[d] = (float)(c->box[d] * 0x1.0p-32);
     }
+    const double band = fixed_band(g->rv2, Lmax);
+    g->rv2lo = (float)(g->rv2 - band);
+    g->rv2hi = (float)(g->rv2 + band);
     if (c->nl_capacity > 0) {
         g->cap = c->nl_capacity;
     } else {
@@ -170,6 +192,8 @@ static size_t carve(const md_config* c, const Geom& g, int step_grid, uint8_t* b
     t.partials = (double*)take(sizeof(double) * kNacc * (size_t)step_grid);
     t.x[0] = (double4*)take(sizeof(double4) * n);
     t.x[1] = (double4*)take(sizeof(double4) * n);
+    t.xq[0] = (int4*)take(sizeof(int4) * n);
+    t.xq[1] = (int4*)take(sizeof(int4) * n);
     t.v = (double*)take(sizeof(double) * 3 * n);
     t.xb = (double*)take(sizeof(double) * 3 * n);
     t.img = (int32_t*)take(sizeof(int32_t) * 3 * n);
@@ -186,7 +210,7 @@ static size_t carve(const md_config* c, const Geom& g, int step_grid, uint8_t* b
     t.imgt = (int32_t*)take(sizeof(int32_t) * 3 * n);
     t.tagt = (int32_t*)take(sizeof(int32_t) * n);
     t.ncount = (int32_t*)take(sizeof(int32_t) * n);
-    t.nl = (int32_t*)take(sizeof(int32_t) * (size_t)g.cap * n);
+    t.nl = (int32_t*)take(sizeof(int32_t) * (size_t)g.cap * (size_t)((n + 63) / 64 * 64));
     if (bonded) {
         t.tcnt_t = (int32_t*)take(sizeof(int32_t) * n);
         t.tcnt_s = (int32_t*)take(sizeof(int32_t) * n);
@@ -205,7 +229,7 @@ static size_t carve(const md_config* c, const Geom& g, int step_grid, uint8_t* b
     return off;
 }
 
-static int step_grid_of(int64_t n) { return (int)((n + kBlock - 1) / kBlock); }
+static int step_grid_of(int64_t n) { return step_grid(n); }
 
 static void fill_params(md_handle h, const md_config* c) {
     PairTable& pt = h->pt;
@@ -240,7 +264,28 @@ static void fill_params(md_handle h, const md_config* c) {
             pt.f[tp] = PairCoef<float>{(float)d.eps4, (float)d.eps24, (float)d.sig2, (float)d.rc2,
                                        (float)d.shift, (float)d.cap2, (float)d.ucap, (float)d.fcap};
             pt.rc2d[tp] = p.rc * p.rc;
+            double Lmax = fmax(c->box[0], fmax(c->box[1], c->box[2]));
+            const double band = fixed_band(p.rc * p.rc, Lmax);
+            pt.rc2lo[tp] = (float)(p.rc * p.rc - band);
+            pt.rc2hi[tp] = (float)(p.rc * p.rc + band);
         }
+    // fast FP32 path: one type, cubic box, no capping radius
+    {
+        const md_pair_params& p = c->pair[0];
+        const bool cubic = c->box[0] == c->box[1] && c->box[1] == c->box[2];
+        h->use_fast = (c->n_types == 1 && cubic && !(p.caprad > 0.0)) ? 1 : 0;
+        const double u = c->box[0] * 0x1.0p-32;
+        FastCoef& f = h->fast;
+        memset(&f, 0, sizeof(f));
+        f.rc2lo = (float)((double)pt.rc2lo[0] / (u * u));
+        f.rc2hi = (float)((double)pt.rc2hi[0] / (u * u));
+        f.sig2u = (float)(p.sigma * p.sigma / (u * u));
+        f.eps24_u = (float)(24.0 * p.eps / u);
+        f.eps4 = (float)(4.0 * p.eps);
+        f.eps24 = (float)(24.0 * p.eps);
+        f.shift = (float)pt.d[0].shift;
+        f.rc2d = pt.rc2d[0];
+    }
     Dyn& dy = h->dy;
     memset(&dy, 0, sizeof(dy));
     dy.dt = c->dt;
@@ -274,6 +319,8 @@ static StepArgs make_args(md_handle h, int mode, int tensor, double* f_out) {
     a.b = h->b;
     a.pt = h->pt;
     a.dy = h->dy;
+    a.fast = h->fast;
+    a.use_fast = h->use_fast;
     a.parity = h->parity;
     a.mode = mode;
     a.tensor = tensor;

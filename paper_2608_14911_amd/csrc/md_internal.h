@@ -52,27 +52,39 @@ struct PairTable {
     PairCoef<double> d[MD_MAX_TYPES * MD_MAX_TYPES];
     PairCoef<float> f[MD_MAX_TYPES * MD_MAX_TYPES];
     double rc2d[MD_MAX_TYPES * MD_MAX_TYPES];
+    // FP32 path: r^2 below lo interacts, above hi does not; in between the
+    // decision is retaken in FP64 from the FP64 positions
+    float rc2lo[MD_MAX_TYPES * MD_MAX_TYPES];
+    float rc2hi[MD_MAX_TYPES * MD_MAX_TYPES];
 };
 
 // Everything a kernel of one handle needs; passed by value.
 struct Geom {
     int64_t n;
     double L[3], hL[3];     // box, half box
+    double invL[3];         // 1 / L
     double invh[3];         // cells per unit length
+    double h[3];            // cell side
     int nc[3];
+    int kc;                 // stencil reach in cells (cells of side >= rv / kc)
     int64_t ncell;
     double rv2;             // list radius squared (FP64, exact same ops as the oracle)
     double disp2;           // (skin/2)^2
     int32_t cap;            // ELL capacity
     int32_t ntypes;
+    // 32-bit fixed-point positions: q = floor(x * qs), dx = (int32)(q_j - q_i) * ql
+    double qs[3];           // 2^32 / L
+    float ql[3];            // L / 2^32
+    float rv2lo, rv2hi;     // fixed-point list test band; FP64 test in between
 };
 
 struct Bufs {
     DevCtl* ctl;
-    double* partials;       // [grid][kNacc]
+    double* partials;       // [kNacc][grid]
     double* hist;           // [MD_HISTORY_CAPACITY][kHistRec]
     double* cur;            // [kHistRec] observables of the last finalize
     double4* x[2];          // positions (w = type), sorted order, by step parity
+    int4* xq[2];            // fixed-point positions (w = type), by step parity
     double* v;              // [3][N] SoA, sorted order
     double* xb;             // [3][N] positions at the last build
     int32_t* img;           // [3][N]
@@ -120,11 +132,23 @@ constexpr uint32_t MD_FLAG_BAD_TYPE = 0x100u;
 
 enum Mode { MODE_STEP = 0, MODE_OBSERVE = 1, MODE_FORCES = 2 };
 
+// Single-type LJ coefficients rescaled to fixed-point length units u = L/2^32
+// (cubic box): r2 and the band limits in u^2, sigma^2 / u^2, 24 eps / u.
+struct FastCoef {
+    float rc2lo, rc2hi;     // band limits on r2 in u^2
+    float sig2u;            // sigma^2 / u^2
+    float eps24_u;          // 24 eps / u
+    float eps4, eps24, shift;
+    double rc2d;            // rc^2 (FP64 re-decision)
+};
+
 struct StepArgs {
     Geom g;
     Bufs b;
     PairTable pt;
     Dyn dy;
+    FastCoef fast;
+    int32_t use_fast;
     int32_t parity;
     int32_t mode;
     int32_t tensor;
@@ -142,6 +166,7 @@ hipError_t launch_rebuild(const Geom& g, const Bufs& b, int parity, int bonded, 
 hipError_t launch_clear_rebuild(const Bufs& b, hipStream_t s);
 hipError_t launch_step(const StepArgs& a, int fp64, int single_type, int bonded, int block,
                        hipStream_t s);
+int step_grid(int64_t n);
 hipError_t launch_finalize(const Bufs& b, int nblocks, int mode, hipStream_t s);
 hipError_t launch_overwrite_state(const Geom& g, const Bufs& b, int parity, const double* pos,
                                   const double* vel, const int32_t* image, hipStream_t s);

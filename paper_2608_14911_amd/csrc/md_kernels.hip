@@ -19,12 +19,24 @@ namespace md {
 
 // ------------------------------------------------------------------ helpers
 
-// Minimum image by compare-and-shift: the same IEEE operations on every
-// side, and exactly antisymmetric (d_ji = -d_ij).
-__device__ __forceinline__ double mimg(double d, double L, double hL) {
-    if (d > hL) d -= L;
-    else if (d < -hL) d += L;
-    return d;
+// Minimum image d - L rint(d / L), branch-free.  For |d| < L (positions in
+// [0, L)) the shift is 0 or +-L and the result is d -/+ L rounded once, the
+// same value a compare-and-shift gives except within an ulp of |d| = L/2,
+// which is never inside the list radius (L >= 3 cells >= 2 rv).  Exactly
+// antisymmetric: d_ji = -d_ij.
+__device__ __forceinline__ double mimg(double d, double L, double invL) {
+    return fma(-L, rint(d * invL), d);
+}
+
+// 32-bit fixed-point coordinate: q = floor(x 2^32 / L) for x in [0, L); a
+// product that rounds up to 2^32 wraps to 0, the same point of the periodic
+// box.  The difference (int32)(q_j - q_i) is the minimum image.
+__device__ __forceinline__ uint32_t quantize(double x, double qs) { return (uint32_t)(uint64_t)(x * qs); }
+__device__ __forceinline__ float qdiff(uint32_t a, uint32_t b, float ql) {
+    return (float)(int32_t)(a - b) * ql;
+}
+__device__ __forceinline__ int4 quantize4(const Geom& g, double x, double y, double z, double w) {
+    return make_int4((int)quantize(x, g.qs[0]), (int)quantize(y, g.qs[1]), (int)quantize(z, g.qs[2]), (int)w);
 }
 
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
@@ -125,6 +137,28 @@ __device__ __forceinline__ bool rebuild_requested(const Bufs& b) {
 }
 
 __device__ __forceinline__ int64_t gtid() { return (int64_t)blockIdx.x * blockDim.x + threadIdx.x; }
+
+// Workgroups are handed to the 8 XCDs round-robin (block b -> XCD b % 8),
+// and each XCD has its own L2.  Remap so that XCD x works on one contiguous
+// 1/8 of the cell-sorted particles: a spatially compact slab whose gathered
+// neighbour records stay in that XCD's L2.  Bijective for any grid size.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int xcd_block(int b, int G) {
+    const int q = G / kXcds, r = G % kXcds;
+    const int x = b % kXcds, k = b / kXcds;
+    return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + k;
+}
+// Verlet-list layout: tiles of 64 particles (one wavefront); inside a tile
+// slot k of all 64 particles is contiguous (256 bytes), and a tile's slots
+// follow each other, so a wavefront streams one contiguous block.
+constexpr int kTile = 64;
+__device__ __forceinline__ int64_t nl_base(int64_t i, int cap) {
+    return (i >> 6) * (int64_t)cap * kTile + (i & (kTile - 1));
+}
+
+__device__ __forceinline__ int64_t gtid_xcd() {
+    return (int64_t)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+}
 __device__ __forceinline__ int64_t gstride() { return (int64_t)gridDim.x * blockDim.x; }
 
 // ------------------------------------------------------------------ init / state I/O
@@ -182,6 +216,7 @@ __global__ void __launch_bounds__(kBlock) k_overwrite_state(Geom g, Bufs b, int 
             b.v[d * n + s] = vel[3 * t + d];
         }
         b.x[parity][s] = make_double4(p[0], p[1], p[2], old.w);
+        b.xq[parity][s] = quantize4(g, p[0], p[1], p[2], old.w);
     }
 }
 
@@ -208,7 +243,8 @@ __global__ void __launch_bounds__(kBlock) k_get_neighbors(Geom g, Bufs b, int32_
         int c = b.ncount[s];
         int cc = c < g.cap ? c : g.cap;
         count[t] = c;
-        for (int k = 0; k < cc && k < cap; ++k) idx[t * (int64_t)cap + k] = b.tag[b.nl[(int64_t)k * n + s]];
+        const int32_t* row = b.nl + nl_base(s, g.cap);
+        for (int k = 0; k < cc && k < cap; ++k) idx[t * (int64_t)cap + k] = b.tag[row[k * kTile]];
     }
 }
 
@@ -369,6 +405,7 @@ __global__ void __launch_bounds__(kBlock) k_commit(Geom g, Bufs b, int parity, i
     for (int64_t s = gtid(); s < n; s += gstride()) {
         double4 p = b.xt[s];
         b.x[parity][s] = p;
+        b.xq[parity][s] = quantize4(g, p.x, p.y, p.z, p.w);
         b.xb[s] = p.x;
         b.xb[n + s] = p.y;
         b.xb[2 * n + s] = p.z;
@@ -385,68 +422,132 @@ __global__ void __launch_bounds__(kBlock) k_commit(Geom g, Bufs b, int parity, i
 
 // ------------------------------------------------------------------ rebuild: Verlet list
 
-// NL(i) = { j != i : r_ij^2 < rv^2 } over the 27 surrounding cells, with
-// r^2 = (dx*dx + dy*dy) + dz*dz in FP64 and no fused multiply-add, so the
-// sets equal those of any implementation performing the same IEEE
-// operations.  Row order: stencil (z, y, x offsets -1..1), then sorted index.
-// Also remaps the bonded topology from tags to sorted indices.
-__global__ void __launch_bounds__(kBlock) k_nl_build(Geom g, Bufs b, int parity, int bonded) {
+// r_ij^2 in FP64 with the operation order of the plain definition
+// ((dx*dx + dy*dy) + dz*dz, no fused multiply-add): the list and cutoff
+// decisions taken with it equal those of any implementation doing the same
+// IEEE operations on the same positions.
+__device__ __forceinline__ double exact_r2(const Geom& g, const double4& a, const double4& b) {
 #pragma clang fp contract(off)
+    const double dx = mimg(b.x - a.x, g.L[0], g.invL[0]);
+    const double dy = mimg(b.y - a.y, g.L[1], g.invL[1]);
+    const double dz = mimg(b.z - a.z, g.L[2], g.invL[2]);
+    return (dx * dx + dy * dy) + dz * dz;
+}
+
+// distance along one axis from a point at offset u inside its cell to the
+// cell o cells away
+__device__ __forceinline__ float cell_gap(int o, float u, float h) {
+    float d = o > 0 ? (float)o * h - u : (o < 0 ? u + (float)(-o - 1) * h : 0.0f);
+    return d > 0.0f ? d : 0.0f;
+}
+
+__device__ __forceinline__ int wrapc(int c, int nc) { return c < 0 ? c + nc : (c >= nc ? c - nc : c); }
+
+// NL(i) = { j != i : r_ij^2 < rv^2 } over the cells within rv of particle i
+// (stencil of (2kc+1)^3 cells of side >= rv/kc, cells farther than rv
+// skipped).  The test runs on the fixed-point positions and is retaken in
+// FP64 (exact_r2) inside a band around rv that bounds the fixed-point
+// rounding, so the sets are those of the FP64 definition.  Row order:
+// stencil (z, y, x offsets), then sorted index.  Also remaps the bonded
+// topology from tags to sorted indices.
+__global__ void __launch_bounds__(kBlock) k_nl_build(Geom g, Bufs b, int parity, int bonded) {
     if (!rebuild_requested(b)) return;
     const int64_t n = g.n;
     const double4* __restrict__ x = b.x[parity];
+    const int4* __restrict__ xq = b.xq[parity];
+    const float hx = (float)g.h[0], hy = (float)g.h[1], hz = (float)g.h[2];
+    const int kc = g.kc;
     int local_max = 0;
     bool overflow = false;
-    for (int64_t i = gtid(); i < n; i += gstride()) {
-        double4 xi = x[i];
+    for (int64_t i = gtid_xcd(); i < n; i += gstride()) {
+        const double4 xi = x[i];
+        const int4 qi = xq[i];
         int cx, cy, cz;
         cell_coords(g, xi.x, xi.y, xi.z, cx, cy, cz);
+        const float uy = (float)(xi.y - cy * g.h[1]);
+        const float uz = (float)(xi.z - cz * g.h[2]);
         int cnt = 0;
-        for (int oz = -1; oz <= 1; ++oz) {
-            int nz = cz + oz;
-            nz = nz < 0 ? nz + g.nc[2] : (nz >= g.nc[2] ? nz - g.nc[2] : nz);
-            for (int oy = -1; oy <= 1; ++oy) {
-                int ny = cy + oy;
-                ny = ny < 0 ? ny + g.nc[1] : (ny >= g.nc[1] ? ny - g.nc[1] : ny);
-                for (int ox = -1; ox <= 1; ++ox) {
-                    int nx = cx + ox;
-                    nx = nx < 0 ? nx + g.nc[0] : (nx >= g.nc[0] ? nx - g.nc[0] : nx);
-                    int64_t c = ((int64_t)nz * g.nc[1] + ny) * g.nc[0] + nx;
-                    int st = b.cstart[c], en = b.cstart[c + 1];
-                    for (int j = st; j < en; ++j) {
-                        if (j == i) continue;
-                        double4 xj = x[j];
-                        double dx = mimg(xj.x - xi.x, g.L[0], g.hL[0]);
-                        double dy = mimg(xj.y - xi.y, g.L[1], g.hL[1]);
-                        double dz = mimg(xj.z - xi.z, g.L[2], g.hL[2]);
-                        double r2 = (dx * dx + dy * dy) + dz * dz;
-                        if (r2 < g.rv2) {
-                            if (cnt < g.cap) b.nl[(int64_t)cnt * n + i] = j;
-                            ++cnt;
-                        }
+        int32_t* __restrict__ nlrow = b.nl + nl_base(i, g.cap);
+        // Cells cx-kc .. cx+kc of one (y, z) row are consecutive in the cell
+        // order, so their particles form one contiguous range of the sorted
+        // arrays (two when the row wraps around the box).
+        auto test_range = [&](int st, int en) {
+            int j = st;
+            for (; j + 4 <= en; j += 4) {
+                int4 qq[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) qq[u] = xq[j + u];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const float dx = qdiff(qq[u].x, qi.x, g.ql[0]);
+                    const float dy = qdiff(qq[u].y, qi.y, g.ql[1]);
+                    const float dz = qdiff(qq[u].z, qi.z, g.ql[2]);
+                    const float r2 = dx * dx + dy * dy + dz * dz;
+                    bool in = r2 < g.rv2lo;
+                    if (!in && r2 < g.rv2hi) in = exact_r2(g, xi, x[j + u]) < g.rv2;
+                    if (in && j + u != i) {
+                        if (cnt < g.cap) nlrow[cnt * kTile] = j + u;
+                        ++cnt;
                     }
+                }
+            }
+            for (; j < en; ++j) {
+                const int4 qj = xq[j];
+                const float dx = qdiff(qj.x, qi.x, g.ql[0]);
+                const float dy = qdiff(qj.y, qi.y, g.ql[1]);
+                const float dz = qdiff(qj.z, qi.z, g.ql[2]);
+                const float r2 = dx * dx + dy * dy + dz * dz;
+                bool in = r2 < g.rv2lo;
+                if (!in && r2 < g.rv2hi) in = exact_r2(g, xi, x[j]) < g.rv2;
+                if (in && j != i) {
+                    if (cnt < g.cap) nlrow[cnt * kTile] = j;
+                    ++cnt;
+                }
+            }
+        };
+        const int xlo = cx - kc, xhi = cx + kc;   // inclusive cell range along x
+        for (int oz = -kc; oz <= kc; ++oz) {
+            const float gz = cell_gap(oz, uz, hz);
+            const float gz2 = gz * gz;
+            if (gz2 > g.rv2hi) continue;
+            const int nz = wrapc(cz + oz, g.nc[2]);
+            for (int oy = -kc; oy <= kc; ++oy) {
+                const float gy = cell_gap(oy, uy, hy);
+                if (gz2 + gy * gy > g.rv2hi) continue;
+                const int ny = wrapc(cy + oy, g.nc[1]);
+                const int64_t rowc = ((int64_t)nz * g.nc[1] + ny) * g.nc[0];
+                if (xlo >= 0 && xhi < g.nc[0]) {
+                    test_range(b.cstart[rowc + xlo], b.cstart[rowc + xhi + 1]);
+                } else if (xlo < 0) {
+                    test_range(b.cstart[rowc + g.nc[0] + xlo], b.cstart[rowc + g.nc[0]]);
+                    test_range(b.cstart[rowc], b.cstart[rowc + xhi + 1]);
+                } else {
+                    test_range(b.cstart[rowc + xlo], b.cstart[rowc + g.nc[0]]);
+                    test_range(b.cstart[rowc], b.cstart[rowc + xhi - g.nc[0] + 1]);
                 }
             }
         }
         b.ncount[i] = cnt;
         if (cnt > local_max) local_max = cnt;
         if (cnt > g.cap) overflow = true;
+        // pad the row to a multiple of 8 with the particle itself (r = 0,
+        // never inside a cutoff) so that step kernels stream whole batches
+        for (int k = cnt; k < ((cnt + 7) & ~7) && k < g.cap; ++k) nlrow[k * kTile] = (int)i;
         if (bonded) {
-            int32_t t = b.tag[i];
-            int tc = b.tcnt_t[t];
-            int nb = tc & 0xff, na = tc >> 8;
+            const int32_t t = b.tag[i];
+            const int tc = b.tcnt_t[t];
+            const int nb = tc & 0xff, na = tc >> 8;
             for (int k = 0; k < nb; ++k) b.bp_s[(int64_t)k * n + i] = b.inv[b.bp_t[(int64_t)k * n + t]];
             for (int k = 0; k < na; ++k) {
-                int2 e = b.ang_t[(int64_t)k * n + t];
-                int role = (int)((uint32_t)e.x >> 30);
-                int o1 = e.x & 0x3fffffff;
+                const int2 e = b.ang_t[(int64_t)k * n + t];
+                const int role = (int)((uint32_t)e.x >> 30);
+                const int o1 = e.x & 0x3fffffff;
                 b.ang_s[(int64_t)k * n + i] = make_int2(b.inv[o1] | (role << 30), b.inv[e.y]);
             }
         }
     }
-    // one atomic per wave
     for (int o = 32; o >= 1; o >>= 1) {
-        int y = __shfl_xor(local_max, o, 64);
+        const int y = __shfl_xor(local_max, o, 64);
         local_max = y > local_max ? y : local_max;
     }
     if ((threadIdx.x & 63) == 0 && local_max > 0) atomicMax(&b.ctl->nl_max, local_max);
@@ -457,248 +558,203 @@ __global__ void k_clear_rebuild(Bufs b) {
     if (threadIdx.x == 0 && blockIdx.x == 0) b.ctl->rebuild = 0;
 }
 
-// ------------------------------------------------------------------ forces + integration
+// ------------------------------------------------------------------ bonded forces
 
-// Fused per-particle kernel: pair forces over the Verlet row, bonded forces,
-// then (MODE_STEP) the velocity-Verlet update with the Langevin force, the
-// periodic wrap, the half-skin displacement test, and per-block FP64 partial
-// sums of energy, kinetic energy and virial.  Positions are double-buffered
-// by step parity so that the update can run in the same kernel as the
-// neighbour gathers.  Real is the precision of the pair / bonded math;
-// coordinate differences are always taken in FP64.
-template <typename Real, bool SINGLE, bool BONDED>
-__global__ void __launch_bounds__(kBlock) k_step(const StepArgs a) {
+// Coordinate differences b - a for the two position formats.
+struct DiffQ {
+    float l0, l1, l2;
+    __device__ void operator()(const int4& a, const int4& b, float& dx, float& dy, float& dz) const {
+        dx = qdiff(b.x, a.x, l0);
+        dy = qdiff(b.y, a.y, l1);
+        dz = qdiff(b.z, a.z, l2);
+    }
+};
+struct Diff64 {
+    double L0, L1, L2, i0, i1, i2;
+    __device__ void operator()(const double4& a, const double4& b, double& dx, double& dy, double& dz) const {
+        dx = mimg(b.x - a.x, L0, i0);
+        dy = mimg(b.y - a.y, L1, i1);
+        dz = mimg(b.z - a.z, L2, i2);
+    }
+};
+
+__device__ __forceinline__ void add_tensor(double* acc, double s, double rx, double ry, double rz, double fx,
+                                           double fy, double fz) {
+    acc[A_TXX] += s * rx * fx;
+    acc[A_TYY] += s * ry * fy;
+    acc[A_TZZ] += s * rz * fz;
+    acc[A_TXY] += s * 0.5 * (rx * fy + ry * fx);
+    acc[A_TXZ] += s * 0.5 * (rx * fz + rz * fx);
+    acc[A_TYZ] += s * 0.5 * (ry * fz + rz * fy);
+}
+
+// FENE bonds and cosine bending angles acting on particle i, from its own
+// rows of the sorted-space topology.  Each bond is evaluated by both ends
+// (half the energy each), each angle by its three members (energy counted
+// by the centre); no atomics.
+template <typename Real, typename P, typename Diff>
+__device__ __forceinline__ void bonded_forces(const Bufs& b, const Dyn& dyn, int64_t n, int64_t i,
+                                              const P* __restrict__ xs, const P& pi, const Diff& diff,
+                                              Real& fx, Real& fy, Real& fz, double* acc, bool tensor,
+                                              bool& flag_bond) {
+    const bool f64 = sizeof(Real) == 8;
+    const int tc = b.tcnt_s[i];
+    const int nb = tc & 0xff, na = tc >> 8;
+    const Real K = f64 ? (Real)dyn.fene_K : (Real)dyn.fene_Kf;
+    const Real R02 = f64 ? (Real)dyn.fene_R02 : (Real)dyn.fene_R02f;
+    const Real hKR02 = f64 ? (Real)dyn.fene_halfKR02 : (Real)dyn.fene_halfKR02f;
+    Real eb = 0, wb = 0;
+    for (int q = 0; q < nb; ++q) {
+        const int m = b.bp_s[(int64_t)q * n + i];
+        Real dx, dy, dz;
+        diff(pi, xs[m], dx, dy, dz);                 // x_m - x_i
+        const Real rx = -dx, ry = -dy, rz = -dz;     // r_i - r_m
+        const Real r2 = rx * rx + ry * ry + rz * rz;
+        const Real qq = r2 / R02;
+        if (!(qq < Real(1))) {
+            flag_bond = true;
+            continue;
+        }
+        const Real om = Real(1) - qq;
+        const Real fr = -K / om;
+        fx += fr * rx;
+        fy += fr * ry;
+        fz += fr * rz;
+        eb += -hKR02 * logr<Real>(om);
+        wb += fr * r2;
+        if (tensor) add_tensor(acc, 0.5, rx, ry, rz, fr * rx, fr * ry, fr * rz);
+    }
+    acc[A_EBOND] += 0.5 * (double)eb;
+    acc[A_VIR] += 0.5 * (double)wb;
+    const Real kb = f64 ? (Real)dyn.k_bend : (Real)dyn.k_bendf;
+    Real ea = 0, wa = 0;
+    for (int q = 0; q < na; ++q) {
+        const int2 e = b.ang_s[(int64_t)q * n + i];
+        const int role = (int)((uint32_t)e.x >> 30);
+        const P p1 = xs[e.x & 0x3fffffff], p2 = xs[e.y];
+        // members (A, B, C), B the centre; i is the one named by role
+        const P& pa = role == 0 ? pi : p1;
+        const P& pb = role == 1 ? pi : (role == 0 ? p1 : p2);
+        const P& pc = role == 2 ? pi : p2;
+        Real b1x, b1y, b1z, b2x, b2y, b2z;
+        diff(pa, pb, b1x, b1y, b1z);                 // b1 = x_B - x_A
+        diff(pb, pc, b2x, b2y, b2z);                 // b2 = x_C - x_B
+        const Real l1sq = b1x * b1x + b1y * b1y + b1z * b1z;
+        const Real l2sq = b2x * b2x + b2y * b2y + b2z * b2z;
+        const Real il1l2 = rsq<Real>(l1sq * l2sq);
+        const Real cs = (b1x * b2x + b1y * b2y + b1z * b2z) * il1l2;
+        const Real i1 = rcp<Real>(l1sq), i2 = rcp<Real>(l2sq);
+        Real Fx, Fy, Fz;
+        if (role == 0) {          // F_A = -k dcos/db1
+            Fx = -kb * (b2x * il1l2 - cs * b1x * i1);
+            Fy = -kb * (b2y * il1l2 - cs * b1y * i1);
+            Fz = -kb * (b2z * il1l2 - cs * b1z * i1);
+            wa += -(b1x * Fx + b1y * Fy + b1z * Fz);                 // (x_A - x_B) . F_A
+            if (tensor) add_tensor(acc, 1.0, -b1x, -b1y, -b1z, Fx, Fy, Fz);
+        } else if (role == 2) {   // F_C = k dcos/db2
+            Fx = kb * (b1x * il1l2 - cs * b2x * i2);
+            Fy = kb * (b1y * il1l2 - cs * b2y * i2);
+            Fz = kb * (b1z * il1l2 - cs * b2z * i2);
+            wa += b2x * Fx + b2y * Fy + b2z * Fz;                    // (x_C - x_B) . F_C
+            if (tensor) add_tensor(acc, 1.0, b2x, b2y, b2z, Fx, Fy, Fz);
+        } else {                  // F_B = -(F_A + F_C)
+            Fx = kb * ((b2x * il1l2 - cs * b1x * i1) - (b1x * il1l2 - cs * b2x * i2));
+            Fy = kb * ((b2y * il1l2 - cs * b1y * i1) - (b1y * il1l2 - cs * b2y * i2));
+            Fz = kb * ((b2z * il1l2 - cs * b1z * i1) - (b1z * il1l2 - cs * b2z * i2));
+            ea += kb * (Real(1) - cs);
+        }
+        fx += Fx;
+        fy += Fy;
+        fz += Fz;
+    }
+    acc[A_EANGLE] += (double)ea;
+    acc[A_VIR] += (double)wa;
+}
+
+// ------------------------------------------------------------------ integration
+
+// Velocity Verlet with the Langevin force for one particle (MODE_STEP), or
+// only the on-step kinetic energy (MODE_OBSERVE / MODE_FORCES):
+//   F_tot   = F(x_n) [- gamma m v' + sqrt(2 gamma m kT/dt) xi_n]
+//   v_n     = v' + dt/(2m) F_tot          (v_n = v' before the first step)
+//   v_{n+h} = v_n + dt/(2m) F_tot,  x_{n+1} = x_n + dt v_{n+h}, wrapped
+// plus the half-skin displacement test against the build positions.
+__device__ __forceinline__ void finish_particle(const StepArgs& a, int64_t i, const double4& xi, int tm,
+                                               const double F[3], double* acc, bool& flag_reb,
+                                               bool& flag_nf) {
     const Geom& g = a.g;
     const Bufs& b = a.b;
     const int64_t n = g.n;
-    const double4* __restrict__ xin = b.x[a.parity];
-    double acc[kNacc];
-#pragma unroll
-    for (int k = 0; k < kNacc; ++k) acc[k] = 0.0;
-    bool flag_rebuild = false, flag_bond = false, flag_nonfinite = false;
-
-    const int64_t i = gtid();
-    if (i < n) {
-        const double4 xi = xin[i];
-        const int ti = SINGLE ? 0 : (int)xi.w;
-        Real fx = 0, fy = 0, fz = 0, ui = 0, wi = 0;
-        Real txx = 0, tyy = 0, tzz = 0, txy = 0, txz = 0, tyz = 0;
-        const bool tensor = a.tensor != 0;
-        int cnt = b.ncount[i];
-        cnt = cnt < g.cap ? cnt : g.cap;
-        const int32_t* __restrict__ row = b.nl + i;
-
-        auto pair = [&](const double4& xj) {
-            double dx = mimg(xj.x - xi.x, g.L[0], g.hL[0]);
-            double dy = mimg(xj.y - xi.y, g.L[1], g.hL[1]);
-            double dz = mimg(xj.z - xi.z, g.L[2], g.hL[2]);
-            double r2d = dx * dx + dy * dy + dz * dz;
-            const int tp = SINGLE ? 0 : ti * MD_MAX_TYPES + (int)xj.w;
-            if (r2d < a.pt.rc2d[tp]) {
-                const PairCoef<Real>& c = coef<Real>(a.pt, tp);
-                Real r2 = (Real)r2d;
-                Real fr, u;
-                if (c.cap2 > Real(0) && r2 < c.cap2) {
-                    fr = c.fcap * rsq<Real>(r2);
-                    u = c.ucap;
-                } else {
-                    Real inv = rcp<Real>(r2);
-                    Real s2 = c.sig2 * inv;
-                    Real s6 = s2 * s2 * s2;
-                    fr = c.eps24 * s6 * (Real(2) * s6 - Real(1)) * inv;
-                    u = c.eps4 * s6 * (s6 - Real(1)) - c.shift;
-                }
-                Real rx = -(Real)dx, ry = -(Real)dy, rz = -(Real)dz;  // r_i - r_j
-                fx += fr * rx;
-                fy += fr * ry;
-                fz += fr * rz;
-                ui += u;
-                wi += fr * r2;
-                if (tensor) {
-                    txx += fr * rx * rx; tyy += fr * ry * ry; tzz += fr * rz * rz;
-                    txy += fr * rx * ry; txz += fr * rx * rz; tyz += fr * ry * rz;
-                }
-            }
-        };
-
-        int k = 0;
-        for (; k + 4 <= cnt; k += 4) {
-            const int j0 = row[(int64_t)(k + 0) * n];
-            const int j1 = row[(int64_t)(k + 1) * n];
-            const int j2 = row[(int64_t)(k + 2) * n];
-            const int j3 = row[(int64_t)(k + 3) * n];
-            const double4 x0 = xin[j0], x1 = xin[j1], x2 = xin[j2], x3 = xin[j3];
-            pair(x0);
-            pair(x1);
-            pair(x2);
-            pair(x3);
-        }
-        for (; k < cnt; ++k) pair(xin[row[(int64_t)k * n]]);
-
-        acc[A_EPAIR] = 0.5 * (double)ui;
-        acc[A_VIR] = 0.5 * (double)wi;
-        if (tensor) {
-            acc[A_TXX] = 0.5 * (double)txx; acc[A_TYY] = 0.5 * (double)tyy; acc[A_TZZ] = 0.5 * (double)tzz;
-            acc[A_TXY] = 0.5 * (double)txy; acc[A_TXZ] = 0.5 * (double)txz; acc[A_TYZ] = 0.5 * (double)tyz;
-        }
-
-        if (BONDED) {
-            const int tc = b.tcnt_s[i];
-            const int nb = tc & 0xff, na = tc >> 8;
-            const Real K = sizeof(Real) == 8 ? (Real)a.dy.fene_K : (Real)a.dy.fene_Kf;
-            const Real R02 = sizeof(Real) == 8 ? (Real)a.dy.fene_R02 : (Real)a.dy.fene_R02f;
-            const Real hKR02 = sizeof(Real) == 8 ? (Real)a.dy.fene_halfKR02 : (Real)a.dy.fene_halfKR02f;
-            Real eb = 0, wb = 0;
-            for (int q = 0; q < nb; ++q) {
-                const int m = b.bp_s[(int64_t)q * n + i];
-                const double4 xm = xin[m];
-                Real rx = -(Real)mimg(xm.x - xi.x, g.L[0], g.hL[0]);
-                Real ry = -(Real)mimg(xm.y - xi.y, g.L[1], g.hL[1]);
-                Real rz = -(Real)mimg(xm.z - xi.z, g.L[2], g.hL[2]);
-                Real r2 = rx * rx + ry * ry + rz * rz;
-                Real qq = r2 / R02;
-                if (!(qq < Real(1))) {
-                    flag_bond = true;
-                    continue;
-                }
-                Real om = Real(1) - qq;
-                Real fr = -K / om;
-                fx += fr * rx;
-                fy += fr * ry;
-                fz += fr * rz;
-                eb += -hKR02 * logr<Real>(om);
-                wb += fr * r2;
-                if (tensor) {
-                    acc[A_TXX] += 0.5 * (double)(fr * rx * rx); acc[A_TYY] += 0.5 * (double)(fr * ry * ry);
-                    acc[A_TZZ] += 0.5 * (double)(fr * rz * rz); acc[A_TXY] += 0.5 * (double)(fr * rx * ry);
-                    acc[A_TXZ] += 0.5 * (double)(fr * rx * rz); acc[A_TYZ] += 0.5 * (double)(fr * ry * rz);
-                }
-            }
-            acc[A_EBOND] = 0.5 * (double)eb;
-            acc[A_VIR] += 0.5 * (double)wb;
-            const Real kb = sizeof(Real) == 8 ? (Real)a.dy.k_bend : (Real)a.dy.k_bendf;
-            Real ea = 0, wa = 0;
-            for (int q = 0; q < na; ++q) {
-                const int2 e = b.ang_s[(int64_t)q * n + i];
-                const int role = (int)((uint32_t)e.x >> 30);
-                const int o1 = e.x & 0x3fffffff, o2 = e.y;
-                const double4 p1 = xin[o1], p2 = xin[o2];
-                // particles (A, B, C) with B the centre
-                const double4& pa = role == 0 ? xi : p1;
-                const double4& pb = role == 1 ? xi : (role == 0 ? p1 : p2);
-                const double4& pc = role == 2 ? xi : p2;
-                Real b1x = (Real)mimg(pb.x - pa.x, g.L[0], g.hL[0]);
-                Real b1y = (Real)mimg(pb.y - pa.y, g.L[1], g.hL[1]);
-                Real b1z = (Real)mimg(pb.z - pa.z, g.L[2], g.hL[2]);
-                Real b2x = (Real)mimg(pc.x - pb.x, g.L[0], g.hL[0]);
-                Real b2y = (Real)mimg(pc.y - pb.y, g.L[1], g.hL[1]);
-                Real b2z = (Real)mimg(pc.z - pb.z, g.L[2], g.hL[2]);
-                Real l1sq = b1x * b1x + b1y * b1y + b1z * b1z;
-                Real l2sq = b2x * b2x + b2y * b2y + b2z * b2z;
-                Real il1l2 = rsq<Real>(l1sq * l2sq);
-                Real cs = (b1x * b2x + b1y * b2y + b1z * b2z) * il1l2;
-                Real i1 = rcp<Real>(l1sq), i2 = rcp<Real>(l2sq);
-                // dcos/db1 and dcos/db2
-                Real g1x = b2x * il1l2 - cs * b1x * i1, g1y = b2y * il1l2 - cs * b1y * i1, g1z = b2z * il1l2 - cs * b1z * i1;
-                Real g2x = b1x * il1l2 - cs * b2x * i2, g2y = b1y * il1l2 - cs * b2y * i2, g2z = b1z * il1l2 - cs * b2z * i2;
-                Real Fx, Fy, Fz;
-                if (role == 0) {
-                    Fx = -kb * g1x; Fy = -kb * g1y; Fz = -kb * g1z;
-                    wa += -(b1x * Fx + b1y * Fy + b1z * Fz);
-                    if (tensor) {
-                        acc[A_TXX] += (double)(-b1x * Fx); acc[A_TYY] += (double)(-b1y * Fy); acc[A_TZZ] += (double)(-b1z * Fz);
-                        acc[A_TXY] += 0.5 * (double)(-b1x * Fy - b1y * Fx); acc[A_TXZ] += 0.5 * (double)(-b1x * Fz - b1z * Fx);
-                        acc[A_TYZ] += 0.5 * (double)(-b1y * Fz - b1z * Fy);
-                    }
-                } else if (role == 2) {
-                    Fx = kb * g2x; Fy = kb * g2y; Fz = kb * g2z;
-                    wa += b2x * Fx + b2y * Fy + b2z * Fz;
-                    if (tensor) {
-                        acc[A_TXX] += (double)(b2x * Fx); acc[A_TYY] += (double)(b2y * Fy); acc[A_TZZ] += (double)(b2z * Fz);
-                        acc[A_TXY] += 0.5 * (double)(b2x * Fy + b2y * Fx); acc[A_TXZ] += 0.5 * (double)(b2x * Fz + b2z * Fx);
-                        acc[A_TYZ] += 0.5 * (double)(b2y * Fz + b2z * Fy);
-                    }
-                } else {
-                    Fx = kb * (g1x - g2x); Fy = kb * (g1y - g2y); Fz = kb * (g1z - g2z);
-                    ea += kb * (Real(1) - cs);
-                }
-                fx += Fx;
-                fy += Fy;
-                fz += Fz;
-            }
-            acc[A_EANGLE] = (double)ea;
-            acc[A_VIR] += (double)wa;
-        }
-
-        const double F[3] = {(double)fx, (double)fy, (double)fz};
-        const int tm = SINGLE ? 0 : ti;
-        const double hdtm = a.dy.hdtm[tm];
-        const double m = a.dy.mass[tm];
-        double vp[3], ft[3];
-        for (int d = 0; d < 3; ++d) vp[d] = b.v[d * n + i];
-        int32_t tg = -1;
-        if (a.dy.langevin || a.mode == MODE_FORCES) tg = b.tag[i];
-        if (a.dy.langevin) {
-            double g0, g1, g2;
-            gauss3(a.dy.seed, 0, (uint64_t)b.ctl->step, (uint64_t)tg, g0, g1, g2);
-            const double gm = a.dy.gm[tm], amp = a.dy.amp[tm];
-            ft[0] = (F[0] - gm * vp[0]) + amp * g0;
-            ft[1] = (F[1] - gm * vp[1]) + amp * g1;
-            ft[2] = (F[2] - gm * vp[2]) + amp * g2;
-        } else {
-            ft[0] = F[0]; ft[1] = F[1]; ft[2] = F[2];
-        }
-        const bool vh_in = b.ctl->vel_half != 0;
-        double von[3], ke = 0.0;
-        for (int d = 0; d < 3; ++d) {
-            von[d] = vh_in ? vp[d] + hdtm * ft[d] : vp[d];
-            ke += von[d] * von[d];
-        }
-        acc[A_EKIN] = 0.5 * m * ke;
-
-        if (a.mode == MODE_STEP) {
-            double xo[3] = {xi.x, xi.y, xi.z};
-            double d2 = 0.0;
-            for (int d = 0; d < 3; ++d) {
-                const double vh = von[d] + hdtm * ft[d];
-                double xn = xo[d] + a.dy.dt * vh;
-                if (xn < 0.0 || xn >= g.L[d]) {
-                    int im = b.img[d * n + i];
-                    if (xn < 0.0) { xn += g.L[d]; im -= 1; }
-                    if (xn >= g.L[d]) { xn -= g.L[d]; im += 1; }
-                    b.img[d * n + i] = im;
-                }
-                if (!isfinite(xn) || !isfinite(vh)) flag_nonfinite = true;
-                xo[d] = xn;
-                b.v[d * n + i] = vh;
-                const double dd = mimg(xn - b.xb[d * n + i], g.L[d], g.hL[d]);
-                d2 += dd * dd;
-            }
-            if (d2 > g.disp2) flag_rebuild = true;
-            b.x[a.parity ^ 1][i] = make_double4(xo[0], xo[1], xo[2], xi.w);
-        } else if (a.mode == MODE_FORCES && a.f_out) {
-            a.f_out[3 * (int64_t)tg] = F[0];
-            a.f_out[3 * (int64_t)tg + 1] = F[1];
-            a.f_out[3 * (int64_t)tg + 2] = F[2];
-        }
+    const double hdtm = a.dy.hdtm[tm];
+    const double m = a.dy.mass[tm];
+    double vp[3], ft[3];
+    for (int d = 0; d < 3; ++d) vp[d] = b.v[d * n + i];
+    int32_t tg = -1;
+    if (a.dy.langevin || a.mode == MODE_FORCES) tg = b.tag[i];
+    if (a.dy.langevin) {
+        double g0, g1, g2;
+        gauss3(a.dy.seed, 0, (uint64_t)b.ctl->step, (uint64_t)tg, g0, g1, g2);
+        const double gm = a.dy.gm[tm], amp = a.dy.amp[tm];
+        ft[0] = (F[0] - gm * vp[0]) + amp * g0;
+        ft[1] = (F[1] - gm * vp[1]) + amp * g1;
+        ft[2] = (F[2] - gm * vp[2]) + amp * g2;
+    } else {
+        ft[0] = F[0];
+        ft[1] = F[1];
+        ft[2] = F[2];
     }
+    const bool vh_in = b.ctl->vel_half != 0;
+    double von[3], ke = 0.0;
+    for (int d = 0; d < 3; ++d) {
+        von[d] = vh_in ? vp[d] + hdtm * ft[d] : vp[d];
+        ke += von[d] * von[d];
+    }
+    acc[A_EKIN] = 0.5 * m * ke;
+    if (a.mode == MODE_STEP) {
+        double xo[3] = {xi.x, xi.y, xi.z};
+        double d2 = 0.0;
+        for (int d = 0; d < 3; ++d) {
+            const double vh = von[d] + hdtm * ft[d];
+            double xn = xo[d] + a.dy.dt * vh;
+            if (xn < 0.0 || xn >= g.L[d]) {
+                int im = b.img[d * n + i];
+                if (xn < 0.0) { xn += g.L[d]; im -= 1; }
+                if (xn >= g.L[d]) { xn -= g.L[d]; im += 1; }
+                b.img[d * n + i] = im;
+            }
+            if (!isfinite(xn) || !isfinite(vh)) flag_nf = true;
+            xo[d] = xn;
+            b.v[d * n + i] = vh;
+            const double dd = mimg(xn - b.xb[d * n + i], g.L[d], g.invL[d]);
+            d2 += dd * dd;
+        }
+        if (d2 > g.disp2) flag_reb = true;
+        b.x[a.parity ^ 1][i] = make_double4(xo[0], xo[1], xo[2], xi.w);
+        b.xq[a.parity ^ 1][i] = quantize4(g, xo[0], xo[1], xo[2], xi.w);
+    } else if (a.mode == MODE_FORCES && a.f_out) {
+        a.f_out[3 * (int64_t)tg] = F[0];
+        a.f_out[3 * (int64_t)tg + 1] = F[1];
+        a.f_out[3 * (int64_t)tg + 2] = F[2];
+    }
+}
 
-    // flags: one store / atomic per wave
-    const bool any_reb = __any(flag_rebuild);
+// Flags (one store or atomic per wave) and the deterministic block
+// reduction of the per-particle sums into partials[k][block].
+__device__ __forceinline__ void block_epilogue(const StepArgs& a, const double* acc, bool flag_reb,
+                                              bool flag_bond, bool flag_nf, int nacc) {
+    const Bufs& b = a.b;
+    const bool any_reb = __any(flag_reb);
     const bool any_bond = __any(flag_bond);
-    const bool any_nf = __any(flag_nonfinite);
+    const bool any_nf = __any(flag_nf);
     if ((threadIdx.x & 63) == 0) {
         if (any_reb) __atomic_store_n(&b.ctl->rebuild_next, 1u, __ATOMIC_RELAXED);
         if (any_bond) atomicOr(&b.ctl->status, MD_FLAG_BOND_BROKEN);
         if (any_nf) atomicOr(&b.ctl->status, MD_FLAG_NONFINITE);
     }
-
-    // deterministic block reduction: wave butterfly, then waves in order
     __shared__ double red[kBlock / 64][kNacc];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int nacc = a.tensor ? kNacc : A_VIR + 1;
     for (int q = 0; q < nacc; ++q) {
-        double s = wave_sum(acc[q]);
+        const double s = wave_sum(acc[q]);
         if (lane == 0) red[w][q] = s;
     }
     __syncthreads();
@@ -706,27 +762,326 @@ __global__ void __launch_bounds__(kBlock) k_step(const StepArgs a) {
         double s = 0.0;
         if ((int)threadIdx.x < nacc)
             for (int ww = 0; ww < kBlock / 64; ++ww) s += red[ww][threadIdx.x];
-        b.partials[(int64_t)blockIdx.x * kNacc + threadIdx.x] = s;
+        b.partials[(int64_t)threadIdx.x * gridDim.x + blockIdx.x] = s;
     }
 }
 
-// One block: reduce the per-block partials in a fixed order, record the
-// step's observables, and (MODE_STEP) advance the step counter and move the
+// ------------------------------------------------------------------ step kernels
+
+// FP64 pair path: FP64 positions gathered from the double-buffered double4
+// array, all pair and bonded math in FP64.
+template <bool SINGLE, bool BONDED>
+__global__ void __launch_bounds__(kBlock) k_step64(const StepArgs a) {
+    const Geom& g = a.g;
+    const Bufs& b = a.b;
+    const int64_t n = g.n;
+    const double4* __restrict__ xin = b.x[a.parity];
+    double acc[kNacc];
+#pragma unroll
+    for (int k = 0; k < kNacc; ++k) acc[k] = 0.0;
+    bool flag_reb = false, flag_bond = false, flag_nf = false;
+    const bool tensor = a.tensor != 0;
+    const int64_t i = gtid_xcd();
+    if (i < n) {
+        const double4 xi = xin[i];
+        const int ti = SINGLE ? 0 : (int)xi.w;
+        double fx = 0, fy = 0, fz = 0, ui = 0, wi = 0;
+        int cnt = b.ncount[i];
+        cnt = cnt < g.cap ? cnt : g.cap;
+        const int32_t* __restrict__ row = b.nl + nl_base(i, g.cap);
+        for (int k = 0; k < cnt; ++k) {
+            const double4 xj = xin[row[k * kTile]];
+            const double dx = mimg(xj.x - xi.x, g.L[0], g.invL[0]);
+            const double dy = mimg(xj.y - xi.y, g.L[1], g.invL[1]);
+            const double dz = mimg(xj.z - xi.z, g.L[2], g.invL[2]);
+            const double r2 = dx * dx + dy * dy + dz * dz;
+            const int tp = SINGLE ? 0 : ti * MD_MAX_TYPES + (int)xj.w;
+            if (exact_r2(g, xi, xj) < a.pt.rc2d[tp]) {
+                const PairCoef<double>& c = a.pt.d[tp];
+                double fr, u;
+                if (c.cap2 > 0.0 && r2 < c.cap2) {
+                    fr = c.fcap / sqrt(r2);
+                    u = c.ucap;
+                } else {
+                    const double inv = 1.0 / r2;
+                    const double s2 = c.sig2 * inv;
+                    const double s6 = s2 * s2 * s2;
+                    fr = c.eps24 * s6 * (2.0 * s6 - 1.0) * inv;
+                    u = c.eps4 * s6 * (s6 - 1.0) - c.shift;
+                }
+                fx -= fr * dx;
+                fy -= fr * dy;
+                fz -= fr * dz;
+                ui += u;
+                wi += fr * r2;
+                if (tensor) add_tensor(acc, 0.5, -dx, -dy, -dz, -fr * dx, -fr * dy, -fr * dz);
+            }
+        }
+        acc[A_EPAIR] = 0.5 * ui;
+        acc[A_VIR] += 0.5 * wi;
+        if (BONDED) {
+            const Diff64 df{g.L[0], g.L[1], g.L[2], g.invL[0], g.invL[1], g.invL[2]};
+            bonded_forces<double, double4, Diff64>(b, a.dy, n, i, xin, xi, df, fx, fy, fz, acc, tensor, flag_bond);
+        }
+        const double F[3] = {fx, fy, fz};
+        finish_particle(a, i, xi, SINGLE ? 0 : ti, F, acc, flag_reb, flag_nf);
+    }
+    block_epilogue(a, acc, flag_reb, flag_bond, flag_nf, tensor ? kNacc : A_VIR + 1);
+}
+
+// FP32 pair path.  Neighbours are gathered as 16-byte fixed-point records;
+// dx = (int32)(q_j - q_i) * L/2^32 is the minimum image with no branch and
+// an absolute error of a few 1e-8; the pair and bonded math is FP32.  A
+// cutoff decision inside the rounding band around rc is retaken in FP64
+// from the FP64 positions, so the set of interacting pairs is that of the
+// FP64 definition.  Neighbour indices are loaded one batch of 8 ahead of
+// the gathers that use them.
+template <bool SINGLE, bool BONDED, bool TENSOR>
+__global__ void __launch_bounds__(kBlock) k_step_q(const StepArgs a) {
+    const Geom& g = a.g;
+    const Bufs& b = a.b;
+    const int64_t n = g.n;
+    const int4* __restrict__ xq = b.xq[a.parity];
+    const double4* __restrict__ x64 = b.x[a.parity];
+    double acc[kNacc];
+#pragma unroll
+    for (int k = 0; k < kNacc; ++k) acc[k] = 0.0;
+    bool flag_reb = false, flag_bond = false, flag_nf = false;
+    const int64_t i = gtid_xcd();
+    if (i < n) {
+        const double4 xi = x64[i];
+        const int4 qi = quantize4(g, xi.x, xi.y, xi.z, xi.w);  // equals xq[i]: same function
+        const int ti = SINGLE ? 0 : qi.w;
+        const float l0 = g.ql[0], l1 = g.ql[1], l2 = g.ql[2];
+        float fx = 0.f, fy = 0.f, fz = 0.f, ue = 0.f, we = 0.f;
+        float txx = 0.f, tyy = 0.f, tzz = 0.f, txy = 0.f, txz = 0.f, tyz = 0.f;
+        int cnt = b.ncount[i];
+        cnt = cnt < g.cap ? cnt : g.cap;
+        const int32_t* __restrict__ row = b.nl + nl_base(i, g.cap);
+        const int self = (int)i;
+
+        auto pair = [&](const int4& qj, int j, bool valid) {
+            const float dx = qdiff(qj.x, qi.x, l0);
+            const float dy = qdiff(qj.y, qi.y, l1);
+            const float dz = qdiff(qj.z, qi.z, l2);
+            const float r2 = dx * dx + dy * dy + dz * dz;
+            const int tp = SINGLE ? 0 : ti * MD_MAX_TYPES + qj.w;
+            bool in = valid && r2 < a.pt.rc2lo[tp];
+            if (valid && !in && r2 < a.pt.rc2hi[tp]) in = exact_r2(g, xi, x64[j]) < a.pt.rc2d[tp];
+            if (in) {
+                const PairCoef<float>& c = a.pt.f[tp];
+                float fr, u;
+                if (c.cap2 > 0.f && r2 < c.cap2) {
+                    fr = c.fcap * __builtin_amdgcn_rsqf(r2);
+                    u = c.ucap;
+                } else {
+                    const float inv = __builtin_amdgcn_rcpf(r2);
+                    const float s2 = c.sig2 * inv;
+                    const float s6 = s2 * s2 * s2;
+                    fr = c.eps24 * s6 * (2.f * s6 - 1.f) * inv;
+                    u = c.eps4 * s6 * (s6 - 1.f) - c.shift;
+                }
+                fx -= fr * dx;
+                fy -= fr * dy;
+                fz -= fr * dz;
+                ue += u;
+                we += fr * r2;
+                if (TENSOR) {
+                    txx += fr * dx * dx; tyy += fr * dy * dy; tzz += fr * dz * dz;
+                    txy += fr * dx * dy; txz += fr * dx * dz; tyz += fr * dy * dz;
+                }
+            }
+        };
+
+        // Neighbour indices are prefetched one batch of 8 ahead.  The loads
+        // are unconditional (slot clamped inside the row capacity) so the
+        // compiler can count them and wait only for the gathers in use;
+        // slots past the row's count select the particle itself, masked.
+        constexpr int B = 8;
+        const int last = cnt > 0 ? cnt - 1 : 0;   // loads past the row repeat its last slot
+        const char* __restrict__ xqb = reinterpret_cast<const char*>(xq);
+        int jn[B];
+#pragma unroll
+        for (int u = 0; u < B; ++u) {
+            const int v = row[(u < last ? u : last) * kTile];
+            jn[u] = u < cnt ? v : self;
+        }
+        for (int k0 = 0; k0 < cnt; k0 += B) {
+            int jc[B];
+            int4 q[B];
+#pragma unroll
+            for (int u = 0; u < B; ++u) {
+                jc[u] = jn[u];
+                q[u] = *reinterpret_cast<const int4*>(xqb + ((uint32_t)jc[u] << 4));
+            }
+#pragma unroll
+            for (int u = 0; u < B; ++u) {
+                const int kk = k0 + B + u;
+                const int v = row[(kk < last ? kk : last) * kTile];
+                jn[u] = kk < cnt ? v : self;
+            }
+#pragma unroll
+            for (int u = 0; u < B; ++u) pair(q[u], jc[u], k0 + u < cnt);
+        }
+        acc[A_EPAIR] = 0.5 * (double)ue;
+        acc[A_VIR] = 0.5 * (double)we;
+        if (TENSOR) {
+            acc[A_TXX] = 0.5 * (double)txx; acc[A_TYY] = 0.5 * (double)tyy; acc[A_TZZ] = 0.5 * (double)tzz;
+            acc[A_TXY] = 0.5 * (double)txy; acc[A_TXZ] = 0.5 * (double)txz; acc[A_TYZ] = 0.5 * (double)tyz;
+        }
+        if (BONDED) {
+            const DiffQ df{l0, l1, l2};
+            bonded_forces<float, int4, DiffQ>(b, a.dy, n, i, xq, qi, df, fx, fy, fz, acc, TENSOR, flag_bond);
+        }
+        const double F[3] = {(double)fx, (double)fy, (double)fz};
+        finish_particle(a, i, xi, SINGLE ? 0 : ti, F, acc, flag_reb, flag_nf);
+    }
+    block_epilogue(a, acc, flag_reb, flag_bond, flag_nf, TENSOR ? kNacc : A_VIR + 1);
+}
+
+
+// FP32 fast path: one particle type, cubic box, no capping radius.  The pair
+// math runs in fixed-point length units (u = L / 2^32): r2 = |dq|^2, the
+// coefficients are rescaled on the host, out-of-range pairs get inv = 0 so
+// that every term vanishes without a branch, and the FP64 re-decision of the
+// rounding band around rc costs one rarely taken branch per batch of 8.
+//   F_i = -(24 eps / u) sum a b-weighted dq,  a = s6 (2 s6 - 1), b = a / r2
+//   U_i = 1/2 (4 eps sum s6 (s6 - 1) - n_in shift),  W_i = 1/2 24 eps sum a
+template <bool BONDED, bool TENSOR>
+__global__ void __launch_bounds__(kBlock) k_step_fast(const StepArgs a) {
+    const Geom& g = a.g;
+    const Bufs& b = a.b;
+    const int64_t n = g.n;
+    const int4* __restrict__ xq = b.xq[a.parity];
+    const double4* __restrict__ x64 = b.x[a.parity];
+    double acc[kNacc];
+#pragma unroll
+    for (int k = 0; k < kNacc; ++k) acc[k] = 0.0;
+    bool flag_reb = false, flag_bond = false, flag_nf = false;
+    const int64_t i = gtid_xcd();
+    if (i < n) {
+        const double4 xi = x64[i];
+        const int4 qi = quantize4(g, xi.x, xi.y, xi.z, xi.w);  // equals xq[i]: same function
+        const FastCoef& fc = a.fast;
+        float fx = 0.f, fy = 0.f, fz = 0.f, ea = 0.f, wa = 0.f, nin = 0.f;
+        float txx = 0.f, tyy = 0.f, tzz = 0.f, txy = 0.f, txz = 0.f, tyz = 0.f;
+        int cnt = b.ncount[i];
+        cnt = cnt < g.cap ? cnt : g.cap;
+        const int nslots = (cnt + 7) & ~7;
+        const int32_t* __restrict__ row = b.nl + nl_base(i, g.cap);
+        const char* __restrict__ xqb = reinterpret_cast<const char*>(xq);
+        const int last = nslots > 0 ? nslots - 1 : 0;  // loads past the row repeat its last slot
+        // Indices are loaded two batches ahead of their gathers (16 loads
+        // of 256 bytes in flight per wavefront) to cover HBM latency.
+        constexpr int B = 8;
+        int jn[B], jn2[B];
+#pragma unroll
+        for (int u = 0; u < B; ++u) {
+            jn[u] = row[(u < last ? u : last) * kTile];
+            jn2[u] = row[(B + u < last ? B + u : last) * kTile];
+        }
+        for (int k0 = 0; k0 < nslots; k0 += B) {
+            int jc[B];
+            int4 q[B];
+#pragma unroll
+            for (int u = 0; u < B; ++u) {
+                jc[u] = jn[u];
+                q[u] = *reinterpret_cast<const int4*>(xqb + ((uint32_t)jc[u] << 4));
+            }
+#pragma unroll
+            for (int u = 0; u < B; ++u) {
+                const int kk = k0 + 2 * B + u;
+                jn[u] = jn2[u];
+                jn2[u] = row[(kk < last ? kk : last) * kTile];
+            }
+            float dx[B], dy[B], dz[B], r2[B];
+            uint32_t inmask = 0, bandmask = 0;
+#pragma unroll
+            for (int u = 0; u < B; ++u) {
+                dx[u] = (float)(int32_t)((uint32_t)q[u].x - (uint32_t)qi.x);
+                dy[u] = (float)(int32_t)((uint32_t)q[u].y - (uint32_t)qi.y);
+                dz[u] = (float)(int32_t)((uint32_t)q[u].z - (uint32_t)qi.z);
+                r2[u] = dx[u] * dx[u] + dy[u] * dy[u] + dz[u] * dz[u];
+                // r2 > 0 excludes the padding self entries
+                const bool lo = r2[u] > 0.f && r2[u] < fc.rc2lo;
+                const bool band = r2[u] >= fc.rc2lo && r2[u] < fc.rc2hi;
+                inmask |= (uint32_t)lo << u;
+                bandmask |= (uint32_t)band << u;
+            }
+            if (__builtin_expect(bandmask != 0, 0)) {
+#pragma unroll
+                for (int u = 0; u < B; ++u)
+                    if ((bandmask >> u) & 1u)
+                        if (exact_r2(g, xi, x64[jc[u]]) < fc.rc2d) inmask |= 1u << u;
+            }
+#pragma unroll
+            for (int u = 0; u < B; ++u) {
+                const bool in = (inmask >> u) & 1u;
+                const float inv = in ? __builtin_amdgcn_rcpf(r2[u]) : 0.f;
+                const float s2 = fc.sig2u * inv;
+                const float s6 = s2 * s2 * s2;
+                const float aa = s6 * (2.f * s6 - 1.f);
+                const float bb = aa * inv;
+                fx += bb * dx[u];
+                fy += bb * dy[u];
+                fz += bb * dz[u];
+                wa += aa;
+                ea += s6 * s6 - s6;
+                nin += in ? 1.f : 0.f;
+                if (TENSOR) {
+                    txx += bb * dx[u] * dx[u]; tyy += bb * dy[u] * dy[u]; tzz += bb * dz[u] * dz[u];
+                    txy += bb * dx[u] * dy[u]; txz += bb * dx[u] * dz[u]; tyz += bb * dy[u] * dz[u];
+                }
+            }
+        }
+        fx *= -fc.eps24_u;
+        fy *= -fc.eps24_u;
+        fz *= -fc.eps24_u;
+        acc[A_EPAIR] = 0.5 * ((double)fc.eps4 * (double)ea - (double)fc.shift * (double)nin);
+        acc[A_VIR] = 0.5 * (double)fc.eps24 * (double)wa;
+        if (TENSOR) {
+            // r_ij f_ij = 24 eps b dq dq (units cancel: b carries 1/u^2)
+            const double s = 0.5 * (double)fc.eps24;
+            acc[A_TXX] = s * txx; acc[A_TYY] = s * tyy; acc[A_TZZ] = s * tzz;
+            acc[A_TXY] = s * txy; acc[A_TXZ] = s * txz; acc[A_TYZ] = s * tyz;
+        }
+        if (BONDED) {
+            const DiffQ df{g.ql[0], g.ql[1], g.ql[2]};
+            bonded_forces<float, int4, DiffQ>(b, a.dy, n, i, xq, qi, df, fx, fy, fz, acc, TENSOR, flag_bond);
+        }
+        const double F[3] = {(double)fx, (double)fy, (double)fz};
+        finish_particle(a, i, xi, 0, F, acc, flag_reb, flag_nf);
+    }
+    block_epilogue(a, acc, flag_reb, flag_bond, flag_nf, TENSOR ? kNacc : A_VIR + 1);
+}
+
+// One block: reduce partials[k][block] in a fixed order, record the step's
+// observables, and (MODE_STEP) advance the step counter and move the
 // rebuild request to the next step.
-constexpr int kFinal = 256;
+constexpr int kFinal = 1024;
 __global__ void __launch_bounds__(kFinal) k_finalize(Bufs b, int nblocks, int mode) {
     __shared__ double red[kFinal / 64][kNacc];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     double s[kNacc];
 #pragma unroll
     for (int k = 0; k < kNacc; ++k) s[k] = 0.0;
-    for (int blk = threadIdx.x; blk < nblocks; blk += kFinal)
+    for (int blk0 = 0; blk0 < nblocks; blk0 += 4 * kFinal) {
+        double v[4][kNacc];
 #pragma unroll
-        for (int k = 0; k < kNacc; ++k) s[k] += b.partials[(int64_t)blk * kNacc + k];
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+        for (int r = 0; r < 4; ++r) {
+            const int blk = blk0 + r * kFinal + threadIdx.x;
+#pragma unroll
+            for (int k = 0; k < kNacc; ++k) v[r][k] = blk < nblocks ? b.partials[(int64_t)k * nblocks + blk] : 0.0;
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int k = 0; k < kNacc; ++k) s[k] += v[r][k];
+    }
 #pragma unroll
     for (int k = 0; k < kNacc; ++k) {
-        double v = wave_sum(s[k]);
-        if (lane == 0) red[w][k] = v;
+        const double t = wave_sum(s[k]);
+        if (lane == 0) red[w][k] = t;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -772,6 +1127,8 @@ static inline int grid_for(int64_t n, int cap_blocks = 4096) {
     if (g > cap_blocks) g = cap_blocks;
     return (int)g;
 }
+
+int step_grid(int64_t n) { return (int)((n + kBlock - 1) / kBlock); }
 
 hipError_t launch_init_load(const Geom& g, const Bufs& b, int parity, const double* pos,
                             const double* vel, const int32_t* type, const int32_t* image,
@@ -824,7 +1181,7 @@ hipError_t launch_clear_rebuild(const Bufs& b, hipStream_t s) {
 
 hipError_t launch_rebuild(const Geom& g, const Bufs& b, int parity, int bonded, hipStream_t s,
                           hipEvent_t ev0, hipEvent_t ev1) {
-    const int gs = grid_for(g.n, 2048);
+    const int gs = grid_for(g.n, 1024);
     if (ev0) (void)hipEventRecord(ev0, s);
     hipLaunchKernelGGL(k_bin, dim3(gs), dim3(kBlock), 0, s, g, b, parity);
     hipLaunchKernelGGL(k_scan_reduce, dim3(kScanBlocks), dim3(kBlock), 0, s, g, b);
@@ -833,24 +1190,37 @@ hipError_t launch_rebuild(const Geom& g, const Bufs& b, int parity, int bonded, 
     hipLaunchKernelGGL(k_scatter, dim3(gs), dim3(kBlock), 0, s, g, b);
     hipLaunchKernelGGL(k_rank_permute, dim3(gs), dim3(kBlock), 0, s, g, b, parity);
     hipLaunchKernelGGL(k_commit, dim3(gs), dim3(kBlock), 0, s, g, b, parity, bonded);
-    hipLaunchKernelGGL(k_nl_build, dim3(grid_for(g.n, 8192)), dim3(kBlock), 0, s, g, b, parity, bonded);
+    hipLaunchKernelGGL(k_nl_build, dim3(grid_for(g.n, 1 << 20)), dim3(kBlock), 0, s, g, b, parity, bonded);
     if (ev1) (void)hipEventRecord(ev1, s);
     return hipGetLastError();
 }
 
 hipError_t launch_step(const StepArgs& a, int fp64, int single_type, int bonded, int block, hipStream_t s) {
     (void)block;
-    const int64_t nb = (a.g.n + kBlock - 1) / kBlock;
-    dim3 grid((unsigned)nb), blk(kBlock);
-#define MD_LAUNCH(R, S, B) hipLaunchKernelGGL((k_step<R, S, B>), grid, blk, 0, s, a)
+    dim3 grid((unsigned)step_grid(a.g.n)), blk(kBlock);
     if (fp64) {
-        if (single_type) { if (bonded) MD_LAUNCH(double, true, true); else MD_LAUNCH(double, true, false); }
-        else { if (bonded) MD_LAUNCH(double, false, true); else MD_LAUNCH(double, false, false); }
+#define MD_L64(S, B) hipLaunchKernelGGL((k_step64<S, B>), grid, blk, 0, s, a)
+        if (single_type) { if (bonded) MD_L64(true, true); else MD_L64(true, false); }
+        else { if (bonded) MD_L64(false, true); else MD_L64(false, false); }
+#undef MD_L64
+    } else if (a.use_fast) {
+#define MD_LF(B, T) hipLaunchKernelGGL((k_step_fast<B, T>), grid, blk, 0, s, a)
+        const bool t = a.tensor != 0;
+        if (bonded) { if (t) MD_LF(true, true); else MD_LF(true, false); }
+        else { if (t) MD_LF(false, true); else MD_LF(false, false); }
+#undef MD_LF
     } else {
-        if (single_type) { if (bonded) MD_LAUNCH(float, true, true); else MD_LAUNCH(float, true, false); }
-        else { if (bonded) MD_LAUNCH(float, false, true); else MD_LAUNCH(float, false, false); }
+#define MD_LQ(S, B, T) hipLaunchKernelGGL((k_step_q<S, B, T>), grid, blk, 0, s, a)
+        const bool t = a.tensor != 0;
+        if (single_type) {
+            if (bonded) { if (t) MD_LQ(true, true, true); else MD_LQ(true, true, false); }
+            else { if (t) MD_LQ(true, false, true); else MD_LQ(true, false, false); }
+        } else {
+            if (bonded) { if (t) MD_LQ(false, true, true); else MD_LQ(false, true, false); }
+            else { if (t) MD_LQ(false, false, true); else MD_LQ(false, false, false); }
+        }
+#undef MD_LQ
     }
-#undef MD_LAUNCH
     return hipGetLastError();
 }
 

@@ -157,7 +157,7 @@ def _p(x):
 # ------------------------------------------------------------------ config helper
 def make_config(n, box, *, n_types=1, pair=None, dt=0.005, skin=0.3, integrator=MD_NVE,
                 force_precision=MD_FP32, temperature=1.0, gamma=0.0, seed=0, n_bonds=0, n_angles=0,
-                fene_K=30.0, fene_R0=1.5, k_bend=0.0, nl_capacity=0, flags=0):
+                fene_K=30.0, fene_R0=1.5, k_bend=0.0, nl_capacity=0, flags=0, cell_factor=0):
     """Fill an md_config.  pair: dict (ti, tj) -> (eps, sigma, rc, shift, caprad)."""
     c = md_config()
     c.struct_size = ctypes.sizeof(md_config)
@@ -176,6 +176,7 @@ def make_config(n, box, *, n_types=1, pair=None, dt=0.005, skin=0.3, integrator=
     c.n_bonds, c.n_angles = int(n_bonds), int(n_angles)
     c.fene_K, c.fene_R0, c.k_bend = float(fene_K), float(fene_R0), float(k_bend)
     c.nl_capacity = int(nl_capacity)
+    c.cell_factor = int(cell_factor)
     c.flags = int(flags)
     return c
 

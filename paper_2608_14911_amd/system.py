@@ -25,7 +25,7 @@ class System:
     def __init__(self, pos, box, vel=None, *, types=None, n_types=1, pair=None, masses=(1.0,),
                  bonds=None, angles=None, dt=0.005, skin=0.3, integrator="nve", precision="fp32",
                  temperature=1.0, gamma=0.0, seed=0, fene_K=30.0, fene_R0=1.5, k_bend=0.0,
-                 nl_capacity=0, flags=0, device="cuda"):
+                 nl_capacity=0, flags=0, cell_factor=0, device="cuda"):
         torch = _torch()
         self.torch = torch
         pos = np.ascontiguousarray(pos, dtype=np.float64)
@@ -41,7 +41,7 @@ class System:
         self.cfg = md.make_config(n, self.box, n_types=n_types, pair=pair, dt=dt, skin=skin, integrator=integ,
                                   force_precision=prec, temperature=temperature, gamma=gamma, seed=seed,
                                   n_bonds=nb, n_angles=na, fene_K=fene_K, fene_R0=fene_R0, k_bend=k_bend,
-                                  nl_capacity=nl_capacity, flags=flags)
+                                  nl_capacity=nl_capacity, flags=flags, cell_factor=cell_factor)
         self.ws_bytes = md.md_workspace_bytes(self.cfg)
         self._ws_raw = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
         base = self._ws_raw.data_ptr()

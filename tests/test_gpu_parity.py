@@ -32,13 +32,15 @@ def tricky(seed, n, L, rv):
     return inputs.wrap_into_box(pos, [L, L, L])
 
 
-@pytest.mark.parametrize("seed,n,L", [(0, 300, 7.0), (1, 2000, 12.0), (2, 5000, 15.3)])
-def test_neighbor_sets_bitexact_random(seed, n, L):
-    banner("NL random seed=%d n=%d L=%g" % (seed, n, L))
+@pytest.mark.parametrize("seed,n,L,cf", [(0, 300, 7.0, 1), (1, 2000, 12.0, 1), (2, 5000, 15.3, 1),
+                                         (3, 2000, 12.0, 2), (4, 300, 7.2, 2), (5, 4000, 14.0, 2)])
+def test_neighbor_sets_bitexact_random(seed, n, L, cf):
+    banner("NL random seed=%d n=%d L=%g cell_factor=%d" % (seed, n, L, cf))
     rc, skin = WCA, 0.3
     rv = rc + skin
     pos = tricky(seed, n, L, rv)
-    s = System(pos, [L, L, L], pair={(0, 0): lj_pair(rc=rc, caprad=0.8)}, skin=skin, nl_capacity=64)
+    s = System(pos, [L, L, L], pair={(0, 0): lj_pair(rc=rc, caprad=0.8)}, skin=skin, nl_capacity=64,
+               cell_factor=cf)
     got = s.neighbors(cap=64)
     ref = oracle.neighbors(pos, [L, L, L], rv)
     for i in range(n):
@@ -97,11 +99,11 @@ def lj_liquid(ncell=6, seed=4, jitter=0.2):
     return pos, box
 
 
-@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
-def test_lj_forces_energy_virial(prec, tol):
-    banner("LJ forces %s" % prec)
-    pos, box = lj_liquid()
-    s = System(pos, box, pair={(0, 0): lj_pair(rc=2.5)}, skin=0.3, precision=prec)
+@pytest.mark.parametrize("prec,tol,cf", [("fp64", 1e-12, 1), ("fp32", 1e-5, 1), ("fp32", 1e-5, 2)])
+def test_lj_forces_energy_virial(prec, tol, cf):
+    banner("LJ forces %s cell_factor=%d" % (prec, cf))
+    pos, box = lj_liquid(ncell=8)
+    s = System(pos, box, pair={(0, 0): lj_pair(rc=2.5)}, skin=0.3, precision=prec, cell_factor=cf)
     Fg = s.forces()
     o = s.observables()
     Fo, oo = oracle.forces(pos, box, oracle_pp(rc=2.5), want_fscale=True)
