@@ -1,0 +1,147 @@
+"""Host-side tests of the C ABI (no GPU needed): the library loads, exports
+every entry point include/md.h declares, its structs have the layout ctypes
+assumes, and argument / geometry validation and workspace sizing behave as
+documented.  Nothing here launches a kernel."""
+import ctypes
+import math
+import os
+import re
+import subprocess
+
+import pytest
+
+from paper_2608_14911_amd import md
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "md.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:md_status|const char\*)\s+(md_\w+)\s*\(", text, re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = md.lib()
+    names = declared_functions()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(md.EXPORTED) == set(names)
+
+
+def test_struct_layout_matches_header(tmp_path):
+    src = tmp_path / "layout.c"
+    src.write_text('''
+#include <stdio.h>
+#include <stddef.h>
+#include "md.h"
+int main(void) {
+  printf("%zu %zu %zu %zu\\n", sizeof(md_config), sizeof(md_obs), sizeof(md_timing), sizeof(md_pair_params));
+  printf("%zu %zu %zu %zu %zu\\n", offsetof(md_config, n_particles), offsetof(md_config, pair),
+         offsetof(md_config, n_bonds), offsetof(md_config, flags), offsetof(md_obs, status_flags));
+  return 0;
+}
+''')
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    out = subprocess.check_output([str(exe)]).decode().split()
+    c_sizes = list(map(int, out))
+    py = [ctypes.sizeof(md.md_config), ctypes.sizeof(md.md_obs), ctypes.sizeof(md.md_timing),
+          ctypes.sizeof(md.md_pair_params), md.md_config.n_particles.offset, md.md_config.pair.offset,
+          md.md_config.n_bonds.offset, md.md_config.flags.offset, md.md_obs.status_flags.offset]
+    assert c_sizes == py
+
+
+def lj_cfg(n=4000, L=20.0, **kw):
+    return md.make_config(n, [L, L, L], **kw)
+
+
+def test_workspace_bytes_grows_with_size_and_capacity():
+    a = md.md_workspace_bytes(lj_cfg(4000))
+    b = md.md_workspace_bytes(lj_cfg(8000))
+    c = md.md_workspace_bytes(lj_cfg(4000, nl_capacity=256))
+    assert 0 < a < b and a < c
+    # the Verlet list dominates: the automatic capacity at density 0.5 and
+    # rv = 2.8 is 1.5 * 46 + 32 -> 104 slots, so 256 slots add 152 int32
+    assert c - a == pytest.approx(4032 * (256 - 104) * 4, rel=0.01)
+    kg = md.make_config(1000, [10.5567] * 3, pair={(0, 0): (1.0, 1.0, 2 ** (1 / 6), math.nan, 0.0)},
+                        n_bonds=980, n_angles=960, skin=0.3)
+    assert md.md_workspace_bytes(kg) > md.md_workspace_bytes(
+        md.make_config(1000, [10.5567] * 3, pair={(0, 0): (1.0, 1.0, 2 ** (1 / 6), math.nan, 0.0)}, skin=0.3))
+
+
+@pytest.mark.parametrize("mutate,code", [
+    (lambda c: setattr(c, "struct_size", 8), md.MD_ERR_ARG),
+    (lambda c: setattr(c, "n_types", 0), md.MD_ERR_ARG),
+    (lambda c: setattr(c, "n_types", 5), md.MD_ERR_ARG),
+    (lambda c: setattr(c, "n_particles", 0), md.MD_ERR_ARG),
+    (lambda c: setattr(c, "dt", 0.0), md.MD_ERR_ARG),
+    (lambda c: setattr(c, "skin", -0.1), md.MD_ERR_ARG),
+    (lambda c: setattr(c, "integrator", 7), md.MD_ERR_ARG),
+    (lambda c: setattr(c, "force_precision", 3), md.MD_ERR_ARG),
+    (lambda c: c.box.__setitem__(1, float("nan")), md.MD_ERR_ARG),
+    (lambda c: setattr(c.pair[0], "sigma", 0.0), md.MD_ERR_ARG),
+    (lambda c: setattr(c, "cell_factor", 3), md.MD_ERR_ARG),
+    (lambda c: c.box.__setitem__(0, 7.0), md.MD_ERR_BOX_TOO_SMALL),     # 2 cells of 2.8
+])
+def test_invalid_configs_are_rejected(mutate, code):
+    c = lj_cfg()
+    mutate(c)
+    with pytest.raises(md.MDError) as e:
+        md.md_workspace_bytes(c)
+    assert e.value.code == code
+    assert md.md_last_error()
+
+
+def test_asymmetric_pair_table_rejected():
+    c = md.make_config(4000, [20.0] * 3, n_types=2,
+                       pair={(0, 0): (1, 1, 2.5, math.nan, 0), (1, 1): (1, 1, 2.5, math.nan, 0),
+                             (0, 1): (1, 1, 2.5, math.nan, 0)})
+    md.md_workspace_bytes(c)
+    c.pair[1].eps = 0.5                      # (0,1) != (1,0)
+    with pytest.raises(md.MDError) as e:
+        md.md_workspace_bytes(c)
+    assert e.value.code == md.MD_ERR_ARG
+
+
+def test_cell_factor_two_needs_five_cells():
+    c = lj_cfg(L=12.0, cell_factor=2)        # 12 / 1.4 = 8 half-cells: fine
+    md.md_workspace_bytes(c)
+    c = lj_cfg(L=6.5, cell_factor=2)         # 6.5 / 1.4 = 4 half-cells < 5
+    with pytest.raises(md.MDError) as e:
+        md.md_workspace_bytes(c)
+    assert e.value.code == md.MD_ERR_BOX_TOO_SMALL
+
+
+def test_init_argument_errors_before_any_device_call():
+    c = lj_cfg()
+    n = ctypes.c_size_t()
+    h = ctypes.c_void_p()
+    lib = md.lib()
+    assert lib.md_init(ctypes.byref(c), None, None, None, None, None, None, None, 0, None,
+                       ctypes.byref(h)) == md.MD_ERR_ARG
+    assert lib.md_init(ctypes.byref(c), None, None, None, None, None, None, None, 0, None, None) == md.MD_ERR_ARG
+    assert lib.md_workspace_bytes(ctypes.byref(c), None) == md.MD_ERR_ARG
+    mass = (ctypes.c_double * 1)(1.0)
+    # a workspace that is too small is rejected before it is touched
+    assert lib.md_init(ctypes.byref(c), ctypes.c_void_p(256), ctypes.c_void_p(256), None,
+                       ctypes.cast(mass, ctypes.c_void_p), None, None, ctypes.c_void_p(256), 16, None,
+                       ctypes.byref(h)) == md.MD_ERR_WORKSPACE
+    # bonds declared but not given
+    c2 = lj_cfg(n_bonds=10)
+    assert lib.md_init(ctypes.byref(c2), ctypes.c_void_p(256), ctypes.c_void_p(256), None,
+                       ctypes.cast(mass, ctypes.c_void_p), None, None, ctypes.c_void_p(256), 1 << 40, None,
+                       ctypes.byref(h)) == md.MD_ERR_ARG
+    # null handles
+    for f in ("md_build_neighbors", "md_status_check", "md_destroy"):
+        assert getattr(lib, f)(None) in (md.MD_ERR_ARG, md.MD_OK)
+    assert lib.md_step(None, 1) == md.MD_ERR_ARG
+
+
+def test_status_strings():
+    for code in (md.MD_OK, md.MD_ERR_ARG, md.MD_ERR_HIP, md.MD_ERR_BOX_TOO_SMALL, md.MD_ERR_NL_OVERFLOW,
+                 md.MD_ERR_BOND_BROKEN, md.MD_ERR_NONFINITE, md.MD_ERR_STATE, md.MD_ERR_WORKSPACE,
+                 md.MD_ERR_TOPOLOGY):
+        assert md.status_string(code).startswith("MD_")
+    assert md.status_string(-99) == "MD_ERR_UNKNOWN"
