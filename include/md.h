@@ -103,8 +103,9 @@ typedef struct md_config {
     int64_t n_angles;          /* cosine bending angles */
     double fene_K, fene_R0;    /* u = -K R0^2/2 ln(1 - r^2/R0^2) */
     double k_bend;             /* u = k (1 - cos theta), theta = 0 straight */
-    int32_t cell_factor;       /* 1 or 2 (0 = 1): cells of side >= (rc+skin)/cell_factor;
-                                  2 is the half-cutoff sub-cell decomposition */
+    int32_t cell_factor;       /* 1 or 2: cells of side >= (rc+skin)/cell_factor;
+                                  2 is the half-cutoff sub-cell decomposition;
+                                  0 = 2 when >= 5 such cells fit per side, else 1 */
     int32_t nl_capacity;       /* neighbours per particle; 0 = from density */
     int32_t block_size;        /* threads per block of the force kernel; 0 = 256 */
     int32_t flags;             /* MD_CFG_* */

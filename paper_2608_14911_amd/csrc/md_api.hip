@@ -131,7 +131,14 @@ static md_status plan_geom(const md_config* c, Geom* g, std::string* why) {
     const double rv = rc_max_of(c) + c->skin;
     g->rv2 = rv * rv;
     g->disp2 = (0.5 * c->skin) * (0.5 * c->skin);
-    g->kc = c->cell_factor > 0 ? c->cell_factor : 1;
+    g->kc = c->cell_factor;
+    if (g->kc == 0) {
+        // automatic: half-cutoff sub-cells (fewer candidate pairs per list
+        // build) whenever the box holds at least 5 of them per side
+        g->kc = 2;
+        for (int d = 0; d < 3; ++d)
+            if ((int)floor(c->box[d] * 2.0 / (rv * (1.0 + 1e-12))) < 5) g->kc = 1;
+    }
     g->ncell = 1;
     double Lmax = 0.0;
     for (int d = 0; d < 3; ++d) {

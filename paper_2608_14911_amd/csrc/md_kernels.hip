@@ -328,15 +328,16 @@ __global__ void __launch_bounds__(kBlock) k_scan_reduce(Geom g, Bufs b) {
     if (threadIdx.x == 0) b.bsum[blockIdx.x] = red[0];
 }
 
-__global__ void __launch_bounds__(1024) k_scan_top(Bufs b) {
+// Exclusive scan of the kScanBlocks chunk sums by one block.
+__global__ void __launch_bounds__(kScanBlocks) k_scan_top(Bufs b) {
     if (!rebuild_requested(b)) return;
-    __shared__ int wsum[16];
+    __shared__ int wsum[kScanBlocks / 64];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    int v = b.bsum[threadIdx.x];
+    const int v = b.bsum[threadIdx.x];
     int x = v;
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
-        int y = __shfl_up(x, o, 64);
+        const int y = __shfl_up(x, o, 64);
         if (lane >= o) x += y;
     }
     if (lane == 63) wsum[w] = x;
@@ -709,7 +710,7 @@ __device__ __forceinline__ void finish_particle(const StepArgs& a, int64_t i, co
         von[d] = vh_in ? vp[d] + hdtm * ft[d] : vp[d];
         ke += von[d] * von[d];
     }
-    acc[A_EKIN] = 0.5 * m * ke;
+    acc[A_EKIN] += 0.5 * m * ke;
     if (a.mode == MODE_STEP) {
         double xo[3] = {xi.x, xi.y, xi.z};
         double d2 = 0.0;
@@ -781,7 +782,10 @@ __global__ void __launch_bounds__(kBlock) k_step64(const StepArgs a) {
     for (int k = 0; k < kNacc; ++k) acc[k] = 0.0;
     bool flag_reb = false, flag_bond = false, flag_nf = false;
     const bool tensor = a.tensor != 0;
-    const int64_t i = gtid_xcd();
+    const int64_t ntile = (n + kBlock - 1) / kBlock;
+    const int64_t bt = xcd_block(blockIdx.x, gridDim.x);
+    for (int64_t t = bt * ntile / gridDim.x; t < (bt + 1) * ntile / gridDim.x; ++t) {
+    const int64_t i = t * kBlock + threadIdx.x;
     if (i < n) {
         const double4 xi = xin[i];
         const int ti = SINGLE ? 0 : (int)xi.w;
@@ -817,7 +821,7 @@ __global__ void __launch_bounds__(kBlock) k_step64(const StepArgs a) {
                 if (tensor) add_tensor(acc, 0.5, -dx, -dy, -dz, -fr * dx, -fr * dy, -fr * dz);
             }
         }
-        acc[A_EPAIR] = 0.5 * ui;
+        acc[A_EPAIR] += 0.5 * ui;
         acc[A_VIR] += 0.5 * wi;
         if (BONDED) {
             const Diff64 df{g.L[0], g.L[1], g.L[2], g.invL[0], g.invL[1], g.invL[2]};
@@ -825,6 +829,7 @@ __global__ void __launch_bounds__(kBlock) k_step64(const StepArgs a) {
         }
         const double F[3] = {fx, fy, fz};
         finish_particle(a, i, xi, SINGLE ? 0 : ti, F, acc, flag_reb, flag_nf);
+    }
     }
     block_epilogue(a, acc, flag_reb, flag_bond, flag_nf, tensor ? kNacc : A_VIR + 1);
 }
@@ -847,7 +852,10 @@ __global__ void __launch_bounds__(kBlock) k_step_q(const StepArgs a) {
 #pragma unroll
     for (int k = 0; k < kNacc; ++k) acc[k] = 0.0;
     bool flag_reb = false, flag_bond = false, flag_nf = false;
-    const int64_t i = gtid_xcd();
+    const int64_t ntile = (n + kBlock - 1) / kBlock;
+    const int64_t bt = xcd_block(blockIdx.x, gridDim.x);
+    for (int64_t t = bt * ntile / gridDim.x; t < (bt + 1) * ntile / gridDim.x; ++t) {
+    const int64_t i = t * kBlock + threadIdx.x;
     if (i < n) {
         const double4 xi = x64[i];
         const int4 qi = quantize4(g, xi.x, xi.y, xi.z, xi.w);  // equals xq[i]: same function
@@ -923,11 +931,11 @@ __global__ void __launch_bounds__(kBlock) k_step_q(const StepArgs a) {
 #pragma unroll
             for (int u = 0; u < B; ++u) pair(q[u], jc[u], k0 + u < cnt);
         }
-        acc[A_EPAIR] = 0.5 * (double)ue;
-        acc[A_VIR] = 0.5 * (double)we;
+        acc[A_EPAIR] += 0.5 * (double)ue;
+        acc[A_VIR] += 0.5 * (double)we;
         if (TENSOR) {
-            acc[A_TXX] = 0.5 * (double)txx; acc[A_TYY] = 0.5 * (double)tyy; acc[A_TZZ] = 0.5 * (double)tzz;
-            acc[A_TXY] = 0.5 * (double)txy; acc[A_TXZ] = 0.5 * (double)txz; acc[A_TYZ] = 0.5 * (double)tyz;
+            acc[A_TXX] += 0.5 * (double)txx; acc[A_TYY] += 0.5 * (double)tyy; acc[A_TZZ] += 0.5 * (double)tzz;
+            acc[A_TXY] += 0.5 * (double)txy; acc[A_TXZ] += 0.5 * (double)txz; acc[A_TYZ] += 0.5 * (double)tyz;
         }
         if (BONDED) {
             const DiffQ df{l0, l1, l2};
@@ -935,6 +943,7 @@ __global__ void __launch_bounds__(kBlock) k_step_q(const StepArgs a) {
         }
         const double F[3] = {(double)fx, (double)fy, (double)fz};
         finish_particle(a, i, xi, SINGLE ? 0 : ti, F, acc, flag_reb, flag_nf);
+    }
     }
     block_epilogue(a, acc, flag_reb, flag_bond, flag_nf, TENSOR ? kNacc : A_VIR + 1);
 }
@@ -958,7 +967,10 @@ __global__ void __launch_bounds__(kBlock) k_step_fast(const StepArgs a) {
 #pragma unroll
     for (int k = 0; k < kNacc; ++k) acc[k] = 0.0;
     bool flag_reb = false, flag_bond = false, flag_nf = false;
-    const int64_t i = gtid_xcd();
+    const int64_t ntile = (n + kBlock - 1) / kBlock;
+    const int64_t bt = xcd_block(blockIdx.x, gridDim.x);
+    for (int64_t t = bt * ntile / gridDim.x; t < (bt + 1) * ntile / gridDim.x; ++t) {
+    const int64_t i = t * kBlock + threadIdx.x;
     if (i < n) {
         const double4 xi = x64[i];
         const int4 qi = quantize4(g, xi.x, xi.y, xi.z, xi.w);  // equals xq[i]: same function
@@ -1037,13 +1049,13 @@ __global__ void __launch_bounds__(kBlock) k_step_fast(const StepArgs a) {
         fx *= -fc.eps24_u;
         fy *= -fc.eps24_u;
         fz *= -fc.eps24_u;
-        acc[A_EPAIR] = 0.5 * ((double)fc.eps4 * (double)ea - (double)fc.shift * (double)nin);
-        acc[A_VIR] = 0.5 * (double)fc.eps24 * (double)wa;
+        acc[A_EPAIR] += 0.5 * ((double)fc.eps4 * (double)ea - (double)fc.shift * (double)nin);
+        acc[A_VIR] += 0.5 * (double)fc.eps24 * (double)wa;
         if (TENSOR) {
             // r_ij f_ij = 24 eps b dq dq (units cancel: b carries 1/u^2)
             const double s = 0.5 * (double)fc.eps24;
-            acc[A_TXX] = s * txx; acc[A_TYY] = s * tyy; acc[A_TZZ] = s * tzz;
-            acc[A_TXY] = s * txy; acc[A_TXZ] = s * txz; acc[A_TYZ] = s * tyz;
+            acc[A_TXX] += s * txx; acc[A_TYY] += s * tyy; acc[A_TZZ] += s * tzz;
+            acc[A_TXY] += s * txy; acc[A_TXZ] += s * txz; acc[A_TYZ] += s * tyz;
         }
         if (BONDED) {
             const DiffQ df{g.ql[0], g.ql[1], g.ql[2]};
@@ -1051,6 +1063,7 @@ __global__ void __launch_bounds__(kBlock) k_step_fast(const StepArgs a) {
         }
         const double F[3] = {(double)fx, (double)fy, (double)fz};
         finish_particle(a, i, xi, 0, F, acc, flag_reb, flag_nf);
+    }
     }
     block_epilogue(a, acc, flag_reb, flag_bond, flag_nf, TENSOR ? kNacc : A_VIR + 1);
 }
@@ -1128,7 +1141,10 @@ static inline int grid_for(int64_t n, int cap_blocks = 4096) {
     return (int)g;
 }
 
-int step_grid(int64_t n) { return (int)((n + kBlock - 1) / kBlock); }
+int step_grid(int64_t n) {
+    const int64_t t = (n + kBlock - 1) / kBlock;
+    return (int)(t < 1024 ? t : 1024);
+}
 
 hipError_t launch_init_load(const Geom& g, const Bufs& b, int parity, const double* pos,
                             const double* vel, const int32_t* type, const int32_t* image,
@@ -1181,11 +1197,11 @@ hipError_t launch_clear_rebuild(const Bufs& b, hipStream_t s) {
 
 hipError_t launch_rebuild(const Geom& g, const Bufs& b, int parity, int bonded, hipStream_t s,
                           hipEvent_t ev0, hipEvent_t ev1) {
-    const int gs = grid_for(g.n, 1024);
+    const int gs = grid_for(g.n, 512);
     if (ev0) (void)hipEventRecord(ev0, s);
     hipLaunchKernelGGL(k_bin, dim3(gs), dim3(kBlock), 0, s, g, b, parity);
     hipLaunchKernelGGL(k_scan_reduce, dim3(kScanBlocks), dim3(kBlock), 0, s, g, b);
-    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, b);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanBlocks), 0, s, b);
     hipLaunchKernelGGL(k_scan_apply, dim3(kScanBlocks), dim3(kBlock), 0, s, g, b);
     hipLaunchKernelGGL(k_scatter, dim3(gs), dim3(kBlock), 0, s, g, b);
     hipLaunchKernelGGL(k_rank_permute, dim3(gs), dim3(kBlock), 0, s, g, b, parity);

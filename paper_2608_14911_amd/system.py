@@ -156,3 +156,41 @@ def from_workload(w, precision="fp32", **kw):
                   temperature=w["temperature"], gamma=w["gamma"], seed=w["seed"],
                   fene_K=w.get("fene_K", 30.0), fene_R0=w.get("fene_R0", 1.5), k_bend=w.get("k_bend", 0.0),
                   **kw)
+
+
+# Capped-WCA push-off of overlapping random-walk chains, modelled on the
+# paper's example (section "Example usage": a capped warm-up at a small time
+# step, then the uncapped potential).  Rows: (capping radius, dt, steps).
+PUSHOFF = ((1.0, 0.002, 500), (0.95, 0.002, 500), (0.9, 0.002, 1000), (0.85, 0.002, 1000),
+           (0.8, 0.002, 1000), (0.0, 0.005, 1000))
+
+
+def push_off(s, rc, schedule=PUSHOFF, chunk=250, max_halvings=4, log=None):
+    """Run the push-off ladder on the GPU system ``s`` (pair type (0, 0)).
+
+    Each stage runs in chunks from a host checkpoint; when a chunk latches a
+    device error (a FENE bond at R0, a non-finite coordinate) the state is
+    restored and the chunk is repeated at half the time step, down to
+    dt / 2**max_halvings.  Large melts hold rare clusters of overlapping
+    beads that a fixed time step tears apart.  Raises RuntimeError when a
+    chunk still fails at the smallest step."""
+    for caprad, dt, nsteps in schedule:
+        s.set_params(pair={(0, 0): lj_pair(1.0, 1.0, rc, math.nan, caprad)})
+        done = 0
+        while done < nsteps:
+            ns = min(chunk, nsteps - done)
+            ck = s.get_state()
+            for k in range(max_halvings + 1):
+                sub = 2 ** k
+                s.set_params(dt=dt / sub)
+                s.step(ns * sub)
+                code = s.status()
+                if code == 0:
+                    break
+                if log:
+                    log("push-off cap %.3g: chunk at dt %.3g failed (%s), halving" % (caprad, dt / sub,
+                                                                                     md.status_string(code)))
+                s.set_state(ck)
+            else:
+                raise RuntimeError("push-off failed at capping radius %g" % caprad)
+            done += ns

@@ -244,3 +244,25 @@ def test_determinism_and_checkpoint_bitwise():
     assert np.array_equal(r["vel"], runs[0]["vel"])
     assert np.array_equal(r["image"], runs[0]["image"])
     s2.close()
+
+
+def test_gpu_pushoff_kg_melt():
+    """The GPU push-off ladder on raw random walks (200 chains x 50 beads at
+    density 0.85) leaves no bead pair closer than 0.75 and no bond longer
+    than 1.3, checked on the oracle's brute-force neighbour sets."""
+    from paper_2608_14911_amd.system import push_off
+    w = inputs.workload_kg(200, 50, seed=31)
+    banner("push-off KG 200x50 seed=31")
+    w0 = dict(w, caprad=1.0, dt=0.002, gamma=1.0, vel=np.zeros_like(w["pos"]))
+    s = from_workload(w0, precision="fp32", nl_capacity=256)
+    push_off(s, w["rc"])
+    st = s.get_state()
+    s.close()
+    pos = st["pos"]
+    L = w["box"]
+    b = w["bonds"]
+    d = pos[b[:, 1]] - pos[b[:, 0]]
+    d -= L * np.round(d / L)
+    assert np.sqrt((d * d).sum(1)).max() < 1.3
+    nl = oracle.neighbors(pos, L, 0.75)
+    assert all(len(r) == 0 for r in nl)
