@@ -161,3 +161,14 @@ def workload_paper_example(n=10000, seed=1005):
             "eps": 1.0, "sigma": 1.0, "rc": 1.12246, "shift": float("nan"), "caprad": 0.8,
             "dt": 0.0001, "skin": 0.3, "temperature": 1.0, "gamma": 1.0, "integrator": "langevin",
             "seed": seed, "name": "paper example, 10,000 particles, box 20^3"}
+
+
+def mlp_init(seed=1004, n_in=32, hidden=64):
+    """He-uniform initial weights of the 32 -> 64 -> 64 -> 1 network, biases
+    zero, drawn from stream 4; FP64 vector in the layout W1 (hidden x n_in,
+    row-major), b1, W2 (hidden x hidden), b2, w3 (hidden), b3."""
+    g = rng(seed, 4)
+    W1 = g.uniform(-1.0, 1.0, size=(hidden, n_in)) * np.sqrt(6.0 / n_in)
+    W2 = g.uniform(-1.0, 1.0, size=(hidden, hidden)) * np.sqrt(6.0 / hidden)
+    w3 = g.uniform(-1.0, 1.0, size=hidden) * np.sqrt(6.0 / hidden)
+    return np.concatenate([W1.ravel(), np.zeros(hidden), W2.ravel(), np.zeros(hidden), w3, np.zeros(1)])
