@@ -109,6 +109,10 @@ typedef struct md_config {
     int32_t nl_capacity;       /* neighbours per particle; 0 = from density */
     int32_t block_size;        /* threads per block of the force kernel; 0 = 256 */
     int32_t flags;             /* MD_CFG_* */
+    double list_cutoff;        /* Verlet list radius = max(list_cutoff, max rc) + skin;
+                                  0 = max rc.  The surrogate needs >= MD_SUR_RCUT */
+    int32_t surrogate;         /* 1: reserve workspace for the learned surrogate */
+    int32_t pad_;
 } md_config;
 
 /* Observables of one step n (positions x_n, on-step velocities v_n). */
@@ -216,6 +220,70 @@ md_status md_status_check(md_handle h);
  * (forces kernel-by-kernel launches while enabled); read and reset it. */
 md_status md_timing_enable(md_handle h, int32_t enable);
 md_status md_timing_read(md_handle h, md_timing* out);
+
+/* ------------------------------------------------------------------------
+ * Learned surrogate of the non-bonded pair force.  The paper has no learned
+ * model; this is an extension built on its pair-force step: a per-particle
+ * radial-descriptor MLP trained by force matching against the plain
+ * potential, which stays available as the fallback and as the judge of the
+ * surrogate's error.  FENE and bending stay plain.
+ *
+ *   g_k(r)   = exp(-(r - mu_k)^2 / (2 w^2)) (cos(pi r / r_d) + 1) / 2,
+ *              w = MD_SUR_WIDTH, mu_k = MD_SUR_MU0 + k (MD_SUR_MU1 - MD_SUR_MU0) / 31,
+ *              r_d = MD_SUR_RCUT, k = 0..31
+ *   G_k(i)   = sum over j != i with r_ij < r_d of g_k(r_ij)
+ *   x_i      = (G(i) - mean) * istd          (fixed standardisation)
+ *   E_i      = w3 . silu(W2 silu(W1 x_i + b1) + b2) + b3,   E = sum_i E_i
+ *   F_i      = -dE/dr_i = sum_j ((a_i + a_j) . g'(r_ij)) (x_j - x_i) / r_ij,
+ *              a_i = dE_i/dG(i)
+ * Parameters theta: FP32 [MD_SUR_NPARAM] = W1 [64][32] row-major, b1 [64],
+ * W2 [64][64], b2 [64], w3 [64], b3 [1].  Precision MD_SUR_FP32: all network
+ * arithmetic in FP32; MD_SUR_BF16: weights and activations rounded to BF16
+ * (round to nearest even) as matrix-core operands, FP32 accumulation.  The
+ * descriptor and pair-force arithmetic is FP32 in both.
+ * All surrogate calls need md_config.surrogate = 1; they return MD_ERR_ARG
+ * otherwise.
+ * ------------------------------------------------------------------------ */
+#define MD_SUR_NBASIS 32
+#define MD_SUR_HIDDEN 64
+#define MD_SUR_NPARAM 6337
+#define MD_SUR_RCUT 2.5
+#define MD_SUR_WIDTH 0.1
+#define MD_SUR_MU0 0.8
+#define MD_SUR_MU1 2.5
+enum { MD_SUR_FP32 = 0, MD_SUR_BF16 = 1 };
+enum { MD_PAIR_PLAIN = 0, MD_PAIR_SURROGATE = 1 };
+
+/* Load the network: theta device FP32 [MD_SUR_NPARAM]; g_mean, g_istd device
+ * FP32 [32] (standardisation constants).  Resets the Adam moments.  The
+ * handle keeps its own copy (the master weights that md_sur_adam updates). */
+md_status md_sur_set(md_handle h, const float* theta, const float* g_mean, const float* g_istd,
+                     int32_t precision);
+/* Copy the handle's master weights to device theta [MD_SUR_NPARAM]. */
+md_status md_sur_get(md_handle h, float* theta);
+/* Non-bonded force model of md_step / md_forces / md_observables:
+ * MD_PAIR_PLAIN (the pair table) or MD_PAIR_SURROGATE (the network; the list
+ * radius minus the skin must reach MD_SUR_RCUT). */
+md_status md_set_pair_mode(md_handle h, int32_t mode);
+/* Descriptors G at the current positions: device FP32 [N][32], tag order. */
+md_status md_sur_descriptors(md_handle h, float* G);
+/* The network on P given descriptor rows: G device FP32 [P][32] (raw, the
+ * handle's standardisation is applied); e device FP32 [P] (may be NULL) and
+ * dedg device FP32 [P][32] = dE_i/dG(i). */
+md_status md_sur_mlp_eval(md_handle h, const float* G, int64_t P, float* e, float* dedg);
+/* Force-matching loss L = mean over frames, particles and components of
+ * (F - F_ref)^2 at the handle's weights, and (grad != NULL or for a later
+ * md_sur_adam) its gradient dL/dtheta by the analytic double backward.
+ *   frames  device FP64 [nf][N][3] positions (tag order; folded into the box)
+ *   f_ref   device FP64 [nf][N][3] reference non-bonded forces
+ *   grad    device FP32 [MD_SUR_NPARAM] or NULL; loss host (may be NULL)
+ * The handle's state is replaced: positions of the last frame, zero
+ * velocities, step 0.  Synchronises when loss != NULL. */
+md_status md_sur_loss_grad(md_handle h, const double* frames, const double* f_ref, int32_t nf, float* grad,
+                           double* loss);
+/* One Adam update (Kingma and Ba 2015, bias-corrected, step t >= 1) of the
+ * master weights with the gradient of the last md_sur_loss_grad. */
+md_status md_sur_adam(md_handle h, int64_t t, double lr, double beta1, double beta2, double eps);
 
 md_status md_destroy(md_handle h);
 const char* md_status_string(md_status s);

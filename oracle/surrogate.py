@@ -137,30 +137,37 @@ def mlp(theta, x):
     return E, gz1 @ W1
 
 
-def energy_forces(theta, m, istd, pos, box, rd=RD):
+def energy_forces(theta, m, istd, pos, box, rd=RD, want_fscale=False):
     """Surrogate energy E = sum_i E_i, per-particle E_i, forces F = -dE/dr,
     the per-particle input gradients a_i = dE_i/dG(i), and the virial
     W = sum over unordered pairs of r_ij . f_ij (the model is radial, so the
-    force splits into central pair terms)."""
+    force splits into central pair terms).  With want_fscale, also
+    sum_j |f_ij| per particle (the scale of the cancellation in F_i)."""
     pr = pairs(pos, box, rd)
     G = descriptors(pos, box, rd, pr)
     x = (G - m) * istd
     Ei, gx = mlp(theta, x)
     a = gx * istd
-    F, W = pair_forces(a, pos, box, rd, pr)
-    return float(Ei.sum()), Ei, F, a, W
+    out = pair_forces(a, pos, box, rd, pr, want_fscale)
+    return (float(Ei.sum()), Ei) + (out[0], a) + out[1:]
 
 
-def pair_forces(a, pos, box, rd=RD, pr=None):
+def pair_forces(a, pos, box, rd=RD, pr=None, want_fscale=False):
     """Forces of E = sum_i E_i(G(i)) given a_i = dE_i/dG(i):
     F_i = sum_j c_ij (x_j - x_i) / r_ij with c_ij = (a_i + a_j) . g'(r_ij),
     and the virial W = -1/2 sum over ordered pairs of c_ij r_ij."""
     I, J, D, r = pr if pr is not None else pairs(pos, box, rd)
     _, dg = basis(r, rd)
     c = ((a[I] + a[J]) * dg).sum(-1)
-    F = np.zeros((np.asarray(pos).shape[0], 3))
+    n = np.asarray(pos).shape[0]
+    F = np.zeros((n, 3))
     np.add.at(F, I, (c / r)[:, None] * D)
-    return F, 0.5 * float((-c * r).sum())
+    W = 0.5 * float((-c * r).sum())
+    if not want_fscale:
+        return F, W
+    fs = np.zeros(n)
+    np.add.at(fs, I, np.abs(c))
+    return F, W, fs
 
 
 def loss_grad(theta, m, istd, frames, f_ref, box, rd=RD, with_grad=True):

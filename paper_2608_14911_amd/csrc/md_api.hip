@@ -53,6 +53,13 @@ struct md_handle_s {
     bool timing = false;
     std::vector<EvQuad> ev_free, ev_pending;
     md_timing tacc;
+    // learned surrogate
+    SurBufs sb;
+    SurConst sc;
+    int has_sur = 0;          // workspace reserved
+    int sur_loaded = 0;       // md_sur_set called
+    int sur_prec = MD_SUR_FP32;
+    int pair_mode = MD_PAIR_PLAIN;
 };
 
 // ------------------------------------------------------------------ helpers
@@ -102,6 +109,8 @@ static md_status validate(const md_config* c, std::string* why) {
     if (c->n_bonds > 0 && !(c->fene_R0 > 0.0 && c->fene_K >= 0.0)) { *why = "FENE needs R0 > 0, K >= 0"; return MD_ERR_ARG; }
     if (c->nl_capacity < 0 || c->nl_capacity > 4096) { *why = "nl_capacity out of range"; return MD_ERR_ARG; }
     if (c->cell_factor < 0 || c->cell_factor > 2) { *why = "cell_factor must be 0, 1 or 2"; return MD_ERR_ARG; }
+    if (!(c->list_cutoff >= 0.0) || !isfinite(c->list_cutoff)) { *why = "list_cutoff must be >= 0"; return MD_ERR_ARG; }
+    if (c->surrogate != 0 && c->surrogate != 1) { *why = "surrogate must be 0 or 1"; return MD_ERR_ARG; }
     return MD_OK;
 }
 
@@ -128,7 +137,7 @@ static md_status plan_geom(const md_config* c, Geom* g, std::string* why) {
     memset(g, 0, sizeof(*g));
     g->n = c->n_particles;
     g->ntypes = c->n_types;
-    const double rv = rc_max_of(c) + c->skin;
+    const double rv = fmax(rc_max_of(c), c->list_cutoff) + c->skin;
     g->rv2 = rv * rv;
     g->disp2 = (0.5 * c->skin) * (0.5 * c->skin);
     g->kc = c->cell_factor;
@@ -180,7 +189,8 @@ static md_status plan_geom(const md_config* c, Geom* g, std::string* why) {
 }
 
 // Carve the workspace; with base == nullptr only the size is computed.
-static size_t carve(const md_config* c, const Geom& g, int step_grid, uint8_t* base, Bufs* b) {
+static size_t carve(const md_config* c, const Geom& g, int step_grid, uint8_t* base, Bufs* b,
+                    SurBufs* sb = nullptr) {
     const int64_t n = g.n;
     const bool bonded = c->n_bonds > 0 || c->n_angles > 0;
     const int maxb = c->n_bonds > 0 ? MD_MAX_BONDS_PER_PARTICLE : 0;
@@ -233,6 +243,27 @@ static size_t carve(const md_config* c, const Geom& g, int step_grid, uint8_t* b
     t.maxb = maxb;
     t.maxa = maxa;
     if (b) *b = t;
+    if (c->surrogate) {
+        SurBufs u;
+        memset(&u, 0, sizeof(u));
+        u.G = (float*)take(sizeof(float) * kSurNB * n);
+        u.a = (float*)take(sizeof(float) * kSurNB * n);
+        u.u = (float*)take(sizeof(float) * kSurNB * n);
+        u.f = (float4*)take(sizeof(float4) * n);
+        u.delta = (float4*)take(sizeof(float4) * n);
+        u.part = (double*)take(sizeof(double) * kSurPart * (size_t)step_grid);
+        u.loss = (double*)take(sizeof(double) * 4);
+        u.w = (float*)take(sizeof(float) * kSurNPpad);
+        u.wp = (float*)take(sizeof(float) * kPrepF);
+        u.wb = (uint16_t*)take(sizeof(uint16_t) * kPrepB);
+        u.gmean = (float*)take(sizeof(float) * kSurNB);
+        u.gistd = (float*)take(sizeof(float) * kSurNB);
+        u.grad = (float*)take(sizeof(float) * kSurNPpad);
+        u.m1 = (float*)take(sizeof(float) * kSurNPpad);
+        u.m2 = (float*)take(sizeof(float) * kSurNPpad);
+        u.gpart = (float*)take(sizeof(float) * kSurNPpad * (size_t)kSurGradBlocks);
+        if (sb) *sb = u;
+    }
     return off;
 }
 
@@ -341,6 +372,39 @@ static void drop_graph(md_handle h) {
     h->graph_parity = -1;
 }
 
+// Basis constants of the surrogate descriptor: centres
+// mu_k = MU0 + k (MU1 - MU0) / 31 rounded once from FP64, exp2 scale
+// log2(e) / (2 w^2), cutoff r_d.
+static void fill_sur_const(SurConst* c) {
+    memset(c, 0, sizeof(*c));
+    for (int k = 0; k < kSurNB; ++k) c->mu[k] = (float)(MD_SUR_MU0 + k * (MD_SUR_MU1 - MD_SUR_MU0) / (kSurNB - 1));
+    const double w2 = MD_SUR_WIDTH * MD_SUR_WIDTH;
+    c->c_exp = (float)(1.4426950408889634 / (2.0 * w2));
+    c->inv_w2 = (float)(1.0 / w2);
+    c->rd2 = (float)(MD_SUR_RCUT * MD_SUR_RCUT);
+    c->pi_rd = (float)(M_PI / MD_SUR_RCUT);
+}
+
+// Force stage: the plain fused kernel, or the surrogate's descriptor,
+// network and pair-force kernels followed by the external-force step
+// kernel.  Returns the surrogate partials for the finalize (or nullptr).
+static hipError_t launch_force_stage(md_handle h, int mode, int tensor, double* f_out, const double** spart) {
+    StepArgs a = make_args(h, mode, tensor, f_out);
+    *spart = nullptr;
+    if (h->pair_mode == MD_PAIR_PLAIN) return launch_step(a, h->fp64, h->single, h->bonded, kBlock, h->stream);
+    hipError_t e;
+    const SurBufs& s = h->sb;
+    if ((e = launch_sur_desc(h->g, h->b, s, h->sc, h->parity, h->step_grid, h->stream)) != hipSuccess) return e;
+    if ((e = launch_sur_mlp(s, s.G, h->g.n, s.a, nullptr, s.part, h->sur_prec == MD_SUR_BF16, h->step_grid,
+                            h->stream)) != hipSuccess)
+        return e;
+    if ((e = launch_sur_force(h->g, h->b, s, h->sc, h->parity, nullptr, 0.0, tensor, h->step_grid, h->stream)) !=
+        hipSuccess)
+        return e;
+    *spart = s.part;
+    return launch_step_ext(a, s, h->bonded, h->stream);
+}
+
 // Enqueue one full step at the handle's current parity and advance the
 // host mirrors.  Events (timing mode) bracket the three stages.
 static hipError_t enqueue_step(md_handle h, const EvQuad* q) {
@@ -349,11 +413,11 @@ static hipError_t enqueue_step(md_handle h, const EvQuad* q) {
     e = launch_rebuild(h->g, h->b, h->parity, h->bonded, h->stream, nullptr, nullptr);
     if (e != hipSuccess) return e;
     if (q) (void)hipEventRecord(q->e[1], h->stream);
-    StepArgs a = make_args(h, MODE_STEP, (h->cfg.flags & MD_CFG_VIRIAL_TENSOR) ? 1 : 0, nullptr);
-    e = launch_step(a, h->fp64, h->single, h->bonded, kBlock, h->stream);
+    const double* spart = nullptr;
+    e = launch_force_stage(h, MODE_STEP, (h->cfg.flags & MD_CFG_VIRIAL_TENSOR) ? 1 : 0, nullptr, &spart);
     if (e != hipSuccess) return e;
     if (q) (void)hipEventRecord(q->e[2], h->stream);
-    e = launch_finalize(h->b, h->step_grid, MODE_STEP, h->stream);
+    e = launch_finalize(h->b, h->step_grid, MODE_STEP, spart, h->stream);
     if (e != hipSuccess) return e;
     if (q) (void)hipEventRecord(q->e[3], h->stream);
     h->parity ^= 1;
@@ -540,7 +604,9 @@ md_status md_init(const md_config* cfg, const double* pos, const double* vel, co
     h->single = cfg->n_types == 1 ? 1 : 0;
     h->fp64 = cfg->force_precision == MD_FP64 ? 1 : 0;
     memset(&h->tacc, 0, sizeof(h->tacc));
-    carve(cfg, g, sg, h->ws, &h->b);
+    carve(cfg, g, sg, h->ws, &h->b, &h->sb);
+    h->has_sur = cfg->surrogate;
+    fill_sur_const(&h->sc);
     fill_params(h, cfg);
     fill_masses(h, mass_by_type);
 
@@ -613,9 +679,9 @@ md_status md_forces(md_handle h, double* f_out) {
     if (!h) return fail(nullptr, MD_ERR_ARG, "NULL handle");
     md_status r = rebuild_now(h, 0);
     if (r != MD_OK) return r;
-    StepArgs a = make_args(h, MODE_FORCES, 1, f_out);
-    HIP_TRY(h, launch_step(a, h->fp64, h->single, h->bonded, kBlock, h->stream));
-    HIP_TRY(h, launch_finalize(h->b, h->step_grid, MODE_FORCES, h->stream));
+    const double* spart = nullptr;
+    HIP_TRY(h, launch_force_stage(h, MODE_FORCES, 1, f_out, &spart));
+    HIP_TRY(h, launch_finalize(h->b, h->step_grid, MODE_FORCES, spart, h->stream));
     return MD_OK;
 }
 
@@ -665,9 +731,9 @@ md_status md_observables(md_handle h, md_obs* out) {
     if (!h || !out) return fail(h, MD_ERR_ARG, "NULL handle or output");
     md_status r = rebuild_now(h, 0);
     if (r != MD_OK) return r;
-    StepArgs a = make_args(h, MODE_OBSERVE, 1, nullptr);
-    HIP_TRY(h, launch_step(a, h->fp64, h->single, h->bonded, kBlock, h->stream));
-    HIP_TRY(h, launch_finalize(h->b, h->step_grid, MODE_OBSERVE, h->stream));
+    const double* spart = nullptr;
+    HIP_TRY(h, launch_force_stage(h, MODE_OBSERVE, 1, nullptr, &spart));
+    HIP_TRY(h, launch_finalize(h->b, h->step_grid, MODE_OBSERVE, spart, h->stream));
     double rec[kHistRec];
     HIP_TRY(h, hipMemcpyAsync(rec, h->b.cur, sizeof(rec), hipMemcpyDeviceToHost, h->stream));
     DevCtl c;
@@ -776,6 +842,138 @@ md_status md_timing_read(md_handle h, md_timing* out) {
     h->ev_pending.clear();
     *out = h->tacc;
     memset(&h->tacc, 0, sizeof(h->tacc));
+    return MD_OK;
+}
+
+// ------------------------------------------------------------------ surrogate ABI
+
+static md_status need_sur(md_handle h) {
+    if (!h) return fail(nullptr, MD_ERR_ARG, "NULL handle");
+    if (!h->has_sur) return fail(h, MD_ERR_ARG, "created without md_config.surrogate = 1");
+    return MD_OK;
+}
+
+md_status md_sur_set(md_handle h, const float* theta, const float* g_mean, const float* g_istd, int32_t precision) {
+    md_status r = need_sur(h);
+    if (r != MD_OK) return r;
+    if (!theta || !g_mean || !g_istd) return fail(h, MD_ERR_ARG, "NULL theta / mean / istd");
+    if (precision != MD_SUR_FP32 && precision != MD_SUR_BF16) return fail(h, MD_ERR_ARG, "bad precision");
+    const SurBufs& s = h->sb;
+    HIP_TRY(h, hipMemcpyAsync(s.w, theta, sizeof(float) * kSurNP, hipMemcpyDeviceToDevice, h->stream));
+    HIP_TRY(h, hipMemcpyAsync(s.gmean, g_mean, sizeof(float) * kSurNB, hipMemcpyDeviceToDevice, h->stream));
+    HIP_TRY(h, hipMemcpyAsync(s.gistd, g_istd, sizeof(float) * kSurNB, hipMemcpyDeviceToDevice, h->stream));
+    HIP_TRY(h, launch_zero_i32((int32_t*)s.m1, kSurNPpad, h->stream));
+    HIP_TRY(h, launch_zero_i32((int32_t*)s.m2, kSurNPpad, h->stream));
+    HIP_TRY(h, launch_zero_i32((int32_t*)s.grad, kSurNPpad, h->stream));
+    HIP_TRY(h, launch_sur_prepare(s, h->stream));
+    h->sur_prec = precision;
+    h->sur_loaded = 1;
+    drop_graph(h);
+    return MD_OK;
+}
+
+md_status md_sur_get(md_handle h, float* theta) {
+    md_status r = need_sur(h);
+    if (r != MD_OK) return r;
+    if (!theta) return fail(h, MD_ERR_ARG, "NULL theta");
+    HIP_TRY(h, hipMemcpyAsync(theta, h->sb.w, sizeof(float) * kSurNP, hipMemcpyDeviceToDevice, h->stream));
+    return MD_OK;
+}
+
+md_status md_set_pair_mode(md_handle h, int32_t mode) {
+    if (!h) return fail(nullptr, MD_ERR_ARG, "NULL handle");
+    if (mode == MD_PAIR_PLAIN) {
+        h->pair_mode = mode;
+        drop_graph(h);
+        return MD_OK;
+    }
+    if (mode != MD_PAIR_SURROGATE) return fail(h, MD_ERR_ARG, "bad pair mode");
+    md_status r = need_sur(h);
+    if (r != MD_OK) return r;
+    if (!h->sur_loaded) return fail(h, MD_ERR_ARG, "md_sur_set has not been called");
+    if (sqrt(h->g.rv2) - h->cfg.skin < MD_SUR_RCUT * (1.0 - 1e-12))
+        return fail(h, MD_ERR_ARG, "list radius minus skin is below the descriptor cutoff; set md_config.list_cutoff");
+    h->pair_mode = mode;
+    drop_graph(h);
+    return MD_OK;
+}
+
+md_status md_sur_descriptors(md_handle h, float* G) {
+    md_status r = need_sur(h);
+    if (r != MD_OK) return r;
+    if (!G) return fail(h, MD_ERR_ARG, "NULL output");
+    if (sqrt(h->g.rv2) - h->cfg.skin < MD_SUR_RCUT * (1.0 - 1e-12))
+        return fail(h, MD_ERR_ARG, "list radius minus skin is below the descriptor cutoff");
+    if ((r = rebuild_now(h, 0)) != MD_OK) return r;
+    HIP_TRY(h, launch_sur_desc(h->g, h->b, h->sb, h->sc, h->parity, h->step_grid, h->stream));
+    HIP_TRY(h, launch_sur_to_tag(h->g, h->b, h->sb.G, G, h->stream));
+    return MD_OK;
+}
+
+md_status md_sur_mlp_eval(md_handle h, const float* G, int64_t P, float* e, float* dedg) {
+    md_status r = need_sur(h);
+    if (r != MD_OK) return r;
+    if (!h->sur_loaded) return fail(h, MD_ERR_ARG, "md_sur_set has not been called");
+    if (P < 0 || (P > 0 && (!G || !dedg))) return fail(h, MD_ERR_ARG, "bad arguments");
+    if (P == 0) return MD_OK;
+    const int64_t tiles = (P + 63) / 64;
+    const int grid = (int)(tiles < 4096 ? tiles : 4096);
+    HIP_TRY(h, launch_sur_mlp(h->sb, G, P, dedg, e, nullptr, h->sur_prec == MD_SUR_BF16, grid, h->stream));
+    return MD_OK;
+}
+
+md_status md_sur_loss_grad(md_handle h, const double* frames, const double* f_ref, int32_t nf, float* grad,
+                           double* loss) {
+    md_status r = need_sur(h);
+    if (r != MD_OK) return r;
+    if (!h->sur_loaded) return fail(h, MD_ERR_ARG, "md_sur_set has not been called");
+    if (!frames || !f_ref || nf < 1) return fail(h, MD_ERR_ARG, "bad frames");
+    if (sqrt(h->g.rv2) - h->cfg.skin < MD_SUR_RCUT * (1.0 - 1e-12))
+        return fail(h, MD_ERR_ARG, "list radius minus skin is below the descriptor cutoff");
+    const int64_t n = h->g.n;
+    const double two_over_m = 2.0 / (3.0 * (double)n * (double)nf);
+    const SurBufs& s = h->sb;
+    const int bf = h->sur_prec == MD_SUR_BF16;
+    drop_graph(h);
+    h->parity = 0;
+    for (int32_t f = 0; f < nf; ++f) {
+        const double* pos = frames + (size_t)f * 3 * n;
+        HIP_TRY(h, launch_init_load(h->g, h->b, 0, pos, nullptr, h->b.type_t, nullptr, h->stream));
+        HIP_TRY(h, launch_set_ctl(h->b, 0, 0, 1, 1, h->stream));
+        if ((r = rebuild_now(h, 0)) != MD_OK) return r;
+        HIP_TRY(h, launch_sur_desc(h->g, h->b, s, h->sc, 0, h->step_grid, h->stream));
+        HIP_TRY(h, launch_sur_mlp(s, s.G, n, s.a, nullptr, nullptr, bf, h->step_grid, h->stream));
+        HIP_TRY(h, launch_sur_force(h->g, h->b, s, h->sc, 0, f_ref + (size_t)f * 3 * n, two_over_m, 0, h->step_grid,
+                                    h->stream));
+        HIP_TRY(h, launch_sur_loss_reduce(s, h->step_grid, f > 0, h->stream));
+        HIP_TRY(h, launch_sur_u(h->g, h->b, s, h->sc, 0, h->step_grid, h->stream));
+        HIP_TRY(h, launch_sur_bwd2(s, n, bf, h->stream));
+        HIP_TRY(h, launch_sur_grad_reduce(s, sur_bwd2_grid(n), f > 0, h->stream));
+    }
+    h->host_step = 0;
+    h->vel_half = 0;
+    h->hist_next = 0;
+    if (grad) HIP_TRY(h, hipMemcpyAsync(grad, s.grad, sizeof(float) * kSurNP, hipMemcpyDeviceToDevice, h->stream));
+    if (loss) {
+        double l = 0.0;
+        HIP_TRY(h, hipMemcpyAsync(&l, s.loss, sizeof(double), hipMemcpyDeviceToHost, h->stream));
+        HIP_TRY(h, hipStreamSynchronize(h->stream));
+        *loss = l / (3.0 * (double)n * (double)nf);
+        DevCtl c;
+        if ((r = read_ctl(h, &c)) != MD_OK) return r;
+        if ((r = status_to_code(h, c.status, c.nl_max)) != MD_OK) return r;
+    }
+    return MD_OK;
+}
+
+md_status md_sur_adam(md_handle h, int64_t t, double lr, double beta1, double beta2, double eps) {
+    md_status r = need_sur(h);
+    if (r != MD_OK) return r;
+    if (!h->sur_loaded) return fail(h, MD_ERR_ARG, "md_sur_set has not been called");
+    if (t < 1 || !(lr >= 0.0) || !(beta1 >= 0.0 && beta1 < 1.0) || !(beta2 >= 0.0 && beta2 < 1.0) || !(eps > 0.0))
+        return fail(h, MD_ERR_ARG, "bad Adam parameters");
+    HIP_TRY(h, launch_sur_adam(h->sb, t, (float)lr, (float)beta1, (float)beta2, (float)eps, h->stream));
+    HIP_TRY(h, launch_sur_prepare(h->sb, h->stream));
     return MD_OK;
 }
 

@@ -1,0 +1,52 @@
+// Device helpers shared by the gfx950 kernel files of the MD step: fixed-
+// point coordinates, wavefront sums, the XCD-aware block order and the
+// Verlet-list layout.
+#pragma once
+
+#include "md_internal.h"
+
+namespace md {
+
+// 32-bit fixed-point coordinate: q = floor(x 2^32 / L) for x in [0, L); a
+// product that rounds up to 2^32 wraps to 0, the same point of the periodic
+// box.  The difference (int32)(q_j - q_i) is the minimum image.
+__device__ __forceinline__ uint32_t quantize(double x, double qs) { return (uint32_t)(uint64_t)(x * qs); }
+__device__ __forceinline__ float qdiff(uint32_t a, uint32_t b, float ql) {
+    return (float)(int32_t)(a - b) * ql;
+}
+__device__ __forceinline__ int4 quantize4(const Geom& g, double x, double y, double z, double w) {
+    return make_int4((int)quantize(x, g.qs[0]), (int)quantize(y, g.qs[1]), (int)quantize(z, g.qs[2]), (int)w);
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ __forceinline__ int64_t gtid() { return (int64_t)blockIdx.x * blockDim.x + threadIdx.x; }
+
+// Workgroups are handed to the 8 XCDs round-robin (block b -> XCD b % 8),
+// and each XCD has its own L2.  Remap so that XCD x works on one contiguous
+// 1/8 of the cell-sorted particles: a spatially compact slab whose gathered
+// neighbour records stay in that XCD's L2.  Bijective for any grid size.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int xcd_block(int b, int G) {
+    const int q = G / kXcds, r = G % kXcds;
+    const int x = b % kXcds, k = b / kXcds;
+    return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + k;
+}
+// Verlet-list layout: tiles of 64 particles (one wavefront); inside a tile
+// slot k of all 64 particles is contiguous (256 bytes), and a tile's slots
+// follow each other, so a wavefront streams one contiguous block.
+constexpr int kTile = 64;
+__device__ __forceinline__ int64_t nl_base(int64_t i, int cap) {
+    return (i >> 6) * (int64_t)cap * kTile + (i & (kTile - 1));
+}
+
+__device__ __forceinline__ int64_t gtid_xcd() {
+    return (int64_t)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+}
+__device__ __forceinline__ int64_t gstride() { return (int64_t)gridDim.x * blockDim.x; }
+
+}  // namespace md

@@ -155,6 +155,72 @@ struct StepArgs {
     double* f_out;              // MODE_FORCES: [N][3] tag order
 };
 
+// ------------------------------------------------------------------ surrogate
+
+constexpr int kSurNB = 32;                  // radial basis functions
+constexpr int kSurH = 64;                   // hidden width
+constexpr int kSurNP = 6337;                // parameters
+constexpr int kSurNPpad = 6400;
+constexpr int kOW1 = 0, kOB1 = 2048, kOW2 = 2112, kOB2 = 6208, kOW3 = 6272, kOB3 = 6336;
+// prepared FP32 weights, rows padded for the LDS image: W1 [64][36],
+// W1T [32][68], W2 [64][68], W2T [64][68], then b1, b2, w3 [64], b3
+constexpr int kPF1 = 36, kPF64 = 68;
+constexpr int kPW1 = 0, kPW1T = 64 * kPF1, kPW2 = kPW1T + 32 * kPF64, kPW2T = kPW2 + 64 * kPF64,
+              kPB1 = kPW2T + 64 * kPF64, kPB2 = kPB1 + 64, kPW3 = kPB2 + 64, kPB3 = kPW3 + 64,
+              kPrepF = kPB3 + 64;
+// prepared BF16 weights, rows padded for the LDS image: W1 [64][40],
+// W1T [32][72], W2 [64][72], W2T [64][72]
+constexpr int kSW1 = 40, kSW64 = 72;
+constexpr int kQW1 = 0, kQW1T = 64 * kSW1, kQW2 = kQW1T + 32 * kSW64, kQW2T = kQW2 + 64 * kSW64,
+              kPrepB = kQW2T + 64 * kSW64;
+constexpr int kSurPart = 9;                 // E, W, tensor[6], loss
+constexpr int kSurGradBlocks = 256;         // blocks of the double-backward kernel
+
+struct SurBufs {
+    float* G;           // [N][32] descriptors, sorted order
+    float* a;           // [N][32] dE_i/dG(i)
+    float* u;           // [N][32] training: dL/da_i
+    float4* f;          // [N] surrogate pair force
+    float4* delta;      // [N] training: dL/dF_i
+    double* part;       // [kSurPart][step grid] block partials
+    double* loss;       // [1] loss accumulated over the frames of a call
+    float* w;           // [kSurNPpad] master weights
+    float* wp;          // [kPrepF] prepared FP32 weights
+    uint16_t* wb;       // [kPrepB] prepared BF16 weights
+    float* gmean;       // [32]
+    float* gistd;       // [32]
+    float* grad;        // [kSurNPpad]
+    float* m1;          // [kSurNPpad] Adam moments
+    float* m2;
+    float* gpart;       // [kSurGradBlocks][kSurNPpad]
+};
+
+struct SurConst {
+    float mu[kSurNB];   // basis centres
+    float c_exp;        // log2(e) / (2 w^2): phi = exp2(-c_exp (r - mu)^2)
+    float inv_w2;       // 1 / w^2
+    float rd2;          // r_d^2
+    float pi_rd;        // pi / r_d
+};
+
+hipError_t launch_sur_prepare(const SurBufs& s, hipStream_t st);
+hipError_t launch_sur_desc(const Geom& g, const Bufs& b, const SurBufs& s, const SurConst& c, int parity,
+                           int grid, hipStream_t st);
+hipError_t launch_sur_mlp(const SurBufs& s, const float* G, int64_t P, float* a, float* e, double* epart,
+                          int bf16, int grid, hipStream_t st);
+hipError_t launch_sur_force(const Geom& g, const Bufs& b, const SurBufs& s, const SurConst& c, int parity,
+                            const double* fref, double two_over_m, int tensor, int grid, hipStream_t st);
+hipError_t launch_sur_u(const Geom& g, const Bufs& b, const SurBufs& s, const SurConst& c, int parity, int grid,
+                        hipStream_t st);
+hipError_t launch_sur_bwd2(const SurBufs& s, int64_t P, int bf16, hipStream_t st);
+hipError_t launch_sur_grad_reduce(const SurBufs& s, int nblk, int accumulate, hipStream_t st);
+int sur_bwd2_grid(int64_t P);
+hipError_t launch_sur_loss_reduce(const SurBufs& s, int grid, int accumulate, hipStream_t st);
+hipError_t launch_sur_adam(const SurBufs& s, int64_t t, float lr, float beta1, float beta2, float eps,
+                           hipStream_t st);
+hipError_t launch_sur_to_tag(const Geom& g, const Bufs& b, const float* src, float* dst, hipStream_t st);
+hipError_t launch_step_ext(const StepArgs& a, const SurBufs& s, int bonded, hipStream_t st);
+
 // launchers (md_kernels.hip)
 hipError_t launch_init_load(const Geom& g, const Bufs& b, int parity, const double* pos,
                             const double* vel, const int32_t* type, const int32_t* image,
@@ -167,7 +233,7 @@ hipError_t launch_clear_rebuild(const Bufs& b, hipStream_t s);
 hipError_t launch_step(const StepArgs& a, int fp64, int single_type, int bonded, int block,
                        hipStream_t s);
 int step_grid(int64_t n);
-hipError_t launch_finalize(const Bufs& b, int nblocks, int mode, hipStream_t s);
+hipError_t launch_finalize(const Bufs& b, int nblocks, int mode, const double* spart, hipStream_t s);
 hipError_t launch_overwrite_state(const Geom& g, const Bufs& b, int parity, const double* pos,
                                   const double* vel, const int32_t* image, hipStream_t s);
 hipError_t launch_get_state(const Geom& g, const Bufs& b, int parity, double* pos, double* vel,

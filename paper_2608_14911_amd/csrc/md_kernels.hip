@@ -13,7 +13,7 @@
 // gathered neighbour is one 32-byte segment; velocities and build positions
 // are SoA planes; the Verlet list is ELL, neighbour-major (entry k of
 // particle i at k*N + i) so that lane i reads consecutive words.
-#include "md_internal.h"
+#include "md_device.h"
 
 namespace md {
 
@@ -26,17 +26,6 @@ namespace md {
 // antisymmetric: d_ji = -d_ij.
 __device__ __forceinline__ double mimg(double d, double L, double invL) {
     return fma(-L, rint(d * invL), d);
-}
-
-// 32-bit fixed-point coordinate: q = floor(x 2^32 / L) for x in [0, L); a
-// product that rounds up to 2^32 wraps to 0, the same point of the periodic
-// box.  The difference (int32)(q_j - q_i) is the minimum image.
-__device__ __forceinline__ uint32_t quantize(double x, double qs) { return (uint32_t)(uint64_t)(x * qs); }
-__device__ __forceinline__ float qdiff(uint32_t a, uint32_t b, float ql) {
-    return (float)(int32_t)(a - b) * ql;
-}
-__device__ __forceinline__ int4 quantize4(const Geom& g, double x, double y, double z, double w) {
-    return make_int4((int)quantize(x, g.qs[0]), (int)quantize(y, g.qs[1]), (int)quantize(z, g.qs[2]), (int)w);
 }
 
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
@@ -57,12 +46,6 @@ __device__ __forceinline__ uint32_t cell_of(const Geom& g, const double4& p) {
     int cx, cy, cz;
     cell_coords(g, p.x, p.y, p.z, cx, cy, cz);
     return (uint32_t)(((int64_t)cz * g.nc[1] + cy) * g.nc[0] + cx);
-}
-
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
 }
 
 // Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11): 10 rounds of two
@@ -136,31 +119,6 @@ __device__ __forceinline__ bool rebuild_requested(const Bufs& b) {
     return __atomic_load_n(&b.ctl->rebuild, __ATOMIC_RELAXED) != 0;
 }
 
-__device__ __forceinline__ int64_t gtid() { return (int64_t)blockIdx.x * blockDim.x + threadIdx.x; }
-
-// Workgroups are handed to the 8 XCDs round-robin (block b -> XCD b % 8),
-// and each XCD has its own L2.  Remap so that XCD x works on one contiguous
-// 1/8 of the cell-sorted particles: a spatially compact slab whose gathered
-// neighbour records stay in that XCD's L2.  Bijective for any grid size.
-constexpr int kXcds = 8;
-__device__ __forceinline__ int xcd_block(int b, int G) {
-    const int q = G / kXcds, r = G % kXcds;
-    const int x = b % kXcds, k = b / kXcds;
-    return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + k;
-}
-// Verlet-list layout: tiles of 64 particles (one wavefront); inside a tile
-// slot k of all 64 particles is contiguous (256 bytes), and a tile's slots
-// follow each other, so a wavefront streams one contiguous block.
-constexpr int kTile = 64;
-__device__ __forceinline__ int64_t nl_base(int64_t i, int cap) {
-    return (i >> 6) * (int64_t)cap * kTile + (i & (kTile - 1));
-}
-
-__device__ __forceinline__ int64_t gtid_xcd() {
-    return (int64_t)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-}
-__device__ __forceinline__ int64_t gstride() { return (int64_t)gridDim.x * blockDim.x; }
-
 // ------------------------------------------------------------------ init / state I/O
 
 // Load tag-ordered FP64 state into the (identity-ordered) sorted arrays,
@@ -183,7 +141,7 @@ __global__ void __launch_bounds__(kBlock) k_init_load(Geom g, Bufs b, int parity
             if (x >= g.L[d]) { x -= g.L[d]; im += 1; }
             p[d] = x;
             b.img[d * n + i] = im;
-            b.v[d * n + i] = vel[3 * i + d];
+            b.v[d * n + i] = vel ? vel[3 * i + d] : 0.0;
         }
         int ty = type ? type[i] : 0;
         if (ty < 0 || ty >= g.ntypes) {
@@ -1068,11 +1026,46 @@ __global__ void __launch_bounds__(kBlock) k_step_fast(const StepArgs a) {
     block_epilogue(a, acc, flag_reb, flag_bond, flag_nf, TENSOR ? kNacc : A_VIR + 1);
 }
 
+// Step with an external non-bonded force (the learned surrogate's pair
+// force, computed by its own kernels at the same positions): F = F_ext +
+// bonded terms, then the same integration and reductions.
+template <bool BONDED>
+__global__ void __launch_bounds__(kBlock) k_step_ext(const StepArgs a, const float4* __restrict__ fext) {
+    const Geom& g = a.g;
+    const Bufs& b = a.b;
+    const int64_t n = g.n;
+    const int4* __restrict__ xq = b.xq[a.parity];
+    const double4* __restrict__ x64 = b.x[a.parity];
+    double acc[kNacc];
+#pragma unroll
+    for (int k = 0; k < kNacc; ++k) acc[k] = 0.0;
+    bool flag_reb = false, flag_bond = false, flag_nf = false;
+    const bool tensor = a.tensor != 0;
+    const int64_t ntile = (n + kBlock - 1) / kBlock;
+    const int64_t bt = xcd_block(blockIdx.x, gridDim.x);
+    for (int64_t t = bt * ntile / gridDim.x; t < (bt + 1) * ntile / gridDim.x; ++t) {
+    const int64_t i = t * kBlock + threadIdx.x;
+    if (i < n) {
+        const double4 xi = x64[i];
+        const int4 qi = quantize4(g, xi.x, xi.y, xi.z, xi.w);
+        const float4 fe = fext[i];
+        float fx = fe.x, fy = fe.y, fz = fe.z;
+        if (BONDED) {
+            const DiffQ df{g.ql[0], g.ql[1], g.ql[2]};
+            bonded_forces<float, int4, DiffQ>(b, a.dy, n, i, xq, qi, df, fx, fy, fz, acc, tensor, flag_bond);
+        }
+        const double F[3] = {(double)fx, (double)fy, (double)fz};
+        finish_particle(a, i, xi, (int)xi.w, F, acc, flag_reb, flag_nf);
+    }
+    }
+    block_epilogue(a, acc, flag_reb, flag_bond, flag_nf, tensor ? kNacc : A_VIR + 1);
+}
+
 // One block: reduce partials[k][block] in a fixed order, record the step's
 // observables, and (MODE_STEP) advance the step counter and move the
 // rebuild request to the next step.
 constexpr int kFinal = 1024;
-__global__ void __launch_bounds__(kFinal) k_finalize(Bufs b, int nblocks, int mode) {
+__global__ void __launch_bounds__(kFinal) k_finalize(Bufs b, int nblocks, int mode, const double* spart) {
     __shared__ double red[kFinal / 64][kNacc];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     double s[kNacc];
@@ -1090,6 +1083,16 @@ __global__ void __launch_bounds__(kFinal) k_finalize(Bufs b, int nblocks, int mo
         for (int r = 0; r < 4; ++r)
 #pragma unroll
             for (int k = 0; k < kNacc; ++k) s[k] += v[r][k];
+        if (spart) {
+            // surrogate pair energy (row 0), virial (row 1) and tensor (rows 2..7)
+            for (int r = 0; r < 4; ++r) {
+                const int blk = blk0 + r * kFinal + threadIdx.x;
+                if (blk >= nblocks) continue;
+                s[A_EPAIR] += spart[blk];
+                s[A_VIR] += spart[(int64_t)nblocks + blk];
+                for (int k = 0; k < 6; ++k) s[A_TXX + k] += spart[(int64_t)(2 + k) * nblocks + blk];
+            }
+        }
     }
 #pragma unroll
     for (int k = 0; k < kNacc; ++k) {
@@ -1240,8 +1243,17 @@ hipError_t launch_step(const StepArgs& a, int fp64, int single_type, int bonded,
     return hipGetLastError();
 }
 
-hipError_t launch_finalize(const Bufs& b, int nblocks, int mode, hipStream_t s) {
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kFinal), 0, s, b, nblocks, mode);
+hipError_t launch_finalize(const Bufs& b, int nblocks, int mode, const double* spart, hipStream_t s) {
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kFinal), 0, s, b, nblocks, mode, spart);
+    return hipGetLastError();
+}
+
+hipError_t launch_step_ext(const StepArgs& a, const SurBufs& sb, int bonded, hipStream_t s) {
+    dim3 grid((unsigned)step_grid(a.g.n)), blk(kBlock);
+    if (bonded)
+        hipLaunchKernelGGL(k_step_ext<true>, grid, blk, 0, s, a, sb.f);
+    else
+        hipLaunchKernelGGL(k_step_ext<false>, grid, blk, 0, s, a, sb.f);
     return hipGetLastError();
 }
 

@@ -1,0 +1,735 @@
+// gfx950 kernels of the learned non-bonded surrogate: radial descriptors over
+// the Verlet list, the 32 -> 64 -> 64 -> 1 SiLU network (forward and input
+// gradient) on tiles of 64 particles, the pair force from the per-particle
+// input gradients, and the force-matching training path (loss sensitivity
+// pass, analytic double backward with block-level weight-gradient products,
+// deterministic reduction, Adam).
+//
+// Network tiles.  A block of 256 threads (4 wavefronts) works on 64
+// particles; activations live in LDS as FP32 rows, weights in LDS as a
+// padded image.  Every product O[p][c] = sum_k A[p][k] W[c][k] leaves its
+// result with one ownership: wavefront w holds particles 16w..16w+15, lane l
+// holds particle 16w + (l & 15) and, per 16-column block cb, the columns
+// 16 cb + 4 (l >> 4) + e, e = 0..3.  The FP32 form computes these dot
+// products on the vector ALUs; the BF16 form issues
+// v_mfma_f32_16x16x16_bf16 with the weights as the 16x16 A operand and the
+// activations as the B operand, whose accumulator layout is that same
+// ownership, so the two forms share every elementwise step.
+#include "md_device.h"
+
+namespace md {
+
+typedef short short4v __attribute__((ext_vector_type(4)));
+typedef float float4v __attribute__((ext_vector_type(4)));
+
+constexpr int kSB = 256;          // threads per block of the network kernels
+constexpr int kSA32 = 36;         // LDS row stride of 32-wide activations (floats)
+constexpr int kSA64 = 68;         // LDS row stride of 64-wide activations
+
+// FP32 -> BF16, round to nearest even (NaN stays NaN).
+__device__ __forceinline__ short bf16_rne(float f) {
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7f800000u) == 0x7f800000u) return (short)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (short)(u >> 16);
+}
+
+__device__ __forceinline__ float sigm(float z) { return __builtin_amdgcn_rcpf(1.f + __expf(-z)); }
+
+// ------------------------------------------------------------------ basis
+
+// f_c(r) = (cos(pi r / r_d) + 1) / 2 and its derivative.
+__device__ __forceinline__ float cutoff_fn(const SurConst& c, float r, float& dfc) {
+    float sn, cs;
+    sincosf(c.pi_rd * r, &sn, &cs);
+    dfc = -0.5f * c.pi_rd * sn;
+    return 0.5f * (cs + 1.f);
+}
+
+// ------------------------------------------------------------------ descriptor
+
+// G_k(i) = sum over list neighbours j with r_ij < r_d of phi_k(r) f_c(r).
+__global__ void __launch_bounds__(kBlock) k_sur_desc(Geom g, Bufs b, SurBufs s, SurConst c, int parity) {
+    const int64_t n = g.n;
+    const int4* __restrict__ xq = b.xq[parity];
+    for (int64_t i = gtid_xcd(); i < n; i += gstride()) {
+        const int4 qi = xq[i];
+        int cnt = b.ncount[i];
+        cnt = cnt < g.cap ? cnt : g.cap;
+        const int32_t* __restrict__ row = b.nl + nl_base(i, g.cap);
+        float G[kSurNB];
+#pragma unroll
+        for (int k = 0; k < kSurNB; ++k) G[k] = 0.f;
+        for (int k = 0; k < cnt; ++k) {
+            const int4 qj = xq[row[k * kTile]];
+            const float dx = qdiff(qj.x, qi.x, g.ql[0]);
+            const float dy = qdiff(qj.y, qi.y, g.ql[1]);
+            const float dz = qdiff(qj.z, qi.z, g.ql[2]);
+            const float r2 = dx * dx + dy * dy + dz * dz;
+            if (r2 < c.rd2 && r2 > 0.f) {
+                const float r = sqrtf(r2);
+                float dfc;
+                const float fc = cutoff_fn(c, r, dfc);
+#pragma unroll
+                for (int q = 0; q < kSurNB; ++q) {
+                    const float t = r - c.mu[q];
+                    G[q] += exp2f(-c.c_exp * t * t) * fc;
+                }
+            }
+        }
+        float4* out = reinterpret_cast<float4*>(s.G + i * kSurNB);
+#pragma unroll
+        for (int q = 0; q < kSurNB / 4; ++q) out[q] = make_float4(G[4 * q], G[4 * q + 1], G[4 * q + 2], G[4 * q + 3]);
+    }
+}
+
+// ------------------------------------------------------------------ block sums
+
+// Deterministic block sum of NV doubles into part[k * gridDim.x + blockIdx.x].
+template <int NV>
+__device__ __forceinline__ void block_store(const double* v, double* part) {
+    __shared__ double red[kBlock / 64][NV];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+        const double t = wave_sum(v[k]);
+        if (lane == 0) red[w][k] = t;
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < NV) {
+        double t = 0.0;
+        for (int ww = 0; ww < (int)(blockDim.x >> 6); ++ww) t += red[ww][threadIdx.x];
+        part[(int64_t)threadIdx.x * gridDim.x + blockIdx.x] = t;
+    }
+}
+
+// ------------------------------------------------------------------ pair force
+
+// F_i = sum_j ((a_i + a_j) . g'(r_ij)) (x_j - x_i) / r_ij over r_ij < r_d.
+// Inference: F into s.f, per-block virial (and tensor) partials into
+// s.part rows 1..7.  Training: delta_i = (2/M) (F_i - F_ref) into s.delta
+// and the squared residual into s.part row 8.
+template <bool TRAIN>
+__global__ void __launch_bounds__(kBlock) k_sur_force(Geom g, Bufs b, SurBufs s, SurConst c, int parity,
+                                                     const double* __restrict__ fref, double two_over_m,
+                                                     int tensor) {
+    const int64_t n = g.n;
+    const int4* __restrict__ xq = b.xq[parity];
+    double acc[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) acc[k] = 0.0;
+    for (int64_t i = gtid_xcd(); i < n; i += gstride()) {
+        const int4 qi = xq[i];
+        float ai[kSurNB];
+        const float4* ap = reinterpret_cast<const float4*>(s.a + i * kSurNB);
+#pragma unroll
+        for (int q = 0; q < kSurNB / 4; ++q) {
+            const float4 v = ap[q];
+            ai[4 * q] = v.x; ai[4 * q + 1] = v.y; ai[4 * q + 2] = v.z; ai[4 * q + 3] = v.w;
+        }
+        int cnt = b.ncount[i];
+        cnt = cnt < g.cap ? cnt : g.cap;
+        const int32_t* __restrict__ row = b.nl + nl_base(i, g.cap);
+        float fx = 0.f, fy = 0.f, fz = 0.f, w = 0.f;
+        float txx = 0.f, tyy = 0.f, tzz = 0.f, txy = 0.f, txz = 0.f, tyz = 0.f;
+        for (int k = 0; k < cnt; ++k) {
+            const int j = row[k * kTile];
+            const int4 qj = xq[j];
+            const float dx = qdiff(qj.x, qi.x, g.ql[0]);
+            const float dy = qdiff(qj.y, qi.y, g.ql[1]);
+            const float dz = qdiff(qj.z, qi.z, g.ql[2]);
+            const float r2 = dx * dx + dy * dy + dz * dz;
+            if (r2 < c.rd2 && r2 > 0.f) {
+                const float r = sqrtf(r2);
+                float dfc;
+                const float fc = cutoff_fn(c, r, dfc);
+                const float4* aj = reinterpret_cast<const float4*>(s.a + (int64_t)j * kSurNB);
+                float cij = 0.f;
+#pragma unroll
+                for (int q = 0; q < kSurNB / 4; ++q) {
+                    const float4 v = aj[q];
+                    const float av[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const int kk = 4 * q + e;
+                        const float t = r - c.mu[kk];
+                        const float ph = exp2f(-c.c_exp * t * t);
+                        const float dg = ph * (dfc - t * c.inv_w2 * fc);
+                        cij += (ai[kk] + av[e]) * dg;
+                    }
+                }
+                const float sc = cij / r;
+                fx += sc * dx;
+                fy += sc * dy;
+                fz += sc * dz;
+                w -= cij * r;
+                if (!TRAIN && tensor) {
+                    // r_ij f_ij with r_ij = -(dx, dy, dz), f_ij = sc (dx, dy, dz)
+                    txx -= sc * dx * dx; tyy -= sc * dy * dy; tzz -= sc * dz * dz;
+                    txy -= sc * dx * dy; txz -= sc * dx * dz; tyz -= sc * dy * dz;
+                }
+            }
+        }
+        if (TRAIN) {
+            const int64_t t = b.tag[i];
+            const double ex = (double)fx - fref[3 * t], ey = (double)fy - fref[3 * t + 1],
+                         ez = (double)fz - fref[3 * t + 2];
+            acc[0] += ex * ex + ey * ey + ez * ez;
+            s.delta[i] = make_float4((float)(two_over_m * ex), (float)(two_over_m * ey), (float)(two_over_m * ez), 0.f);
+        } else {
+            s.f[i] = make_float4(fx, fy, fz, 0.f);
+            acc[0] += 0.5 * (double)w;
+            if (tensor) {
+                acc[1] += 0.5 * (double)txx; acc[2] += 0.5 * (double)tyy; acc[3] += 0.5 * (double)tzz;
+                acc[4] += 0.5 * (double)txy; acc[5] += 0.5 * (double)txz; acc[6] += 0.5 * (double)tyz;
+            }
+        }
+    }
+    if (TRAIN) {
+        block_store<1>(acc, s.part + (int64_t)8 * gridDim.x);
+    } else {
+        block_store<7>(acc, s.part + (int64_t)1 * gridDim.x);
+    }
+}
+
+// u_i = sum_j ((delta_i - delta_j) . (x_j - x_i) / r_ij) g'(r_ij): the
+// sensitivity of the loss to a_i (each a_i enters the pair terms of i as
+// the first and of its neighbours as the second index).
+__global__ void __launch_bounds__(kBlock) k_sur_u(Geom g, Bufs b, SurBufs s, SurConst c, int parity) {
+    const int64_t n = g.n;
+    const int4* __restrict__ xq = b.xq[parity];
+    for (int64_t i = gtid_xcd(); i < n; i += gstride()) {
+        const int4 qi = xq[i];
+        const float4 di = s.delta[i];
+        int cnt = b.ncount[i];
+        cnt = cnt < g.cap ? cnt : g.cap;
+        const int32_t* __restrict__ row = b.nl + nl_base(i, g.cap);
+        float U[kSurNB];
+#pragma unroll
+        for (int k = 0; k < kSurNB; ++k) U[k] = 0.f;
+        for (int k = 0; k < cnt; ++k) {
+            const int j = row[k * kTile];
+            const int4 qj = xq[j];
+            const float dx = qdiff(qj.x, qi.x, g.ql[0]);
+            const float dy = qdiff(qj.y, qi.y, g.ql[1]);
+            const float dz = qdiff(qj.z, qi.z, g.ql[2]);
+            const float r2 = dx * dx + dy * dy + dz * dz;
+            if (r2 < c.rd2 && r2 > 0.f) {
+                const float r = sqrtf(r2);
+                float dfc;
+                const float fc = cutoff_fn(c, r, dfc);
+                const float4 dj = s.delta[j];
+                const float proj = ((di.x - dj.x) * dx + (di.y - dj.y) * dy + (di.z - dj.z) * dz) / r;
+#pragma unroll
+                for (int q = 0; q < kSurNB; ++q) {
+                    const float t = r - c.mu[q];
+                    const float ph = exp2f(-c.c_exp * t * t);
+                    U[q] += proj * ph * (dfc - t * c.inv_w2 * fc);
+                }
+            }
+        }
+        float4* out = reinterpret_cast<float4*>(s.u + i * kSurNB);
+#pragma unroll
+        for (int q = 0; q < kSurNB / 4; ++q) out[q] = make_float4(U[4 * q], U[4 * q + 1], U[4 * q + 2], U[4 * q + 3]);
+    }
+}
+
+// ------------------------------------------------------------------ network tiles
+
+// Weight images in LDS.  FP32: the prepared FP32 image (row strides 36/68)
+// with the biases; BF16: the prepared BF16 image (row strides 40/72) and the
+// FP32 biases.
+template <bool BF16>
+struct WImage;
+template <>
+struct WImage<false> {
+    alignas(16) float w[kPrepF];
+    __device__ const float* W1() const { return w + kPW1; }
+    __device__ const float* W1T() const { return w + kPW1T; }
+    __device__ const float* W2() const { return w + kPW2; }
+    __device__ const float* W2T() const { return w + kPW2T; }
+    __device__ const float* bias() const { return w + kPB1; }   // b1, b2, w3, b3
+    __device__ void load(const SurBufs& s) {
+        const float4* src = reinterpret_cast<const float4*>(s.wp);
+        float4* dst = reinterpret_cast<float4*>(w);
+        for (int k = threadIdx.x; k < kPrepF / 4; k += blockDim.x) dst[k] = src[k];
+    }
+};
+template <>
+struct WImage<true> {
+    alignas(16) uint16_t w[kPrepB];
+    alignas(16) float bb[kPrepF - kPB1];
+    __device__ const uint16_t* W1() const { return w + kQW1; }
+    __device__ const uint16_t* W1T() const { return w + kQW1T; }
+    __device__ const uint16_t* W2() const { return w + kQW2; }
+    __device__ const uint16_t* W2T() const { return w + kQW2T; }
+    __device__ const float* bias() const { return bb; }
+    __device__ void load(const SurBufs& s) {
+        const uint4* src = reinterpret_cast<const uint4*>(s.wb);
+        uint4* dst = reinterpret_cast<uint4*>(w);
+        for (int k = threadIdx.x; k < kPrepB / 8; k += blockDim.x) dst[k] = src[k];
+        for (int k = threadIdx.x; k < kPrepF - kPB1; k += blockDim.x) bb[k] = s.wp[kPB1 + k];
+    }
+};
+
+// O[p][c] = sum_k A[p][k] W[c][k] for the NC columns this lane owns (see the
+// file comment).  A: LDS rows of stride SA; W: LDS rows of stride SW.
+template <int NC, int K, int SA, int SW>
+__device__ __forceinline__ void tile_gemm(const float* __restrict__ A, const float* __restrict__ W, float* out,
+                                          int p, int hq) {
+#pragma unroll
+    for (int v = 0; v < NC / 4; ++v) out[v] = 0.f;
+#pragma unroll 2
+    for (int k = 0; k < K; k += 4) {
+        const float4 x = *reinterpret_cast<const float4*>(A + p * SA + k);
+#pragma unroll
+        for (int cb = 0; cb < NC / 16; ++cb)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const float4 wv = *reinterpret_cast<const float4*>(W + (16 * cb + 4 * hq + e) * SW + k);
+                out[4 * cb + e] += x.x * wv.x + x.y * wv.y + x.z * wv.z + x.w * wv.w;
+            }
+    }
+}
+
+template <int NC, int K, int SA, int SW>
+__device__ __forceinline__ void tile_gemm(const float* __restrict__ A, const uint16_t* __restrict__ W, float* out,
+                                          int p, int hq) {
+    const int r = threadIdx.x & 15;
+#pragma unroll
+    for (int cb = 0; cb < NC / 16; ++cb) {
+        float4v acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int kb = 0; kb < K / 16; ++kb) {
+            const float4 x = *reinterpret_cast<const float4*>(A + p * SA + 16 * kb + 4 * hq);
+            const short4v bop = {bf16_rne(x.x), bf16_rne(x.y), bf16_rne(x.z), bf16_rne(x.w)};
+            const short4v aop = *reinterpret_cast<const short4v*>(W + (16 * cb + r) * SW + 16 * kb + 4 * hq);
+            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(aop, bop, acc, 0, 0, 0);
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) out[4 * cb + e] = acc[e];
+    }
+}
+
+// C[h][m] += sum over the tile's 64 particles p of A[p][h] B[p][m] for the
+// entries this lane accumulates: h = 16 w + 4 (l >> 4) + e, m = 16 mb + (l & 15).
+template <bool BF16, int NM, int SA, int SB>
+__device__ __forceinline__ void tile_wgrad(const float* __restrict__ A, const float* __restrict__ B, float* acc) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, hq = lane >> 4, r = lane & 15;
+    if (BF16) {
+#pragma unroll
+        for (int pb = 0; pb < 4; ++pb) {
+            short4v aop, bop[NM / 16];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int p = 16 * pb + 4 * hq + j;
+                aop[j] = bf16_rne(A[p * SA + 16 * w + r]);
+#pragma unroll
+                for (int mb = 0; mb < NM / 16; ++mb) bop[mb][j] = bf16_rne(B[p * SB + 16 * mb + r]);
+            }
+#pragma unroll
+            for (int mb = 0; mb < NM / 16; ++mb) {
+                float4v c = {acc[4 * mb], acc[4 * mb + 1], acc[4 * mb + 2], acc[4 * mb + 3]};
+                c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(aop, bop[mb], c, 0, 0, 0);
+#pragma unroll
+                for (int e = 0; e < 4; ++e) acc[4 * mb + e] = c[e];
+            }
+        }
+    } else {
+#pragma unroll 4
+        for (int p = 0; p < 64; ++p) {
+            const float4 a4 = *reinterpret_cast<const float4*>(A + p * SA + 16 * w + 4 * hq);
+            const float av[4] = {a4.x, a4.y, a4.z, a4.w};
+#pragma unroll
+            for (int mb = 0; mb < NM / 16; ++mb) {
+                const float bv = B[p * SB + 16 * mb + r];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) acc[4 * mb + e] += av[e] * bv;
+            }
+        }
+    }
+}
+
+// Sum over the 16 lanes that share (l >> 4) (the wavefront's particles).
+__device__ __forceinline__ float sum16(float v) {
+#pragma unroll
+    for (int o = 1; o < 16; o <<= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Load 64 rows of raw descriptors, standardised: X[p][k] = (G - mean) istd,
+// and optionally V[p][k] = U[p][k] istd.  Rows at or past P are zero.
+__device__ __forceinline__ void load_rows(const SurBufs& s, const float* __restrict__ G, const float* __restrict__ U,
+                                          int64_t base, int64_t P, float* sX, float* sV) {
+    const int t = threadIdx.x;
+    const int p = t >> 2, c0 = (t & 3) * 8;
+    const bool ok = base + p < P;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int c = c0 + 4 * h;
+        float4 gv = make_float4(0.f, 0.f, 0.f, 0.f), uv = gv;
+        if (ok) {
+            gv = *reinterpret_cast<const float4*>(G + (base + p) * kSurNB + c);
+            if (U) uv = *reinterpret_cast<const float4*>(U + (base + p) * kSurNB + c);
+        }
+        const float4 m = *reinterpret_cast<const float4*>(s.gmean + c);
+        const float4 is = *reinterpret_cast<const float4*>(s.gistd + c);
+        float4 x = make_float4((gv.x - m.x) * is.x, (gv.y - m.y) * is.y, (gv.z - m.z) * is.z, (gv.w - m.w) * is.w);
+        if (!ok) x = make_float4(0.f, 0.f, 0.f, 0.f);
+        *reinterpret_cast<float4*>(sX + p * kSA32 + c) = x;
+        if (U) *reinterpret_cast<float4*>(sV + p * kSA32 + c) = make_float4(uv.x * is.x, uv.y * is.y, uv.z * is.z, uv.w * is.w);
+    }
+}
+
+// Forward and input gradient on tiles of 64 rows:
+//   z1 = W1 x + b1, h1 = silu(z1), z2 = W2 h1 + b2, E = w3 . silu(z2) + b3,
+//   gz2 = w3 silu'(z2), gz1 = (W2^T gz2) silu'(z1), dE/dG = (W1^T gz1) istd.
+template <bool BF16>
+__global__ void __launch_bounds__(kSB) k_sur_mlp(SurBufs s, const float* __restrict__ G, int64_t P,
+                                                 float* __restrict__ aout, float* __restrict__ eout,
+                                                 double* __restrict__ epart) {
+    __shared__ WImage<BF16> wi;
+    __shared__ __attribute__((aligned(16))) float sX[64 * kSA32];
+    __shared__ __attribute__((aligned(16))) float sA[64 * kSA64];
+    __shared__ __attribute__((aligned(16))) float sB[64 * kSA64];
+    wi.load(s);
+    __syncthreads();   // the weight image is complete before any lane reads it
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, hq = lane >> 4;
+    const int p = 16 * w + (lane & 15);
+    const float* b1 = wi.bias();
+    const float* b2 = b1 + 64;
+    const float* w3 = b1 + 128;
+    const float b3 = b1[192];
+    double esum = 0.0;
+    const int64_t ntile = (P + 63) / 64;
+    for (int64_t tile = blockIdx.x; tile < ntile; tile += gridDim.x) {
+        const int64_t base = tile * 64;
+        __syncthreads();   // previous tile done with sX/sA/sB
+        load_rows(s, G, nullptr, base, P, sX, nullptr);
+        __syncthreads();
+        float z[16], s1[16];
+        tile_gemm<64, 32, kSA32, BF16 ? kSW1 : kPF1>(sX, wi.W1(), z, p, hq);
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            const int h = 16 * (v >> 2) + 4 * hq + (v & 3);
+            const float zz = z[v] + b1[h];
+            const float sg = sigm(zz);
+            s1[v] = sg * (1.f + zz * (1.f - sg));
+            sA[p * kSA64 + h] = zz * sg;
+        }
+        __syncthreads();
+        tile_gemm<64, 64, kSA64, BF16 ? kSW64 : kPF64>(sA, wi.W2(), z, p, hq);
+        float e = 0.f;
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            const int h = 16 * (v >> 2) + 4 * hq + (v & 3);
+            const float zz = z[v] + b2[h];
+            const float sg = sigm(zz);
+            e += w3[h] * zz * sg;
+            sB[p * kSA64 + h] = w3[h] * sg * (1.f + zz * (1.f - sg));
+        }
+        e += __shfl_xor(e, 16, 64);
+        e += __shfl_xor(e, 32, 64);
+        const bool valid = base + p < P;
+        if (hq == 0 && valid) {
+            if (eout) eout[base + p] = e + b3;
+            esum += (double)(e + b3);
+        }
+        __syncthreads();
+        tile_gemm<64, 64, kSA64, BF16 ? kSW64 : kPF64>(sB, wi.W2T(), z, p, hq);
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            const int h = 16 * (v >> 2) + 4 * hq + (v & 3);
+            sA[p * kSA64 + h] = z[v] * s1[v];
+        }
+        __syncthreads();
+        float gx[8];
+        tile_gemm<32, 64, kSA64, BF16 ? kSW64 : kPF64>(sA, wi.W1T(), gx, p, hq);
+        if (valid) {
+#pragma unroll
+            for (int cb = 0; cb < 2; ++cb) {
+                const int k0 = 16 * cb + 4 * hq;
+                const float4 is = *reinterpret_cast<const float4*>(s.gistd + k0);
+                *reinterpret_cast<float4*>(aout + (base + p) * kSurNB + k0) =
+                    make_float4(gx[4 * cb] * is.x, gx[4 * cb + 1] * is.y, gx[4 * cb + 2] * is.z, gx[4 * cb + 3] * is.w);
+            }
+        }
+    }
+    if (epart) {
+        __syncthreads();
+        block_store<1>(&esum, epart);
+    }
+}
+
+// Double backward on tiles of 64 rows.  With x = standardised G, v = u istd
+// (u = dL/da): forward z1, z2; tangents t1 = W1 v, t2 = W2 (silu'(z1) t1);
+//   dW1 += r1 x^T + gz1 v^T,  db1 += r1,
+//   dW2 += r2 h1^T + gz2 (silu'(z1) t1)^T,  db2 += r2,  dw3 += silu'(z2) t2,
+// with gz2 = w3 silu'(z2), r2 = w3 silu''(z2) t2, gh1 = W2^T gz2,
+// r1 = (W2^T r2) silu'(z1) + gh1 t1 silu''(z1), gz1 = gh1 silu'(z1).
+// Each block accumulates over its tiles and writes one partial gradient row.
+template <bool BF16>
+__global__ void __launch_bounds__(kSB) k_sur_bwd2(SurBufs s, int64_t P) {
+    __shared__ WImage<BF16> wi;
+    __shared__ __attribute__((aligned(16))) float sX[64 * kSA32];
+    __shared__ __attribute__((aligned(16))) float sV[64 * kSA32];
+    __shared__ __attribute__((aligned(16))) float sH[64 * kSA64];    // h1, then r1
+    __shared__ __attribute__((aligned(16))) float sT[64 * kSA64];    // silu'(z1) t1, then gz1
+    __shared__ __attribute__((aligned(16))) float sG[64 * kSA64];    // gz2
+    __shared__ __attribute__((aligned(16))) float sR[64 * kSA64];    // r2
+    wi.load(s);
+    __syncthreads();   // the weight image is complete before any lane reads it
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, hq = lane >> 4;
+    const int p = 16 * w + (lane & 15);
+    const float* b1 = wi.bias();
+    const float* b2 = b1 + 64;
+    const float* w3 = b1 + 128;
+    float aW1[8], aW2[16], aB1[16], aB2[16], aW3[16];
+#pragma unroll
+    for (int v = 0; v < 16; ++v) { aW2[v] = 0.f; aB1[v] = 0.f; aB2[v] = 0.f; aW3[v] = 0.f; }
+#pragma unroll
+    for (int v = 0; v < 8; ++v) aW1[v] = 0.f;
+    const int64_t ntile = (P + 63) / 64;
+    for (int64_t tile = blockIdx.x; tile < ntile; tile += gridDim.x) {
+        const int64_t base = tile * 64;
+        const bool valid = base + p < P;
+        __syncthreads();
+        load_rows(s, s.G, s.u, base, P, sX, sV);
+        __syncthreads();
+        float z1[16], t1[16], s1[16], d1[16];
+        tile_gemm<64, 32, kSA32, BF16 ? kSW1 : kPF1>(sX, wi.W1(), z1, p, hq);
+        tile_gemm<64, 32, kSA32, BF16 ? kSW1 : kPF1>(sV, wi.W1(), t1, p, hq);
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            const int h = 16 * (v >> 2) + 4 * hq + (v & 3);
+            const float zz = z1[v] + b1[h];
+            const float sg = sigm(zz);
+            s1[v] = sg * (1.f + zz * (1.f - sg));
+            d1[v] = sg * (1.f - sg) * (2.f + zz * (1.f - 2.f * sg));
+            sH[p * kSA64 + h] = valid ? zz * sg : 0.f;
+            sT[p * kSA64 + h] = valid ? s1[v] * t1[v] : 0.f;
+        }
+        __syncthreads();
+        float z2[16], t2[16];
+        tile_gemm<64, 64, kSA64, BF16 ? kSW64 : kPF64>(sH, wi.W2(), z2, p, hq);
+        tile_gemm<64, 64, kSA64, BF16 ? kSW64 : kPF64>(sT, wi.W2(), t2, p, hq);
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            const int h = 16 * (v >> 2) + 4 * hq + (v & 3);
+            const float zz = z2[v] + b2[h];
+            const float sg = sigm(zz);
+            const float s2 = sg * (1.f + zz * (1.f - sg));
+            const float d2 = sg * (1.f - sg) * (2.f + zz * (1.f - 2.f * sg));
+            const float r2 = valid ? w3[h] * d2 * t2[v] : 0.f;
+            sG[p * kSA64 + h] = valid ? w3[h] * s2 : 0.f;
+            sR[p * kSA64 + h] = r2;
+            aB2[v] += sum16(r2);
+            aW3[v] += sum16(valid ? s2 * t2[v] : 0.f);
+        }
+        __syncthreads();
+        float gh[16], q[16];
+        tile_gemm<64, 64, kSA64, BF16 ? kSW64 : kPF64>(sG, wi.W2T(), gh, p, hq);
+        tile_gemm<64, 64, kSA64, BF16 ? kSW64 : kPF64>(sR, wi.W2T(), q, p, hq);
+        tile_wgrad<BF16, 64, kSA64, kSA64>(sR, sH, aW2);
+        tile_wgrad<BF16, 64, kSA64, kSA64>(sG, sT, aW2);
+        __syncthreads();   // sH / sT are rewritten below
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            const int h = 16 * (v >> 2) + 4 * hq + (v & 3);
+            const float r1 = valid ? q[v] * s1[v] + gh[v] * t1[v] * d1[v] : 0.f;
+            sH[p * kSA64 + h] = r1;
+            sT[p * kSA64 + h] = valid ? gh[v] * s1[v] : 0.f;
+            aB1[v] += sum16(r1);
+        }
+        __syncthreads();
+        tile_wgrad<BF16, 32, kSA64, kSA32>(sH, sX, aW1);
+        tile_wgrad<BF16, 32, kSA64, kSA32>(sT, sV, aW1);
+    }
+    // write this block's partial gradient
+    float* out = s.gpart + (int64_t)blockIdx.x * kSurNPpad;
+    const int r = lane & 15;
+#pragma unroll
+    for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) out[kOW2 + (16 * w + 4 * hq + e) * 64 + 16 * mb + r] = aW2[4 * mb + e];
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) out[kOW1 + (16 * w + 4 * hq + e) * 32 + 16 * mb + r] = aW1[4 * mb + e];
+    __syncthreads();
+    float* red = sX;   // [4 waves][3][64]
+    if (r == 0) {
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            const int h = 16 * (v >> 2) + 4 * hq + (v & 3);
+            red[(w * 3 + 0) * 64 + h] = aB1[v];
+            red[(w * 3 + 1) * 64 + h] = aB2[v];
+            red[(w * 3 + 2) * 64 + h] = aW3[v];
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < 192) {
+        const int kind = threadIdx.x >> 6, h = threadIdx.x & 63;
+        float t = 0.f;
+        for (int ww = 0; ww < 4; ++ww) t += red[(ww * 3 + kind) * 64 + h];
+        out[(kind == 0 ? kOB1 : kind == 1 ? kOB2 : kOW3) + h] = t;
+    }
+    if (threadIdx.x == 192) out[kOB3] = 0.f;
+}
+
+// grad[k] (+)= sum over blocks of gpart[blk][k], in block order.
+__global__ void __launch_bounds__(kBlock) k_sur_grad_reduce(SurBufs s, int nblk, int accumulate) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= kSurNP) return;
+    float t = 0.f;
+    for (int b = 0; b < nblk; ++b) t += s.gpart[(int64_t)b * kSurNPpad + k];
+    s.grad[k] = accumulate ? s.grad[k] + t : t;
+}
+
+// loss (+)= sum of the loss partials, in block order.
+__global__ void k_sur_loss_reduce(SurBufs s, int grid, int accumulate) {
+    if (threadIdx.x != 0) return;
+    double t = 0.0;
+    for (int b = 0; b < grid; ++b) t += s.part[(int64_t)8 * grid + b];
+    s.loss[0] = accumulate ? s.loss[0] + t : t;
+}
+
+// Adam (Kingma and Ba 2015) on the master weights, then nothing else: the
+// caller refreshes the prepared images.
+__global__ void __launch_bounds__(kBlock) k_sur_adam(SurBufs s, float lr, float beta1, float beta2, float eps,
+                                                     float bc1, float bc2) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= kSurNP) return;
+    const float g = s.grad[k];
+    const float m = beta1 * s.m1[k] + (1.f - beta1) * g;
+    const float v = beta2 * s.m2[k] + (1.f - beta2) * g * g;
+    s.m1[k] = m;
+    s.m2[k] = v;
+    s.w[k] -= lr * (m / bc1) / (sqrtf(v / bc2) + eps);
+}
+
+// Prepared images of the master weights: FP32 W1, W1^T, W2, W2^T with padded
+// rows plus the biases, and the BF16 (round to nearest even) copies.
+__global__ void __launch_bounds__(kBlock) k_sur_prepare(SurBufs s) {
+    const float* w = s.w;
+    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < 64 * 64; k += gridDim.x * blockDim.x) {
+        const int r = k >> 6, c = k & 63;
+        // W2 [r][c] and its transpose
+        const float w2 = w[kOW2 + r * 64 + c];
+        s.wp[kPW2 + r * kPF64 + c] = w2;
+        s.wp[kPW2T + c * kPF64 + r] = w2;
+        s.wb[kQW2 + r * kSW64 + c] = (uint16_t)bf16_rne(w2);
+        s.wb[kQW2T + c * kSW64 + r] = (uint16_t)bf16_rne(w2);
+        if (c < 32) {
+            const float w1 = w[kOW1 + r * 32 + c];
+            s.wp[kPW1 + r * kPF1 + c] = w1;
+            s.wp[kPW1T + c * kPF64 + r] = w1;
+            s.wb[kQW1 + r * kSW1 + c] = (uint16_t)bf16_rne(w1);
+            s.wb[kQW1T + c * kSW64 + r] = (uint16_t)bf16_rne(w1);
+        }
+        if (r == 0) {
+            s.wp[kPB1 + c] = w[kOB1 + c];
+            s.wp[kPB2 + c] = w[kOB2 + c];
+            s.wp[kPW3 + c] = w[kOW3 + c];
+            if (c == 0) s.wp[kPB3] = w[kOB3];
+        }
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_sur_to_tag(Geom g, Bufs b, const float* src, float* dst) {
+    for (int64_t i = gtid(); i < g.n; i += gstride()) {
+        const int64_t t = b.tag[i];
+        const float4* a = reinterpret_cast<const float4*>(src + i * kSurNB);
+        float4* o = reinterpret_cast<float4*>(dst + t * kSurNB);
+#pragma unroll
+        for (int q = 0; q < kSurNB / 4; ++q) o[q] = a[q];
+    }
+}
+
+// ------------------------------------------------------------------ launchers
+
+static inline int sgrid(int64_t n, int cap_blocks) {
+    int64_t g = (n + kBlock - 1) / kBlock;
+    if (g < 1) g = 1;
+    if (g > cap_blocks) g = cap_blocks;
+    return (int)g;
+}
+
+int sur_bwd2_grid(int64_t P) {
+    int64_t t = (P + 63) / 64;
+    if (t < 1) t = 1;
+    return (int)(t < kSurGradBlocks ? t : kSurGradBlocks);
+}
+
+hipError_t launch_sur_prepare(const SurBufs& s, hipStream_t st) {
+    hipLaunchKernelGGL(k_sur_prepare, dim3(16), dim3(kBlock), 0, st, s);
+    return hipGetLastError();
+}
+
+hipError_t launch_sur_desc(const Geom& g, const Bufs& b, const SurBufs& s, const SurConst& c, int parity, int grid,
+                           hipStream_t st) {
+    hipLaunchKernelGGL(k_sur_desc, dim3(grid), dim3(kBlock), 0, st, g, b, s, c, parity);
+    return hipGetLastError();
+}
+
+hipError_t launch_sur_mlp(const SurBufs& s, const float* G, int64_t P, float* a, float* e, double* epart,
+                          int bf16, int grid, hipStream_t st) {
+    if (bf16)
+        hipLaunchKernelGGL(k_sur_mlp<true>, dim3(grid), dim3(kSB), 0, st, s, G, P, a, e, epart);
+    else
+        hipLaunchKernelGGL(k_sur_mlp<false>, dim3(grid), dim3(kSB), 0, st, s, G, P, a, e, epart);
+    return hipGetLastError();
+}
+
+hipError_t launch_sur_force(const Geom& g, const Bufs& b, const SurBufs& s, const SurConst& c, int parity,
+                            const double* fref, double two_over_m, int tensor, int grid, hipStream_t st) {
+    if (fref)
+        hipLaunchKernelGGL(k_sur_force<true>, dim3(grid), dim3(kBlock), 0, st, g, b, s, c, parity, fref,
+                           two_over_m, 0);
+    else
+        hipLaunchKernelGGL(k_sur_force<false>, dim3(grid), dim3(kBlock), 0, st, g, b, s, c, parity, nullptr, 0.0,
+                           tensor);
+    return hipGetLastError();
+}
+
+hipError_t launch_sur_u(const Geom& g, const Bufs& b, const SurBufs& s, const SurConst& c, int parity, int grid,
+                        hipStream_t st) {
+    hipLaunchKernelGGL(k_sur_u, dim3(grid), dim3(kBlock), 0, st, g, b, s, c, parity);
+    return hipGetLastError();
+}
+
+hipError_t launch_sur_bwd2(const SurBufs& s, int64_t P, int bf16, hipStream_t st) {
+    const int grid = sur_bwd2_grid(P);
+    if (bf16)
+        hipLaunchKernelGGL(k_sur_bwd2<true>, dim3(grid), dim3(kSB), 0, st, s, P);
+    else
+        hipLaunchKernelGGL(k_sur_bwd2<false>, dim3(grid), dim3(kSB), 0, st, s, P);
+    return hipGetLastError();
+}
+
+hipError_t launch_sur_grad_reduce(const SurBufs& s, int nblk, int accumulate, hipStream_t st) {
+    hipLaunchKernelGGL(k_sur_grad_reduce, dim3((kSurNP + kBlock - 1) / kBlock), dim3(kBlock), 0, st, s, nblk,
+                       accumulate);
+    return hipGetLastError();
+}
+
+hipError_t launch_sur_loss_reduce(const SurBufs& s, int grid, int accumulate, hipStream_t st) {
+    hipLaunchKernelGGL(k_sur_loss_reduce, dim3(1), dim3(64), 0, st, s, grid, accumulate);
+    return hipGetLastError();
+}
+
+hipError_t launch_sur_adam(const SurBufs& s, int64_t t, float lr, float beta1, float beta2, float eps,
+                           hipStream_t st) {
+    const float bc1 = (float)(1.0 - pow((double)beta1, (double)t));
+    const float bc2 = (float)(1.0 - pow((double)beta2, (double)t));
+    hipLaunchKernelGGL(k_sur_adam, dim3((kSurNP + kBlock - 1) / kBlock), dim3(kBlock), 0, st, s, lr, beta1, beta2,
+                       eps, bc1, bc2);
+    return hipGetLastError();
+}
+
+hipError_t launch_sur_to_tag(const Geom& g, const Bufs& b, const float* src, float* dst, hipStream_t st) {
+    hipLaunchKernelGGL(k_sur_to_tag, dim3(sgrid(g.n, 4096)), dim3(kBlock), 0, st, g, b, src, dst);
+    return hipGetLastError();
+}
+
+}  // namespace md

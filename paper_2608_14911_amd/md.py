@@ -39,11 +39,23 @@ MD_MAX_TYPES = 4
 MD_HISTORY_CAPACITY = 8192
 MD_CFG_VIRIAL_TENSOR = 0x1
 MD_CFG_NO_GRAPH = 0x2
+MD_SUR_NBASIS = 32
+MD_SUR_HIDDEN = 64
+MD_SUR_NPARAM = 6337
+MD_SUR_RCUT = 2.5
+MD_SUR_WIDTH = 0.1
+MD_SUR_MU0 = 0.8
+MD_SUR_MU1 = 2.5
+MD_SUR_FP32 = 0
+MD_SUR_BF16 = 1
+MD_PAIR_PLAIN = 0
+MD_PAIR_SURROGATE = 1
 
 EXPORTED = ["md_workspace_bytes", "md_init", "md_set_params", "md_build_neighbors", "md_forces",
             "md_step", "md_observables", "md_history", "md_get_state", "md_set_state",
             "md_get_neighbors", "md_status_check", "md_timing_enable", "md_timing_read",
-            "md_destroy", "md_status_string", "md_last_error"]
+            "md_destroy", "md_status_string", "md_last_error", "md_sur_set", "md_sur_get",
+            "md_set_pair_mode", "md_sur_descriptors", "md_sur_mlp_eval", "md_sur_loss_grad", "md_sur_adam"]
 
 
 class md_pair_params(ctypes.Structure):
@@ -60,7 +72,8 @@ class md_config(ctypes.Structure):
                 ("pair", md_pair_params * (MD_MAX_TYPES * MD_MAX_TYPES)), ("n_bonds", ctypes.c_int64),
                 ("n_angles", ctypes.c_int64), ("fene_K", ctypes.c_double), ("fene_R0", ctypes.c_double),
                 ("k_bend", ctypes.c_double), ("cell_factor", ctypes.c_int32),
-                ("nl_capacity", ctypes.c_int32), ("block_size", ctypes.c_int32), ("flags", ctypes.c_int32)]
+                ("nl_capacity", ctypes.c_int32), ("block_size", ctypes.c_int32), ("flags", ctypes.c_int32),
+                ("list_cutoff", ctypes.c_double), ("surrogate", ctypes.c_int32), ("pad_", ctypes.c_int32)]
 
 
 class md_obs(ctypes.Structure):
@@ -118,6 +131,13 @@ def lib():
         "md_timing_enable": [P, I32],
         "md_timing_read": [P, ctypes.POINTER(md_timing)],
         "md_destroy": [P],
+        "md_sur_set": [P, P, P, P, I32],
+        "md_sur_get": [P, P],
+        "md_set_pair_mode": [P, I32],
+        "md_sur_descriptors": [P, P],
+        "md_sur_mlp_eval": [P, P, I64, P, P],
+        "md_sur_loss_grad": [P, P, P, I32, P, ctypes.POINTER(ctypes.c_double)],
+        "md_sur_adam": [P, I64, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -157,7 +177,8 @@ def _p(x):
 # ------------------------------------------------------------------ config helper
 def make_config(n, box, *, n_types=1, pair=None, dt=0.005, skin=0.3, integrator=MD_NVE,
                 force_precision=MD_FP32, temperature=1.0, gamma=0.0, seed=0, n_bonds=0, n_angles=0,
-                fene_K=30.0, fene_R0=1.5, k_bend=0.0, nl_capacity=0, flags=0, cell_factor=0):
+                fene_K=30.0, fene_R0=1.5, k_bend=0.0, nl_capacity=0, flags=0, cell_factor=0,
+                list_cutoff=0.0, surrogate=0):
     """Fill an md_config.  pair: dict (ti, tj) -> (eps, sigma, rc, shift, caprad)."""
     c = md_config()
     c.struct_size = ctypes.sizeof(md_config)
@@ -178,6 +199,8 @@ def make_config(n, box, *, n_types=1, pair=None, dt=0.005, skin=0.3, integrator=
     c.nl_capacity = int(nl_capacity)
     c.cell_factor = int(cell_factor)
     c.flags = int(flags)
+    c.list_cutoff = float(list_cutoff)
+    c.surrogate = int(surrogate)
     return c
 
 
@@ -263,3 +286,34 @@ def md_timing_read(h):
 
 def md_destroy(h):
     _check(lib().md_destroy(h), "md_destroy")
+
+
+def md_sur_set(h, theta, g_mean, g_istd, precision):
+    _check(lib().md_sur_set(h, _p(theta), _p(g_mean), _p(g_istd), int(precision)), "md_sur_set", h)
+
+
+def md_sur_get(h, theta):
+    _check(lib().md_sur_get(h, _p(theta)), "md_sur_get", h)
+
+
+def md_set_pair_mode(h, mode):
+    _check(lib().md_set_pair_mode(h, int(mode)), "md_set_pair_mode", h)
+
+
+def md_sur_descriptors(h, G):
+    _check(lib().md_sur_descriptors(h, _p(G)), "md_sur_descriptors", h)
+
+
+def md_sur_mlp_eval(h, G, P, e, dedg):
+    _check(lib().md_sur_mlp_eval(h, _p(G), int(P), _p(e), _p(dedg)), "md_sur_mlp_eval", h)
+
+
+def md_sur_loss_grad(h, frames, f_ref, nf, grad=None, want_loss=True):
+    loss = ctypes.c_double()
+    _check(lib().md_sur_loss_grad(h, _p(frames), _p(f_ref), int(nf), _p(grad),
+                                  ctypes.byref(loss) if want_loss else None), "md_sur_loss_grad", h)
+    return loss.value if want_loss else None
+
+
+def md_sur_adam(h, t, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+    _check(lib().md_sur_adam(h, int(t), float(lr), float(beta1), float(beta2), float(eps)), "md_sur_adam", h)

@@ -25,7 +25,7 @@ class System:
     def __init__(self, pos, box, vel=None, *, types=None, n_types=1, pair=None, masses=(1.0,),
                  bonds=None, angles=None, dt=0.005, skin=0.3, integrator="nve", precision="fp32",
                  temperature=1.0, gamma=0.0, seed=0, fene_K=30.0, fene_R0=1.5, k_bend=0.0,
-                 nl_capacity=0, flags=0, cell_factor=0, device="cuda"):
+                 nl_capacity=0, flags=0, cell_factor=0, list_cutoff=0.0, surrogate=False, device="cuda"):
         torch = _torch()
         self.torch = torch
         pos = np.ascontiguousarray(pos, dtype=np.float64)
@@ -41,7 +41,8 @@ class System:
         self.cfg = md.make_config(n, self.box, n_types=n_types, pair=pair, dt=dt, skin=skin, integrator=integ,
                                   force_precision=prec, temperature=temperature, gamma=gamma, seed=seed,
                                   n_bonds=nb, n_angles=na, fene_K=fene_K, fene_R0=fene_R0, k_bend=k_bend,
-                                  nl_capacity=nl_capacity, flags=flags, cell_factor=cell_factor)
+                                  nl_capacity=nl_capacity, flags=flags, cell_factor=cell_factor,
+                                  list_cutoff=list_cutoff, surrogate=int(bool(surrogate)))
         self.ws_bytes = md.md_workspace_bytes(self.cfg)
         self._ws_raw = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
         base = self._ws_raw.data_ptr()
@@ -131,6 +132,64 @@ class System:
 
     def status(self):
         return md.md_status_check(self.h)
+
+    # ------------------------------------------------------------ surrogate
+    def _dev(self, x, dtype):
+        t = self.torch
+        if isinstance(x, t.Tensor):
+            return x.to(device=self.device, dtype=dtype).contiguous()
+        return t.as_tensor(np.ascontiguousarray(x), device=self.device, dtype=dtype)
+
+    def sur_set(self, theta, g_mean, g_istd, precision="fp32"):
+        """Load network parameters (6,337 values) and the descriptor
+        standardisation (mean, 1/std per basis function)."""
+        t = self.torch
+        self._sur = [self._dev(theta, t.float32), self._dev(g_mean, t.float32), self._dev(g_istd, t.float32)]
+        prec = md.MD_SUR_BF16 if precision == "bf16" else md.MD_SUR_FP32
+        md.md_sur_set(self.h, self._sur[0].data_ptr(), self._sur[1].data_ptr(), self._sur[2].data_ptr(), prec)
+        self.stream.synchronize()
+
+    def sur_get(self):
+        t = self.torch
+        th = t.zeros(md.MD_SUR_NPARAM, dtype=t.float32, device=self.device)
+        md.md_sur_get(self.h, th.data_ptr())
+        self.stream.synchronize()
+        return th.cpu().numpy()
+
+    def set_pair_mode(self, mode):
+        md.md_set_pair_mode(self.h, md.MD_PAIR_SURROGATE if mode == "surrogate" else md.MD_PAIR_PLAIN)
+
+    def descriptors(self):
+        t = self.torch
+        G = t.zeros((self.n, md.MD_SUR_NBASIS), dtype=t.float32, device=self.device)
+        md.md_sur_descriptors(self.h, G.data_ptr())
+        self.stream.synchronize()
+        return G
+
+    def mlp_eval(self, G):
+        """Per-row energies and dE/dG for descriptor rows G [P, 32]."""
+        t = self.torch
+        G = self._dev(G, t.float32)
+        P = G.shape[0]
+        e = t.zeros(P, dtype=t.float32, device=self.device)
+        a = t.zeros((P, md.MD_SUR_NBASIS), dtype=t.float32, device=self.device)
+        md.md_sur_mlp_eval(self.h, G.data_ptr(), P, e.data_ptr(), a.data_ptr())
+        self.stream.synchronize()
+        return e, a
+
+    def loss_grad(self, frames, f_ref, want_grad=True):
+        """Force-matching loss over device frames [nf, N, 3] (FP64) and
+        reference forces [nf, N, 3] (FP64); returns (loss, grad or None)."""
+        t = self.torch
+        frames = self._dev(frames, t.float64)
+        f_ref = self._dev(f_ref, t.float64)
+        g = t.zeros(md.MD_SUR_NPARAM, dtype=t.float32, device=self.device) if want_grad else None
+        loss = md.md_sur_loss_grad(self.h, frames.data_ptr(), f_ref.data_ptr(), frames.shape[0],
+                                   None if g is None else g.data_ptr())
+        return loss, g
+
+    def adam(self, t, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+        md.md_sur_adam(self.h, t, lr, beta1, beta2, eps)
 
     def close(self):
         if not self._closed:

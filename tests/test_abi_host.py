@@ -40,6 +40,8 @@ int main(void) {
   printf("%zu %zu %zu %zu\\n", sizeof(md_config), sizeof(md_obs), sizeof(md_timing), sizeof(md_pair_params));
   printf("%zu %zu %zu %zu %zu\\n", offsetof(md_config, n_particles), offsetof(md_config, pair),
          offsetof(md_config, n_bonds), offsetof(md_config, flags), offsetof(md_obs, status_flags));
+  printf("%zu %zu %d %d\\n", offsetof(md_config, list_cutoff), offsetof(md_config, surrogate),
+         MD_SUR_NPARAM, MD_SUR_NBASIS);
   return 0;
 }
 ''')
@@ -49,7 +51,8 @@ int main(void) {
     c_sizes = list(map(int, out))
     py = [ctypes.sizeof(md.md_config), ctypes.sizeof(md.md_obs), ctypes.sizeof(md.md_timing),
           ctypes.sizeof(md.md_pair_params), md.md_config.n_particles.offset, md.md_config.pair.offset,
-          md.md_config.n_bonds.offset, md.md_config.flags.offset, md.md_obs.status_flags.offset]
+          md.md_config.n_bonds.offset, md.md_config.flags.offset, md.md_obs.status_flags.offset,
+          md.md_config.list_cutoff.offset, md.md_config.surrogate.offset, md.MD_SUR_NPARAM, md.MD_SUR_NBASIS]
     assert c_sizes == py
 
 
@@ -145,3 +148,30 @@ def test_status_strings():
                  md.MD_ERR_TOPOLOGY):
         assert md.status_string(code).startswith("MD_")
     assert md.status_string(-99) == "MD_ERR_UNKNOWN"
+
+
+def test_list_cutoff_and_surrogate_workspace():
+    base = lj_cfg(4000, pair={(0, 0): (1.0, 1.0, 2 ** (1 / 6), math.nan, 0.0)}, skin=0.4)
+    a = md.md_workspace_bytes(base)
+    wide = lj_cfg(4000, pair={(0, 0): (1.0, 1.0, 2 ** (1 / 6), math.nan, 0.0)}, skin=0.4, list_cutoff=2.5)
+    b = md.md_workspace_bytes(wide)
+    sur = lj_cfg(4000, pair={(0, 0): (1.0, 1.0, 2 ** (1 / 6), math.nan, 0.0)}, skin=0.4, list_cutoff=2.5,
+                 surrogate=1)
+    c = md.md_workspace_bytes(sur)
+    assert a < b < c
+    # descriptor, input-gradient and sensitivity rows (3 x 128 B), two float4
+    # per particle, and the fixed network buffers (< 8 MB)
+    assert 4000 * (3 * 128 + 32) <= c - b < 4000 * (3 * 128 + 32) + 8 * 2 ** 20
+    for bad in (-1.0, float("nan")):
+        with pytest.raises(md.MDError):
+            md.md_workspace_bytes(lj_cfg(4000, list_cutoff=bad))
+    with pytest.raises(md.MDError):
+        md.md_workspace_bytes(lj_cfg(4000, surrogate=2))
+
+
+def test_surrogate_calls_reject_null_handle():
+    lib = md.lib()
+    assert lib.md_sur_set(None, None, None, None, 0) == md.MD_ERR_ARG
+    assert lib.md_set_pair_mode(None, 1) == md.MD_ERR_ARG
+    assert lib.md_sur_adam(None, 1, 1e-3, 0.9, 0.999, 1e-8) == md.MD_ERR_ARG
+    assert lib.md_sur_loss_grad(None, None, None, 1, None, None) == md.MD_ERR_ARG
