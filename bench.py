@@ -40,7 +40,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="lj1m", choices=["lj1m", "kg2m", "kg1k"])
+    ap.add_argument("--workload", default="lj1m", choices=["lj1m", "kg2m", "kg1k", "batch"])
+    ap.add_argument("--no-autotune", action="store_true", help="batch: keep the sampler's skin, cell factor 2")
     ap.add_argument("--no-events", action="store_true",
                     help="time with a hipGraph replay and no per-kernel events")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -128,6 +129,97 @@ def cpu_baseline(w, name, budget_s, quiet):
                       "after 1 untimed step" % (steps, n)}
 
 
+def member_alg_bytes(m, n, skin):
+    """Algorithmic bytes per atom-step of one member: half Verlet list
+    (int32) at its density and list radius, FP64 x / v streams, FP32 force,
+    topology for melts."""
+    rc = m["pair"][(0, 0)][2]
+    rv = rc + skin
+    rho = n / float(m["box"][0]) ** 3
+    half = rho * 2.0 / 3.0 * math.pi * rv ** 3
+    return 4 + 4 * half + 24 + 12 + 132 + (16 if m.get("kind") == "kg" else 0)
+
+
+def bench_batch(a):
+    import torch
+    from paper_2608_14911_amd import autotune, inputs
+    from paper_2608_14911_amd.system import Batch, System, lj_pair, prepare_replica
+    t0 = time.time()
+    reps = inputs.batch_replicas(256, seed=1003)
+    out = []
+    for k, r in enumerate(reps):
+        out.append(prepare_replica(r))
+        if k % 32 == 31:
+            log("replicas prepared: %d / %d (%.0f s)" % (k + 1, len(reps), time.time() - t0), a.quiet)
+    reps = out
+    if a.no_autotune:
+        choice = {"lj": (0.3, 2), "kg": (0.4, 2)}
+        table = []
+    else:
+        choice, table = autotune.tune(reps, steps=30, log=lambda m: log(m, a.quiet))
+    reps = autotune.apply(reps, choice)
+    ntot = sum(r["pos"].shape[0] for r in reps)
+    b = Batch(reps)
+    b.step(a.warmup)
+    o0 = b.observables()
+    b.timing(True)
+    torch.cuda.synchronize()
+    ts = time.perf_counter()
+    b.step(a.steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - ts
+    tm = b.timing()
+    b.timing(False)
+    o1 = b.observables()
+    b.close()
+    # the same members one by one (graph-replayed standalone handles)
+    t_sum = 0.0
+    for r in reps:
+        s = System(r["pos"], r["box"], r["vel"], pair=r["pair"], bonds=r.get("bonds"), angles=r.get("angles"),
+                   k_bend=r.get("k_bend", 0.0), dt=r["dt"], skin=r["skin"], integrator=r["integrator"],
+                   temperature=r["temperature"], gamma=r["gamma"], seed=r["seed"], cell_factor=r["cell_factor"])
+        s.step(4)
+        s.stream.synchronize()
+        t1 = time.perf_counter()
+        s.step(20)
+        s.stream.synchronize()
+        t_sum += (time.perf_counter() - t1) / 20
+        s.close()
+    value = ntot * a.steps / el
+    k_ms = tm["ms_step_kernels"] / max(tm["n_step_kernels"], 1)
+    alg = sum(member_alg_bytes(r, r["pos"].shape[0], r["skin"]) * r["pos"].shape[0] for r in reps)
+    ach = alg / (k_ms * 1e-3) / 1e9
+    rec = {
+        "metric": "atom-steps/s (1M LJ, 2M KG melt)",
+        "value": value, "unit": "atom-steps/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+        "ms_per_step": 1e3 * el / a.steps, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": "batch of 256 replicas (128 LJ fluids, 128 polymer melts), %d particles" % ntot,
+                   "n_particles": ntot, "replicas": len(reps), "sizes": "log-uniform 2048..65536",
+                   "precision": "FP32 pair/bonded math, FP64 positions, velocities and reductions",
+                   "parallelism": "single GPU", "autotuned": {k: {"skin": v[0], "cell_factor": v[1]}
+                                                             for k, v in choice.items()}},
+        "standalone_sum_atom_steps_per_s": ntot / t_sum,
+        "batched_over_standalone": value / (ntot / t_sum),
+        "n_rebuilds_total": sum(x["n_rebuilds"] - y["n_rebuilds"] for x, y in zip(o1, o0)),
+        "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": ach / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_batch_step (fused forces + integration, all replicas)", "kernel_ms": k_ms,
+                     "alg_bytes_per_launch": alg},
+        "kernel_breakdown_ms_per_step": {
+            "rebuild_stage": tm["ms_rebuild"] / max(tm["n_rebuild"], 1), "step_kernel": k_ms,
+            "finalize": tm["ms_finalize"] / max(tm["n_finalize"], 1)},
+        "autotune_trials": table,
+    }
+    if not a.no_cpu_baseline:
+        w = dict(reps[0])
+        eps, sig, rc, shift, cap = w["pair"][(0, 0)]
+        w.update({"eps": eps, "sigma": sig, "rc": rc, "shift": shift})
+        rec["cpu_baseline"] = cpu_baseline(w, "batch", a.cpu_seconds, a.quiet)
+        rec["cpu_baseline"]["sample"] += " (replica 0 of the batch)"
+    print(json.dumps(rec), flush=True)
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -139,6 +231,8 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     torch.cuda.set_device(0)
+    if a.workload == "batch":
+        return bench_batch(a)
     w, s = make_system(a.workload, a.quiet, a.cell_factor)
     n = s.n
     s.step(a.warmup)

@@ -271,6 +271,12 @@ md_status md_sur_descriptors(md_handle h, float* G);
  * handle's standardisation is applied); e device FP32 [P] (may be NULL) and
  * dedg device FP32 [P][32] = dE_i/dG(i). */
 md_status md_sur_mlp_eval(md_handle h, const float* G, int64_t P, float* e, float* dedg);
+/* Surrogate pair forces at the current positions for given input gradients
+ * a_i = dE_i/dG(i): F_i = sum_j ((a_i + a_j) . g'(r_ij)) (x_j - x_i) / r_ij.
+ * dedg device FP32 [N][32] tag order; f_out device FP64 [N][3] tag order.
+ * A constant a_i = c makes E a pair potential (a linear readout of G), whose
+ * forces are linear in c. */
+md_status md_sur_pair_forces(md_handle h, const float* dedg, double* f_out);
 /* Force-matching loss L = mean over frames, particles and components of
  * (F - F_ref)^2 at the handle's weights, and (grad != NULL or for a later
  * md_sur_adam) its gradient dL/dtheta by the analytic double backward.
@@ -286,6 +292,45 @@ md_status md_sur_loss_grad(md_handle h, const double* frames, const double* f_re
 md_status md_sur_adam(md_handle h, int64_t t, double lr, double beta1, double beta2, double eps);
 
 md_status md_destroy(md_handle h);
+
+/* ------------------------------------------------------------------------
+ * Batches: many independent periodic systems advanced together, one kernel
+ * launch per stage for all of them (replicas of uneven size; the paper's
+ * per-system step applied to each, with its load-balancing concern met by
+ * tiles of 256 particles that never straddle systems).  Each member keeps
+ * its own cells, list, rebuild trigger, thermostat stream and observables;
+ * a member's trajectory is the one a standalone handle with the same
+ * configuration computes.  Members need one particle type, FP32 pair math,
+ * a cubic box, no capping radius, no surrogate, and at most 262144
+ * particles.
+ * ------------------------------------------------------------------------ */
+typedef struct md_batch_s* md_batch;
+
+/* Workspace bytes for the batch cfgs[0..nsys-1] (host arithmetic only). */
+md_status md_batch_workspace_bytes(const md_config* cfgs, int32_t nsys, size_t* bytes);
+/* Create the batch.  pos[s], vel[s]: device FP64 [n_s][3]; mass_by_type[s]:
+ * host FP64 [1]; bonds[s] / angles[s]: host int32 topology as for md_init, or
+ * bonds / angles NULL for none; workspace: device, >= md_batch_workspace_bytes(),
+ * 256-byte aligned, caller-owned.  Synchronises the stream. */
+md_status md_batch_init(const md_config* cfgs, int32_t nsys, const double* const* pos, const double* const* vel,
+                        const double* const* mass_by_type, const int32_t* const* bonds,
+                        const int32_t* const* angles, void* workspace, size_t ws_bytes, void* stream,
+                        md_batch* out);
+/* Advance every member nsteps (asynchronous; replayed from a hipGraph of two
+ * steps). */
+md_status md_batch_step(md_batch b, int64_t nsteps);
+/* Observables of every member at the current step into host out[nsys];
+ * synchronises; returns the first member's latched device error, if any. */
+md_status md_batch_observables(md_batch b, md_obs* out);
+/* State of member sys, as md_get_state. */
+md_status md_batch_get_state(md_batch b, int32_t sys, double* pos, double* vel, int32_t* image,
+                             double* pos_build, int64_t* step, int32_t* vel_half);
+/* HIP-event timing of the batch's stages, as md_timing_enable / md_timing_read. */
+md_status md_batch_timing_enable(md_batch b, int32_t enable);
+md_status md_batch_timing_read(md_batch b, md_timing* out);
+md_status md_batch_destroy(md_batch b);
+const char* md_batch_last_error(md_batch b);
+
 const char* md_status_string(md_status s);
 const char* md_last_error(md_handle h);
 

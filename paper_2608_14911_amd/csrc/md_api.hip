@@ -190,7 +190,7 @@ static md_status plan_geom(const md_config* c, Geom* g, std::string* why) {
 
 // Carve the workspace; with base == nullptr only the size is computed.
 static size_t carve(const md_config* c, const Geom& g, int step_grid, uint8_t* base, Bufs* b,
-                    SurBufs* sb = nullptr) {
+                    SurBufs* sb = nullptr, bool ext_cells = false) {
     const int64_t n = g.n;
     const bool bonded = c->n_bonds > 0 || c->n_angles > 0;
     const int maxb = c->n_bonds > 0 ? MD_MAX_BONDS_PER_PARTICLE : 0;
@@ -218,8 +218,10 @@ static size_t carve(const md_config* c, const Geom& g, int step_grid, uint8_t* b
     t.tag = (int32_t*)take(sizeof(int32_t) * n);
     t.inv = (int32_t*)take(sizeof(int32_t) * n);
     t.cellid = (uint32_t*)take(sizeof(uint32_t) * n);
-    t.ccount = (int32_t*)take(sizeof(int32_t) * g.ncell);
-    t.cstart = (int32_t*)take(sizeof(int32_t) * (g.ncell + 1));
+    if (!ext_cells) {   // batch members use the batch's concatenated cell arrays
+        t.ccount = (int32_t*)take(sizeof(int32_t) * g.ncell);
+        t.cstart = (int32_t*)take(sizeof(int32_t) * (g.ncell + 1));
+    }
     t.bsum = (int32_t*)take(sizeof(int32_t) * kScanBlocks);
     t.tmp = (int32_t*)take(sizeof(int32_t) * n);
     t.xt = (double4*)take(sizeof(double4) * n);
@@ -573,9 +575,25 @@ md_status md_workspace_bytes(const md_config* cfg, size_t* bytes) {
     return MD_OK;
 }
 
+// External cell arrays of a batch member (nullptr for a standalone handle).
+struct CellExt {
+    int32_t* ccount;
+    int32_t* cstart;
+};
+
+static md_status init_core(const md_config* cfg, const double* pos, const double* vel, const int32_t* type,
+                           const double* mass_by_type, const int32_t* bonds, const int32_t* angles, void* workspace,
+                           size_t ws_bytes, void* stream, const CellExt* ext, md_handle* out);
+
 md_status md_init(const md_config* cfg, const double* pos, const double* vel, const int32_t* type,
                   const double* mass_by_type, const int32_t* bonds, const int32_t* angles, void* workspace,
                   size_t ws_bytes, void* stream, md_handle* out) {
+    return init_core(cfg, pos, vel, type, mass_by_type, bonds, angles, workspace, ws_bytes, stream, nullptr, out);
+}
+
+static md_status init_core(const md_config* cfg, const double* pos, const double* vel, const int32_t* type,
+                           const double* mass_by_type, const int32_t* bonds, const int32_t* angles, void* workspace,
+                           size_t ws_bytes, void* stream, const CellExt* ext, md_handle* out) {
     if (!out) return fail(nullptr, MD_ERR_ARG, "out is NULL");
     *out = nullptr;
     Geom g;
@@ -588,7 +606,7 @@ md_status md_init(const md_config* cfg, const double* pos, const double* vel, co
     for (int t = 0; t < cfg->n_types; ++t)
         if (!(mass_by_type[t] > 0.0) || !isfinite(mass_by_type[t])) return fail(nullptr, MD_ERR_ARG, "mass must be > 0");
     const int sg = step_grid_of(g.n);
-    const size_t need = carve(cfg, g, sg, nullptr, nullptr);
+    const size_t need = carve(cfg, g, sg, nullptr, nullptr, nullptr, ext != nullptr);
     if (ws_bytes < need) return fail(nullptr, MD_ERR_WORKSPACE, "workspace smaller than md_workspace_bytes()");
     if (((uintptr_t)workspace & 255) != 0) return fail(nullptr, MD_ERR_WORKSPACE, "workspace must be 256-byte aligned");
 
@@ -604,7 +622,11 @@ md_status md_init(const md_config* cfg, const double* pos, const double* vel, co
     h->single = cfg->n_types == 1 ? 1 : 0;
     h->fp64 = cfg->force_precision == MD_FP64 ? 1 : 0;
     memset(&h->tacc, 0, sizeof(h->tacc));
-    carve(cfg, g, sg, h->ws, &h->b, &h->sb);
+    carve(cfg, g, sg, h->ws, &h->b, &h->sb, ext != nullptr);
+    if (ext) {
+        h->b.ccount = ext->ccount;
+        h->b.cstart = ext->cstart;
+    }
     h->has_sur = cfg->surrogate;
     fill_sur_const(&h->sc);
     fill_params(h, cfg);
@@ -922,6 +944,20 @@ md_status md_sur_mlp_eval(md_handle h, const float* G, int64_t P, float* e, floa
     return MD_OK;
 }
 
+md_status md_sur_pair_forces(md_handle h, const float* dedg, double* f_out) {
+    md_status r = need_sur(h);
+    if (r != MD_OK) return r;
+    if (!dedg || !f_out) return fail(h, MD_ERR_ARG, "NULL argument");
+    if (sqrt(h->g.rv2) - h->cfg.skin < MD_SUR_RCUT * (1.0 - 1e-12))
+        return fail(h, MD_ERR_ARG, "list radius minus skin is below the descriptor cutoff");
+    if ((r = rebuild_now(h, 0)) != MD_OK) return r;
+    const SurBufs& s = h->sb;
+    HIP_TRY(h, launch_sur_from_tag(h->g, h->b, dedg, s.a, h->stream));
+    HIP_TRY(h, launch_sur_force(h->g, h->b, s, h->sc, h->parity, nullptr, 0.0, 0, h->step_grid, h->stream));
+    HIP_TRY(h, launch_sur_f_to_tag(h->g, h->b, s.f, f_out, h->stream));
+    return MD_OK;
+}
+
 md_status md_sur_loss_grad(md_handle h, const double* frames, const double* f_ref, int32_t nf, float* grad,
                            double* loss) {
     md_status r = need_sur(h);
@@ -974,6 +1010,374 @@ md_status md_sur_adam(md_handle h, int64_t t, double lr, double beta1, double be
         return fail(h, MD_ERR_ARG, "bad Adam parameters");
     HIP_TRY(h, launch_sur_adam(h->sb, t, (float)lr, (float)beta1, (float)beta2, (float)eps, h->stream));
     HIP_TRY(h, launch_sur_prepare(h->sb, h->stream));
+    return MD_OK;
+}
+
+// ------------------------------------------------------------------ batches
+
+}  // extern "C"
+
+struct md_batch_s {
+    int nsys = 0;
+    std::vector<md_handle> sys;
+    hipStream_t stream = nullptr;
+    BatchCells bc;
+    SysEntry* tabs[2][2] = {};      // device [nsys] per (mode: step / observe, parity)
+    int32_t* tile_sys = nullptr;    // device [ntiles]
+    int64_t ntiles = 0;
+    double* obs = nullptr;          // device [nsys][kHistRec]
+    int parity = 0;
+    int64_t host_step = 0;
+    hipGraphExec_t gexec = nullptr;
+    int graph_parity = -1;
+    std::string err;
+    bool timing = false;
+    std::vector<EvQuad> ev_free, ev_pending;
+    md_timing tacc;
+};
+
+namespace {
+
+struct BatchPlan {
+    std::vector<Geom> g;
+    std::vector<size_t> ws_off, ws_size;
+    std::vector<int64_t> c_off, tile0;
+    std::vector<int32_t> ntiles;
+    int64_t ncell_total = 0, ntiles_total = 0, n_total = 0;
+    size_t off_ctl = 0, off_count = 0, off_start = 0, off_bsum = 0, off_coff = 0, off_base = 0, off_tiles = 0,
+           off_tab = 0, off_obs = 0, total = 0;
+};
+
+md_status plan_batch(const md_config* cfgs, int32_t nsys, BatchPlan* p, std::string* why) {
+    if (!cfgs || nsys < 1) {
+        *why = "need at least one system";
+        return MD_ERR_ARG;
+    }
+    p->g.resize(nsys);
+    p->ws_off.resize(nsys);
+    p->ws_size.resize(nsys);
+    p->c_off.resize(nsys + 1);
+    p->tile0.resize(nsys);
+    p->ntiles.resize(nsys);
+    for (int s = 0; s < nsys; ++s) {
+        const md_config* c = &cfgs[s];
+        md_status st = plan_geom(c, &p->g[s], why);
+        if (st != MD_OK) {
+            *why = "system " + std::to_string(s) + ": " + *why;
+            return st;
+        }
+        const md_pair_params& pp = c->pair[0];
+        if (c->n_types != 1 || c->force_precision != MD_FP32 || pp.caprad > 0.0 || c->box[0] != c->box[1] ||
+            c->box[1] != c->box[2] || c->surrogate) {
+            *why = "system " + std::to_string(s) +
+                   ": batch members need one particle type, FP32 pair math, a cubic box, no capping radius "
+                   "and no surrogate";
+            return MD_ERR_ARG;
+        }
+        if (c->n_particles > (int64_t)kBlock * 1024) {
+            *why = "system " + std::to_string(s) + ": batch members hold at most 262144 particles";
+            return MD_ERR_ARG;
+        }
+        const int64_t nt = (c->n_particles + kBlock - 1) / kBlock;
+        p->ntiles[s] = (int32_t)nt;
+        p->tile0[s] = p->ntiles_total;
+        p->ntiles_total += nt;
+        p->n_total += c->n_particles;
+        p->c_off[s] = p->ncell_total;
+        p->ncell_total += p->g[s].ncell + 1;   // each system's cells and its end sentinel
+        p->ws_size[s] = carve(c, p->g[s], (int)nt, nullptr, nullptr, nullptr, true);
+    }
+    p->c_off[nsys] = p->ncell_total;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off += align256(bytes);
+        return o;
+    };
+    p->off_ctl = take(sizeof(DevCtl));
+    p->off_count = take(sizeof(int32_t) * (p->ncell_total + 1));
+    p->off_start = take(sizeof(int32_t) * (p->ncell_total + 1));
+    p->off_bsum = take(sizeof(int32_t) * kScanBlocks);
+    p->off_coff = take(sizeof(int64_t) * (nsys + 1));
+    p->off_base = take(sizeof(int32_t) * nsys);
+    p->off_tiles = take(sizeof(int32_t) * p->ntiles_total);
+    p->off_tab = take(sizeof(SysEntry) * nsys * 4);
+    p->off_obs = take(sizeof(double) * kHistRec * nsys);
+    for (int s = 0; s < nsys; ++s) p->ws_off[s] = take(p->ws_size[s]);
+    p->total = off;
+    return MD_OK;
+}
+
+md_status bfail(md_batch b, md_status st, const std::string& msg) {
+    if (b) b->err = msg;
+    g_last_error = msg;
+    return st;
+}
+
+#define BHIP_TRY(b, call)                                                                   \
+    do {                                                                                    \
+        hipError_t e_ = (call);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            return bfail((b), MD_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+hipError_t batch_enqueue_step(md_batch b, const EvQuad* q = nullptr) {
+    if (q) (void)hipEventRecord(q->e[0], b->stream);
+    hipError_t e = launch_batch_rebuild(b->bc, b->tabs[0][b->parity], b->tile_sys, b->ntiles, b->parity, b->stream);
+    if (e != hipSuccess) return e;
+    if (q) (void)hipEventRecord(q->e[1], b->stream);
+    e = launch_batch_step(b->tabs[0][b->parity], b->tile_sys, b->ntiles, b->parity, MODE_STEP, 0, b->stream);
+    if (e != hipSuccess) return e;
+    if (q) (void)hipEventRecord(q->e[2], b->stream);
+    e = launch_batch_finalize(b->tabs[0][b->parity], b->nsys, MODE_STEP, b->stream);
+    if (e != hipSuccess) return e;
+    if (q) (void)hipEventRecord(q->e[3], b->stream);
+    b->parity ^= 1;
+    b->host_step += 1;
+    return hipSuccess;
+}
+
+void batch_sync_members(md_batch b) {
+    for (md_handle h : b->sys) {
+        h->parity = b->parity;
+        h->host_step = b->host_step;
+        h->vel_half = 1;
+        drop_graph(h);
+    }
+}
+
+void batch_drop_graph(md_batch b) {
+    if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+    b->gexec = nullptr;
+    b->graph_parity = -1;
+}
+
+}  // namespace
+
+extern "C" {
+
+md_status md_batch_workspace_bytes(const md_config* cfgs, int32_t nsys, size_t* bytes) {
+    if (!bytes) return fail(nullptr, MD_ERR_ARG, "bytes is NULL");
+    BatchPlan p;
+    std::string why;
+    md_status st = plan_batch(cfgs, nsys, &p, &why);
+    if (st != MD_OK) return fail(nullptr, st, why);
+    *bytes = p.total;
+    return MD_OK;
+}
+
+md_status md_batch_destroy(md_batch b) {
+    if (!b) return MD_OK;
+    (void)hipStreamSynchronize(b->stream);
+    batch_drop_graph(b);
+    for (auto& q : b->ev_free)
+        for (int k = 0; k < 4; ++k) (void)hipEventDestroy(q.e[k]);
+    for (auto& q : b->ev_pending)
+        for (int k = 0; k < 4; ++k) (void)hipEventDestroy(q.e[k]);
+    for (md_handle h : b->sys) md_destroy(h);
+    delete b;
+    return MD_OK;
+}
+
+md_status md_batch_init(const md_config* cfgs, int32_t nsys, const double* const* pos, const double* const* vel,
+                        const double* const* mass_by_type, const int32_t* const* bonds,
+                        const int32_t* const* angles, void* workspace, size_t ws_bytes, void* stream,
+                        md_batch* out) {
+    if (!out) return fail(nullptr, MD_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    BatchPlan p;
+    std::string why;
+    md_status st = plan_batch(cfgs, nsys, &p, &why);
+    if (st != MD_OK) return fail(nullptr, st, why);
+    if (!pos || !vel || !mass_by_type || !workspace) return fail(nullptr, MD_ERR_ARG, "NULL argument");
+    if (ws_bytes < p.total) return fail(nullptr, MD_ERR_WORKSPACE, "workspace smaller than md_batch_workspace_bytes()");
+    if (((uintptr_t)workspace & 255) != 0) return fail(nullptr, MD_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+    md_batch b = new (std::nothrow) md_batch_s();
+    if (!b) return fail(nullptr, MD_ERR_ARG, "out of host memory");
+    memset(&b->tacc, 0, sizeof(b->tacc));
+    b->nsys = nsys;
+    b->stream = (hipStream_t)stream;
+    uint8_t* ws = (uint8_t*)workspace;
+    int32_t* gcount = (int32_t*)(ws + p.off_count);
+    int32_t* gstart = (int32_t*)(ws + p.off_start);
+    for (int m = 0; m < 2; ++m)
+        for (int q = 0; q < 2; ++q) b->tabs[m][q] = (SysEntry*)(ws + p.off_tab) + (size_t)(2 * m + q) * nsys;
+    b->tile_sys = (int32_t*)(ws + p.off_tiles);
+    b->ntiles = p.ntiles_total;
+    b->obs = (double*)(ws + p.off_obs);
+    memset(&b->bc, 0, sizeof(b->bc));
+    b->bc.gg.ncell = p.ncell_total;
+    b->bc.gg.n = p.n_total;
+    b->bc.gb.ctl = (DevCtl*)(ws + p.off_ctl);
+    b->bc.gb.ccount = gcount;
+    b->bc.gb.cstart = gstart;
+    b->bc.gb.bsum = (int32_t*)(ws + p.off_bsum);
+    b->bc.tab = b->tabs[0][0];
+    b->bc.c_off = (int64_t*)(ws + p.off_coff);
+    b->bc.base = (int32_t*)(ws + p.off_base);
+    b->bc.nsys = nsys;
+    auto bail = [&](md_status r) {
+        md_batch_destroy(b);
+        return r;
+    };
+    if (launch_zero_i32((int32_t*)b->bc.gb.ctl, sizeof(DevCtl) / 4, b->stream) != hipSuccess ||
+        launch_zero_i32(gcount, p.ncell_total + 1, b->stream) != hipSuccess)
+        return bail(fail(nullptr, MD_ERR_HIP, "batch init: kernel launch failed"));
+    for (int s = 0; s < nsys; ++s) {
+        CellExt ext{gcount + p.c_off[s], gstart + p.c_off[s]};
+        md_handle h = nullptr;
+        md_status r = init_core(&cfgs[s], pos[s], vel[s], nullptr, mass_by_type[s], bonds ? bonds[s] : nullptr,
+                                angles ? angles[s] : nullptr, ws + p.ws_off[s], p.ws_size[s], stream, &ext, &h);
+        if (r != MD_OK) {
+            std::string m = "system " + std::to_string(s) + ": " + g_last_error;
+            md_batch_destroy(b);
+            return fail(nullptr, r, m);
+        }
+        b->sys.push_back(h);
+    }
+    std::vector<SysEntry> tab((size_t)4 * nsys);
+    std::vector<int32_t> tiles(p.ntiles_total);
+    for (int s = 0; s < nsys; ++s) {
+        md_handle h = b->sys[s];
+        if (!h->use_fast) return bail(fail(nullptr, MD_ERR_ARG, "batch member outside the FP32 fast path"));
+        for (int m = 0; m < 2; ++m)
+            for (int q = 0; q < 2; ++q) {
+                SysEntry& e = tab[(size_t)(2 * m + q) * nsys + s];
+                memset(&e, 0, sizeof(SysEntry));
+                e.a = make_args(h, m == 0 ? MODE_STEP : MODE_OBSERVE, m, nullptr);
+                e.a.parity = q;
+                e.a.use_fast = 1;
+                e.tile0 = p.tile0[s];
+                e.ntiles = p.ntiles[s];
+                e.bonded = h->bonded;
+                e.c_off = p.c_off[s];
+            }
+        for (int64_t t = 0; t < p.ntiles[s]; ++t) tiles[p.tile0[s] + t] = s;
+    }
+    if (hipMemcpyAsync(b->tabs[0][0], tab.data(), sizeof(SysEntry) * tab.size(), hipMemcpyHostToDevice,
+                       b->stream) != hipSuccess ||
+        hipMemcpyAsync(b->tile_sys, tiles.data(), sizeof(int32_t) * tiles.size(), hipMemcpyHostToDevice,
+                       b->stream) != hipSuccess ||
+        hipMemcpyAsync(b->bc.c_off, p.c_off.data(), sizeof(int64_t) * (nsys + 1), hipMemcpyHostToDevice,
+                       b->stream) != hipSuccess ||
+        hipStreamSynchronize(b->stream) != hipSuccess)
+        return bail(fail(nullptr, MD_ERR_HIP, "batch table upload failed"));
+    *out = b;
+    return MD_OK;
+}
+
+md_status md_batch_step(md_batch b, int64_t nsteps) {
+    if (!b) return fail(nullptr, MD_ERR_ARG, "NULL batch");
+    if (nsteps < 0) return bfail(b, MD_ERR_ARG, "nsteps < 0");
+    int64_t left = nsteps;
+    while (left > 0) {
+        if (b->timing) {
+            EvQuad q;
+            if (!b->ev_free.empty()) {
+                q = b->ev_free.back();
+                b->ev_free.pop_back();
+            } else {
+                for (int k = 0; k < 4; ++k) BHIP_TRY(b, hipEventCreate(&q.e[k]));
+            }
+            b->ev_pending.push_back(q);
+            BHIP_TRY(b, batch_enqueue_step(b, &b->ev_pending.back()));
+            --left;
+            continue;
+        }
+        if (left >= 2 && b->stream != nullptr) {
+            if (b->graph_parity != b->parity) {
+                batch_drop_graph(b);
+                hipGraph_t graph = nullptr;
+                const int p0 = b->parity;
+                const int64_t s0 = b->host_step;
+                BHIP_TRY(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+                hipError_t e1 = batch_enqueue_step(b);
+                hipError_t e2 = e1 == hipSuccess ? batch_enqueue_step(b) : e1;
+                hipError_t e3 = hipStreamEndCapture(b->stream, &graph);
+                b->parity = p0;
+                b->host_step = s0;
+                if (e2 != hipSuccess || e3 != hipSuccess) {
+                    if (graph) (void)hipGraphDestroy(graph);
+                    return bfail(b, MD_ERR_HIP, "batch graph capture failed");
+                }
+                hipError_t e4 = hipGraphInstantiate(&b->gexec, graph, nullptr, nullptr, 0);
+                (void)hipGraphDestroy(graph);
+                if (e4 != hipSuccess) {
+                    b->gexec = nullptr;
+                    return bfail(b, MD_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e4));
+                }
+                b->graph_parity = p0;
+            }
+            BHIP_TRY(b, hipGraphLaunch(b->gexec, b->stream));
+            b->host_step += 2;
+            left -= 2;
+            continue;
+        }
+        BHIP_TRY(b, batch_enqueue_step(b));
+        --left;
+    }
+    batch_sync_members(b);
+    return MD_OK;
+}
+
+md_status md_batch_observables(md_batch b, md_obs* out) {
+    if (!b || !out) return fail(nullptr, MD_ERR_ARG, "NULL argument");
+    SysEntry* to = b->tabs[1][b->parity];
+    BHIP_TRY(b, launch_batch_rebuild(b->bc, to, b->tile_sys, b->ntiles, b->parity, b->stream));
+    BHIP_TRY(b, launch_batch_step(to, b->tile_sys, b->ntiles, b->parity, MODE_OBSERVE, 1, b->stream));
+    BHIP_TRY(b, launch_batch_finalize(to, b->nsys, MODE_OBSERVE, b->stream));
+    BHIP_TRY(b, launch_batch_gather_obs(to, b->nsys, b->obs, b->stream));
+    std::vector<double> rec((size_t)kHistRec * b->nsys);
+    BHIP_TRY(b, hipMemcpyAsync(rec.data(), b->obs, sizeof(double) * rec.size(), hipMemcpyDeviceToHost, b->stream));
+    BHIP_TRY(b, hipStreamSynchronize(b->stream));
+    md_status worst = MD_OK;
+    for (int s = 0; s < b->nsys; ++s) {
+        fill_obs(b->sys[s], &rec[(size_t)s * kHistRec], &out[s]);
+        const md_status r = status_to_code(b->sys[s], out[s].status_flags, out[s].nl_max_count);
+        if (r != MD_OK && worst == MD_OK) {
+            worst = r;
+            b->err = "system " + std::to_string(s) + ": " + b->sys[s]->err;
+            g_last_error = b->err;
+        }
+    }
+    return worst;
+}
+
+md_status md_batch_get_state(md_batch b, int32_t sys, double* pos, double* vel, int32_t* image, double* pos_build,
+                             int64_t* step, int32_t* vel_half) {
+    if (!b || sys < 0 || sys >= b->nsys) return fail(nullptr, MD_ERR_ARG, "bad batch or system index");
+    md_status r = md_get_state(b->sys[sys], pos, vel, image, pos_build, step, vel_half);
+    if (r != MD_OK) bfail(b, r, b->sys[sys]->err);
+    return r;
+}
+
+const char* md_batch_last_error(md_batch b) { return b ? b->err.c_str() : g_last_error.c_str(); }
+
+md_status md_batch_timing_enable(md_batch b, int32_t enable) {
+    if (!b) return fail(nullptr, MD_ERR_ARG, "NULL batch");
+    b->timing = enable != 0;
+    return MD_OK;
+}
+
+md_status md_batch_timing_read(md_batch b, md_timing* out) {
+    if (!b || !out) return fail(nullptr, MD_ERR_ARG, "NULL argument");
+    BHIP_TRY(b, hipStreamSynchronize(b->stream));
+    for (const EvQuad& q : b->ev_pending) {
+        float x = 0, y = 0, z = 0;
+        BHIP_TRY(b, hipEventElapsedTime(&x, q.e[0], q.e[1]));
+        BHIP_TRY(b, hipEventElapsedTime(&y, q.e[1], q.e[2]));
+        BHIP_TRY(b, hipEventElapsedTime(&z, q.e[2], q.e[3]));
+        b->tacc.n_rebuild += 1;
+        b->tacc.ms_rebuild += x;
+        b->tacc.n_step_kernels += 1;
+        b->tacc.ms_step_kernels += y;
+        b->tacc.n_finalize += 1;
+        b->tacc.ms_finalize += z;
+        b->ev_free.push_back(q);
+    }
+    b->ev_pending.clear();
+    *out = b->tacc;
+    memset(&b->tacc, 0, sizeof(b->tacc));
     return MD_OK;
 }
 

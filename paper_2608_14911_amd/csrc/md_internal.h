@@ -219,7 +219,38 @@ hipError_t launch_sur_loss_reduce(const SurBufs& s, int grid, int accumulate, hi
 hipError_t launch_sur_adam(const SurBufs& s, int64_t t, float lr, float beta1, float beta2, float eps,
                            hipStream_t st);
 hipError_t launch_sur_to_tag(const Geom& g, const Bufs& b, const float* src, float* dst, hipStream_t st);
+hipError_t launch_sur_from_tag(const Geom& g, const Bufs& b, const float* src, float* dst, hipStream_t st);
+hipError_t launch_sur_f_to_tag(const Geom& g, const Bufs& b, const float4* src, double* dst, hipStream_t st);
 hipError_t launch_step_ext(const StepArgs& a, const SurBufs& s, int bonded, hipStream_t st);
+
+// ------------------------------------------------------------------ batches
+
+// One system of a batch as the per-tile kernels see it.  Tiles of kBlock
+// particles never straddle systems; tile0 is the system's first global tile.
+struct SysEntry {
+    StepArgs a;             // parity / mode fields unused: kernel arguments
+    int64_t tile0;
+    int32_t ntiles;
+    int32_t bonded;
+    int64_t c_off;          // first cell in the concatenated cell arrays
+};
+
+// Concatenated cell arrays of a batch and the descriptor of their scan.
+struct BatchCells {
+    Geom gg;                // gg.ncell = all cells (each system's ncell + 1)
+    Bufs gb;                // gb.ccount / gb.cstart / gb.bsum / gb.ctl (any-rebuild flag)
+    const SysEntry* tab;    // device table (any parity)
+    int64_t* c_off;         // [nsys + 1] first cell per system
+    int32_t* base;          // [nsys] scan prefix at each system's first cell
+    int32_t nsys;
+};
+
+hipError_t launch_batch_rebuild(const BatchCells& bc, const SysEntry* tab, const int32_t* tile_sys, int64_t ntiles,
+                                int parity, hipStream_t s);
+hipError_t launch_batch_step(const SysEntry* tab, const int32_t* tile_sys, int64_t ntiles, int parity, int mode,
+                             int tensor, hipStream_t s);
+hipError_t launch_batch_finalize(const SysEntry* tab, int nsys, int mode, hipStream_t s);
+hipError_t launch_batch_gather_obs(const SysEntry* tab, int nsys, double* out, hipStream_t s);
 
 // launchers (md_kernels.hip)
 hipError_t launch_init_load(const Geom& g, const Bufs& b, int parity, const double* pos,

@@ -230,14 +230,15 @@ __global__ void __launch_bounds__(kBlock) k_copy_i32(int32_t* dst, const int32_t
 // rebuild, so the whole step can be enqueued (and graph-captured) without a
 // host round trip.
 
+__device__ __forceinline__ void bin_one(const Geom& g, const Bufs& b, int64_t i, int parity) {
+    const uint32_t c = cell_of(g, b.x[parity][i]);
+    b.cellid[i] = c;
+    atomicAdd(&b.ccount[c], 1);
+}
+
 __global__ void __launch_bounds__(kBlock) k_bin(Geom g, Bufs b, int parity) {
     if (!rebuild_requested(b)) return;
-    const double4* __restrict__ x = b.x[parity];
-    for (int64_t i = gtid(); i < g.n; i += gstride()) {
-        uint32_t c = cell_of(g, x[i]);
-        b.cellid[i] = c;
-        atomicAdd(&b.ccount[c], 1);
-    }
+    for (int64_t i = gtid(); i < g.n; i += gstride()) bin_one(g, b, i, parity);
 }
 
 __device__ int block_exclusive_scan(int v, int& total) {
@@ -322,22 +323,23 @@ __global__ void __launch_bounds__(kBlock) k_scan_apply(Geom g, Bufs b) {
 }
 
 // Scatter into cell segments; counts return to zero for the next build.
+__device__ __forceinline__ void scatter_one(const Bufs& b, int64_t i) {
+    const uint32_t c = b.cellid[i];
+    const int slot = b.cstart[c] + atomicSub(&b.ccount[c], 1) - 1;
+    b.tmp[slot] = (int32_t)i;
+}
+
 __global__ void __launch_bounds__(kBlock) k_scatter(Geom g, Bufs b) {
     if (!rebuild_requested(b)) return;
-    for (int64_t i = gtid(); i < g.n; i += gstride()) {
-        uint32_t c = b.cellid[i];
-        int slot = b.cstart[c] + atomicSub(&b.ccount[c], 1) - 1;
-        b.tmp[slot] = (int32_t)i;
-    }
+    for (int64_t i = gtid(); i < g.n; i += gstride()) scatter_one(b, i);
 }
 
 // Order inside a cell by particle tag: the sorted order is then a function
 // of the positions alone, so a run resumed from a saved build snapshot
 // reproduces it exactly.  Gathers all per-particle arrays into temporaries.
-__global__ void __launch_bounds__(kBlock) k_rank_permute(Geom g, Bufs b, int parity) {
-    if (!rebuild_requested(b)) return;
+__device__ __forceinline__ void permute_one(const Geom& g, const Bufs& b, int64_t s, int parity) {
     const int64_t n = g.n;
-    for (int64_t s = gtid(); s < n; s += gstride()) {
+    {
         int32_t i = b.tmp[s];
         uint32_t c = b.cellid[i];
         int32_t ti = b.tag[i];
@@ -354,14 +356,18 @@ __global__ void __launch_bounds__(kBlock) k_rank_permute(Geom g, Bufs b, int par
     }
 }
 
-__global__ void __launch_bounds__(kBlock) k_commit(Geom g, Bufs b, int parity, int bonded) {
+__global__ void __launch_bounds__(kBlock) k_rank_permute(Geom g, Bufs b, int parity) {
     if (!rebuild_requested(b)) return;
+    for (int64_t s = gtid(); s < g.n; s += gstride()) permute_one(g, b, s, parity);
+}
+
+__device__ __forceinline__ void commit_one(const Geom& g, const Bufs& b, int64_t s, int parity, int bonded) {
     const int64_t n = g.n;
-    if (gtid() == 0) {
+    if (s == 0) {
         b.ctl->n_rebuilds += 1;
         b.ctl->nl_max = 0;
     }
-    for (int64_t s = gtid(); s < n; s += gstride()) {
+    {
         double4 p = b.xt[s];
         b.x[parity][s] = p;
         b.xq[parity][s] = quantize4(g, p.x, p.y, p.z, p.w);
@@ -377,6 +383,11 @@ __global__ void __launch_bounds__(kBlock) k_commit(Geom g, Bufs b, int parity, i
         b.inv[t] = (int32_t)s;
         if (bonded) b.tcnt_s[s] = b.tcnt_t[t];
     }
+}
+
+__global__ void __launch_bounds__(kBlock) k_commit(Geom g, Bufs b, int parity, int bonded) {
+    if (!rebuild_requested(b)) return;
+    for (int64_t s = gtid(); s < g.n; s += gstride()) commit_one(g, b, s, parity, bonded);
 }
 
 // ------------------------------------------------------------------ rebuild: Verlet list
@@ -409,16 +420,14 @@ __device__ __forceinline__ int wrapc(int c, int nc) { return c < 0 ? c + nc : (c
 // rounding, so the sets are those of the FP64 definition.  Row order:
 // stencil (z, y, x offsets), then sorted index.  Also remaps the bonded
 // topology from tags to sorted indices.
-__global__ void __launch_bounds__(kBlock) k_nl_build(Geom g, Bufs b, int parity, int bonded) {
-    if (!rebuild_requested(b)) return;
+__device__ __forceinline__ void nl_one(const Geom& g, const Bufs& b, int64_t i, int parity, int bonded,
+                                       int& local_max, bool& overflow) {
     const int64_t n = g.n;
     const double4* __restrict__ x = b.x[parity];
     const int4* __restrict__ xq = b.xq[parity];
-    const float hx = (float)g.h[0], hy = (float)g.h[1], hz = (float)g.h[2];
+    const float hy = (float)g.h[1], hz = (float)g.h[2];
     const int kc = g.kc;
-    int local_max = 0;
-    bool overflow = false;
-    for (int64_t i = gtid_xcd(); i < n; i += gstride()) {
+    {
         const double4 xi = x[i];
         const int4 qi = xq[i];
         int cx, cy, cz;
@@ -505,12 +514,24 @@ __global__ void __launch_bounds__(kBlock) k_nl_build(Geom g, Bufs b, int parity,
             }
         }
     }
+}
+
+// Longest row and overflow flag, one atomic per wavefront.
+__device__ __forceinline__ void nl_epilogue(const Bufs& b, int local_max, bool overflow) {
     for (int o = 32; o >= 1; o >>= 1) {
         const int y = __shfl_xor(local_max, o, 64);
         local_max = y > local_max ? y : local_max;
     }
     if ((threadIdx.x & 63) == 0 && local_max > 0) atomicMax(&b.ctl->nl_max, local_max);
     if (__any(overflow) && (threadIdx.x & 63) == 0) atomicOr(&b.ctl->status, MD_FLAG_NL_OVERFLOW);
+}
+
+__global__ void __launch_bounds__(kBlock) k_nl_build(Geom g, Bufs b, int parity, int bonded) {
+    if (!rebuild_requested(b)) return;
+    int local_max = 0;
+    bool overflow = false;
+    for (int64_t i = gtid_xcd(); i < g.n; i += gstride()) nl_one(g, b, i, parity, bonded, local_max, overflow);
+    nl_epilogue(b, local_max, overflow);
 }
 
 __global__ void k_clear_rebuild(Bufs b) {
@@ -700,7 +721,12 @@ __device__ __forceinline__ void finish_particle(const StepArgs& a, int64_t i, co
 // Flags (one store or atomic per wave) and the deterministic block
 // reduction of the per-particle sums into partials[k][block].
 __device__ __forceinline__ void block_epilogue(const StepArgs& a, const double* acc, bool flag_reb,
-                                              bool flag_bond, bool flag_nf, int nacc) {
+                                              bool flag_bond, bool flag_nf, int nacc, int64_t slot = -1,
+                                              int64_t nslots = 0) {
+    if (slot < 0) {
+        slot = blockIdx.x;
+        nslots = gridDim.x;
+    }
     const Bufs& b = a.b;
     const bool any_reb = __any(flag_reb);
     const bool any_bond = __any(flag_bond);
@@ -721,7 +747,7 @@ __device__ __forceinline__ void block_epilogue(const StepArgs& a, const double* 
         double s = 0.0;
         if ((int)threadIdx.x < nacc)
             for (int ww = 0; ww < kBlock / 64; ++ww) s += red[ww][threadIdx.x];
-        b.partials[(int64_t)threadIdx.x * gridDim.x + blockIdx.x] = s;
+        b.partials[(int64_t)threadIdx.x * nslots + slot] = s;
     }
 }
 
@@ -915,21 +941,14 @@ __global__ void __launch_bounds__(kBlock) k_step_q(const StepArgs a) {
 //   F_i = -(24 eps / u) sum a b-weighted dq,  a = s6 (2 s6 - 1), b = a / r2
 //   U_i = 1/2 (4 eps sum s6 (s6 - 1) - n_in shift),  W_i = 1/2 24 eps sum a
 template <bool BONDED, bool TENSOR>
-__global__ void __launch_bounds__(kBlock) k_step_fast(const StepArgs a) {
+__device__ __forceinline__ void fast_particle(const StepArgs& a, int64_t i, double* acc, bool& flag_reb,
+                                              bool& flag_bond, bool& flag_nf) {
     const Geom& g = a.g;
     const Bufs& b = a.b;
     const int64_t n = g.n;
     const int4* __restrict__ xq = b.xq[a.parity];
     const double4* __restrict__ x64 = b.x[a.parity];
-    double acc[kNacc];
-#pragma unroll
-    for (int k = 0; k < kNacc; ++k) acc[k] = 0.0;
-    bool flag_reb = false, flag_bond = false, flag_nf = false;
-    const int64_t ntile = (n + kBlock - 1) / kBlock;
-    const int64_t bt = xcd_block(blockIdx.x, gridDim.x);
-    for (int64_t t = bt * ntile / gridDim.x; t < (bt + 1) * ntile / gridDim.x; ++t) {
-    const int64_t i = t * kBlock + threadIdx.x;
-    if (i < n) {
+    {
         const double4 xi = x64[i];
         const int4 qi = quantize4(g, xi.x, xi.y, xi.z, xi.w);  // equals xq[i]: same function
         const FastCoef& fc = a.fast;
@@ -1022,6 +1041,20 @@ __global__ void __launch_bounds__(kBlock) k_step_fast(const StepArgs a) {
         const double F[3] = {(double)fx, (double)fy, (double)fz};
         finish_particle(a, i, xi, 0, F, acc, flag_reb, flag_nf);
     }
+}
+
+template <bool BONDED, bool TENSOR>
+__global__ void __launch_bounds__(kBlock) k_step_fast(const StepArgs a) {
+    const int64_t n = a.g.n;
+    double acc[kNacc];
+#pragma unroll
+    for (int k = 0; k < kNacc; ++k) acc[k] = 0.0;
+    bool flag_reb = false, flag_bond = false, flag_nf = false;
+    const int64_t ntile = (n + kBlock - 1) / kBlock;
+    const int64_t bt = xcd_block(blockIdx.x, gridDim.x);
+    for (int64_t t = bt * ntile / gridDim.x; t < (bt + 1) * ntile / gridDim.x; ++t) {
+        const int64_t i = t * kBlock + threadIdx.x;
+        if (i < n) fast_particle<BONDED, TENSOR>(a, i, acc, flag_reb, flag_bond, flag_nf);
     }
     block_epilogue(a, acc, flag_reb, flag_bond, flag_nf, TENSOR ? kNacc : A_VIR + 1);
 }
@@ -1065,7 +1098,7 @@ __global__ void __launch_bounds__(kBlock) k_step_ext(const StepArgs a, const flo
 // observables, and (MODE_STEP) advance the step counter and move the
 // rebuild request to the next step.
 constexpr int kFinal = 1024;
-__global__ void __launch_bounds__(kFinal) k_finalize(Bufs b, int nblocks, int mode, const double* spart) {
+__device__ __forceinline__ void finalize_body(const Bufs& b, int nblocks, int mode, const double* spart) {
     __shared__ double red[kFinal / 64][kNacc];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     double s[kNacc];
@@ -1133,6 +1166,134 @@ __global__ void __launch_bounds__(kFinal) k_finalize(Bufs b, int nblocks, int mo
             c->rebuild = 0;
         }
     }
+}
+
+__global__ void __launch_bounds__(kFinal) k_finalize(Bufs b, int nblocks, int mode, const double* spart) {
+    finalize_body(b, nblocks, mode, spart);
+}
+
+// ------------------------------------------------------------------ batches
+//
+// Per-tile kernels of a batch: block -> global tile (XCD-aware order) ->
+// system -> the single-system body on that system's arrays.  The rebuild
+// kernels return at once for systems whose own rebuild flag is clear.
+
+struct TileRef {
+    const SysEntry* e;
+    int64_t lt;     // tile inside the system
+    int64_t i;      // particle inside the system
+};
+
+__device__ __forceinline__ TileRef tile_ref(const SysEntry* __restrict__ tab, const int32_t* __restrict__ tile_sys) {
+    const int64_t t = xcd_block(blockIdx.x, gridDim.x);
+    const SysEntry* e = tab + tile_sys[t];
+    const int64_t lt = t - e->tile0;
+    return TileRef{e, lt, lt * kBlock + threadIdx.x};
+}
+
+__global__ void k_batch_any(BatchCells bc) {
+    __shared__ int any;
+    if (threadIdx.x == 0) any = 0;
+    __syncthreads();
+    for (int s = threadIdx.x; s < bc.nsys; s += blockDim.x)
+        if (rebuild_requested(bc.tab[s].a.b)) any = 1;
+    __syncthreads();
+    if (threadIdx.x == 0) bc.gb.ctl->rebuild = (uint32_t)any;
+}
+
+__global__ void __launch_bounds__(kBlock) k_batch_bin(const SysEntry* __restrict__ tab,
+                                                      const int32_t* __restrict__ tile_sys, int parity) {
+    const TileRef r = tile_ref(tab, tile_sys);
+    const Bufs& b = r.e->a.b;
+    if (!rebuild_requested(b)) return;
+    const Geom& g = r.e->a.g;
+    if (r.i < g.n) bin_one(g, b, r.i, parity);
+}
+
+// prefix of the concatenated counts at each system's first cell
+__global__ void k_batch_bases(BatchCells bc) {
+    if (!rebuild_requested(bc.gb)) return;
+    for (int s = threadIdx.x; s < bc.nsys; s += blockDim.x) bc.base[s] = bc.gb.cstart[bc.c_off[s]];
+}
+
+// cell starts of rebuilding systems become offsets inside the system
+__global__ void __launch_bounds__(kBlock) k_batch_localize(BatchCells bc) {
+    if (!rebuild_requested(bc.gb)) return;
+    for (int64_t c = gtid(); c < bc.gg.ncell; c += gstride()) {
+        int lo = 0, hi = bc.nsys;   // system with c_off[s] <= c < c_off[s + 1]
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (bc.c_off[mid] <= c) lo = mid; else hi = mid;
+        }
+        if (rebuild_requested(bc.tab[lo].a.b)) bc.gb.cstart[c] -= bc.base[lo];
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_batch_scatter(const SysEntry* __restrict__ tab,
+                                                          const int32_t* __restrict__ tile_sys) {
+    const TileRef r = tile_ref(tab, tile_sys);
+    const Bufs& b = r.e->a.b;
+    if (!rebuild_requested(b)) return;
+    if (r.i < r.e->a.g.n) scatter_one(b, r.i);
+}
+
+__global__ void __launch_bounds__(kBlock) k_batch_permute(const SysEntry* __restrict__ tab,
+                                                          const int32_t* __restrict__ tile_sys, int parity) {
+    const TileRef r = tile_ref(tab, tile_sys);
+    const Bufs& b = r.e->a.b;
+    if (!rebuild_requested(b)) return;
+    const Geom& g = r.e->a.g;
+    if (r.i < g.n) permute_one(g, b, r.i, parity);
+}
+
+__global__ void __launch_bounds__(kBlock) k_batch_commit(const SysEntry* __restrict__ tab,
+                                                         const int32_t* __restrict__ tile_sys, int parity) {
+    const TileRef r = tile_ref(tab, tile_sys);
+    const Bufs& b = r.e->a.b;
+    if (!rebuild_requested(b)) return;
+    const Geom& g = r.e->a.g;
+    if (r.i < g.n) commit_one(g, b, r.i, parity, r.e->bonded);
+}
+
+__global__ void __launch_bounds__(kBlock) k_batch_nl(const SysEntry* __restrict__ tab,
+                                                     const int32_t* __restrict__ tile_sys, int parity) {
+    const TileRef r = tile_ref(tab, tile_sys);
+    const Bufs& b = r.e->a.b;
+    if (!rebuild_requested(b)) return;
+    const Geom& g = r.e->a.g;
+    int local_max = 0;
+    bool overflow = false;
+    if (r.i < g.n) nl_one(g, b, r.i, parity, r.e->bonded, local_max, overflow);
+    nl_epilogue(b, local_max, overflow);
+}
+
+// Fused force + integrate for one tile of one system (FP32 fast path: one
+// particle type, cubic box, no capping radius), partials at the tile's slot.
+// The table holds each system's arguments for one (mode, parity); they are
+// read in place, never copied.
+template <bool TENSOR>
+__global__ void __launch_bounds__(kBlock) k_batch_step(const SysEntry* __restrict__ tab,
+                                                       const int32_t* __restrict__ tile_sys) {
+    const TileRef r = tile_ref(tab, tile_sys);
+    const StepArgs& a = r.e->a;
+    double acc[kNacc];
+#pragma unroll
+    for (int k = 0; k < kNacc; ++k) acc[k] = 0.0;
+    bool flag_reb = false, flag_bond = false, flag_nf = false;
+    if (r.i < a.g.n) {
+        if (r.e->bonded) fast_particle<true, TENSOR>(a, r.i, acc, flag_reb, flag_bond, flag_nf);
+        else fast_particle<false, TENSOR>(a, r.i, acc, flag_reb, flag_bond, flag_nf);
+    }
+    block_epilogue(a, acc, flag_reb, flag_bond, flag_nf, TENSOR ? kNacc : A_VIR + 1, r.lt, r.e->ntiles);
+}
+
+__global__ void __launch_bounds__(kFinal) k_batch_finalize(const SysEntry* __restrict__ tab, int mode) {
+    const SysEntry& e = tab[blockIdx.x];
+    finalize_body(e.a.b, e.ntiles, mode, nullptr);
+}
+
+__global__ void k_batch_gather_obs(const SysEntry* __restrict__ tab, int nsys, double* out) {
+    for (int k = threadIdx.x; k < nsys * kHistRec; k += blockDim.x) out[k] = tab[k / kHistRec].a.b.cur[k % kHistRec];
 }
 
 // ------------------------------------------------------------------ launchers
@@ -1254,6 +1415,48 @@ hipError_t launch_step_ext(const StepArgs& a, const SurBufs& sb, int bonded, hip
         hipLaunchKernelGGL(k_step_ext<true>, grid, blk, 0, s, a, sb.f);
     else
         hipLaunchKernelGGL(k_step_ext<false>, grid, blk, 0, s, a, sb.f);
+    return hipGetLastError();
+}
+
+}  // namespace md
+
+namespace md {
+
+hipError_t launch_batch_rebuild(const BatchCells& bc, const SysEntry* tab, const int32_t* tile_sys, int64_t ntiles,
+                                int parity, hipStream_t s) {
+    const dim3 tg((unsigned)ntiles), blk(kBlock);
+    hipLaunchKernelGGL(k_batch_any, dim3(1), dim3(256), 0, s, bc);
+    hipLaunchKernelGGL(k_batch_bin, tg, blk, 0, s, tab, tile_sys, parity);
+    hipLaunchKernelGGL(k_scan_reduce, dim3(kScanBlocks), dim3(kBlock), 0, s, bc.gg, bc.gb);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanBlocks), 0, s, bc.gb);
+    hipLaunchKernelGGL(k_scan_apply, dim3(kScanBlocks), dim3(kBlock), 0, s, bc.gg, bc.gb);
+    hipLaunchKernelGGL(k_batch_bases, dim3(1), dim3(256), 0, s, bc);
+    hipLaunchKernelGGL(k_batch_localize, dim3(grid_for(bc.gg.ncell, 4096)), blk, 0, s, bc);
+    hipLaunchKernelGGL(k_batch_scatter, tg, blk, 0, s, tab, tile_sys);
+    hipLaunchKernelGGL(k_batch_permute, tg, blk, 0, s, tab, tile_sys, parity);
+    hipLaunchKernelGGL(k_batch_commit, tg, blk, 0, s, tab, tile_sys, parity);
+    hipLaunchKernelGGL(k_batch_nl, tg, blk, 0, s, tab, tile_sys, parity);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_step(const SysEntry* tab, const int32_t* tile_sys, int64_t ntiles, int parity, int mode,
+                             int tensor, hipStream_t s) {
+    (void)parity;
+    (void)mode;
+    if (tensor)
+        hipLaunchKernelGGL(k_batch_step<true>, dim3((unsigned)ntiles), dim3(kBlock), 0, s, tab, tile_sys);
+    else
+        hipLaunchKernelGGL(k_batch_step<false>, dim3((unsigned)ntiles), dim3(kBlock), 0, s, tab, tile_sys);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_finalize(const SysEntry* tab, int nsys, int mode, hipStream_t s) {
+    hipLaunchKernelGGL(k_batch_finalize, dim3(nsys), dim3(kFinal), 0, s, tab, mode);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_gather_obs(const SysEntry* tab, int nsys, double* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_batch_gather_obs, dim3(1), dim3(256), 0, s, tab, nsys, out);
     return hipGetLastError();
 }
 

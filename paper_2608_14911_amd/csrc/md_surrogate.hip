@@ -646,6 +646,26 @@ __global__ void __launch_bounds__(kBlock) k_sur_to_tag(Geom g, Bufs b, const flo
     }
 }
 
+__global__ void __launch_bounds__(kBlock) k_sur_from_tag(Geom g, Bufs b, const float* src, float* dst) {
+    for (int64_t i = gtid(); i < g.n; i += gstride()) {
+        const int64_t t = b.tag[i];
+        const float4* a = reinterpret_cast<const float4*>(src + t * kSurNB);
+        float4* o = reinterpret_cast<float4*>(dst + i * kSurNB);
+#pragma unroll
+        for (int q = 0; q < kSurNB / 4; ++q) o[q] = a[q];
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_sur_f_to_tag(Geom g, Bufs b, const float4* src, double* dst) {
+    for (int64_t i = gtid(); i < g.n; i += gstride()) {
+        const int64_t t = b.tag[i];
+        const float4 f = src[i];
+        dst[3 * t] = f.x;
+        dst[3 * t + 1] = f.y;
+        dst[3 * t + 2] = f.z;
+    }
+}
+
 // ------------------------------------------------------------------ launchers
 
 static inline int sgrid(int64_t n, int cap_blocks) {
@@ -732,4 +752,16 @@ hipError_t launch_sur_to_tag(const Geom& g, const Bufs& b, const float* src, flo
     return hipGetLastError();
 }
 
+}  // namespace md
+
+namespace md {
+hipError_t launch_sur_from_tag(const Geom& g, const Bufs& b, const float* src, float* dst, hipStream_t st) {
+    hipLaunchKernelGGL(k_sur_from_tag, dim3(sgrid(g.n, 4096)), dim3(kBlock), 0, st, g, b, src, dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_sur_f_to_tag(const Geom& g, const Bufs& b, const float4* src, double* dst, hipStream_t st) {
+    hipLaunchKernelGGL(k_sur_f_to_tag, dim3(sgrid(g.n, 4096)), dim3(kBlock), 0, st, g, b, src, dst);
+    return hipGetLastError();
+}
 }  // namespace md

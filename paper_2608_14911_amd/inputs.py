@@ -172,3 +172,47 @@ def mlp_init(seed=1004, n_in=32, hidden=64):
     W2 = g.uniform(-1.0, 1.0, size=(hidden, hidden)) * np.sqrt(6.0 / hidden)
     w3 = g.uniform(-1.0, 1.0, size=hidden) * np.sqrt(6.0 / hidden)
     return np.concatenate([W1.ravel(), np.zeros(hidden), W2.ravel(), np.zeros(hidden), w3, np.zeros(1)])
+
+
+def batch_replicas(nsys=256, seed=1003, n_min=2048, n_max=65536):
+    """Replicas of uneven size for a batch.  From stream 3 of ``seed``, per
+    replica r: N = round(exp(U[ln n_min, ln n_max])), density U[0.70, 0.90],
+    temperature U[0.7, 1.2], and for the melts a chain length U{10..200}.
+    Even r: LJ fluid (rc 2.5 shifted, NVE, dt 0.005, skin 0.3) started from a
+    random subset of ceil((N/4)^(1/3))^3 * 4 FCC sites rescaled to the
+    density, jitter 0.05.  Odd r: Kremer-Grest melt (WCA + FENE + bending
+    1.5, Langevin gamma 0.5, dt 0.01, skin 0.4) of round(N / L_c) random
+    walks (raw: a push-off is needed).  Each replica's own positions and
+    velocities come from seed 100000 * seed + r (streams 1 and 2)."""
+    g = rng(seed, STREAM_BATCH)
+    out = []
+    for r in range(nsys):
+        n = int(round(math.exp(g.uniform(math.log(n_min), math.log(n_max)))))
+        rho = float(g.uniform(0.70, 0.90))
+        temp = float(g.uniform(0.7, 1.2))
+        lc = int(g.integers(10, 201))
+        sub = 100000 * seed + r
+        if r % 2 == 0:
+            nc = int(math.ceil((n / 4.0) ** (1.0 / 3.0)))
+            L = (n / rho) ** (1.0 / 3.0)
+            sites, _ = fcc_lattice(nc, 4.0 * nc ** 3 / L ** 3)
+            gp = rng(sub, STREAM_POS)
+            pick = gp.choice(sites.shape[0], size=n, replace=False)
+            pos = sites[np.sort(pick)] + gp.uniform(-0.05, 0.05, size=(n, 3))
+            box = np.array([L, L, L])
+            out.append({"kind": "lj", "pos": wrap_into_box(pos, box), "box": box,
+                        "vel": maxwell_boltzmann(n, temp, seed=sub), "bonds": None, "angles": None,
+                        "pair": {(0, 0): (1.0, 1.0, 2.5, float("nan"), 0.0)}, "dt": 0.005, "skin": 0.3,
+                        "integrator": "nve", "temperature": temp, "gamma": 0.0, "seed": sub, "k_bend": 0.0,
+                        "density": rho})
+        else:
+            nch = max(1, int(round(n / lc)))
+            w = random_walk_chains(nch, lc, rho, bond=0.97, seed=sub)
+            n = nch * lc
+            out.append({"kind": "kg", "pos": w["pos"], "box": w["box"],
+                        "vel": maxwell_boltzmann(n, temp, seed=sub, zero_momentum=False, exact=False),
+                        "bonds": w["bonds"], "angles": w["angles"],
+                        "pair": {(0, 0): (1.0, 1.0, WCA_RC, float("nan"), 0.0)}, "dt": 0.01, "skin": 0.4,
+                        "integrator": "langevin", "temperature": temp, "gamma": 0.5, "seed": sub, "k_bend": 1.5,
+                        "density": rho, "chain_len": lc})
+    return out

@@ -55,7 +55,10 @@ EXPORTED = ["md_workspace_bytes", "md_init", "md_set_params", "md_build_neighbor
             "md_step", "md_observables", "md_history", "md_get_state", "md_set_state",
             "md_get_neighbors", "md_status_check", "md_timing_enable", "md_timing_read",
             "md_destroy", "md_status_string", "md_last_error", "md_sur_set", "md_sur_get",
-            "md_set_pair_mode", "md_sur_descriptors", "md_sur_mlp_eval", "md_sur_loss_grad", "md_sur_adam"]
+            "md_set_pair_mode", "md_sur_descriptors", "md_sur_mlp_eval", "md_sur_pair_forces", "md_sur_loss_grad",
+            "md_sur_adam", "md_batch_workspace_bytes", "md_batch_init", "md_batch_step",
+            "md_batch_observables", "md_batch_get_state", "md_batch_destroy", "md_batch_last_error",
+            "md_batch_timing_enable", "md_batch_timing_read"]
 
 
 class md_pair_params(ctypes.Structure):
@@ -136,6 +139,7 @@ def lib():
         "md_set_pair_mode": [P, I32],
         "md_sur_descriptors": [P, P],
         "md_sur_mlp_eval": [P, P, I64, P, P],
+        "md_sur_pair_forces": [P, P, P],
         "md_sur_loss_grad": [P, P, P, I32, P, ctypes.POINTER(ctypes.c_double)],
         "md_sur_adam": [P, I64, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double],
     }
@@ -143,6 +147,21 @@ def lib():
         f = getattr(L, name)
         f.argtypes = args
         f.restype = ctypes.c_int32
+    for name, args in {
+        "md_batch_workspace_bytes": [P, I32, ctypes.POINTER(SZ)],
+        "md_batch_init": [P, I32, P, P, P, P, P, P, SZ, P, ctypes.POINTER(P)],
+        "md_batch_step": [P, I64],
+        "md_batch_observables": [P, P],
+        "md_batch_get_state": [P, I32, P, P, P, P, ctypes.POINTER(I64), ctypes.POINTER(I32)],
+        "md_batch_destroy": [P],
+        "md_batch_timing_enable": [P, I32],
+        "md_batch_timing_read": [P, ctypes.POINTER(md_timing)],
+    }.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = ctypes.c_int32
+    L.md_batch_last_error.argtypes = [P]
+    L.md_batch_last_error.restype = ctypes.c_char_p
     L.md_status_string.argtypes = [ctypes.c_int32]
     L.md_status_string.restype = ctypes.c_char_p
     L.md_last_error.argtypes = [P]
@@ -317,3 +336,89 @@ def md_sur_loss_grad(h, frames, f_ref, nf, grad=None, want_loss=True):
 
 def md_sur_adam(h, t, lr, beta1=0.9, beta2=0.999, eps=1e-8):
     _check(lib().md_sur_adam(h, int(t), float(lr), float(beta1), float(beta2), float(eps)), "md_sur_adam", h)
+
+
+def md_sur_pair_forces(h, dedg, f_out):
+    _check(lib().md_sur_pair_forces(h, _p(dedg), _p(f_out)), "md_sur_pair_forces", h)
+
+
+# ------------------------------------------------------------------ batches
+def _bcheck(code, fn, b=None):
+    if code != MD_OK:
+        raise MDError(code, fn, lib().md_batch_last_error(b).decode())
+
+
+def _ptr_array(ptrs):
+    return (ctypes.c_void_p * len(ptrs))(*[None if p is None else int(p) for p in ptrs])
+
+
+def md_batch_workspace_bytes(cfgs):
+    arr = (md_config * len(cfgs))(*cfgs)
+    n = ctypes.c_size_t()
+    _bcheck(lib().md_batch_workspace_bytes(ctypes.cast(arr, ctypes.c_void_p), len(cfgs), ctypes.byref(n)),
+            "md_batch_workspace_bytes")
+    return n.value
+
+
+def md_batch_init(cfgs, pos_ptrs, vel_ptrs, masses, bonds, angles, workspace, ws_bytes, stream):
+    """masses / bonds / angles: lists of host numpy arrays (bonds / angles
+    entries may be None)."""
+    nsys = len(cfgs)
+    arr = (md_config * nsys)(*cfgs)
+    keep = []
+
+    def host_list(xs, dtype):
+        if xs is None:
+            return None
+        out = []
+        for x in xs:
+            if x is None:
+                out.append(None)
+            else:
+                a = np.ascontiguousarray(x, dtype=dtype)
+                keep.append(a)
+                out.append(a.ctypes.data)
+        return _ptr_array(out)
+
+    m = host_list(masses, np.float64)
+    bp = host_list(bonds, np.int32)
+    ap = host_list(angles, np.int32)
+    h = ctypes.c_void_p()
+    code = lib().md_batch_init(ctypes.cast(arr, ctypes.c_void_p), nsys, _ptr_array(pos_ptrs), _ptr_array(vel_ptrs),
+                               m, bp, ap, _p(workspace), ws_bytes, _p(stream), ctypes.byref(h))
+    _bcheck(code, "md_batch_init")
+    return h
+
+
+def md_batch_step(b, nsteps):
+    _bcheck(lib().md_batch_step(b, int(nsteps)), "md_batch_step", b)
+
+
+def md_batch_observables(b, nsys, check=True):
+    arr = (md_obs * nsys)()
+    code = lib().md_batch_observables(b, ctypes.cast(arr, ctypes.c_void_p))
+    if check:
+        _bcheck(code, "md_batch_observables", b)
+    return [arr[k].as_dict() for k in range(nsys)]
+
+
+def md_batch_get_state(b, sys, pos, vel, image=None, pos_build=None):
+    step = ctypes.c_int64()
+    vh = ctypes.c_int32()
+    _bcheck(lib().md_batch_get_state(b, int(sys), _p(pos), _p(vel), _p(image), _p(pos_build), ctypes.byref(step),
+                                     ctypes.byref(vh)), "md_batch_get_state", b)
+    return step.value, vh.value
+
+
+def md_batch_destroy(b):
+    _bcheck(lib().md_batch_destroy(b), "md_batch_destroy")
+
+
+def md_batch_timing_enable(b, enable):
+    _bcheck(lib().md_batch_timing_enable(b, int(bool(enable))), "md_batch_timing_enable", b)
+
+
+def md_batch_timing_read(b):
+    t = md_timing()
+    _bcheck(lib().md_batch_timing_read(b, ctypes.byref(t)), "md_batch_timing_read", b)
+    return {k: getattr(t, k) for k, _ in t._fields_}

@@ -101,15 +101,16 @@ class System:
                 "pos_build": pb.cpu().numpy(), "step": step, "vel_half": vh}
 
     def set_state(self, state, with_build=True):
+        """Replace the state; arrays may be numpy or torch tensors."""
         t = self.torch
-        pos = t.as_tensor(np.ascontiguousarray(state["pos"], dtype=np.float64), device=self.device)
-        vel = t.as_tensor(np.ascontiguousarray(state["vel"], dtype=np.float64), device=self.device)
+        pos = self._dev(state["pos"], t.float64)
+        vel = self._dev(state["vel"], t.float64)
         img = None
         if state.get("image") is not None:
-            img = t.as_tensor(np.ascontiguousarray(state["image"], dtype=np.int32), device=self.device)
+            img = self._dev(state["image"], t.int32)
         pb = None
         if with_build and state.get("pos_build") is not None:
-            pb = t.as_tensor(np.ascontiguousarray(state["pos_build"], dtype=np.float64), device=self.device)
+            pb = self._dev(state["pos_build"], t.float64)
         md.md_set_state(self.h, pos.data_ptr(), vel.data_ptr(), None if img is None else img.data_ptr(),
                         None if pb is None else pb.data_ptr(), state.get("step", 0), state.get("vel_half", 0))
         self.stream.synchronize()
@@ -177,6 +178,15 @@ class System:
         self.stream.synchronize()
         return e, a
 
+    def sur_pair_forces(self, dedg):
+        """Surrogate pair forces at the current positions for given
+        per-particle input gradients dedg [N, 32] (device FP64 [N, 3])."""
+        t = self.torch
+        a = self._dev(dedg, t.float32)
+        f = t.zeros((self.n, 3), dtype=t.float64, device=self.device)
+        md.md_sur_pair_forces(self.h, a.data_ptr(), f.data_ptr())
+        return f
+
     def loss_grad(self, frames, f_ref, want_grad=True):
         """Force-matching loss over device frames [nf, N, 3] (FP64) and
         reference forces [nf, N, 3] (FP64); returns (loss, grad or None)."""
@@ -194,6 +204,110 @@ class System:
     def close(self):
         if not self._closed:
             md.md_destroy(self.h)
+            self._closed = True
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def prepare_replica(m, log=None):
+    """Push off a raw Kremer-Grest replica on the GPU (capped WCA ladder, then
+    200 steps at its own run parameters); returns the member dict with the
+    new positions and velocities.  LJ replicas are returned unchanged."""
+    if m.get("kind") != "kg":
+        return m
+    rc = m["pair"][(0, 0)][2]
+    s = System(m["pos"], m["box"], np.zeros_like(m["pos"]), pair={(0, 0): lj_pair(rc=rc, caprad=1.0)},
+               bonds=m["bonds"], angles=m["angles"], k_bend=m["k_bend"], dt=0.002, skin=m["skin"],
+               integrator="langevin", temperature=m["temperature"], gamma=1.0, seed=m["seed"], nl_capacity=256)
+    push_off(s, rc, chunk=1000, log=log)
+    s.set_params(dt=m["dt"], gamma=m["gamma"])
+    s.step(200)
+    st = s.get_state()
+    code = s.status()
+    s.close()
+    if code != 0:
+        raise RuntimeError("replica push-off failed: %s" % md.status_string(code))
+    out = dict(m)
+    out["pos"], out["vel"] = st["pos"], st["vel"]
+    return out
+
+
+class Batch:
+    """Many independent systems advanced together (md_batch_*).
+
+    ``members``: list of dicts with the keys of ``System`` (pos, box, vel,
+    pair, bonds, angles, dt, skin, integrator, temperature, gamma, seed,
+    k_bend, cell_factor, nl_capacity, masses)."""
+
+    def __init__(self, members, device="cuda"):
+        torch = _torch()
+        self.torch = torch
+        self.device = torch.device(device)
+        self.cfgs, self._keep, pos_p, vel_p, masses, bonds, angles = [], [], [], [], [], [], []
+        self.n = []
+        for m in members:
+            pos = np.ascontiguousarray(m["pos"], dtype=np.float64)
+            n = pos.shape[0]
+            vel = m.get("vel")
+            vel = np.zeros_like(pos) if vel is None else np.ascontiguousarray(vel, dtype=np.float64)
+            b, a = m.get("bonds"), m.get("angles")
+            integ = md.MD_LANGEVIN if m.get("integrator", "nve") == "langevin" else md.MD_NVE
+            cfg = md.make_config(n, m["box"], pair=m.get("pair"), dt=m.get("dt", 0.005), skin=m.get("skin", 0.3),
+                                 integrator=integ, force_precision=md.MD_FP32,
+                                 temperature=m.get("temperature", 1.0), gamma=m.get("gamma", 0.0),
+                                 seed=m.get("seed", 0), n_bonds=0 if b is None else len(b),
+                                 n_angles=0 if a is None else len(a), fene_K=m.get("fene_K", 30.0),
+                                 fene_R0=m.get("fene_R0", 1.5), k_bend=m.get("k_bend", 0.0),
+                                 nl_capacity=m.get("nl_capacity", 0), cell_factor=m.get("cell_factor", 0))
+            dp = torch.as_tensor(pos, device=self.device)
+            dv = torch.as_tensor(vel, device=self.device)
+            self._keep += [dp, dv]
+            self.cfgs.append(cfg)
+            pos_p.append(dp.data_ptr())
+            vel_p.append(dv.data_ptr())
+            masses.append(np.asarray(m.get("masses", (1.0,)), dtype=np.float64))
+            bonds.append(b)
+            angles.append(a)
+            self.n.append(n)
+        self.nsys = len(members)
+        self.ws_bytes = md.md_batch_workspace_bytes(self.cfgs)
+        self._ws_raw = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
+        self.ws_ptr = (self._ws_raw.data_ptr() + 255) & ~255
+        self.stream = torch.cuda.current_stream(self.device)
+        self.h = md.md_batch_init(self.cfgs, pos_p, vel_p, masses, bonds, angles, self.ws_ptr, self.ws_bytes,
+                                  self.stream.cuda_stream)
+        self._keep = []
+        self._closed = False
+
+    def step(self, n):
+        md.md_batch_step(self.h, n)
+
+    def observables(self, check=True):
+        return md.md_batch_observables(self.h, self.nsys, check)
+
+    def timing(self, enable=None):
+        if enable is not None:
+            md.md_batch_timing_enable(self.h, enable)
+            return None
+        return md.md_batch_timing_read(self.h)
+
+    def get_state(self, s):
+        t = self.torch
+        n = self.n[s]
+        z = lambda dt_: t.zeros((n, 3), dtype=dt_, device=self.device)
+        pos, vel, pb, img = z(t.float64), z(t.float64), z(t.float64), z(t.int32)
+        step, vh = md.md_batch_get_state(self.h, s, pos.data_ptr(), vel.data_ptr(), img.data_ptr(), pb.data_ptr())
+        self.stream.synchronize()
+        return {"pos": pos.cpu().numpy(), "vel": vel.cpu().numpy(), "image": img.cpu().numpy(),
+                "pos_build": pb.cpu().numpy(), "step": step, "vel_half": vh}
+
+    def close(self):
+        if not self._closed:
+            md.md_batch_destroy(self.h)
             self._closed = True
 
     def __del__(self):

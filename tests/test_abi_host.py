@@ -8,6 +8,7 @@ import os
 import re
 import subprocess
 
+import numpy as np
 import pytest
 
 from paper_2608_14911_amd import md
@@ -175,3 +176,43 @@ def test_surrogate_calls_reject_null_handle():
     assert lib.md_set_pair_mode(None, 1) == md.MD_ERR_ARG
     assert lib.md_sur_adam(None, 1, 1e-3, 0.9, 0.999, 1e-8) == md.MD_ERR_ARG
     assert lib.md_sur_loss_grad(None, None, None, 1, None, None) == md.MD_ERR_ARG
+
+
+def test_batch_workspace_and_member_validation():
+    a = lj_cfg(4000)
+    b = md.make_config(1000, [10.5567] * 3, pair={(0, 0): (1.0, 1.0, 2 ** (1 / 6), math.nan, 0.0)},
+                       n_bonds=980, skin=0.4)
+    both = md.md_batch_workspace_bytes([a, b])
+    # each member's workspace without its own cell arrays, plus shared cells and tables
+    assert both > md.md_batch_workspace_bytes([a]) > 0
+    assert both > md.md_workspace_bytes(b)
+    bad = [lj_cfg(4000, force_precision=md.MD_FP64),
+           lj_cfg(4000, pair={(0, 0): (1.0, 1.0, 2.5, math.nan, 0.9)}),
+           md.make_config(4000, [20.0, 20.0, 21.0]),
+           md.make_config(4000, [20.0] * 3, n_types=2,
+                          pair={(0, 0): (1, 1, 2.5, math.nan, 0), (0, 1): (1, 1, 2.5, math.nan, 0),
+                                (1, 1): (1, 1, 2.5, math.nan, 0)})]
+    for c in bad:
+        with pytest.raises(md.MDError):
+            md.md_batch_workspace_bytes([a, c])
+    with pytest.raises(md.MDError):
+        md.md_batch_workspace_bytes([])
+
+
+def test_batch_replica_sampler_matches_its_definition():
+    from paper_2608_14911_amd import inputs
+    reps = inputs.batch_replicas(256, seed=1003)
+    ns = np.array([r["pos"].shape[0] for r in reps])
+    assert len(reps) == 256 and sum(r["kind"] == "kg" for r in reps) == 128
+    assert ns.min() >= 2048 // 2 and ns.max() <= 65536 + 200
+    assert 4.0e6 < ns.sum() < 5.5e6
+    for r in reps:
+        L = r["box"][0]
+        rho = r["pos"].shape[0] / L ** 3
+        assert abs(rho - r["density"]) < 1e-9 * rho
+        assert 0.70 <= r["density"] <= 0.90 and 0.7 <= r["temperature"] <= 1.2
+        assert (r["pos"] >= 0).all() and (r["pos"] < L).all()
+        if r["kind"] == "kg":
+            assert 10 <= r["chain_len"] <= 200 and r["pos"].shape[0] % r["chain_len"] == 0
+    # log-uniform sizes: the median is near the geometric mean of the range
+    assert 6000 < np.median(ns) < 17000

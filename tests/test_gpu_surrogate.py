@@ -196,3 +196,50 @@ def test_surrogate_nve_conserves_its_energy():
     assert s.status() == 0
     assert abs(et[-1] - et[0]) < 0.02 * ek.std() * 10 and et.std() < 0.05 * ek.std()
     s.close()
+
+
+def test_pair_forces_of_a_linear_readout():
+    """A constant input gradient c (a linear readout of G) gives pair-potential
+    forces linear in c; compared with the oracle's pair forces."""
+    w, pos, box = melt()
+    banner("surrogate pair forces, constant input gradient")
+    s = sur_system(w, pos, bonded=False)
+    c = np.random.default_rng(2).normal(size=32)
+    a = np.tile(c, (pos.shape[0], 1)).astype(np.float32)
+    F = s.sur_pair_forces(a).cpu().numpy()
+    Fo, W, fs = S.pair_forces(a.astype(np.float64), pos, box, want_fscale=True)
+    err = np.linalg.norm(F - Fo) / np.linalg.norm(Fo)
+    print("linear readout forces rel err %.3g" % err)
+    assert err < 1e-5
+    assert (np.linalg.norm(F - Fo, axis=1) <= 1e-5 * fs + 1e-12).all()
+    # linearity in c
+    F2 = s.sur_pair_forces(2.0 * a).cpu().numpy()
+    assert np.abs(F2 - 2.0 * F).max() <= 1e-6 * np.abs(F).max()
+    s.close()
+
+
+def test_trained_network_gains_over_the_untrained_one():
+    """Force matching on frames of a plain-method run: the trained network's
+    held-out force RMSE is well below the untrained one's.  The linear
+    readout of the descriptors (a pair potential) is reported beside it:
+    the target, WCA, is itself a pair potential."""
+    from paper_2608_14911_amd import surrogate_experiment as X
+    banner("surrogate gain: 10,000 beads, 24 frames")
+    w, frames, fref = X.make_dataset(10, 1000, 24, 50, seed=77)
+    ftr, rtr, fva, rva = frames[:20], fref[:20], frames[20:], fref[20:]
+    s = System(frames[0].cpu().numpy(), w["box"], pair={(0, 0): lj_pair(rc=WCA)}, skin=0.4, list_cutoff=S.RD,
+               surrogate=True)
+    mean, istd = X.descriptor_stats(s, ftr)
+    th0 = inputs.mlp_init(77)
+    s.sur_set(th0, mean, istd, "fp32")
+    r0 = X.rmse(s, fva, rva)
+    X.train(s, th0, mean, istd, "bf16", ftr, rtr, epochs=12, lr0=3e-3, seed=77)
+    r1 = X.rmse(s, fva, rva)
+    c = X.linear_readout(s, ftr, rtr, 8)
+    rl = X.linear_rmse(s, c, fva, rva)
+    rms = float((rva * rva).mean().sqrt())
+    print("held-out force RMSE / RMS F_ref: untrained %.3f, trained (BF16) %.3f, linear readout %.4f" % (
+        r0 / rms, r1 / rms, rl / rms))
+    assert r1 < 0.6 * r0
+    assert rl < r0
+    s.close()
