@@ -32,7 +32,20 @@ HBM_PEAK_GBS = 8000.0
 #   LJ 1M:  NL 4 + 38.8*4 = 159, positions 24, force 12, integration 132 -> 327
 #   KG 2M:  NL 4 + 6.3*4 = 29, positions 24, force 12, topology 16,
 #           integration 132 -> 213
-ALG_BYTES = {"lj1m": 327.0, "kg2m": 213.0, "kg1k": 213.0}
+#   surrogate 1M: 2 descriptor-list passes 2 x (4 + 43.4 x 4) = 355, a_i write
+#           + read 256, positions 48, force 12, bonded 16, integration 132 -> 819
+ALG_BYTES = {"lj1m": 327.0, "kg2m": 213.0, "kg1k": 213.0, "sur1m": 819.0}
+# HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE passes (scaled by a 512 MiB copy: x2.0 and x1.0), valid only for
+# the kernel source they were taken on (SHA-256 prefix of md_kernels.hip).
+TRAFFIC = {"lj1m": {"bytes": 252704.5 * 2.0 * 1024 + 74141.2 * 1024, "source": "72ad319a722a2287"}}
+
+
+def kernel_source_hash():
+    import hashlib
+    p = os.path.join(ROOT, "paper_2608_14911_amd", "csrc", "md_kernels.hip")
+    with open(p, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
 def parse():
@@ -40,7 +53,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="lj1m", choices=["lj1m", "kg2m", "kg1k", "batch"])
+    ap.add_argument("--workload", default="lj1m", choices=["lj1m", "kg2m", "kg1k", "batch", "sur1m"])
+    ap.add_argument("--sur-precision", default="bf16", choices=["fp32", "bf16"],
+                    help="sur1m: network precision of the surrogate")
     ap.add_argument("--no-autotune", action="store_true", help="batch: keep the sampler's skin, cell factor 2")
     ap.add_argument("--no-events", action="store_true",
                     help="time with a hipGraph replay and no per-kernel events")
@@ -68,6 +83,8 @@ def make_system(name, quiet, cell_factor=0):
         return w, s
     if name == "kg2m":
         w = inputs.workload_kg(2000, 1000, seed=1002)
+    elif name == "sur1m":
+        w = inputs.workload_kg(1000, 1000, seed=1014)
     else:
         w = inputs.workload_kg1k()
         w["k_bend"] = 1.5
@@ -90,7 +107,8 @@ def make_system(name, quiet, cell_factor=0):
     s.close()
     w1 = dict(w)
     w1["pos"], w1["vel"] = st["pos"], st["vel"]
-    s = from_workload(w1, precision="fp32", cell_factor=cell_factor)
+    extra = {"list_cutoff": 2.5, "surrogate": True} if name == "sur1m" else {}
+    s = from_workload(w1, precision="fp32", cell_factor=cell_factor, **extra)
     s.set_state(st)
     s.step(1)
     if s.status() != 0:
@@ -235,6 +253,16 @@ def main():
         return bench_batch(a)
     w, s = make_system(a.workload, a.quiet, a.cell_factor)
     n = s.n
+    if a.workload == "sur1m":
+        # the surrogate replaces the WCA pair force: random-init network of
+        # the 32 -> 64 -> 64 -> 1 architecture (throughput does not depend on
+        # the weights), descriptor standardisation from the current state
+        from paper_2608_14911_amd import inputs as _inp
+        G = s.descriptors().double()
+        mean = G.mean(0)
+        istd = 1.0 / torch.sqrt(G.var(0, unbiased=False) + 1e-6)
+        s.sur_set(_inp.mlp_init(1004) * 0.05, mean.float(), istd.float(), a.sur_precision)
+        s.set_pair_mode("surrogate")
     s.step(a.warmup)
     o0 = s.observables()
     s.history()
@@ -254,7 +282,8 @@ def main():
     value = n * a.steps / el
     ms = 1e3 * el / a.steps
     rec = {
-        "metric": "atom-steps/s (1M LJ, 2M KG melt)",
+        "metric": "atom-steps/s (1M LJ, 2M KG melt)" if a.workload != "sur1m" else
+                  "atom-steps/s (1M KG melt, learned surrogate pair force)",
         "value": value,
         "unit": "atom-steps/s",
         "n_gpus": 1,
@@ -278,9 +307,13 @@ def main():
         k_ms = tm["ms_step_kernels"] / max(tm["n_step_kernels"], 1)
         alg = ALG_BYTES[a.workload] * n
         ach = alg / (k_ms * 1e-3) / 1e9
+        tr = TRAFFIC.get(a.workload)
+        traffic = tr["bytes"] if tr and tr["source"] == kernel_source_hash() else None
         rec["roofline"] = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                           "frac": ach / HBM_PEAK_GBS, "traffic": None,
-                           "kernel": "k_step (fused pair+bonded forces, velocity Verlet, reductions)",
+                           "frac": ach / HBM_PEAK_GBS, "traffic": traffic,
+                           "kernel": ("k_step (fused pair+bonded forces, velocity Verlet, reductions)"
+                                      if a.workload != "sur1m" else
+                                      "surrogate force stage (k_sur_desc, k_sur_mlp, k_sur_force, k_step_ext)"),
                            "kernel_ms": k_ms, "alg_bytes_per_launch": alg}
         rec["kernel_breakdown_ms_per_step"] = {
             "rebuild_stage": tm["ms_rebuild"] / max(tm["n_rebuild"], 1),
