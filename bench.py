@@ -254,14 +254,16 @@ def main():
     w, s = make_system(a.workload, a.quiet, a.cell_factor)
     n = s.n
     if a.workload == "sur1m":
-        # the surrogate replaces the WCA pair force: random-init network of
-        # the 32 -> 64 -> 64 -> 1 architecture (throughput does not depend on
-        # the weights), descriptor standardisation from the current state
-        from paper_2608_14911_amd import inputs as _inp
-        G = s.descriptors().double()
-        mean = G.mean(0)
-        istd = 1.0 / torch.sqrt(G.var(0, unbiased=False) + 1e-6)
-        s.sur_set(_inp.mlp_init(1004) * 0.05, mean.float(), istd.float(), a.sur_precision)
+        # the surrogate replaces the WCA pair force: the network trained by
+        # surrogate_experiment.py on a 100k-bead plain-method melt (without
+        # excluded volume from a trained network the FENE bonds collapse the
+        # chains, so random weights cannot be timed over many steps)
+        wpath = os.path.join(ROOT, "paper_2608_14911_amd", "data", "surrogate_kg.npz")
+        if not os.path.exists(wpath):
+            raise SystemExit("missing %s: python -m paper_2608_14911_amd.surrogate_experiment --save %s"
+                             % (wpath, wpath))
+        wd = np.load(wpath)
+        s.sur_set(wd["theta_" + a.sur_precision], wd["g_mean"], wd["g_istd"], a.sur_precision)
         s.set_pair_mode("surrogate")
     s.step(a.warmup)
     o0 = s.observables()

@@ -250,6 +250,7 @@ static size_t carve(const md_config* c, const Geom& g, int step_grid, uint8_t* b
         memset(&u, 0, sizeof(u));
         u.G = (float*)take(sizeof(float) * kSurNB * n);
         u.a = (float*)take(sizeof(float) * kSurNB * n);
+        u.ab = (uint16_t*)take(sizeof(uint16_t) * kSurNB * n);
         u.u = (float*)take(sizeof(float) * kSurNB * n);
         u.f = (float4*)take(sizeof(float4) * n);
         u.delta = (float4*)take(sizeof(float4) * n);
@@ -385,6 +386,9 @@ static void fill_sur_const(SurConst* c) {
     c->inv_w2 = (float)(1.0 / w2);
     c->rd2 = (float)(MD_SUR_RCUT * MD_SUR_RCUT);
     c->pi_rd = (float)(M_PI / MD_SUR_RCUT);
+    const double dmu = (MD_SUR_MU1 - MD_SUR_MU0) / (kSurNB - 1);
+    c->dmu = (float)dmu;
+    c->ratio = (float)exp2(-2.0 * (1.4426950408889634 / (2.0 * w2)) * dmu * dmu);
 }
 
 // Force stage: the plain fused kernel, or the surrogate's descriptor,
@@ -397,10 +401,12 @@ static hipError_t launch_force_stage(md_handle h, int mode, int tensor, double* 
     hipError_t e;
     const SurBufs& s = h->sb;
     if ((e = launch_sur_desc(h->g, h->b, s, h->sc, h->parity, h->step_grid, h->stream)) != hipSuccess) return e;
-    if ((e = launch_sur_mlp(s, s.G, h->g.n, s.a, nullptr, s.part, h->sur_prec == MD_SUR_BF16, h->step_grid,
-                            h->stream)) != hipSuccess)
+    // BF16 form: the input gradients travel to the pair-force pass as BF16
+    const int bf = h->sur_prec == MD_SUR_BF16;
+    if ((e = launch_sur_mlp(s, s.G, h->g.n, bf ? nullptr : s.a, nullptr, s.part, bf, h->step_grid, h->stream,
+                            bf ? s.ab : nullptr)) != hipSuccess)
         return e;
-    if ((e = launch_sur_force(h->g, h->b, s, h->sc, h->parity, nullptr, 0.0, tensor, h->step_grid, h->stream)) !=
+    if ((e = launch_sur_force(h->g, h->b, s, h->sc, h->parity, nullptr, 0.0, tensor, h->step_grid, h->stream, bf)) !=
         hipSuccess)
         return e;
     *spart = s.part;

@@ -179,6 +179,7 @@ constexpr int kSurGradBlocks = 256;         // blocks of the double-backward ker
 struct SurBufs {
     float* G;           // [N][32] descriptors, sorted order
     float* a;           // [N][32] dE_i/dG(i)
+    uint16_t* ab;       // [N][32] the same in BF16 (the BF16 form's pair-force pass)
     float* u;           // [N][32] training: dL/da_i
     float4* f;          // [N] surrogate pair force
     float4* delta;      // [N] training: dL/dF_i
@@ -201,15 +202,18 @@ struct SurConst {
     float inv_w2;       // 1 / w^2
     float rd2;          // r_d^2
     float pi_rd;        // pi / r_d
+    float dmu;          // centre spacing
+    float ratio;        // exp2(-2 c_exp dmu^2): step of the basis recurrences
 };
 
 hipError_t launch_sur_prepare(const SurBufs& s, hipStream_t st);
 hipError_t launch_sur_desc(const Geom& g, const Bufs& b, const SurBufs& s, const SurConst& c, int parity,
                            int grid, hipStream_t st);
 hipError_t launch_sur_mlp(const SurBufs& s, const float* G, int64_t P, float* a, float* e, double* epart,
-                          int bf16, int grid, hipStream_t st);
+                          int bf16, int grid, hipStream_t st, uint16_t* a16 = nullptr);
 hipError_t launch_sur_force(const Geom& g, const Bufs& b, const SurBufs& s, const SurConst& c, int parity,
-                            const double* fref, double two_over_m, int tensor, int grid, hipStream_t st);
+                            const double* fref, double two_over_m, int tensor, int grid, hipStream_t st,
+                            int a_bf16 = 0);
 hipError_t launch_sur_u(const Geom& g, const Bufs& b, const SurBufs& s, const SurConst& c, int parity, int grid,
                         hipStream_t st);
 hipError_t launch_sur_bwd2(const SurBufs& s, int64_t P, int bf16, hipStream_t st);

@@ -40,10 +40,38 @@ __device__ __forceinline__ float sigm(float z) { return __builtin_amdgcn_rcpf(1.
 
 // f_c(r) = (cos(pi r / r_d) + 1) / 2 and its derivative.
 __device__ __forceinline__ float cutoff_fn(const SurConst& c, float r, float& dfc) {
+    // argument in [0, pi]: the hardware sine / cosine are accurate to a few
+    // 1e-7 there
     float sn, cs;
-    sincosf(c.pi_rd * r, &sn, &cs);
+    __sincosf(c.pi_rd * r, &sn, &cs);
     dfc = -0.5f * c.pi_rd * sn;
     return 0.5f * (cs + 1.f);
+}
+
+// phi_k(r) = exp(-(r - mu_k)^2 / (2 w^2)) for k = 0..31 by two-sided
+// recurrences from pivots k = 8 and 24: with t = r - mu_p,
+//   phi_{p+1} / phi_p = exp2(c (2 D t - D^2)),  phi_{p-1} / phi_p = exp2(c (-2 D t - D^2)),
+// and each further ratio is the previous one times exp2(-2 c D^2)
+// (c = log2(e) / (2 w^2), D the centre spacing): 6 exponentials per pair
+// instead of 32, chains of at most 8 products.
+__device__ __forceinline__ void gauss_basis(const SurConst& c, float r, float* phi) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int p = 8 + 16 * h;
+        const float t = r - c.mu[p];
+        phi[p] = __builtin_amdgcn_exp2f(-c.c_exp * t * t);
+        float up = __builtin_amdgcn_exp2f(c.c_exp * (2.f * c.dmu * t - c.dmu * c.dmu));
+        float dn = __builtin_amdgcn_exp2f(c.c_exp * (-2.f * c.dmu * t - c.dmu * c.dmu));
+#pragma unroll
+        for (int m = 1; m <= 8; ++m) {
+            phi[p - m] = phi[p - m + 1] * dn;
+            dn *= c.ratio;
+            if (m <= 7) {
+                phi[p + m] = phi[p + m - 1] * up;
+                up *= c.ratio;
+            }
+        }
+    }
 }
 
 // ------------------------------------------------------------------ descriptor
@@ -70,11 +98,10 @@ __global__ void __launch_bounds__(kBlock) k_sur_desc(Geom g, Bufs b, SurBufs s, 
                 const float r = sqrtf(r2);
                 float dfc;
                 const float fc = cutoff_fn(c, r, dfc);
+                float ph[kSurNB];
+                gauss_basis(c, r, ph);
 #pragma unroll
-                for (int q = 0; q < kSurNB; ++q) {
-                    const float t = r - c.mu[q];
-                    G[q] += exp2f(-c.c_exp * t * t) * fc;
-                }
+                for (int q = 0; q < kSurNB; ++q) G[q] += ph[q] * fc;
             }
         }
         float4* out = reinterpret_cast<float4*>(s.G + i * kSurNB);
@@ -109,7 +136,34 @@ __device__ __forceinline__ void block_store(const double* v, double* part) {
 // Inference: F into s.f, per-block virial (and tensor) partials into
 // s.part rows 1..7.  Training: delta_i = (2/M) (F_i - F_ref) into s.delta
 // and the squared residual into s.part row 8.
-template <bool TRAIN>
+__device__ __forceinline__ float bf16_to_f32(uint32_t h) { return __uint_as_float(h << 16); }
+
+// Row of 32 input gradients: FP32, or BF16 (A16).
+template <bool A16>
+__device__ __forceinline__ void load_a(const SurBufs& s, int64_t j, float* av) {
+    if (A16) {
+        const uint4* p = reinterpret_cast<const uint4*>(s.ab + j * kSurNB);
+#pragma unroll
+        for (int q = 0; q < kSurNB / 8; ++q) {
+            const uint4 v = p[q];
+            const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                av[8 * q + 2 * e] = bf16_to_f32(w[e] & 0xffffu);
+                av[8 * q + 2 * e + 1] = bf16_to_f32(w[e] >> 16);
+            }
+        }
+    } else {
+        const float4* p = reinterpret_cast<const float4*>(s.a + j * kSurNB);
+#pragma unroll
+        for (int q = 0; q < kSurNB / 4; ++q) {
+            const float4 v = p[q];
+            av[4 * q] = v.x; av[4 * q + 1] = v.y; av[4 * q + 2] = v.z; av[4 * q + 3] = v.w;
+        }
+    }
+}
+
+template <bool TRAIN, bool A16>
 __global__ void __launch_bounds__(kBlock) k_sur_force(Geom g, Bufs b, SurBufs s, SurConst c, int parity,
                                                      const double* __restrict__ fref, double two_over_m,
                                                      int tensor) {
@@ -121,12 +175,7 @@ __global__ void __launch_bounds__(kBlock) k_sur_force(Geom g, Bufs b, SurBufs s,
     for (int64_t i = gtid_xcd(); i < n; i += gstride()) {
         const int4 qi = xq[i];
         float ai[kSurNB];
-        const float4* ap = reinterpret_cast<const float4*>(s.a + i * kSurNB);
-#pragma unroll
-        for (int q = 0; q < kSurNB / 4; ++q) {
-            const float4 v = ap[q];
-            ai[4 * q] = v.x; ai[4 * q + 1] = v.y; ai[4 * q + 2] = v.z; ai[4 * q + 3] = v.w;
-        }
+        load_a<A16>(s, i, ai);
         int cnt = b.ncount[i];
         cnt = cnt < g.cap ? cnt : g.cap;
         const int32_t* __restrict__ row = b.nl + nl_base(i, g.cap);
@@ -143,20 +192,16 @@ __global__ void __launch_bounds__(kBlock) k_sur_force(Geom g, Bufs b, SurBufs s,
                 const float r = sqrtf(r2);
                 float dfc;
                 const float fc = cutoff_fn(c, r, dfc);
-                const float4* aj = reinterpret_cast<const float4*>(s.a + (int64_t)j * kSurNB);
+                float av[kSurNB];
+                load_a<A16>(s, j, av);
+                float ph[kSurNB];
+                gauss_basis(c, r, ph);
                 float cij = 0.f;
 #pragma unroll
-                for (int q = 0; q < kSurNB / 4; ++q) {
-                    const float4 v = aj[q];
-                    const float av[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) {
-                        const int kk = 4 * q + e;
-                        const float t = r - c.mu[kk];
-                        const float ph = exp2f(-c.c_exp * t * t);
-                        const float dg = ph * (dfc - t * c.inv_w2 * fc);
-                        cij += (ai[kk] + av[e]) * dg;
-                    }
+                for (int kk = 0; kk < kSurNB; ++kk) {
+                    const float t = r - c.mu[kk];
+                    const float dg = ph[kk] * (dfc - t * c.inv_w2 * fc);
+                    cij += (ai[kk] + av[kk]) * dg;
                 }
                 const float sc = cij / r;
                 fx += sc * dx;
@@ -220,11 +265,12 @@ __global__ void __launch_bounds__(kBlock) k_sur_u(Geom g, Bufs b, SurBufs s, Sur
                 const float fc = cutoff_fn(c, r, dfc);
                 const float4 dj = s.delta[j];
                 const float proj = ((di.x - dj.x) * dx + (di.y - dj.y) * dy + (di.z - dj.z) * dz) / r;
+                float ph[kSurNB];
+                gauss_basis(c, r, ph);
 #pragma unroll
                 for (int q = 0; q < kSurNB; ++q) {
                     const float t = r - c.mu[q];
-                    const float ph = exp2f(-c.c_exp * t * t);
-                    U[q] += proj * ph * (dfc - t * c.inv_w2 * fc);
+                    U[q] += proj * ph[q] * (dfc - t * c.inv_w2 * fc);
                 }
             }
         }
@@ -381,17 +427,72 @@ __device__ __forceinline__ void load_rows(const SurBufs& s, const float* __restr
     }
 }
 
+// Activation storage of the inference tiles: FP32 rows, or BF16 rows in
+// the BF16 form (each value rounded once when stored, then used as a
+// matrix-core operand by every product that reads it).
+template <bool BF16>
+struct Act {
+    using T = float;
+    static constexpr int S32 = kSA32, S64 = kSA64;
+    __device__ static T put(float v) { return v; }
+};
+template <>
+struct Act<true> {
+    using T = uint16_t;
+    static constexpr int S32 = 40, S64 = 72;
+    __device__ static T put(float v) { return (uint16_t)bf16_rne(v); }
+};
+
+template <int NC, int K, int SA, int SW>
+__device__ __forceinline__ void tile_gemm(const uint16_t* __restrict__ A, const uint16_t* __restrict__ W,
+                                          float* out, int p, int hq) {
+    const int r = threadIdx.x & 15;
+#pragma unroll
+    for (int cb = 0; cb < NC / 16; ++cb) {
+        float4v acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int kb = 0; kb < K / 16; ++kb) {
+            const short4v bop = *reinterpret_cast<const short4v*>(A + p * SA + 16 * kb + 4 * hq);
+            const short4v aop = *reinterpret_cast<const short4v*>(W + (16 * cb + r) * SW + 16 * kb + 4 * hq);
+            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(aop, bop, acc, 0, 0, 0);
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) out[4 * cb + e] = acc[e];
+    }
+}
+
+template <bool BF16>
+__device__ __forceinline__ void load_x(const SurBufs& s, const float* __restrict__ G, int64_t base, int64_t P,
+                                       typename Act<BF16>::T* sX) {
+    const int t = threadIdx.x;
+    const int p = t >> 2, c0 = (t & 3) * 8;
+    const bool ok = base + p < P;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int c = c0 + 4 * h;
+        float4 gv = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (ok) gv = *reinterpret_cast<const float4*>(G + (base + p) * kSurNB + c);
+        const float4 m = *reinterpret_cast<const float4*>(s.gmean + c);
+        const float4 is = *reinterpret_cast<const float4*>(s.gistd + c);
+        const float xv[4] = {(gv.x - m.x) * is.x, (gv.y - m.y) * is.y, (gv.z - m.z) * is.z, (gv.w - m.w) * is.w};
+#pragma unroll
+        for (int e = 0; e < 4; ++e) sX[p * Act<BF16>::S32 + c + e] = Act<BF16>::put(ok ? xv[e] : 0.f);
+    }
+}
+
 // Forward and input gradient on tiles of 64 rows:
 //   z1 = W1 x + b1, h1 = silu(z1), z2 = W2 h1 + b2, E = w3 . silu(z2) + b3,
 //   gz2 = w3 silu'(z2), gz1 = (W2^T gz2) silu'(z1), dE/dG = (W1^T gz1) istd.
 template <bool BF16>
 __global__ void __launch_bounds__(kSB) k_sur_mlp(SurBufs s, const float* __restrict__ G, int64_t P,
                                                  float* __restrict__ aout, float* __restrict__ eout,
-                                                 double* __restrict__ epart) {
+                                                 double* __restrict__ epart, uint16_t* __restrict__ aout16) {
+    using AT = typename Act<BF16>::T;
+    constexpr int S32 = Act<BF16>::S32, S64 = Act<BF16>::S64;
     __shared__ WImage<BF16> wi;
-    __shared__ __attribute__((aligned(16))) float sX[64 * kSA32];
-    __shared__ __attribute__((aligned(16))) float sA[64 * kSA64];
-    __shared__ __attribute__((aligned(16))) float sB[64 * kSA64];
+    __shared__ __attribute__((aligned(16))) AT sX[64 * S32];
+    __shared__ __attribute__((aligned(16))) AT sA[64 * S64];
+    __shared__ __attribute__((aligned(16))) AT sB[64 * S64];
     wi.load(s);
     __syncthreads();   // the weight image is complete before any lane reads it
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, hq = lane >> 4;
@@ -405,20 +506,20 @@ __global__ void __launch_bounds__(kSB) k_sur_mlp(SurBufs s, const float* __restr
     for (int64_t tile = blockIdx.x; tile < ntile; tile += gridDim.x) {
         const int64_t base = tile * 64;
         __syncthreads();   // previous tile done with sX/sA/sB
-        load_rows(s, G, nullptr, base, P, sX, nullptr);
+        load_x<BF16>(s, G, base, P, sX);
         __syncthreads();
         float z[16], s1[16];
-        tile_gemm<64, 32, kSA32, BF16 ? kSW1 : kPF1>(sX, wi.W1(), z, p, hq);
+        tile_gemm<64, 32, S32, BF16 ? kSW1 : kPF1>(sX, wi.W1(), z, p, hq);
 #pragma unroll
         for (int v = 0; v < 16; ++v) {
             const int h = 16 * (v >> 2) + 4 * hq + (v & 3);
             const float zz = z[v] + b1[h];
             const float sg = sigm(zz);
             s1[v] = sg * (1.f + zz * (1.f - sg));
-            sA[p * kSA64 + h] = zz * sg;
+            sA[p * S64 + h] = Act<BF16>::put(zz * sg);
         }
         __syncthreads();
-        tile_gemm<64, 64, kSA64, BF16 ? kSW64 : kPF64>(sA, wi.W2(), z, p, hq);
+        tile_gemm<64, 64, S64, BF16 ? kSW64 : kPF64>(sA, wi.W2(), z, p, hq);
         float e = 0.f;
 #pragma unroll
         for (int v = 0; v < 16; ++v) {
@@ -426,7 +527,7 @@ __global__ void __launch_bounds__(kSB) k_sur_mlp(SurBufs s, const float* __restr
             const float zz = z[v] + b2[h];
             const float sg = sigm(zz);
             e += w3[h] * zz * sg;
-            sB[p * kSA64 + h] = w3[h] * sg * (1.f + zz * (1.f - sg));
+            sB[p * S64 + h] = Act<BF16>::put(w3[h] * sg * (1.f + zz * (1.f - sg)));
         }
         e += __shfl_xor(e, 16, 64);
         e += __shfl_xor(e, 32, 64);
@@ -436,22 +537,28 @@ __global__ void __launch_bounds__(kSB) k_sur_mlp(SurBufs s, const float* __restr
             esum += (double)(e + b3);
         }
         __syncthreads();
-        tile_gemm<64, 64, kSA64, BF16 ? kSW64 : kPF64>(sB, wi.W2T(), z, p, hq);
+        tile_gemm<64, 64, S64, BF16 ? kSW64 : kPF64>(sB, wi.W2T(), z, p, hq);
 #pragma unroll
         for (int v = 0; v < 16; ++v) {
             const int h = 16 * (v >> 2) + 4 * hq + (v & 3);
-            sA[p * kSA64 + h] = z[v] * s1[v];
+            sA[p * S64 + h] = Act<BF16>::put(z[v] * s1[v]);
         }
         __syncthreads();
         float gx[8];
-        tile_gemm<32, 64, kSA64, BF16 ? kSW64 : kPF64>(sA, wi.W1T(), gx, p, hq);
+        tile_gemm<32, 64, S64, BF16 ? kSW64 : kPF64>(sA, wi.W1T(), gx, p, hq);
         if (valid) {
 #pragma unroll
             for (int cb = 0; cb < 2; ++cb) {
                 const int k0 = 16 * cb + 4 * hq;
                 const float4 is = *reinterpret_cast<const float4*>(s.gistd + k0);
-                *reinterpret_cast<float4*>(aout + (base + p) * kSurNB + k0) =
-                    make_float4(gx[4 * cb] * is.x, gx[4 * cb + 1] * is.y, gx[4 * cb + 2] * is.z, gx[4 * cb + 3] * is.w);
+                const float4 av = make_float4(gx[4 * cb] * is.x, gx[4 * cb + 1] * is.y, gx[4 * cb + 2] * is.z,
+                                              gx[4 * cb + 3] * is.w);
+                if (aout) *reinterpret_cast<float4*>(aout + (base + p) * kSurNB + k0) = av;
+                if (aout16) {
+                    const uint32_t lo = (uint16_t)bf16_rne(av.x) | ((uint32_t)(uint16_t)bf16_rne(av.y) << 16);
+                    const uint32_t hi = (uint16_t)bf16_rne(av.z) | ((uint32_t)(uint16_t)bf16_rne(av.w) << 16);
+                    *reinterpret_cast<uint2*>(aout16 + (base + p) * kSurNB + k0) = make_uint2(lo, hi);
+                }
             }
         }
     }
@@ -693,22 +800,26 @@ hipError_t launch_sur_desc(const Geom& g, const Bufs& b, const SurBufs& s, const
 }
 
 hipError_t launch_sur_mlp(const SurBufs& s, const float* G, int64_t P, float* a, float* e, double* epart,
-                          int bf16, int grid, hipStream_t st) {
+                          int bf16, int grid, hipStream_t st, uint16_t* a16) {
     if (bf16)
-        hipLaunchKernelGGL(k_sur_mlp<true>, dim3(grid), dim3(kSB), 0, st, s, G, P, a, e, epart);
+        hipLaunchKernelGGL(k_sur_mlp<true>, dim3(grid), dim3(kSB), 0, st, s, G, P, a, e, epart, a16);
     else
-        hipLaunchKernelGGL(k_sur_mlp<false>, dim3(grid), dim3(kSB), 0, st, s, G, P, a, e, epart);
+        hipLaunchKernelGGL(k_sur_mlp<false>, dim3(grid), dim3(kSB), 0, st, s, G, P, a, e, epart, a16);
     return hipGetLastError();
 }
 
 hipError_t launch_sur_force(const Geom& g, const Bufs& b, const SurBufs& s, const SurConst& c, int parity,
-                            const double* fref, double two_over_m, int tensor, int grid, hipStream_t st) {
+                            const double* fref, double two_over_m, int tensor, int grid, hipStream_t st,
+                            int a_bf16) {
     if (fref)
-        hipLaunchKernelGGL(k_sur_force<true>, dim3(grid), dim3(kBlock), 0, st, g, b, s, c, parity, fref,
+        hipLaunchKernelGGL((k_sur_force<true, false>), dim3(grid), dim3(kBlock), 0, st, g, b, s, c, parity, fref,
                            two_over_m, 0);
+    else if (a_bf16)
+        hipLaunchKernelGGL((k_sur_force<false, true>), dim3(grid), dim3(kBlock), 0, st, g, b, s, c, parity, nullptr,
+                           0.0, tensor);
     else
-        hipLaunchKernelGGL(k_sur_force<false>, dim3(grid), dim3(kBlock), 0, st, g, b, s, c, parity, nullptr, 0.0,
-                           tensor);
+        hipLaunchKernelGGL((k_sur_force<false, false>), dim3(grid), dim3(kBlock), 0, st, g, b, s, c, parity,
+                           nullptr, 0.0, tensor);
     return hipGetLastError();
 }
 

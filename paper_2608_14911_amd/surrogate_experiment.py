@@ -235,6 +235,8 @@ def main():
     ap.add_argument("--out", default="")
     ap.add_argument("--epochs", type=int, default=0)
     ap.add_argument("--lr", type=float, default=3e-3)
+    ap.add_argument("--save", default="", help="write the trained models (npz: theta_fp32, theta_bf16, "
+                                               "g_mean, g_istd) to this path")
     a = ap.parse_args()
     import torch
     torch.cuda.set_device(0)
@@ -270,6 +272,9 @@ def main():
         res["trained_" + prec] = rmse(s, fva, rva)
         res["train_seconds_" + prec] = time.time() - t1
         res["history_" + prec] = hist
+    if a.save:
+        np.savez(a.save, theta_fp32=models["fp32"], theta_bf16=models["bf16"],
+                 g_mean=mean.cpu().numpy(), g_istd=istd.cpu().numpy())
     # the FP32-trained weights evaluated with BF16 operands
     s.sur_set(models["fp32"], mean, istd, "bf16")
     res["trained_fp32_eval_bf16"] = rmse(s, fva, rva)
