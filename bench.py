@@ -63,6 +63,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quiet", action="store_true")
     ap.add_argument("--cell-factor", type=int, default=0, help="cells per list radius (1 or 2; 0 = library default)")
+    ap.add_argument("--nl-build", default="auto", choices=["auto", "tiles", "per-particle"],
+                    help="Verlet-list build: one wavefront per 64-particle tile, one particle per lane, "
+                         "or the library's choice by cell occupancy")
     ap.add_argument("--calib-copy", action="store_true",
                     help="after the run, copy 512 MiB three times (torch copy kernel) so that hardware "
                          "byte counters can be scaled against a transfer of known size")
@@ -74,12 +77,12 @@ def log(msg, quiet=False):
         print("[bench] " + msg, file=sys.stderr, flush=True)
 
 
-def make_system(name, quiet, cell_factor=0):
+def make_system(name, quiet, cell_factor=0, flags=0):
     from paper_2608_14911_amd import inputs
     from paper_2608_14911_amd.system import from_workload
     if name == "lj1m":
         w = inputs.workload_lj(ncell=64, seed=1001)
-        s = from_workload(w, precision="fp32", cell_factor=cell_factor)
+        s = from_workload(w, precision="fp32", cell_factor=cell_factor, flags=flags)
         return w, s
     if name == "kg2m":
         w = inputs.workload_kg(2000, 1000, seed=1002)
@@ -98,7 +101,7 @@ def make_system(name, quiet, cell_factor=0):
     w0["dt"] = 0.002
     w0["gamma"] = 1.0
     w0["vel"] = np.zeros_like(w["pos"])
-    s = from_workload(w0, precision="fp32", cell_factor=cell_factor, nl_capacity=256)
+    s = from_workload(w0, precision="fp32", cell_factor=cell_factor, nl_capacity=256, flags=flags)
     t0 = time.time()
     push_off(s, w["rc"], log=lambda m: log(m, quiet))
     s.set_params(dt=w["dt"], gamma=w["gamma"])
@@ -108,7 +111,7 @@ def make_system(name, quiet, cell_factor=0):
     w1 = dict(w)
     w1["pos"], w1["vel"] = st["pos"], st["vel"]
     extra = {"list_cutoff": 2.5, "surrogate": True} if name == "sur1m" else {}
-    s = from_workload(w1, precision="fp32", cell_factor=cell_factor, **extra)
+    s = from_workload(w1, precision="fp32", cell_factor=cell_factor, flags=flags, **extra)
     s.set_state(st)
     s.step(1)
     if s.status() != 0:
@@ -251,7 +254,9 @@ def main():
     torch.cuda.set_device(0)
     if a.workload == "batch":
         return bench_batch(a)
-    w, s = make_system(a.workload, a.quiet, a.cell_factor)
+    from paper_2608_14911_amd import md as md_
+    nl_flags = {"auto": 0, "tiles": md_.MD_CFG_NL_TILES, "per-particle": md_.MD_CFG_NL_PER_PARTICLE}[a.nl_build]
+    w, s = make_system(a.workload, a.quiet, a.cell_factor, nl_flags)
     n = s.n
     if a.workload == "sur1m":
         # the surrogate replaces the WCA pair force: the network trained by

@@ -140,13 +140,21 @@ static md_status plan_geom(const md_config* c, Geom* g, std::string* why) {
     const double rv = fmax(rc_max_of(c), c->list_cutoff) + c->skin;
     g->rv2 = rv * rv;
     g->disp2 = (0.5 * c->skin) * (0.5 * c->skin);
+    // Dense cells (>= 8 particles expected in a cell of side rv) build the
+    // list one wavefront per tile with cells of side rv; sparser systems one
+    // particle per lane, preferably with half-cutoff sub-cells (fewer
+    // candidate pairs), whenever the box holds at least 5 of them per side.
+    const double density = (double)c->n_particles / (c->box[0] * c->box[1] * c->box[2]);
+    const bool dense = (c->flags & MD_CFG_NL_TILES) ||
+                       (density * rv * rv * rv >= 8.0 && !(c->flags & MD_CFG_NL_PER_PARTICLE));
     g->kc = c->cell_factor;
     if (g->kc == 0) {
-        // automatic: half-cutoff sub-cells (fewer candidate pairs per list
-        // build) whenever the box holds at least 5 of them per side
-        g->kc = 2;
-        for (int d = 0; d < 3; ++d)
-            if ((int)floor(c->box[d] * 2.0 / (rv * (1.0 + 1e-12))) < 5) g->kc = 1;
+        bool fit1 = true, fit2 = true;
+        for (int d = 0; d < 3; ++d) {
+            if ((int)floor(c->box[d] / (rv * (1.0 + 1e-12))) < 3) fit1 = false;
+            if ((int)floor(c->box[d] * 2.0 / (rv * (1.0 + 1e-12))) < 5) fit2 = false;
+        }
+        g->kc = (dense && fit1) ? 1 : (fit2 ? 2 : 1);
     }
     g->ncell = 1;
     double Lmax = 0.0;
@@ -184,6 +192,26 @@ static md_status plan_geom(const md_config* c, Geom* g, std::string* why) {
         if (cap < 16) cap = 16;
         if (cap > 4096) cap = 4096;
         g->cap = cap;
+    }
+    g->nl_tile = ((c->flags & MD_CFG_NL_TILES) || (dense && g->kc == 1)) ? 1 : 0;
+    g->nl_cubic = (c->box[0] == c->box[1] && c->box[1] == c->box[2]) ? 1 : 0;
+    {
+        // rv^2 -/+ band over ql^2 (ql = L 2^-32 exactly), rounded outwards to float
+        const double ql = c->box[0] * 0x1.0p-32;
+        const double lo = (g->rv2 - band) / (ql * ql), hi = (g->rv2 + band) / (ql * ql);
+        float flo = (float)lo, fhi = (float)hi;
+        if ((double)flo > lo) flo = nextafterf(flo, 0.0f);
+        if ((double)fhi < hi) fhi = nextafterf(fhi, INFINITY);
+        g->rq2lo = flo;
+        g->rq2hi = fhi;
+        // 16-bit prefilter: dx16 = (int32)(q_j - q_i) >> 16 is within e = U + ql
+        // of the FP64 difference (U = L 2^-16), so |r16^2 U^2 - r^2| stays
+        // below 2 rv sqrt(3) e + 3 e^2 around rv; 1.5x that, rounded outwards
+        const double U = c->box[0] * 0x1.0p-16, e = U + ql;
+        const double B16 = 1.5 * (2.0 * rv * sqrt(3.0) * e + 3.0 * e * e);
+        const double l16 = floor((g->rv2 - B16) / (U * U)), h16 = ceil((g->rv2 + B16) / (U * U));
+        g->r16lo = (uint32_t)fmax(0.0, fmin(l16, 4294967295.0));
+        g->r16hi = (uint32_t)fmax(0.0, fmin(h16, 4294967295.0));
     }
     return MD_OK;
 }
@@ -228,6 +256,7 @@ static size_t carve(const md_config* c, const Geom& g, int step_grid, uint8_t* b
     t.vt = (double*)take(sizeof(double) * 3 * n);
     t.imgt = (int32_t*)take(sizeof(int32_t) * 3 * n);
     t.tagt = (int32_t*)take(sizeof(int32_t) * n);
+    t.tsc = (int32_t*)take(sizeof(int32_t) * n);
     t.ncount = (int32_t*)take(sizeof(int32_t) * n);
     t.nl = (int32_t*)take(sizeof(int32_t) * (size_t)g.cap * (size_t)((n + 63) / 64 * 64));
     if (bonded) {

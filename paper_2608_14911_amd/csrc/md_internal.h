@@ -76,6 +76,13 @@ struct Geom {
     double qs[3];           // 2^32 / L
     float ql[3];            // L / 2^32
     float rv2lo, rv2hi;     // fixed-point list test band; FP64 test in between
+    int32_t nl_tile;        // list build: 1 = one wavefront per 64-particle tile with
+                            // candidates broadcast through the scalar cache, 0 = one
+                            // particle per lane
+    int32_t nl_cubic;       // cubic box: the tile build tests r^2 in fixed-point units
+    float rq2lo, rq2hi;     // the list band in units of (L 2^-32)^2 (cubic box)
+    uint32_t r16lo, r16hi;  // a wider band in units of (L 2^-16)^2 for the 16-bit
+                            // prefilter of the tile build (cubic box)
 };
 
 struct Bufs {
@@ -100,6 +107,7 @@ struct Bufs {
     double* vt;
     int32_t* imgt;
     int32_t* tagt;
+    int32_t* tsc;           // [N] tags in scatter order (rank inside a cell)
     int32_t* nl;            // [cap][N] neighbour-major ELL, sorted indices
     int32_t* ncount;        // [N]
     // topology, tag space (static) and sorted space (remapped at each build)

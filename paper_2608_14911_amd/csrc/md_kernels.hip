@@ -15,6 +15,7 @@
 // particle i at k*N + i) so that lane i reads consecutive words.
 #include "md_device.h"
 
+
 namespace md {
 
 // ------------------------------------------------------------------ helpers
@@ -230,15 +231,40 @@ __global__ void __launch_bounds__(kBlock) k_copy_i32(int32_t* dst, const int32_t
 // rebuild, so the whole step can be enqueued (and graph-captured) without a
 // host round trip.
 
-__device__ __forceinline__ void bin_one(const Geom& g, const Bufs& b, int64_t i, int parity) {
-    const uint32_t c = cell_of(g, b.x[parity][i]);
-    b.cellid[i] = c;
-    atomicAdd(&b.ccount[c], 1);
+// Runs of equal cells over the lanes of a wavefront.  Particles arrive in
+// the previous build's cell order, so a run is usually a whole cell's share
+// of the wavefront and one atomic serves it.  Active lanes are a prefix of
+// the wavefront.  Returns the run's first lane and its length.
+__device__ __forceinline__ void cell_run(uint32_t c, bool active, int& first, int& len) {
+    const int lane = threadIdx.x & 63;
+    const uint32_t prev = __shfl_up(c, 1, 64);
+    const uint64_t heads = __ballot(active && (lane == 0 || c != prev));
+    // bits 0 .. k: (2 << k) - 1, which is all ones for k = 63
+    const uint64_t upto = heads & ((2ull << lane) - 1);
+    first = upto ? 63 - __clzll(upto) : 0;
+    const uint64_t after = heads & ~((2ull << first) - 1);
+    const int nact = __popcll(__ballot(active));
+    const int next = after ? __ffsll((unsigned long long)after) - 1 : nact;
+    len = next - first;
+}
+
+__device__ __forceinline__ void bin_one(const Geom& g, const Bufs& b, int64_t i, bool active, int parity) {
+    uint32_t c = 0xffffffffu;
+    if (active) {
+        c = cell_of(g, b.x[parity][i]);
+        b.cellid[i] = c;
+    }
+    int first, len;
+    cell_run(c, active, first, len);
+    if (active && (threadIdx.x & 63) == first) atomicAdd(&b.ccount[c], len);
 }
 
 __global__ void __launch_bounds__(kBlock) k_bin(Geom g, Bufs b, int parity) {
     if (!rebuild_requested(b)) return;
-    for (int64_t i = gtid(); i < g.n; i += gstride()) bin_one(g, b, i, parity);
+    for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x; i0 < g.n; i0 += gstride()) {
+        const int64_t i = i0 + threadIdx.x;
+        bin_one(g, b, i, i < g.n, parity);
+    }
 }
 
 __device__ int block_exclusive_scan(int v, int& total) {
@@ -322,16 +348,31 @@ __global__ void __launch_bounds__(kBlock) k_scan_apply(Geom g, Bufs b) {
     if (blockIdx.x == 0 && threadIdx.x == 0) b.cstart[g.ncell] = (int32_t)g.n;
 }
 
-// Scatter into cell segments; counts return to zero for the next build.
-__device__ __forceinline__ void scatter_one(const Bufs& b, int64_t i) {
-    const uint32_t c = b.cellid[i];
-    const int slot = b.cstart[c] + atomicSub(&b.ccount[c], 1) - 1;
-    b.tmp[slot] = (int32_t)i;
+// Scatter into cell segments, one atomic per run of equal cells; counts
+// return to zero for the next build.  The tags are copied beside the slots
+// so that the ranking below reads them contiguously.
+__device__ __forceinline__ void scatter_one(const Bufs& b, int64_t i, bool active) {
+    const uint32_t c = active ? b.cellid[i] : 0xffffffffu;
+    int first, len;
+    cell_run(c, active, first, len);
+    const int lane = threadIdx.x & 63;
+    int top = 0;
+    if (active && lane == first) top = atomicSub(&b.ccount[c], len);
+    top = __shfl(top, first, 64);
+    if (active) {
+        // the run owns slots [start + top - len, start + top)
+        const int slot = b.cstart[c] + top - len + (lane - first);
+        b.tmp[slot] = (int32_t)i;
+        b.tsc[slot] = b.tag[i];
+    }
 }
 
 __global__ void __launch_bounds__(kBlock) k_scatter(Geom g, Bufs b) {
     if (!rebuild_requested(b)) return;
-    for (int64_t i = gtid(); i < g.n; i += gstride()) scatter_one(b, i);
+    for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x; i0 < g.n; i0 += gstride()) {
+        const int64_t i = i0 + threadIdx.x;
+        scatter_one(b, i, i < g.n);
+    }
 }
 
 // Order inside a cell by particle tag: the sorted order is then a function
@@ -342,10 +383,10 @@ __device__ __forceinline__ void permute_one(const Geom& g, const Bufs& b, int64_
     {
         int32_t i = b.tmp[s];
         uint32_t c = b.cellid[i];
-        int32_t ti = b.tag[i];
+        int32_t ti = b.tsc[s];
         int st = b.cstart[c], en = b.cstart[c + 1];
         int r = 0;
-        for (int u = st; u < en; ++u) r += (b.tag[b.tmp[u]] < ti);
+        for (int u = st; u < en; ++u) r += (b.tsc[u] < ti);
         int64_t nw = st + r;
         b.xt[nw] = b.x[parity][i];
         for (int d = 0; d < 3; ++d) {
@@ -412,6 +453,20 @@ __device__ __forceinline__ float cell_gap(int o, float u, float h) {
 }
 
 __device__ __forceinline__ int wrapc(int c, int nc) { return c < 0 ? c + nc : (c >= nc ? c - nc : c); }
+
+// Bond and angle partners of sorted particle i from tags to sorted indices.
+__device__ __forceinline__ void remap_bonded(const Bufs& b, int64_t n, int64_t i) {
+    const int32_t t = b.tag[i];
+    const int tc = b.tcnt_t[t];
+    const int nb = tc & 0xff, na = tc >> 8;
+    for (int k = 0; k < nb; ++k) b.bp_s[(int64_t)k * n + i] = b.inv[b.bp_t[(int64_t)k * n + t]];
+    for (int k = 0; k < na; ++k) {
+        const int2 e = b.ang_t[(int64_t)k * n + t];
+        const int role = (int)((uint32_t)e.x >> 30);
+        const int o1 = e.x & 0x3fffffff;
+        b.ang_s[(int64_t)k * n + i] = make_int2(b.inv[o1] | (role << 30), b.inv[e.y]);
+    }
+}
 
 // NL(i) = { j != i : r_ij^2 < rv^2 } over the cells within rv of particle i
 // (stencil of (2kc+1)^3 cells of side >= rv/kc, cells farther than rv
@@ -501,18 +556,7 @@ __device__ __forceinline__ void nl_one(const Geom& g, const Bufs& b, int64_t i, 
         // pad the row to a multiple of 8 with the particle itself (r = 0,
         // never inside a cutoff) so that step kernels stream whole batches
         for (int k = cnt; k < ((cnt + 7) & ~7) && k < g.cap; ++k) nlrow[k * kTile] = (int)i;
-        if (bonded) {
-            const int32_t t = b.tag[i];
-            const int tc = b.tcnt_t[t];
-            const int nb = tc & 0xff, na = tc >> 8;
-            for (int k = 0; k < nb; ++k) b.bp_s[(int64_t)k * n + i] = b.inv[b.bp_t[(int64_t)k * n + t]];
-            for (int k = 0; k < na; ++k) {
-                const int2 e = b.ang_t[(int64_t)k * n + t];
-                const int role = (int)((uint32_t)e.x >> 30);
-                const int o1 = e.x & 0x3fffffff;
-                b.ang_s[(int64_t)k * n + i] = make_int2(b.inv[o1] | (role << 30), b.inv[e.y]);
-            }
-        }
+        if (bonded) remap_bonded(b, n, i);
     }
 }
 
@@ -531,6 +575,166 @@ __global__ void __launch_bounds__(kBlock) k_nl_build(Geom g, Bufs b, int parity,
     int local_max = 0;
     bool overflow = false;
     for (int64_t i = gtid_xcd(); i < g.n; i += gstride()) nl_one(g, b, i, parity, bonded, local_max, overflow);
+    nl_epilogue(b, local_max, overflow);
+}
+
+// The same lists built one wavefront per 64-particle tile of the sorted order
+// (the tile of the list layout).  The tile's particles lie in a few
+// consecutive cells; lanes of one (y, z) cell row form a segment whose x-cells
+// span [x0, x1].  The segment's candidates are the particles of cells
+// [x0 - kc, x1 + kc] in each of the (2kc+1)^2 neighbouring rows, streamed in
+// nl_one's order (rows z-major, a wrapped x-range high part first, sorted
+// index) through the scalar cache: every lane tests every candidate, so there
+// are no per-lane gathers.  A candidate outside a lane's own stencil is at
+// least kc cell sides >= rv away and never passes the test, and a lane's own
+// candidates keep their relative order, so each row equals nl_one's entry for
+// entry.  A segment is cut where its x-span plus the stencil would exceed the
+// row (no candidate twice).  Cubic boxes prefilter on the upper 16 bits of
+// the fixed-point differences with integer r^2 (two 24-bit multiplies of
+// sign-extended upper words per axis), with a band that bounds the
+// truncation; inside it the 32-bit test and then FP64 decide.
+typedef int int4v __attribute__((ext_vector_type(4)));
+typedef const __attribute__((address_space(4))) int4v* __restrict__ scalar_int4_ptr;
+typedef const __attribute__((address_space(4))) int32_t* __restrict__ scalar_i32_ptr;
+
+template <bool CUBIC>
+__device__ __forceinline__ void nl_tile(const Geom& g, const Bufs& b, int64_t t, int parity, int bonded,
+                                        int& local_max, bool& overflow) {
+    const int lane = threadIdx.x & (kTile - 1);
+    const int64_t n = g.n, p = t * kTile + lane;
+    const int nv = (n - t * kTile < kTile) ? (int)(n - t * kTile) : kTile;
+    const bool valid = lane < nv;
+    const double4* __restrict__ x = b.x[parity];
+    // the particle data are not written by this kernel: uniform loads through
+    // the constant address space become scalar loads
+    const scalar_int4_ptr xqs = (scalar_int4_ptr)(const void*)b.xq[parity];
+    const scalar_i32_ptr cs = (scalar_i32_ptr)(const void*)b.cstart;
+    const int cap = g.cap, kc = g.kc, nx = g.nc[0];
+    int cxl = -1, cyl = -1, czl = -1;
+    uint32_t qx = 0, qy = 0, qz = 0;
+    double4 xi = make_double4(0.0, 0.0, 0.0, 0.0);
+    if (valid) {
+        xi = x[p];
+        cell_coords(g, xi.x, xi.y, xi.z, cxl, cyl, czl);
+        const int4 q = b.xq[parity][p];
+        qx = (uint32_t)q.x;
+        qy = (uint32_t)q.y;
+        qz = (uint32_t)q.z;
+    }
+    uint32_t* __restrict__ tnl = (uint32_t*)(b.nl + t * (int64_t)cap * kTile);
+    char* __restrict__ tnlb = (char*)tnl;           // byte base: 32-bit offsets from a scalar base
+    const uint32_t lane4 = (uint32_t)lane << 2;
+    const int self = (int)p;
+    int cnt = 0;
+    // A hit goes to slot min(cnt, cap - 1): an overflowing row overwrites its
+    // last slot, and the overflow flag then voids the list.
+    auto hit = [&](int j) {
+        const int slot = cnt < cap ? cnt : cap - 1;
+        *(uint32_t*)(tnlb + (((uint32_t)slot << 8) | lane4)) = (uint32_t)j;
+        ++cnt;
+    };
+    auto test = [&](int j, const int4v qj) {
+        if (CUBIC) {
+            // 16-bit prefilter: the high halves of the fixed-point differences
+            // (24-bit multiplies of the upper words), decided outside a band
+            // that bounds its truncation; inside it the 32-bit test, then FP64
+            const int32_t ex = (int32_t)((uint32_t)qj.x - qx), ey = (int32_t)((uint32_t)qj.y - qy),
+                          ez = (int32_t)((uint32_t)qj.z - qz);
+            const int hx = ex >> 16, hy = ey >> 16, hz = ez >> 16;
+            const uint32_t r16 = (uint32_t)__mul24(hx, hx) + (uint32_t)__mul24(hy, hy) + (uint32_t)__mul24(hz, hz);
+            if (r16 < g.r16lo && j != self) hit(j);
+            // lanes with r16 in [lo, hi): one unsigned compare, as a wave mask
+            const uint64_t band = __builtin_amdgcn_uicmp(r16 - g.r16lo, g.r16hi - g.r16lo, 36 /* ult */);
+            if (__builtin_expect(band != 0, 0)) {
+                if ((band >> lane) & 1) {
+                    const float dx = (float)ex, dy = (float)ey, dz = (float)ez;
+                    const float r2 = dx * dx + dy * dy + dz * dz;
+                    bool in = r2 < g.rq2lo;
+                    if (!in && r2 < g.rq2hi) in = exact_r2(g, xi, x[j]) < g.rv2;
+                    if (in && j != self) hit(j);
+                }
+            }
+        } else {
+            const float dx = qdiff((uint32_t)qj.x, qx, g.ql[0]);
+            const float dy = qdiff((uint32_t)qj.y, qy, g.ql[1]);
+            const float dz = qdiff((uint32_t)qj.z, qz, g.ql[2]);
+            const float r2 = dx * dx + dy * dy + dz * dz;
+            if (r2 < g.rv2lo && j != self) hit(j);
+            const uint64_t band = __builtin_amdgcn_uicmp(__float_as_uint(r2) - __float_as_uint(g.rv2lo),
+                                                         __float_as_uint(g.rv2hi) - __float_as_uint(g.rv2lo), 36);
+            if (__builtin_expect(band != 0, 0)) {
+                if (((band >> lane) & 1) && exact_r2(g, xi, x[j]) < g.rv2 && j != self) hit(j);
+            }
+        }
+    };
+    // candidates [j, e) through the scalar cache, 8 and 4 at a time
+    auto scan = [&](int j, const int e) {
+        for (; j + 8 <= e; j += 8) {
+            int4v q[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) q[u] = xqs[j + u];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) test(j + u, q[u]);
+        }
+        for (; j + 4 <= e; j += 4) {
+            const int4v q0 = xqs[j], q1 = xqs[j + 1], q2 = xqs[j + 2], q3 = xqs[j + 3];
+            test(j, q0);
+            test(j + 1, q1);
+            test(j + 2, q2);
+            test(j + 3, q3);
+        }
+        for (; j < e; ++j) test(j, xqs[j]);
+    };
+    int lo = 0;
+    while (lo < nv) {
+        const int x0 = __builtin_amdgcn_readlane(cxl, lo);
+        const int y0 = __builtin_amdgcn_readlane(cyl, lo);
+        const int z0 = __builtin_amdgcn_readlane(czl, lo);
+        const int xlim = x0 + nx - 2 * kc - 1;
+        const int hi = lo + (int)__popcll(__ballot(valid && lane >= lo && cyl == y0 && czl == z0 && cxl <= xlim));
+        const int x1 = __builtin_amdgcn_readlane(cxl, hi - 1);
+        if (lane >= lo && lane < hi) {
+            const int xa = x0 - kc, xb = x1 + kc;
+            for (int oz = -kc; oz <= kc; ++oz) {
+                const int nz = wrapc(z0 + oz, g.nc[2]);
+                for (int oy = -kc; oy <= kc; ++oy) {
+                    const int ny = wrapc(y0 + oy, g.nc[1]);
+                    const int64_t rowc = ((int64_t)nz * g.nc[1] + ny) * nx;
+                    if (xa >= 0 && xb < nx) {
+                        scan(cs[rowc + xa], cs[rowc + xb + 1]);
+                    } else if (xa < 0) {
+                        scan(cs[rowc + nx + xa], cs[rowc + nx]);
+                        scan(cs[rowc], cs[rowc + xb + 1]);
+                    } else {
+                        scan(cs[rowc + xa], cs[rowc + nx]);
+                        scan(cs[rowc], cs[rowc + xb - nx + 1]);
+                    }
+                }
+            }
+        }
+        lo = hi;
+    }
+    if (valid) {
+        b.ncount[p] = cnt;
+        if (cnt > local_max) local_max = cnt;
+        if (cnt > cap) overflow = true;
+        for (int k = cnt; k < ((cnt + 7) & ~7) && k < cap; ++k) tnl[((uint32_t)k << 6) + (uint32_t)lane] = (uint32_t)p;
+        if (bonded) remap_bonded(b, n, p);
+    }
+}
+
+constexpr int kNlBlock = kBlock;
+__global__ void __launch_bounds__(kNlBlock) k_nl_tiles(Geom g, Bufs b, int parity, int bonded) {
+    if (!rebuild_requested(b)) return;
+    // wave-uniform tile index (readfirstlane keeps it in scalar registers)
+    const int64_t t = (int64_t)xcd_block(blockIdx.x, gridDim.x) * (kNlBlock / kTile) +
+                      __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kTile));
+    int local_max = 0;
+    bool overflow = false;
+    if (t * kTile < g.n) {
+        if (g.nl_cubic) nl_tile<true>(g, b, t, parity, bonded, local_max, overflow);
+        else nl_tile<false>(g, b, t, parity, bonded, local_max, overflow);
+    }
     nl_epilogue(b, local_max, overflow);
 }
 
@@ -1207,7 +1411,7 @@ __global__ void __launch_bounds__(kBlock) k_batch_bin(const SysEntry* __restrict
     const Bufs& b = r.e->a.b;
     if (!rebuild_requested(b)) return;
     const Geom& g = r.e->a.g;
-    if (r.i < g.n) bin_one(g, b, r.i, parity);
+    bin_one(g, b, r.i, r.i < g.n, parity);
 }
 
 // prefix of the concatenated counts at each system's first cell
@@ -1234,7 +1438,7 @@ __global__ void __launch_bounds__(kBlock) k_batch_scatter(const SysEntry* __rest
     const TileRef r = tile_ref(tab, tile_sys);
     const Bufs& b = r.e->a.b;
     if (!rebuild_requested(b)) return;
-    if (r.i < r.e->a.g.n) scatter_one(b, r.i);
+    scatter_one(b, r.i, r.i < r.e->a.g.n);
 }
 
 __global__ void __launch_bounds__(kBlock) k_batch_permute(const SysEntry* __restrict__ tab,
@@ -1263,7 +1467,15 @@ __global__ void __launch_bounds__(kBlock) k_batch_nl(const SysEntry* __restrict_
     const Geom& g = r.e->a.g;
     int local_max = 0;
     bool overflow = false;
-    if (r.i < g.n) nl_one(g, b, r.i, parity, r.e->bonded, local_max, overflow);
+    if (g.nl_tile) {
+        const int64_t t = r.lt * (kBlock / kTile) + __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kTile));
+        if (t * kTile < g.n) {
+            if (g.nl_cubic) nl_tile<true>(g, b, t, parity, r.e->bonded, local_max, overflow);
+            else nl_tile<false>(g, b, t, parity, r.e->bonded, local_max, overflow);
+        }
+    } else if (r.i < g.n) {
+        nl_one(g, b, r.i, parity, r.e->bonded, local_max, overflow);
+    }
     nl_epilogue(b, local_max, overflow);
 }
 
@@ -1374,7 +1586,11 @@ hipError_t launch_rebuild(const Geom& g, const Bufs& b, int parity, int bonded, 
     hipLaunchKernelGGL(k_scatter, dim3(gs), dim3(kBlock), 0, s, g, b);
     hipLaunchKernelGGL(k_rank_permute, dim3(gs), dim3(kBlock), 0, s, g, b, parity);
     hipLaunchKernelGGL(k_commit, dim3(gs), dim3(kBlock), 0, s, g, b, parity, bonded);
-    hipLaunchKernelGGL(k_nl_build, dim3(grid_for(g.n, 1 << 20)), dim3(kBlock), 0, s, g, b, parity, bonded);
+    if (g.nl_tile)
+        hipLaunchKernelGGL(k_nl_tiles, dim3((unsigned)((g.n + kNlBlock - 1) / kNlBlock)), dim3(kNlBlock), 0, s, g, b,
+                           parity, bonded);
+    else
+        hipLaunchKernelGGL(k_nl_build, dim3(grid_for(g.n, 1 << 20)), dim3(kBlock), 0, s, g, b, parity, bonded);
     if (ev1) (void)hipEventRecord(ev1, s);
     return hipGetLastError();
 }

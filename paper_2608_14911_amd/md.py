@@ -39,6 +39,8 @@ MD_MAX_TYPES = 4
 MD_HISTORY_CAPACITY = 8192
 MD_CFG_VIRIAL_TENSOR = 0x1
 MD_CFG_NO_GRAPH = 0x2
+MD_CFG_NL_PER_PARTICLE = 0x4
+MD_CFG_NL_TILES = 0x8
 MD_SUR_NBASIS = 32
 MD_SUR_HIDDEN = 64
 MD_SUR_NPARAM = 6337

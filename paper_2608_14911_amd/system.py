@@ -115,7 +115,9 @@ class System:
                         None if pb is None else pb.data_ptr(), state.get("step", 0), state.get("vel_half", 0))
         self.stream.synchronize()
 
-    def neighbors(self, cap=None):
+    def neighbors(self, cap=None, sort=True):
+        """Neighbour tags of every particle (by tag), sorted, or in row order
+        with sort=False."""
         t = self.torch
         cap = cap or int(self.cfg.nl_capacity or 512)
         cnt = t.zeros(self.n, dtype=t.int32, device=self.device)
@@ -123,6 +125,8 @@ class System:
         md.md_get_neighbors(self.h, cnt.data_ptr(), idx.data_ptr(), cap)
         c = cnt.cpu().numpy()
         m = idx.cpu().numpy()
+        if not sort:
+            return [m[i, :c[i]].copy() for i in range(self.n)]
         return [np.sort(m[i, :c[i]]) for i in range(self.n)]
 
     def timing(self, enable=None):
