@@ -76,11 +76,12 @@ enum { MD_FP64 = 0, MD_FP32 = 1 };       /* md_config.force_precision */
 /* md_config.flags */
 #define MD_CFG_VIRIAL_TENSOR 0x1  /* accumulate the 6-component virial every step */
 #define MD_CFG_NO_GRAPH 0x2       /* md_step launches kernels one by one, no hipGraph */
-#define MD_CFG_NL_PER_PARTICLE 0x4 /* build the Verlet list one particle per lane */
-#define MD_CFG_NL_TILES 0x8        /* build it one wavefront per 64-particle tile; without
-                                      either flag: tiles when cells of side rc+skin hold
-                                      >= 8 particles on average, else per particle.  Both
-                                      builds give the same lists, entry for entry */
+#define MD_CFG_NL_PER_PARTICLE 0x4 /* build the Verlet list one particle per lane (half-
+                                      cutoff cells when cell_factor = 0 and they fit) */
+#define MD_CFG_NL_TILES 0x8        /* build it one wavefront per 64-particle tile.  Default:
+                                      tiles when cells of side rc+skin hold >= 8 particles
+                                      on average, else per particle.  Both builds give the
+                                      same lists, entry for entry, for equal cells */
 
 /* One type pair of the LennardJones / LennardJonesCapped potential
  * (section "Example usage"): u(r) = 4 eps [(sigma/r)^12 - (sigma/r)^6] - shift

@@ -10,7 +10,7 @@
 namespace md {
 
 constexpr int kBlock = 256;            // threads per block of the streaming kernels
-constexpr int kScanBlocks = 256;       // blocks of the 3-phase cell-count scan (<= 1024)
+constexpr int kScanBlocks = 1024;      // blocks of the 3-phase cell-count scan (<= 1024)
 constexpr int kMaxGrid = 65535 * 16;   // cap for 1-D grids
 constexpr int kNacc = 11;              // reduced quantities per step, see Acc
 constexpr int kHistRec = 16;           // doubles per history record

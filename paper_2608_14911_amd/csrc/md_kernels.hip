@@ -337,12 +337,22 @@ __global__ void __launch_bounds__(kBlock) k_scan_apply(Geom g, Bufs b) {
     int64_t lo, hi;
     scan_chunk(g, blockIdx.x, lo, hi);
     int running = b.bsum[blockIdx.x];
-    for (int64_t base = lo; base < hi; base += kBlock) {
-        int64_t c = base + threadIdx.x;
-        int v = (c < hi) ? b.ccount[c] : 0;
+    // four consecutive cells per thread and step
+    for (int64_t base = lo; base < hi; base += 4 * kBlock) {
+        const int64_t c0 = base + 4 * (int64_t)threadIdx.x;
+        int v[4], sum = 0;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            v[u] = (c0 + u < hi) ? b.ccount[c0 + u] : 0;
+            sum += v[u];
+        }
         int tot;
-        int e = block_exclusive_scan(v, tot);
-        if (c < hi) b.cstart[c] = running + e;
+        int e = block_exclusive_scan(sum, tot);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            if (c0 + u < hi) b.cstart[c0 + u] = running + e;
+            e += v[u];
+        }
         running += tot;
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) b.cstart[g.ncell] = (int32_t)g.n;
@@ -386,7 +396,12 @@ __device__ __forceinline__ void permute_one(const Geom& g, const Bufs& b, int64_
         int32_t ti = b.tsc[s];
         int st = b.cstart[c], en = b.cstart[c + 1];
         int r = 0;
-        for (int u = st; u < en; ++u) r += (b.tsc[u] < ti);
+        int u = st;
+        for (; u + 4 <= en; u += 4) {
+            const int a0 = b.tsc[u], a1 = b.tsc[u + 1], a2 = b.tsc[u + 2], a3 = b.tsc[u + 3];
+            r += (a0 < ti) + (a1 < ti) + (a2 < ti) + (a3 < ti);
+        }
+        for (; u < en; ++u) r += (b.tsc[u] < ti);
         int64_t nw = st + r;
         b.xt[nw] = b.x[parity][i];
         for (int d = 0; d < 3; ++d) {
@@ -597,43 +612,29 @@ typedef int int4v __attribute__((ext_vector_type(4)));
 typedef const __attribute__((address_space(4))) int4v* __restrict__ scalar_int4_ptr;
 typedef const __attribute__((address_space(4))) int32_t* __restrict__ scalar_i32_ptr;
 
-template <bool CUBIC>
-__device__ __forceinline__ void nl_tile(const Geom& g, const Bufs& b, int64_t t, int parity, int bonded,
-                                        int& local_max, bool& overflow) {
-    const int lane = threadIdx.x & (kTile - 1);
-    const int64_t n = g.n, p = t * kTile + lane;
-    const int nv = (n - t * kTile < kTile) ? (int)(n - t * kTile) : kTile;
-    const bool valid = lane < nv;
-    const double4* __restrict__ x = b.x[parity];
-    // the particle data are not written by this kernel: uniform loads through
-    // the constant address space become scalar loads
-    const scalar_int4_ptr xqs = (scalar_int4_ptr)(const void*)b.xq[parity];
-    const scalar_i32_ptr cs = (scalar_i32_ptr)(const void*)b.cstart;
-    const int cap = g.cap, kc = g.kc, nx = g.nc[0];
-    int cxl = -1, cyl = -1, czl = -1;
-    uint32_t qx = 0, qy = 0, qz = 0;
-    double4 xi = make_double4(0.0, 0.0, 0.0, 0.0);
-    if (valid) {
-        xi = x[p];
-        cell_coords(g, xi.x, xi.y, xi.z, cxl, cyl, czl);
-        const int4 q = b.xq[parity][p];
-        qx = (uint32_t)q.x;
-        qy = (uint32_t)q.y;
-        qz = (uint32_t)q.z;
-    }
-    uint32_t* __restrict__ tnl = (uint32_t*)(b.nl + t * (int64_t)cap * kTile);
-    char* __restrict__ tnlb = (char*)tnl;           // byte base: 32-bit offsets from a scalar base
-    const uint32_t lane4 = (uint32_t)lane << 2;
-    const int self = (int)p;
-    int cnt = 0;
+// Row builder state of one lane (one particle of a tile): its fixed-point
+// and FP64 position, its row in the tile's list block and the row length.
+struct NlRow {
+    uint32_t qx, qy, qz;
+    double4 xi;
+    int self, cnt, cap;
+    char* tnlb;          // byte base of the tile's list block (32-bit offsets from it)
+    uint32_t lane4;
+
     // A hit goes to slot min(cnt, cap - 1): an overflowing row overwrites its
     // last slot, and the overflow flag then voids the list.
-    auto hit = [&](int j) {
+    __device__ __forceinline__ void hit(int j) {
         const int slot = cnt < cap ? cnt : cap - 1;
         *(uint32_t*)(tnlb + (((uint32_t)slot << 8) | lane4)) = (uint32_t)j;
         ++cnt;
-    };
-    auto test = [&](int j, const int4v qj) {
+    }
+
+    // Candidate j at fixed-point position qj, counted when ok.  All lanes of
+    // the wavefront call it together (the band test is a wavefront mask).
+    template <bool CUBIC>
+    __device__ __forceinline__ void test(const Geom& g, const double4* __restrict__ x, int j, const int4v qj,
+                                         bool ok) {
+        const int lane = threadIdx.x & 63;
         if (CUBIC) {
             // 16-bit prefilter: the high halves of the fixed-point differences
             // (24-bit multiplies of the upper words), decided outside a band
@@ -642,11 +643,11 @@ __device__ __forceinline__ void nl_tile(const Geom& g, const Bufs& b, int64_t t,
                           ez = (int32_t)((uint32_t)qj.z - qz);
             const int hx = ex >> 16, hy = ey >> 16, hz = ez >> 16;
             const uint32_t r16 = (uint32_t)__mul24(hx, hx) + (uint32_t)__mul24(hy, hy) + (uint32_t)__mul24(hz, hz);
-            if (r16 < g.r16lo && j != self) hit(j);
+            if (ok && r16 < g.r16lo && j != self) hit(j);
             // lanes with r16 in [lo, hi): one unsigned compare, as a wave mask
             const uint64_t band = __builtin_amdgcn_uicmp(r16 - g.r16lo, g.r16hi - g.r16lo, 36 /* ult */);
             if (__builtin_expect(band != 0, 0)) {
-                if ((band >> lane) & 1) {
+                if (ok && ((band >> lane) & 1)) {
                     const float dx = (float)ex, dy = (float)ey, dz = (float)ez;
                     const float r2 = dx * dx + dy * dy + dz * dz;
                     bool in = r2 < g.rq2lo;
@@ -659,14 +660,71 @@ __device__ __forceinline__ void nl_tile(const Geom& g, const Bufs& b, int64_t t,
             const float dy = qdiff((uint32_t)qj.y, qy, g.ql[1]);
             const float dz = qdiff((uint32_t)qj.z, qz, g.ql[2]);
             const float r2 = dx * dx + dy * dy + dz * dz;
-            if (r2 < g.rv2lo && j != self) hit(j);
+            if (ok && r2 < g.rv2lo && j != self) hit(j);
             const uint64_t band = __builtin_amdgcn_uicmp(__float_as_uint(r2) - __float_as_uint(g.rv2lo),
                                                          __float_as_uint(g.rv2hi) - __float_as_uint(g.rv2lo), 36);
             if (__builtin_expect(band != 0, 0)) {
-                if (((band >> lane) & 1) && exact_r2(g, xi, x[j]) < g.rv2 && j != self) hit(j);
+                if (ok && ((band >> lane) & 1) && exact_r2(g, xi, x[j]) < g.rv2 && j != self) hit(j);
             }
         }
-    };
+    }
+};
+
+// Lane setup shared by the tile builds: particle p = t*64 + lane, its cell
+// and its row state.
+__device__ __forceinline__ NlRow nl_row_setup(const Geom& g, const Bufs& b, int64_t t, int parity, bool valid,
+                                              int& cxl, int& cyl, int& czl) {
+    const int lane = threadIdx.x & (kTile - 1);
+    const int64_t p = t * kTile + lane;
+    NlRow r;
+    r.qx = r.qy = r.qz = 0;
+    r.xi = make_double4(0.0, 0.0, 0.0, 0.0);
+    cxl = cyl = czl = -1;
+    if (valid) {
+        r.xi = b.x[parity][p];
+        cell_coords(g, r.xi.x, r.xi.y, r.xi.z, cxl, cyl, czl);
+        const int4 q = b.xq[parity][p];
+        r.qx = (uint32_t)q.x;
+        r.qy = (uint32_t)q.y;
+        r.qz = (uint32_t)q.z;
+    }
+    r.self = (int)p;
+    r.cnt = 0;
+    r.cap = g.cap;
+    r.tnlb = (char*)(b.nl + t * (int64_t)g.cap * kTile);
+    r.lane4 = (uint32_t)lane << 2;
+    return r;
+}
+
+// Row count, padding to a multiple of 8 with the particle itself, and the
+// bonded remap.
+__device__ __forceinline__ void nl_row_finish(const Geom& g, const Bufs& b, const NlRow& r, bool valid, int bonded,
+                                              int& local_max, bool& overflow) {
+    if (!valid) return;
+    const int64_t p = r.self;
+    b.ncount[p] = r.cnt;
+    if (r.cnt > local_max) local_max = r.cnt;
+    if (r.cnt > g.cap) overflow = true;
+    for (int k = r.cnt; k < ((r.cnt + 7) & ~7) && k < g.cap; ++k)
+        *(uint32_t*)(r.tnlb + (((uint32_t)k << 8) | r.lane4)) = (uint32_t)p;
+    if (bonded) remap_bonded(b, g.n, p);
+}
+
+template <bool CUBIC>
+__device__ __forceinline__ void nl_tile(const Geom& g, const Bufs& b, int64_t t, int parity, int bonded,
+                                        int& local_max, bool& overflow) {
+    const int lane = threadIdx.x & (kTile - 1);
+    const int64_t n = g.n;
+    const int nv = (n - t * kTile < kTile) ? (int)(n - t * kTile) : kTile;
+    const bool valid = lane < nv;
+    const double4* __restrict__ x = b.x[parity];
+    // the particle data are not written by this kernel: uniform loads through
+    // the constant address space become scalar loads
+    const scalar_int4_ptr xqs = (scalar_int4_ptr)(const void*)b.xq[parity];
+    const scalar_i32_ptr cs = (scalar_i32_ptr)(const void*)b.cstart;
+    const int kc = g.kc, nx = g.nc[0];
+    int cxl, cyl, czl;
+    NlRow row = nl_row_setup(g, b, t, parity, valid, cxl, cyl, czl);
     // candidates [j, e) through the scalar cache, 8 and 4 at a time
     auto scan = [&](int j, const int e) {
         for (; j + 8 <= e; j += 8) {
@@ -674,16 +732,16 @@ __device__ __forceinline__ void nl_tile(const Geom& g, const Bufs& b, int64_t t,
 #pragma unroll
             for (int u = 0; u < 8; ++u) q[u] = xqs[j + u];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) test(j + u, q[u]);
+            for (int u = 0; u < 8; ++u) row.test<CUBIC>(g, x, j + u, q[u], true);
         }
         for (; j + 4 <= e; j += 4) {
             const int4v q0 = xqs[j], q1 = xqs[j + 1], q2 = xqs[j + 2], q3 = xqs[j + 3];
-            test(j, q0);
-            test(j + 1, q1);
-            test(j + 2, q2);
-            test(j + 3, q3);
+            row.test<CUBIC>(g, x, j, q0, true);
+            row.test<CUBIC>(g, x, j + 1, q1, true);
+            row.test<CUBIC>(g, x, j + 2, q2, true);
+            row.test<CUBIC>(g, x, j + 3, q3, true);
         }
-        for (; j < e; ++j) test(j, xqs[j]);
+        for (; j < e; ++j) row.test<CUBIC>(g, x, j, xqs[j], true);
     };
     int lo = 0;
     while (lo < nv) {
@@ -714,13 +772,7 @@ __device__ __forceinline__ void nl_tile(const Geom& g, const Bufs& b, int64_t t,
         }
         lo = hi;
     }
-    if (valid) {
-        b.ncount[p] = cnt;
-        if (cnt > local_max) local_max = cnt;
-        if (cnt > cap) overflow = true;
-        for (int k = cnt; k < ((cnt + 7) & ~7) && k < cap; ++k) tnl[((uint32_t)k << 6) + (uint32_t)lane] = (uint32_t)p;
-        if (bonded) remap_bonded(b, n, p);
-    }
+    nl_row_finish(g, b, row, valid, bonded, local_max, overflow);
 }
 
 constexpr int kNlBlock = kBlock;
