@@ -56,7 +56,8 @@ def parse():
     ap.add_argument("--workload", default="lj1m", choices=["lj1m", "kg2m", "kg1k", "batch", "sur1m"])
     ap.add_argument("--sur-precision", default="bf16", choices=["fp32", "bf16"],
                     help="sur1m: network precision of the surrogate")
-    ap.add_argument("--no-autotune", action="store_true", help="batch: keep the sampler's skin, cell factor 2")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="batch: keep the sampler's skin and the library's automatic cells and list build")
     ap.add_argument("--no-events", action="store_true",
                     help="time with a hipGraph replay and no per-kernel events")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -164,7 +165,7 @@ def member_alg_bytes(m, n, skin):
 def bench_batch(a):
     import torch
     from paper_2608_14911_amd import autotune, inputs
-    from paper_2608_14911_amd.system import Batch, System, lj_pair, prepare_replica
+    from paper_2608_14911_amd.system import Batch, System, lj_pair, nl_build_flags, prepare_replica
     t0 = time.time()
     reps = inputs.batch_replicas(256, seed=1003)
     out = []
@@ -174,7 +175,7 @@ def bench_batch(a):
             log("replicas prepared: %d / %d (%.0f s)" % (k + 1, len(reps), time.time() - t0), a.quiet)
     reps = out
     if a.no_autotune:
-        choice = {"lj": (0.3, 2), "kg": (0.4, 2)}
+        choice = {"lj": (0.3, 0, "auto"), "kg": (0.4, 0, "auto")}
         table = []
     else:
         choice, table = autotune.tune(reps, steps=30, log=lambda m: log(m, a.quiet))
@@ -198,7 +199,8 @@ def bench_batch(a):
     for r in reps:
         s = System(r["pos"], r["box"], r["vel"], pair=r["pair"], bonds=r.get("bonds"), angles=r.get("angles"),
                    k_bend=r.get("k_bend", 0.0), dt=r["dt"], skin=r["skin"], integrator=r["integrator"],
-                   temperature=r["temperature"], gamma=r["gamma"], seed=r["seed"], cell_factor=r["cell_factor"])
+                   temperature=r["temperature"], gamma=r["gamma"], seed=r["seed"], cell_factor=r["cell_factor"],
+                   flags=nl_build_flags(r["nl_build"]))
         s.step(4)
         s.stream.synchronize()
         t1 = time.perf_counter()
@@ -218,8 +220,9 @@ def bench_batch(a):
         "config": {"workload": "batch of 256 replicas (128 LJ fluids, 128 polymer melts), %d particles" % ntot,
                    "n_particles": ntot, "replicas": len(reps), "sizes": "log-uniform 2048..65536",
                    "precision": "FP32 pair/bonded math, FP64 positions, velocities and reductions",
-                   "parallelism": "single GPU", "autotuned": {k: {"skin": v[0], "cell_factor": v[1]}
-                                                             for k, v in choice.items()}},
+                   "parallelism": "single GPU",
+                   "autotuned": {k: {"skin": v[0], "cell_factor": v[1] or "auto", "nl_build": v[2]}
+                                 for k, v in choice.items()}},
         "standalone_sum_atom_steps_per_s": ntot / t_sum,
         "batched_over_standalone": value / (ntot / t_sum),
         "n_rebuilds_total": sum(x["n_rebuilds"] - y["n_rebuilds"] for x, y in zip(o1, o0)),

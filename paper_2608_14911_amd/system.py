@@ -240,12 +240,18 @@ def prepare_replica(m, log=None):
     return out
 
 
+def nl_build_flags(name):
+    """md_config.flags bits for a list-build choice."""
+    return {"auto": 0, "tiles": md.MD_CFG_NL_TILES, "per_particle": md.MD_CFG_NL_PER_PARTICLE}[name]
+
+
 class Batch:
     """Many independent systems advanced together (md_batch_*).
 
     ``members``: list of dicts with the keys of ``System`` (pos, box, vel,
     pair, bonds, angles, dt, skin, integrator, temperature, gamma, seed,
-    k_bend, cell_factor, nl_capacity, masses)."""
+    k_bend, cell_factor, nl_capacity, masses) and ``nl_build`` ("auto",
+    "tiles" or "per_particle": the Verlet-list build)."""
 
     def __init__(self, members, device="cuda"):
         torch = _torch()
@@ -266,7 +272,8 @@ class Batch:
                                  seed=m.get("seed", 0), n_bonds=0 if b is None else len(b),
                                  n_angles=0 if a is None else len(a), fene_K=m.get("fene_K", 30.0),
                                  fene_R0=m.get("fene_R0", 1.5), k_bend=m.get("k_bend", 0.0),
-                                 nl_capacity=m.get("nl_capacity", 0), cell_factor=m.get("cell_factor", 0))
+                                 nl_capacity=m.get("nl_capacity", 0), cell_factor=m.get("cell_factor", 0),
+                                 flags=nl_build_flags(m.get("nl_build", "auto")))
             dp = torch.as_tensor(pos, device=self.device)
             dv = torch.as_tensor(vel, device=self.device)
             self._keep += [dp, dv]
