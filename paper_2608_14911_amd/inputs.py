@@ -110,6 +110,36 @@ def random_walk_chains(n_chains, chain_len, density, bond=0.97, seed=0):
             "chain_len": chain_len, "n_chains": n_chains}
 
 
+def lattice_melt(n_chains, chain_len, density, jitter=0.05, seed=0):
+    """Chains laid along a boustrophedon path through a simple cubic lattice
+    (m^3 >= n sites, spacing a = (n / density)^(1/3) / m), cut into
+    ``n_chains`` consecutive pieces of ``chain_len`` beads, with uniform
+    jitter +-``jitter``*a per component (stream 2).  Bonds join lattice
+    neighbours (length a), so no bead overlaps and no push-off is needed.
+    Returns dict(pos, box, bonds, angles, chain_len, n_chains)."""
+    n = n_chains * chain_len
+    m = int(np.ceil(n ** (1.0 / 3.0) - 1e-9))
+    L = (n / density) ** (1.0 / 3.0)
+    a = L / m
+    # boustrophedon order: x reverses on odd rows, y on odd planes, so that
+    # consecutive sites are lattice neighbours
+    iz, j, i = np.meshgrid(np.arange(m), np.arange(m), np.arange(m), indexing="ij")
+    iy = np.where(iz % 2 == 1, m - 1 - j, j)          # j-th row visited in plane iz
+    ix = np.where((iz * m + j) % 2 == 1, m - 1 - i, i)  # direction alternates with every row
+    sites = np.stack([ix.ravel(), iy.ravel(), iz.ravel()], axis=1)[:n].astype(np.float64)
+    g = rng(seed, STREAM_POS)
+    pos = (sites + 0.5 + g.uniform(-jitter, jitter, size=(n, 3))) * a
+    box = np.array([L, L, L])
+    pos = wrap_into_box(pos, box)
+    base = (np.arange(n_chains) * chain_len)[:, None]
+    k = np.arange(chain_len - 1)[None, :]
+    bonds = np.stack([(base + k).ravel(), (base + k + 1).ravel()], axis=1).astype(np.int32)
+    k = np.arange(chain_len - 2)[None, :]
+    angles = np.stack([(base + k).ravel(), (base + k + 1).ravel(), (base + k + 2).ravel()], axis=1).astype(np.int32)
+    return {"pos": pos, "box": box, "bonds": bonds, "angles": angles,
+            "chain_len": chain_len, "n_chains": n_chains}
+
+
 # ------------------------------------------------------------------ workloads
 def kg_params(rc=WCA_RC, fene_K=30.0, fene_R0=1.5, k_bend=0.0):
     return {"eps": 1.0, "sigma": 1.0, "rc": rc, "shift": float("nan"), "caprad": 0.0,

@@ -11,7 +11,7 @@ import subprocess
 import numpy as np
 import pytest
 
-from paper_2608_14911_amd import md
+from paper_2608_14911_amd import inputs, md
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "md.h")
@@ -216,3 +216,27 @@ def test_batch_replica_sampler_matches_its_definition():
             assert 10 <= r["chain_len"] <= 200 and r["pos"].shape[0] % r["chain_len"] == 0
     # log-uniform sizes: the median is near the geometric mean of the range
     assert 6000 < np.median(ns) < 17000
+
+
+def test_lattice_melt_bonds_join_lattice_neighbours():
+    """The lattice melt's path visits every site once and each bond joins
+    lattice neighbours: bond lengths stay within the jitter of the spacing,
+    no two beads come closer than the spacing minus the jitter, and the
+    density is the requested one."""
+    for nc, cl in [(4, 50), (13, 77), (7, 300)]:
+        w = inputs.lattice_melt(nc, cl, 0.85, jitter=0.05, seed=3)
+        pos, box, b = w["pos"], w["box"], w["bonds"]
+        n = nc * cl
+        assert pos.shape == (n, 3) and abs(n / np.prod(box) - 0.85) < 1e-12
+        m = int(np.ceil(n ** (1.0 / 3.0) - 1e-9))
+        a = box[0] / m
+        d = pos[b[:, 1]] - pos[b[:, 0]]
+        d -= box * np.round(d / box)
+        r = np.linalg.norm(d, axis=1)
+        # each bead moves by at most 0.05 a per component
+        assert r.min() >= a * (1 - 0.1) - 1e-12 and r.max() <= a * np.sqrt(1.1 ** 2 + 2 * 0.1 ** 2) + 1e-12
+        # sites distinct: rounding back to the lattice gives n different sites
+        sites = np.floor(pos / a).astype(np.int64) % m
+        key = (sites[:, 2] * m + sites[:, 1]) * m + sites[:, 0]
+        assert np.unique(key).size == n
+        assert w["angles"].shape == (nc * (cl - 2), 3)

@@ -1,0 +1,102 @@
+"""Parity at the full benchmark sizes, in the configuration bench.py times.
+
+The 1,048,576-particle LJ fluid (FCC 64^3 with jitter, rc 2.5, skin 0.3,
+NVE) and a 2,000,000-bead Kremer-Grest melt (2,000 chains x 1,000 beads at
+density 0.85, WCA + FENE + bending 1.5, Langevin, skin 0.4) run with FP32
+pair math and the library's automatic choices.  That is the tile list build
+on cells of side rc+skin for the fluid, and the per-particle build on
+half-cutoff cells for the melt.  The FP64 oracle (linked cells, all host
+threads) computes every particle's force at full size, so the check is
+element by element, not sampled:
+
+* every particle's force within 1e-5 of the oracle's, relative to the sum
+  of its pair force magnitudes, and the norm of the difference within 1e-5
+  of the force norm;
+* pair, bond and angle energies and the virial within 1e-5 (relative);
+* neighbour rows of 4,096 sampled particles equal to the oracle's brute-
+  force sets bit for bit, at the build positions;
+* the same again after 40 steps with several list rebuilds.
+
+The melt starts from chains laid on a simple cubic lattice
+(``inputs.lattice_melt``), which has no overlapping beads and so needs no
+push-off.  The benchmark's pushed-off random walks exercise the same
+kernels.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from gpu_helpers import WCA, assert_forces_close, banner, oracle_pp, rel
+from paper_2608_14911_amd import inputs, md
+from paper_2608_14911_amd.system import from_workload
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+NSAMPLE = 4096
+
+
+def sampled_rows(s, sample, cap):
+    """Neighbour tags of the sampled tags, sorted (rows come back by tag)."""
+    cnt = torch.zeros(s.n, dtype=torch.int32, device=s.device)
+    idx = torch.full((s.n, cap), -1, dtype=torch.int32, device=s.device)
+    md.md_get_neighbors(s.h, cnt.data_ptr(), idx.data_ptr(), cap)
+    sel = torch.as_tensor(sample, device=s.device)
+    c = cnt[sel].cpu().numpy()
+    m = idx[sel].cpu().numpy()
+    del cnt, idx
+    return [np.sort(m[k, :c[k]]) for k in range(len(sample))]
+
+
+def check(s, w, pp, rv, cap, bonded, what):
+    F = s.forces()
+    o = s.observables()
+    st = s.get_state()
+    kw = {}
+    if bonded:
+        kw = dict(bonds=w["bonds"], angles=w["angles"], fene_K=w["fene_K"], fene_R0=w["fene_R0"],
+                  k_bend=w["k_bend"])
+    Fo, oo = oracle.forces(st["pos"], w["box"], pp, want_fscale=True, **kw)
+    assert_forces_close(F, Fo, oo["fscale"], TOL, what)
+    keys = ("e_pair", "e_bond", "e_angle", "virial") if bonded else ("e_pair", "virial")
+    for k in keys:
+        assert rel(o[k], oo[k]) < TOL, (what, k, o[k], oo[k])
+    # rows against brute force at the positions the list was built from
+    g = np.random.default_rng(7)
+    sample = np.sort(g.choice(s.n, size=NSAMPLE, replace=False))
+    got = sampled_rows(s, sample, cap)
+    ref = oracle.neighbors(st["pos_build"], w["box"], rv, query=sample, cap=cap)
+    for k in range(NSAMPLE):
+        assert np.array_equal(got[k], ref[k]), (what, int(sample[k]))
+    return o
+
+
+def test_lj_1m_full_size():
+    w = inputs.workload_lj(ncell=64, seed=1001)
+    banner("full-size LJ fluid n=%d" % w["pos"].shape[0])
+    s = from_workload(w, precision="fp32")
+    pp = oracle_pp(rc=w["rc"])
+    rv = w["rc"] + w["skin"]
+    check(s, w, pp, rv, 256, False, "LJ 1M start")
+    s.step(40)
+    o = check(s, w, pp, rv, 256, False, "LJ 1M after 40 steps")
+    assert o["n_rebuilds"] >= 3 and o["status_flags"] == 0
+    s.close()
+
+
+def test_kg_2m_full_size():
+    w = inputs.lattice_melt(2000, 1000, 0.85, jitter=0.05, seed=1002)
+    w.update(inputs.kg_params(k_bend=1.5))
+    w["vel"] = inputs.maxwell_boltzmann(w["pos"].shape[0], 1.0, seed=1002, zero_momentum=False, exact=False)
+    w.update({"dt": 0.01, "skin": 0.4, "temperature": 1.0, "gamma": 0.5, "integrator": "langevin",
+              "seed": 1002})
+    banner("full-size KG melt n=%d" % w["pos"].shape[0])
+    s = from_workload(w, precision="fp32")
+    pp = oracle_pp(rc=WCA)
+    rv = WCA + w["skin"]
+    check(s, w, pp, rv, 128, True, "KG 2M start")
+    s.step(40)
+    o = check(s, w, pp, rv, 128, True, "KG 2M after 40 steps")
+    assert o["n_rebuilds"] >= 2 and o["status_flags"] == 0
+    s.close()
