@@ -12,7 +12,9 @@ element by element, not sampled:
 * every particle's force within 1e-5 of the oracle's, relative to the sum
   of its pair force magnitudes, and the norm of the difference within 1e-5
   of the force norm;
-* pair, bond and angle energies and the virial within 1e-5 (relative);
+* pair, bond and angle energies within 1e-5 (relative), the virial within
+  1e-5 of its condition (the sum of |r_ij . f_ij|, bounded from the
+  oracle's per-particle force sums);
 * neighbour rows of 4,096 sampled particles equal to the oracle's brute-
   force sets bit for bit, at the build positions;
 * the same again after 40 steps with several list rebuilds.
@@ -49,6 +51,15 @@ def sampled_rows(s, sample, cap):
     return [np.sort(m[k, :c[k]]) for k in range(len(sample))]
 
 
+def virial_close(got, ref, fscale, rmax):
+    """|W - W_ref| <= TOL * max(|W_ref|, sum of |r_ij . f_ij|): the pair terms
+    have both signs, so the sum is bounded by its own condition
+    (sum_ij |r f| <= rmax * sum_i sum_j |f_ij| / 2 with rmax the largest
+    interaction range)."""
+    scale = 0.5 * rmax * float(np.sum(fscale))
+    return abs(got - ref) <= TOL * max(abs(ref), scale)
+
+
 def check(s, w, pp, rv, cap, bonded, what):
     F = s.forces()
     o = s.observables()
@@ -59,9 +70,11 @@ def check(s, w, pp, rv, cap, bonded, what):
                   k_bend=w["k_bend"])
     Fo, oo = oracle.forces(st["pos"], w["box"], pp, want_fscale=True, **kw)
     assert_forces_close(F, Fo, oo["fscale"], TOL, what)
-    keys = ("e_pair", "e_bond", "e_angle", "virial") if bonded else ("e_pair", "virial")
+    keys = ("e_pair", "e_bond", "e_angle") if bonded else ("e_pair",)
     for k in keys:
         assert rel(o[k], oo[k]) < TOL, (what, k, o[k], oo[k])
+    rmax = max(w["rc"], w.get("fene_R0", 0.0) if bonded else 0.0)
+    assert virial_close(o["virial"], oo["virial"], oo["fscale"], rmax), (what, o["virial"], oo["virial"])
     # rows against brute force at the positions the list was built from
     g = np.random.default_rng(7)
     sample = np.sort(g.choice(s.n, size=NSAMPLE, replace=False))
@@ -100,3 +113,44 @@ def test_kg_2m_full_size():
     o = check(s, w, pp, rv, 128, True, "KG 2M after 40 steps")
     assert o["n_rebuilds"] >= 2 and o["status_flags"] == 0
     s.close()
+
+
+def lattice_replica(r):
+    """A melt replica of the sampler laid on a lattice instead of pushed off:
+    same bead count, chain length and density."""
+    n = r["pos"].shape[0]
+    lc = r["chain_len"]
+    w = inputs.lattice_melt(n // lc, lc, r["density"], jitter=0.05, seed=r["seed"])
+    out = dict(r)
+    out.update(pos=w["pos"], box=w["box"], bonds=w["bonds"], angles=w["angles"])
+    return out
+
+
+def test_batch_256_full_size():
+    """The benchmark's 256 replicas (4.7M particles; melts on lattices) in one
+    batch with the automatic builds: after 20 steps, the observables of 32
+    members (evaluated at their current positions) match the oracle's
+    energies and virial at those positions within 1e-5."""
+    from paper_2608_14911_amd.system import Batch
+    reps = inputs.batch_replicas(256, seed=1003)
+    reps = [lattice_replica(r) if r["kind"] == "kg" else r for r in reps]
+    banner("full-size batch: %d replicas, %d particles" % (len(reps), sum(r["pos"].shape[0] for r in reps)))
+    b = Batch(reps)
+    b.step(20)
+    sample = list(range(0, 256, 16)) + list(range(1, 256, 16))
+    ob = b.observables()
+    for k in sample:
+        r, st = reps[k], b.get_state(k)
+        assert st["step"] == 20 and ob[k]["step"] == 20 and ob[k]["status_flags"] == 0, k
+        row = r["pair"][(0, 0)]
+        pp = oracle_pp(eps=row[0], sigma=row[1], rc=row[2], shift=row[3], caprad=row[4])
+        kw = {}
+        if r["kind"] == "kg":
+            kw = dict(bonds=r["bonds"], angles=r["angles"], k_bend=r["k_bend"])
+        _, oo = oracle.forces(st["pos"], r["box"], pp, want_fscale=True, **kw)
+        keys = ("e_pair", "e_bond", "e_angle") if r["kind"] == "kg" else ("e_pair",)
+        for key in keys:
+            assert rel(ob[k][key], oo[key]) < TOL, (k, r["kind"], key, ob[k][key], oo[key])
+        rmax = max(row[2], 1.5 if r["kind"] == "kg" else 0.0)
+        assert virial_close(ob[k]["virial"], oo["virial"], oo["fscale"], rmax), (k, ob[k]["virial"], oo["virial"])
+    b.close()
