@@ -154,3 +154,49 @@ def test_batch_256_full_size():
         rmax = max(row[2], 1.5 if r["kind"] == "kg" else 0.0)
         assert virial_close(ob[k]["virial"], oo["virial"], oo["fscale"], rmax), (k, ob[k]["virial"], oo["virial"])
     b.close()
+
+
+@pytest.mark.parametrize("prec,tol", [("bf16", 3e-2), ("fp32", 1e-5)])
+def test_surrogate_1m_full_size(prec, tol):
+    """The learned surrogate on a 1,000,000-bead melt (the trained weights the
+    benchmark times, list radius 2.5 + skin): 64 sampled beads' forces
+    against the FP64 surrogate oracle.  A bead's surrogate force depends on
+    the beads within 2 r_d of it only, so the oracle evaluates, per sampled
+    bead, the beads within 2 r_d + 0.5 of it (periodic minimum image in the
+    full box) and the bead's force there is exact.  FENE and bending come
+    from the plain oracle on the whole melt."""
+    import os
+    from oracle import surrogate as S
+    w = inputs.lattice_melt(1000, 1000, 0.85, jitter=0.05, seed=1014)
+    w.update(inputs.kg_params(k_bend=1.5))
+    w["vel"] = inputs.maxwell_boltzmann(w["pos"].shape[0], 1.0, seed=1014, zero_momentum=False, exact=False)
+    w.update({"dt": 0.01, "skin": 0.4, "temperature": 1.0, "gamma": 0.5, "integrator": "langevin",
+              "seed": 1014})
+    banner("full-size surrogate %s n=%d" % (prec, w["pos"].shape[0]))
+    s = from_workload(w, precision="fp32", list_cutoff=2.5, surrogate=True)
+    wd = np.load(os.path.join(os.path.dirname(inputs.__file__), "data", "surrogate_kg.npz"))
+    th = wd["theta_" + prec]
+    s.sur_set(th, wd["g_mean"], wd["g_istd"], prec)
+    s.set_pair_mode("surrogate")
+    Fg = s.forces()
+    pos, box = s.get_state()["pos"], w["box"]
+    Fb, ob = oracle.forces(pos, box, oracle_pp(eps=0.0, rc=WCA), bonds=w["bonds"], angles=w["angles"],
+                           k_bend=1.5, want_fscale=True)
+    g = np.random.default_rng(11)
+    sample = g.choice(pos.shape[0], size=64, replace=False)
+    th64 = th.astype(np.float64)
+    m64, istd64 = wd["g_mean"].astype(np.float64), wd["g_istd"].astype(np.float64)
+    worst = 0.0
+    for i in sample:
+        d = pos - pos[i]
+        d -= box * np.round(d / box)
+        near = np.nonzero((d * d).sum(1) < (2 * S.RD + 0.5) ** 2)[0]
+        k = int(np.nonzero(near == i)[0][0])
+        _, _, Fs, _, _, fs = S.energy_forces(th64, m64, istd64, pos[near], box, want_fscale=True)
+        ref = Fs[k] + Fb[i]
+        scale = fs[k] + ob["fscale"][i]
+        err = np.linalg.norm(Fg[i] - ref)
+        worst = max(worst, err / scale)
+        assert err <= tol * scale + 1e-12, (prec, int(i), err, scale)
+    print("%s: worst per-bead ratio %.3g" % (prec, worst))
+    s.close()
