@@ -108,7 +108,7 @@ struct Bufs {
     int32_t* imgt;
     int32_t* tagt;
     int32_t* tsc;           // [N] tags in scatter order (rank inside a cell)
-    int32_t* nl;            // [cap][N] neighbour-major ELL, sorted indices
+    int32_t* nl;            // ELL in 64-particle tiles [N/64][cap][64], sorted indices
     int32_t* ncount;        // [N]
     // topology, tag space (static) and sorted space (remapped at each build)
     int32_t* tcnt_t;        // [N] nbond | nangle << 8

@@ -9,10 +9,12 @@
 // (computeEnergy()).
 //
 // Layout: particles are kept sorted by cell so that a wavefront's 64 lanes
-// stream neighbouring particles; positions are double4 (x, y, z, type) so a
-// gathered neighbour is one 32-byte segment; velocities and build positions
-// are SoA planes; the Verlet list is ELL, neighbour-major (entry k of
-// particle i at k*N + i) so that lane i reads consecutive words.
+// stream neighbouring particles; positions are double4 (x, y, z, type) and
+// fixed-point int4 (qx, qy, qz, type), so a gathered neighbour is one 32- or
+// 16-byte segment; velocities and build positions are SoA planes; the
+// Verlet list is ELL in tiles of 64 particles (entry k of particle i at
+// (i / 64) * cap * 64 + k * 64 + i % 64), so that the 64 lanes of a
+// wavefront read 256 contiguous bytes per entry.
 #include "md_device.h"
 
 
