@@ -196,12 +196,15 @@ __global__ void __launch_bounds__(kBlock) k_sur_force(Geom g, Bufs b, SurBufs s,
                 load_a<A16>(s, j, av);
                 float ph[kSurNB];
                 gauss_basis(c, r, ph);
+                // g'_k = phi_k (f_c' - (r - mu_k) f_c / w^2): one subtract, two
+                // fused multiply-adds and a multiply per basis function
+                const float B = c.inv_w2 * fc;
                 float cij = 0.f;
 #pragma unroll
                 for (int kk = 0; kk < kSurNB; ++kk) {
                     const float t = r - c.mu[kk];
-                    const float dg = ph[kk] * (dfc - t * c.inv_w2 * fc);
-                    cij += (ai[kk] + av[kk]) * dg;
+                    const float dg = ph[kk] * fmaf(-t, B, dfc);
+                    cij = fmaf(ai[kk] + av[kk], dg, cij);
                 }
                 const float sc = cij / r;
                 fx += sc * dx;
@@ -267,10 +270,11 @@ __global__ void __launch_bounds__(kBlock) k_sur_u(Geom g, Bufs b, SurBufs s, Sur
                 const float proj = ((di.x - dj.x) * dx + (di.y - dj.y) * dy + (di.z - dj.z) * dz) / r;
                 float ph[kSurNB];
                 gauss_basis(c, r, ph);
+                const float B = c.inv_w2 * fc;
 #pragma unroll
                 for (int q = 0; q < kSurNB; ++q) {
                     const float t = r - c.mu[q];
-                    U[q] += proj * ph[q] * (dfc - t * c.inv_w2 * fc);
+                    U[q] = fmaf(proj * ph[q], fmaf(-t, B, dfc), U[q]);
                 }
             }
         }
