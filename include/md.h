@@ -152,6 +152,21 @@ typedef struct md_handle_s* md_handle;
  * config and MD_ERR_BOX_TOO_SMALL when fewer than 3 cells fit per side. */
 md_status md_workspace_bytes(const md_config* cfg, size_t* bytes);
 
+/* What a configuration resolves to (host arithmetic only, no device call):
+ * the cell grid of the binning (CellGrid) and the Verlet-list build, after
+ * the automatic choices of cell_factor = 0, nl_capacity = 0 and the
+ * MD_CFG_NL_* flags.  Returns the same errors as md_workspace_bytes. */
+#define MD_NL_BUILD_PER_PARTICLE 0 /* one particle per lane */
+#define MD_NL_BUILD_TILES 1        /* one wavefront per 64-particle tile */
+typedef struct md_plan {
+    int32_t cells[3];          /* cells per side */
+    int32_t cell_factor;       /* 1 or 2: cells of side >= list_radius / cell_factor */
+    int32_t nl_capacity;       /* list slots per particle */
+    int32_t nl_build;          /* MD_NL_BUILD_* */
+    double list_radius;        /* max(rc, list_cutoff) + skin */
+} md_plan;
+md_status md_plan_config(const md_config* cfg, md_plan* out);
+
 /* Create a simulation (storage.addParticles + decompose of the paper).
  *   pos, vel      device, FP64 [N][3], particle-id (tag) order; positions may
  *                 lie outside the box, they are folded in with image counters

@@ -612,6 +612,20 @@ md_status md_workspace_bytes(const md_config* cfg, size_t* bytes) {
     return MD_OK;
 }
 
+md_status md_plan_config(const md_config* cfg, md_plan* out) {
+    if (!out) return fail(nullptr, MD_ERR_ARG, "out is NULL");
+    Geom g;
+    std::string why;
+    md_status st = plan_geom(cfg, &g, &why);
+    if (st != MD_OK) return fail(nullptr, st, why);
+    for (int d = 0; d < 3; ++d) out->cells[d] = g.nc[d];
+    out->cell_factor = g.kc;
+    out->nl_capacity = g.cap;
+    out->nl_build = g.nl_tile ? MD_NL_BUILD_TILES : MD_NL_BUILD_PER_PARTICLE;
+    out->list_radius = sqrt(g.rv2);
+    return MD_OK;
+}
+
 // External cell arrays of a batch member (nullptr for a standalone handle).
 struct CellExt {
     int32_t* ccount;

@@ -53,7 +53,7 @@ MD_SUR_BF16 = 1
 MD_PAIR_PLAIN = 0
 MD_PAIR_SURROGATE = 1
 
-EXPORTED = ["md_workspace_bytes", "md_init", "md_set_params", "md_build_neighbors", "md_forces",
+EXPORTED = ["md_workspace_bytes", "md_plan_config", "md_init", "md_set_params", "md_build_neighbors", "md_forces",
             "md_step", "md_observables", "md_history", "md_get_state", "md_set_state",
             "md_get_neighbors", "md_status_check", "md_timing_enable", "md_timing_read",
             "md_destroy", "md_status_string", "md_last_error", "md_sur_set", "md_sur_get",
@@ -101,6 +101,15 @@ class md_timing(ctypes.Structure):
                 ("n_finalize", ctypes.c_int64), ("ms_finalize", ctypes.c_double)]
 
 
+class md_plan(ctypes.Structure):
+    _fields_ = [("cells", ctypes.c_int32 * 3), ("cell_factor", ctypes.c_int32), ("nl_capacity", ctypes.c_int32),
+                ("nl_build", ctypes.c_int32), ("list_radius", ctypes.c_double)]
+
+
+MD_NL_BUILD_PER_PARTICLE = 0
+MD_NL_BUILD_TILES = 1
+
+
 class MDError(RuntimeError):
     def __init__(self, code, fn, msg):
         super().__init__("%s -> %s: %s" % (fn, status_string(code), msg))
@@ -122,6 +131,7 @@ def lib():
     P, I32, I64, SZ = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
     sig = {
         "md_workspace_bytes": [ctypes.POINTER(md_config), ctypes.POINTER(SZ)],
+        "md_plan_config": [ctypes.POINTER(md_config), ctypes.POINTER(md_plan)],
         "md_init": [ctypes.POINTER(md_config), P, P, P, P, P, P, P, SZ, P, ctypes.POINTER(P)],
         "md_set_params": [P, ctypes.POINTER(md_config)],
         "md_build_neighbors": [P],
@@ -230,6 +240,15 @@ def md_workspace_bytes(cfg):
     n = ctypes.c_size_t()
     _check(lib().md_workspace_bytes(ctypes.byref(cfg), ctypes.byref(n)), "md_workspace_bytes")
     return n.value
+
+
+def md_plan_config(cfg):
+    """Cell grid and list build the configuration resolves to (dict)."""
+    p = md_plan()
+    _check(lib().md_plan_config(ctypes.byref(cfg), ctypes.byref(p)), "md_plan_config")
+    return {"cells": list(p.cells), "cell_factor": p.cell_factor, "nl_capacity": p.nl_capacity,
+            "nl_build": "tiles" if p.nl_build == MD_NL_BUILD_TILES else "per_particle",
+            "list_radius": p.list_radius}
 
 
 def md_init(cfg, pos, vel, type, mass_by_type, bonds, angles, workspace, ws_bytes, stream):

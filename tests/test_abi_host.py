@@ -43,6 +43,8 @@ int main(void) {
          offsetof(md_config, n_bonds), offsetof(md_config, flags), offsetof(md_obs, status_flags));
   printf("%zu %zu %d %d\\n", offsetof(md_config, list_cutoff), offsetof(md_config, surrogate),
          MD_SUR_NPARAM, MD_SUR_NBASIS);
+  printf("%zu %zu %d %d\\n", sizeof(md_plan), offsetof(md_plan, list_radius), MD_CFG_NL_PER_PARTICLE,
+         MD_CFG_NL_TILES);
   return 0;
 }
 ''')
@@ -53,7 +55,8 @@ int main(void) {
     py = [ctypes.sizeof(md.md_config), ctypes.sizeof(md.md_obs), ctypes.sizeof(md.md_timing),
           ctypes.sizeof(md.md_pair_params), md.md_config.n_particles.offset, md.md_config.pair.offset,
           md.md_config.n_bonds.offset, md.md_config.flags.offset, md.md_obs.status_flags.offset,
-          md.md_config.list_cutoff.offset, md.md_config.surrogate.offset, md.MD_SUR_NPARAM, md.MD_SUR_NBASIS]
+          md.md_config.list_cutoff.offset, md.md_config.surrogate.offset, md.MD_SUR_NPARAM, md.MD_SUR_NBASIS,
+          ctypes.sizeof(md.md_plan), md.md_plan.list_radius.offset, md.MD_CFG_NL_PER_PARTICLE, md.MD_CFG_NL_TILES]
     assert c_sizes == py
 
 
@@ -240,3 +243,36 @@ def test_lattice_melt_bonds_join_lattice_neighbours():
         key = (sites[:, 2] * m + sites[:, 1]) * m + sites[:, 0]
         assert np.unique(key).size == n
         assert w["angles"].shape == (nc * (cl - 2), 3)
+
+
+def test_plan_chooses_cells_and_list_build():
+    """The automatic choices: dense fluids (>= 8 particles per cell of side
+    rc+skin) take the tile list build on those cells; melts the per-particle
+    build on half-cutoff cells when 5 of them fit per side, else on full
+    cells; the flags force either build; a box of 3 list radii gets 3 cells."""
+    lj = dict(pair={(0, 0): (1.0, 1.0, 2.5, float("nan"), 0.0)}, skin=0.3)
+    wca = dict(pair={(0, 0): (1.0, 1.0, 2.0 ** (1 / 6), float("nan"), 0.0)}, skin=0.4)
+    L = (1048576 / 0.8442) ** (1 / 3)
+    p = md.md_plan_config(md.make_config(1048576, [L] * 3, **lj))
+    assert p["nl_build"] == "tiles" and p["cell_factor"] == 1 and p["cells"] == [int(L / 2.8)] * 3
+    assert abs(p["list_radius"] - 2.8) < 1e-12
+    # the automatic capacity: 1.5 x the expected neighbours + 32, a multiple of 8
+    expect = 0.8442 * 4.0 / 3.0 * math.pi * 2.8 ** 3
+    assert p["nl_capacity"] == (math.ceil(1.5 * expect + 32) + 7) // 8 * 8
+    L2 = (2000000 / 0.85) ** (1 / 3)
+    p = md.md_plan_config(md.make_config(2000000, [L2] * 3, **wca))
+    rv = 2.0 ** (1 / 6) + 0.4
+    assert p["nl_build"] == "per_particle" and p["cell_factor"] == 2
+    assert p["cells"] == [int(L2 * 2 / (rv * (1 + 1e-12)))] * 3
+    p = md.md_plan_config(md.make_config(2000000, [L2] * 3, flags=md.MD_CFG_NL_TILES, **wca))
+    assert p["nl_build"] == "tiles" and p["cell_factor"] == 2
+    p = md.md_plan_config(md.make_config(1048576, [L] * 3, flags=md.MD_CFG_NL_PER_PARTICLE, **lj))
+    assert p["nl_build"] == "per_particle" and p["cell_factor"] == 2
+    p = md.md_plan_config(md.make_config(1048576, [L] * 3, cell_factor=2, **lj))
+    assert p["nl_build"] == "per_particle"
+    # a dense box of 3 list radii: 3 full cells per side and tiles
+    p = md.md_plan_config(md.make_config(1000, [8.4 * 1.0000001] * 3, **lj))
+    assert p["cells"] == [3, 3, 3] and p["cell_factor"] == 1 and p["nl_build"] == "tiles"
+    # a sparse box of 4.3 list radii holds 8 half cells per side: half cells, per particle
+    p = md.md_plan_config(md.make_config(100, [12.0] * 3, **lj))
+    assert p["cell_factor"] == 2 and p["nl_build"] == "per_particle" and p["cells"] == [8, 8, 8]
