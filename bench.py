@@ -292,6 +292,8 @@ def main():
     hist = s.history()
     value = n * a.steps / el
     ms = 1e3 * el / a.steps
+    from paper_2608_14911_amd import md as md_
+    plan = md_.md_plan_config(s.cfg)
     rec = {
         "metric": "atom-steps/s (1M LJ, 2M KG melt)" if a.workload != "sur1m" else
                   "atom-steps/s (1M KG melt, learned surrogate pair force)",
@@ -309,7 +311,9 @@ def main():
         "config": {"workload": w["name"], "n_particles": n, "rc": w["rc"], "skin": w["skin"],
                    "dt": w["dt"], "integrator": w["integrator"],
                    "precision": "FP32 pair/bonded math, FP64 positions, velocities and reductions",
-                   "parallelism": "single GPU", "cell_factor": s.cfg.cell_factor or "auto"},
+                   "parallelism": "single GPU", "cell_factor": plan["cell_factor"],
+                   "cells_per_side": plan["cells"][0], "list_build": plan["nl_build"],
+                   "list_capacity": plan["nl_capacity"]},
         "n_rebuilds": o1["n_rebuilds"] - o0["n_rebuilds"],
         "energy_drift_per_particle": (o1["e_total"] - o0["e_total"]) / n,
         "nl_max_count": o1["nl_max_count"],
