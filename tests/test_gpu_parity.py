@@ -340,3 +340,53 @@ def test_gpu_pushoff_kg_melt():
     assert np.sqrt((d * d).sum(1)).max() < 1.3
     nl = oracle.neighbors(pos, L, 0.75)
     assert all(len(r) == 0 for r in nl)
+
+
+@pytest.mark.parametrize("build", ["tiles", "per_particle"])
+def test_degenerate_systems(build):
+    """Edge cases through both list builds: one particle (no neighbour, zero
+    force, free flight); a pair exactly at the cutoff and one ulp inside it;
+    65 particles (a full tile and a tile of one); particles farther apart
+    than the list radius (every list empty)."""
+    from paper_2608_14911_amd import md
+    from paper_2608_14911_amd.system import nl_build_flags
+    flags = nl_build_flags(build)
+    banner("degenerate systems, %s build" % build)
+    L = 10.0
+    # one particle
+    s = System(np.array([[1.0, 2.0, 3.0]]), [L, L, L], np.array([[0.5, -0.25, 0.125]]),
+               pair={(0, 0): lj_pair(rc=2.5)}, skin=0.3, dt=0.01, flags=flags)
+    assert [len(r) for r in s.neighbors(cap=8)] == [0]
+    assert np.abs(s.forces()).max() == 0.0
+    s.step(10)
+    st = s.get_state()
+    np.testing.assert_allclose(st["pos"][0], [1.05, 1.975, 3.0125], rtol=0, atol=1e-12)
+    s.close()
+    # a pair at the cutoff (no force, listed) and one ulp inside it (force)
+    for r, expect_force in [(2.5, False), (np.nextafter(2.5, 0.0), True)]:
+        # 0.5 + r is exact at both distances, so the FP64 difference is r itself
+        pos = np.array([[0.5, 5.0, 5.0], [0.5 + r, 5.0, 5.0]])
+        assert pos[1, 0] - pos[0, 0] == r
+        s = System(pos, [L, L, L], pair={(0, 0): lj_pair(rc=2.5)}, skin=0.3, precision="fp64", flags=flags)
+        F = s.forces()
+        Fo, _ = oracle.forces(pos, [L, L, L], oracle_pp(rc=2.5))
+        assert np.array_equal(F != 0.0, Fo != 0.0) and (np.abs(F).max() > 0) == expect_force
+        np.testing.assert_allclose(F, Fo, rtol=1e-12, atol=0)
+        assert [len(x) for x in s.neighbors(cap=8)] == [1, 1]
+        s.close()
+    # 65 particles: a full tile and a tile of one
+    g = np.random.default_rng(21)
+    pos = g.uniform(0, L, size=(65, 3))
+    s = System(pos, [L, L, L], pair={(0, 0): lj_pair(rc=2.5, caprad=0.8)}, skin=0.3, flags=flags)
+    ref = oracle.neighbors(pos, [L, L, L], 2.8)
+    assert all(np.array_equal(a, b) for a, b in zip(s.neighbors(cap=64), ref))
+    Fo, oo = oracle.forces(pos, [L, L, L], oracle_pp(rc=2.5, caprad=0.8), want_fscale=True)
+    assert_forces_close(s.forces(), Fo, oo["fscale"], 1e-5, "65 particles")
+    s.close()
+    # sparse: a 4x4x4 lattice of spacing 3 > rv in a box of 12
+    grid = np.stack(np.meshgrid(*[np.arange(4) * 3.0 + 0.5] * 3, indexing="ij"), -1).reshape(-1, 3)
+    s = System(grid, [12.0] * 3, pair={(0, 0): lj_pair(rc=2.5)}, skin=0.3, flags=flags)
+    assert all(len(x) == 0 for x in s.neighbors(cap=8))
+    assert np.abs(s.forces()).max() == 0.0
+    assert s.observables()["nl_max_count"] == 0
+    s.close()
