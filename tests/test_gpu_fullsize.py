@@ -60,7 +60,7 @@ def virial_close(got, ref, fscale, rmax):
     return abs(got - ref) <= TOL * max(abs(ref), scale)
 
 
-def check(s, w, pp, rv, cap, bonded, what):
+def check(s, w, pp, rv, cap, bonded, what, nsample=NSAMPLE):
     F = s.forces()
     o = s.observables()
     st = s.get_state()
@@ -77,10 +77,10 @@ def check(s, w, pp, rv, cap, bonded, what):
     assert virial_close(o["virial"], oo["virial"], oo["fscale"], rmax), (what, o["virial"], oo["virial"])
     # rows against brute force at the positions the list was built from
     g = np.random.default_rng(7)
-    sample = np.sort(g.choice(s.n, size=NSAMPLE, replace=False))
+    sample = np.sort(g.choice(s.n, size=nsample, replace=False))
     got = sampled_rows(s, sample, cap)
     ref = oracle.neighbors(st["pos_build"], w["box"], rv, query=sample, cap=cap)
-    for k in range(NSAMPLE):
+    for k in range(nsample):
         assert np.array_equal(got[k], ref[k]), (what, int(sample[k]))
     return o
 
@@ -199,4 +199,20 @@ def test_surrogate_1m_full_size(prec, tol):
         worst = max(worst, err / scale)
         assert err <= tol * scale + 1e-12, (prec, int(i), err, scale)
     print("%s: worst per-bead ratio %.3g" % (prec, worst))
+    s.close()
+
+
+def test_lj_16m_large():
+    """A 16,384,000-particle LJ fluid (FCC 160^3, 16x the benchmark): list
+    offsets and cell indices far beyond the benchmark's; every force against
+    the oracle and sampled rows bit-exact, before and after a few steps."""
+    w = inputs.workload_lj(ncell=160, seed=1007)
+    banner("large LJ fluid n=%d" % w["pos"].shape[0])
+    s = from_workload(w, precision="fp32")
+    pp = oracle_pp(rc=w["rc"])
+    rv = w["rc"] + w["skin"]
+    check(s, w, pp, rv, 128, False, "LJ 16M start", nsample=512)
+    s.step(12)
+    o = check(s, w, pp, rv, 128, False, "LJ 16M after 12 steps", nsample=512)
+    assert o["n_rebuilds"] >= 2 and o["status_flags"] == 0
     s.close()
