@@ -1391,13 +1391,18 @@ __device__ __forceinline__ void finalize_body(const Bufs& b, int nblocks, int mo
         if (lane == 0) red[w][k] = t;
     }
     __syncthreads();
+    // one lane per quantity sums the wavefront totals (fixed order), so the
+    // serial part below reads finished sums only
+    __shared__ double fin[kNacc];
+    if (threadIdx.x < kNacc) {
+        double v = 0.0;
+        for (int ww = 0; ww < kFinal / 64; ++ww) v += red[ww][threadIdx.x];
+        fin[threadIdx.x] = v;
+    }
+    __syncthreads();
     if (threadIdx.x == 0) {
         double tot[kNacc];
-        for (int k = 0; k < kNacc; ++k) {
-            double v = 0.0;
-            for (int ww = 0; ww < kFinal / 64; ++ww) v += red[ww][k];
-            tot[k] = v;
-        }
+        for (int k = 0; k < kNacc; ++k) tot[k] = fin[k];
         DevCtl* c = b.ctl;
         const int64_t step = c->step;
         double rec[kHistRec];
