@@ -492,6 +492,7 @@ __device__ __forceinline__ void remap_bonded(const Bufs& b, int64_t n, int64_t i
 // rounding, so the sets are those of the FP64 definition.  Row order:
 // stencil (z, y, x offsets), then sorted index.  Also remaps the bonded
 // topology from tags to sorted indices.
+constexpr int kNlLds = 24;  // row slots staged in LDS by the per-particle build (24 KB per block)
 __device__ __forceinline__ void nl_one(const Geom& g, const Bufs& b, int64_t i, int parity, int bonded,
                                        int& local_max, bool& overflow) {
     const int64_t n = g.n;
@@ -508,6 +509,16 @@ __device__ __forceinline__ void nl_one(const Geom& g, const Bufs& b, int64_t i, 
         const float uz = (float)(xi.z - cz * g.h[2]);
         int cnt = 0;
         int32_t* __restrict__ nlrow = b.nl + nl_base(i, g.cap);
+        // The first kNlLds slots of each row collect in LDS, [slot][lane] per
+        // wavefront, and leave in whole-wavefront stores at the end: the
+        // hits of the lanes fall in different iterations, so direct stores
+        // would cost one partly masked store instruction per hit event.
+        __shared__ int32_t nlbuf[kBlock / 64][kNlLds][64];
+        const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
+        auto put = [&](int k, int j) {
+            if (k < kNlLds) nlbuf[wv][k][ln] = j;
+            else nlrow[k * kTile] = j;
+        };
         // Cells cx-kc .. cx+kc of one (y, z) row are consecutive in the cell
         // order, so their particles form one contiguous range of the sorted
         // arrays (two when the row wraps around the box).
@@ -526,7 +537,7 @@ __device__ __forceinline__ void nl_one(const Geom& g, const Bufs& b, int64_t i, 
                     bool in = r2 < g.rv2lo;
                     if (!in && r2 < g.rv2hi) in = exact_r2(g, xi, x[j + u]) < g.rv2;
                     if (in && j + u != i) {
-                        if (cnt < g.cap) nlrow[cnt * kTile] = j + u;
+                        if (cnt < g.cap) put(cnt, j + u);
                         ++cnt;
                     }
                 }
@@ -540,7 +551,7 @@ __device__ __forceinline__ void nl_one(const Geom& g, const Bufs& b, int64_t i, 
                 bool in = r2 < g.rv2lo;
                 if (!in && r2 < g.rv2hi) in = exact_r2(g, xi, x[j]) < g.rv2;
                 if (in && j != i) {
-                    if (cnt < g.cap) nlrow[cnt * kTile] = j;
+                    if (cnt < g.cap) put(cnt, j);
                     ++cnt;
                 }
             }
@@ -572,7 +583,11 @@ __device__ __forceinline__ void nl_one(const Geom& g, const Bufs& b, int64_t i, 
         if (cnt > g.cap) overflow = true;
         // pad the row to a multiple of 8 with the particle itself (r = 0,
         // never inside a cutoff) so that step kernels stream whole batches
-        for (int k = cnt; k < ((cnt + 7) & ~7) && k < g.cap; ++k) nlrow[k * kTile] = (int)i;
+        const int nslot = min(((cnt + 7) & ~7), g.cap);
+        for (int k = cnt; k < nslot; ++k) put(k, (int)i);
+#pragma unroll
+        for (int k = 0; k < kNlLds; ++k)
+            if (k < nslot) nlrow[k * kTile] = nlbuf[wv][k][ln];
         if (bonded) remap_bonded(b, n, i);
     }
 }
