@@ -521,15 +521,17 @@ __device__ __forceinline__ void nl_one(const Geom& g, const Bufs& b, int64_t i, 
         };
         // Cells cx-kc .. cx+kc of one (y, z) row are consecutive in the cell
         // order, so their particles form one contiguous range of the sorted
-        // arrays (two when the row wraps around the box).
+        // arrays (two when the row wraps around the box).  Candidates are
+        // gathered four at a time, the last one repeated past the end of the
+        // range, so a short range costs one memory round trip.
         auto test_range = [&](int st, int en) {
-            int j = st;
-            for (; j + 4 <= en; j += 4) {
+            for (int j = st; j < en; j += 4) {
                 int4 qq[4];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) qq[u] = xq[j + u];
+                for (int u = 0; u < 4; ++u) qq[u] = xq[min(j + u, en - 1)];
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
+                    if (j + u >= en) break;
                     const float dx = qdiff(qq[u].x, qi.x, g.ql[0]);
                     const float dy = qdiff(qq[u].y, qi.y, g.ql[1]);
                     const float dz = qdiff(qq[u].z, qi.z, g.ql[2]);
@@ -542,41 +544,45 @@ __device__ __forceinline__ void nl_one(const Geom& g, const Bufs& b, int64_t i, 
                     }
                 }
             }
-            for (; j < en; ++j) {
-                const int4 qj = xq[j];
-                const float dx = qdiff(qj.x, qi.x, g.ql[0]);
-                const float dy = qdiff(qj.y, qi.y, g.ql[1]);
-                const float dz = qdiff(qj.z, qi.z, g.ql[2]);
-                const float r2 = dx * dx + dy * dy + dz * dz;
-                bool in = r2 < g.rv2lo;
-                if (!in && r2 < g.rv2hi) in = exact_r2(g, xi, x[j]) < g.rv2;
-                if (in && j != i) {
-                    if (cnt < g.cap) put(cnt, j);
-                    ++cnt;
-                }
-            }
         };
         const int xlo = cx - kc, xhi = cx + kc;   // inclusive cell range along x
-        for (int oz = -kc; oz <= kc; ++oz) {
+        const int nx = g.nc[0];
+        const bool wl = xlo < 0, wh = xhi >= nx;
+        const int side = 2 * kc + 1, nv = 2 * side * side;
+        const int32_t* __restrict__ cs = b.cstart;
+        // Piece v is the first or second range of stencil row v / 2 (rows
+        // z-major, empty when the row is out of reach or does not wrap).  The
+        // cell bounds of piece v + 1 are loaded before the candidates of
+        // piece v are tested, so the two loads overlap.
+        auto piece = [&](int v, int& a, int& e) {
+            a = e = 0;
+            const int r = v >> 1, pc = v & 1;
+            const int oz = r / side - kc, oy = r % side - kc;
             const float gz = cell_gap(oz, uz, hz);
             const float gz2 = gz * gz;
-            if (gz2 > g.rv2hi) continue;
-            const int nz = wrapc(cz + oz, g.nc[2]);
-            for (int oy = -kc; oy <= kc; ++oy) {
-                const float gy = cell_gap(oy, uy, hy);
-                if (gz2 + gy * gy > g.rv2hi) continue;
-                const int ny = wrapc(cy + oy, g.nc[1]);
-                const int64_t rowc = ((int64_t)nz * g.nc[1] + ny) * g.nc[0];
-                if (xlo >= 0 && xhi < g.nc[0]) {
-                    test_range(b.cstart[rowc + xlo], b.cstart[rowc + xhi + 1]);
-                } else if (xlo < 0) {
-                    test_range(b.cstart[rowc + g.nc[0] + xlo], b.cstart[rowc + g.nc[0]]);
-                    test_range(b.cstart[rowc], b.cstart[rowc + xhi + 1]);
-                } else {
-                    test_range(b.cstart[rowc + xlo], b.cstart[rowc + g.nc[0]]);
-                    test_range(b.cstart[rowc], b.cstart[rowc + xhi - g.nc[0] + 1]);
-                }
+            if (gz2 > g.rv2hi) return;
+            const float gy = cell_gap(oy, uy, hy);
+            if (gz2 + gy * gy > g.rv2hi) return;
+            const int nz = wrapc(cz + oz, g.nc[2]), ny = wrapc(cy + oy, g.nc[1]);
+            const int64_t rowc = ((int64_t)nz * g.nc[1] + ny) * nx;
+            if (!wl && !wh) {
+                if (pc == 0) { a = cs[rowc + xlo]; e = cs[rowc + xhi + 1]; }
+            } else if (wl) {
+                if (pc == 0) { a = cs[rowc + nx + xlo]; e = cs[rowc + nx]; }
+                else { a = cs[rowc]; e = cs[rowc + xhi + 1]; }
+            } else {
+                if (pc == 0) { a = cs[rowc + xlo]; e = cs[rowc + nx]; }
+                else { a = cs[rowc]; e = cs[rowc + xhi - nx + 1]; }
             }
+        };
+        int pa, pe;
+        piece(0, pa, pe);
+        for (int v = 0; v < nv; ++v) {
+            int na = 0, ne = 0;
+            if (v + 1 < nv) piece(v + 1, na, ne);
+            test_range(pa, pe);
+            pa = na;
+            pe = ne;
         }
         b.ncount[i] = cnt;
         if (cnt > local_max) local_max = cnt;
@@ -592,13 +598,19 @@ __device__ __forceinline__ void nl_one(const Geom& g, const Bufs& b, int64_t i, 
     }
 }
 
-// Longest row and overflow flag, one atomic per wavefront.
+// Longest row and overflow flag.  Atomics on one address serialize (tens of
+// ns each, measured), so a wavefront raises the maximum only when its own
+// row is longer than the value it reads; a stale read costs one redundant
+// atomic, never a wrong maximum.
 __device__ __forceinline__ void nl_epilogue(const Bufs& b, int local_max, bool overflow) {
     for (int o = 32; o >= 1; o >>= 1) {
         const int y = __shfl_xor(local_max, o, 64);
         local_max = y > local_max ? y : local_max;
     }
-    if ((threadIdx.x & 63) == 0 && local_max > 0) atomicMax(&b.ctl->nl_max, local_max);
+    if ((threadIdx.x & 63) == 0 && local_max > 0) {
+        const int cur = __hip_atomic_load(&b.ctl->nl_max, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (local_max > cur) atomicMax(&b.ctl->nl_max, local_max);
+    }
     if (__any(overflow) && (threadIdx.x & 63) == 0) atomicOr(&b.ctl->status, MD_FLAG_NL_OVERFLOW);
 }
 
