@@ -141,11 +141,13 @@ static md_status plan_geom(const md_config* c, Geom* g, std::string* why) {
     g->rv2 = rv * rv;
     g->disp2 = (0.5 * c->skin) * (0.5 * c->skin);
     // List build: dense systems (>= 8 particles expected in a cell of side
-    // rv) one wavefront per 64-particle tile on cells of side rv; others one
-    // particle per lane, preferably on half-cutoff sub-cells (fewer candidate
-    // pairs) whenever the box holds at least 5 of them per side.  Measured on
-    // MI355X: the tile build is 18% faster on the LJ fluid and 9% slower on
-    // the melt (3 beads per cell) than the per-particle build.
+    // rv) one wavefront per 64-particle tile, others one particle per lane,
+    // both on cells of side rv; half-cutoff sub-cells only when the box holds
+    // fewer than 3 cells of side rv per axis.  Measured on MI355X (2M-bead
+    // melt, 3 beads per cell): the per-particle build on cells of side rv
+    // beats half-cutoff sub-cells by 12% in whole-step throughput (fewer
+    // stencil rows, each a memory round trip) and the tile build, whose
+    // shared candidate stream is 2.4-7.7x longer than a lane's own.
     const double density = (double)c->n_particles / (c->box[0] * c->box[1] * c->box[2]);
     const bool per_particle = (c->flags & MD_CFG_NL_PER_PARTICLE) != 0;
     const bool dense = density * rv * rv * rv >= 8.0 && !per_particle;
@@ -156,7 +158,7 @@ static md_status plan_geom(const md_config* c, Geom* g, std::string* why) {
             if ((int)floor(c->box[d] / (rv * (1.0 + 1e-12))) < 3) fit1 = false;
             if ((int)floor(c->box[d] * 2.0 / (rv * (1.0 + 1e-12))) < 5) fit2 = false;
         }
-        g->kc = (dense && fit1) ? 1 : (fit2 ? 2 : 1);
+        g->kc = fit1 ? 1 : (fit2 ? 2 : 1);
     }
     g->ncell = 1;
     double Lmax = 0.0;
@@ -691,6 +693,7 @@ static md_status init_core(const md_config* cfg, const double* pos, const double
     // control block and cell counters start at zero
     if (launch_zero_i32((int32_t*)h->b.ctl, sizeof(DevCtl) / 4, h->stream) != hipSuccess ||
         launch_zero_i32(h->b.ccount, g.ncell, h->stream) != hipSuccess ||
+        launch_zero_i32(h->b.bsum, kScanBlocks, h->stream) != hipSuccess ||
         launch_zero_i32(h->b.ncount, g.n, h->stream) != hipSuccess ||
         launch_zero_i32((int32_t*)h->b.partials, 2 * kNacc * (int64_t)sg, h->stream) != hipSuccess)
         return bail(fail(nullptr, MD_ERR_HIP, "kernel launch failed during init"));

@@ -250,7 +250,7 @@ __device__ __forceinline__ void cell_run(uint32_t c, bool active, int& first, in
     len = next - first;
 }
 
-__device__ __forceinline__ void bin_one(const Geom& g, const Bufs& b, int64_t i, bool active, int parity) {
+__device__ __forceinline__ uint32_t bin_one(const Geom& g, const Bufs& b, int64_t i, bool active, int parity) {
     uint32_t c = 0xffffffffu;
     if (active) {
         c = cell_of(g, b.x[parity][i]);
@@ -259,13 +259,27 @@ __device__ __forceinline__ void bin_one(const Geom& g, const Bufs& b, int64_t i,
     int first, len;
     cell_run(c, active, first, len);
     if (active && (threadIdx.x & 63) == first) atomicAdd(&b.ccount[c], len);
+    return c;
+}
+
+// Cells are scanned in kScanBlocks chunks of consecutive cells.  Binning also
+// sums each chunk's particles (one atomic per run of equal chunks in a
+// wavefront), so the scan needs no separate reduction pass.
+__device__ __forceinline__ int64_t scan_chunk_cells(const Geom& g) {
+    return (g.ncell + kScanBlocks - 1) / kScanBlocks;
 }
 
 __global__ void __launch_bounds__(kBlock) k_bin(Geom g, Bufs b, int parity) {
     if (!rebuild_requested(b)) return;
+    const int64_t chunk = scan_chunk_cells(g);
     for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x; i0 < g.n; i0 += gstride()) {
         const int64_t i = i0 + threadIdx.x;
-        bin_one(g, b, i, i < g.n, parity);
+        const bool active = i < g.n;
+        const uint32_t c = bin_one(g, b, i, active, parity);
+        const uint32_t ch = active ? (uint32_t)(c / chunk) : 0xffffffffu;
+        int first, len;
+        cell_run(ch, active, first, len);
+        if (active && (threadIdx.x & 63) == first) atomicAdd(&b.bsum[ch], len);
     }
 }
 
@@ -292,7 +306,7 @@ __device__ int block_exclusive_scan(int v, int& total) {
 }
 
 __device__ __forceinline__ void scan_chunk(const Geom& g, int blk, int64_t& lo, int64_t& hi) {
-    int64_t chunk = (g.ncell + kScanBlocks - 1) / kScanBlocks;
+    const int64_t chunk = scan_chunk_cells(g);
     lo = blk * chunk;
     hi = lo + chunk;
     if (hi > g.ncell) hi = g.ncell;
@@ -334,11 +348,9 @@ __global__ void __launch_bounds__(kScanBlocks) k_scan_top(Bufs b) {
     b.bsum[threadIdx.x] = off + x - v;
 }
 
-__global__ void __launch_bounds__(kBlock) k_scan_apply(Geom g, Bufs b) {
-    if (!rebuild_requested(b)) return;
+__device__ __forceinline__ void scan_apply_body(const Geom& g, const Bufs& b, int running) {
     int64_t lo, hi;
     scan_chunk(g, blockIdx.x, lo, hi);
-    int running = b.bsum[blockIdx.x];
     // four consecutive cells per thread and step
     for (int64_t base = lo; base < hi; base += 4 * kBlock) {
         const int64_t c0 = base + 4 * (int64_t)threadIdx.x;
@@ -358,6 +370,24 @@ __global__ void __launch_bounds__(kBlock) k_scan_apply(Geom g, Bufs b) {
         running += tot;
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) b.cstart[g.ncell] = (int32_t)g.n;
+}
+
+// Batches: chunk offsets from k_scan_reduce and k_scan_top.
+__global__ void __launch_bounds__(kBlock) k_scan_apply(Geom g, Bufs b) {
+    if (!rebuild_requested(b)) return;
+    scan_apply_body(g, b, b.bsum[blockIdx.x]);
+}
+
+// One system: the chunk sums come from k_bin, and each block adds up the
+// sums of the chunks before its own (at most kScanBlocks values, read from
+// the L2), which replaces the reduction and top-level scan kernels.
+__global__ void __launch_bounds__(kBlock) k_scan_chunks(Geom g, Bufs b) {
+    if (!rebuild_requested(b)) return;
+    int part = 0;
+    for (int k = threadIdx.x; k < (int)blockIdx.x; k += kBlock) part += b.bsum[k];
+    int off;
+    (void)block_exclusive_scan(part, off);
+    scan_apply_body(g, b, off);
 }
 
 // Scatter into cell segments, one atomic per run of equal cells; counts
@@ -381,6 +411,8 @@ __device__ __forceinline__ void scatter_one(const Bufs& b, int64_t i, bool activ
 
 __global__ void __launch_bounds__(kBlock) k_scatter(Geom g, Bufs b) {
     if (!rebuild_requested(b)) return;
+    // the chunk sums were read by the scan: clear them for the next build
+    for (int64_t k = gtid(); k < kScanBlocks; k += gstride()) b.bsum[k] = 0;
     for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x; i0 < g.n; i0 += gstride()) {
         const int64_t i = i0 + threadIdx.x;
         scatter_one(b, i, i < g.n);
@@ -1666,9 +1698,7 @@ hipError_t launch_rebuild(const Geom& g, const Bufs& b, int parity, int bonded, 
     const int gs = grid_for(g.n, 512);
     if (ev0) (void)hipEventRecord(ev0, s);
     hipLaunchKernelGGL(k_bin, dim3(gs), dim3(kBlock), 0, s, g, b, parity);
-    hipLaunchKernelGGL(k_scan_reduce, dim3(kScanBlocks), dim3(kBlock), 0, s, g, b);
-    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanBlocks), 0, s, b);
-    hipLaunchKernelGGL(k_scan_apply, dim3(kScanBlocks), dim3(kBlock), 0, s, g, b);
+    hipLaunchKernelGGL(k_scan_chunks, dim3(kScanBlocks), dim3(kBlock), 0, s, g, b);
     hipLaunchKernelGGL(k_scatter, dim3(gs), dim3(kBlock), 0, s, g, b);
     hipLaunchKernelGGL(k_rank_permute, dim3(gs), dim3(kBlock), 0, s, g, b, parity);
     hipLaunchKernelGGL(k_commit, dim3(gs), dim3(kBlock), 0, s, g, b, parity, bonded);

@@ -247,9 +247,10 @@ def test_lattice_melt_bonds_join_lattice_neighbours():
 
 def test_plan_chooses_cells_and_list_build():
     """The automatic choices: dense fluids (>= 8 particles per cell of side
-    rc+skin) take the tile list build on those cells; melts the per-particle
-    build on half-cutoff cells when 5 of them fit per side, else on full
-    cells; the flags force either build; a box of 3 list radii gets 3 cells."""
+    rc+skin) take the tile list build, melts the per-particle build, both on
+    cells of side rc+skin; half-cutoff cells only when fewer than 3 full
+    cells fit per side; the flags force either build; a box of 3 list radii
+    gets 3 cells."""
     lj = dict(pair={(0, 0): (1.0, 1.0, 2.5, float("nan"), 0.0)}, skin=0.3)
     wca = dict(pair={(0, 0): (1.0, 1.0, 2.0 ** (1 / 6), float("nan"), 0.0)}, skin=0.4)
     L = (1048576 / 0.8442) ** (1 / 3)
@@ -262,17 +263,23 @@ def test_plan_chooses_cells_and_list_build():
     L2 = (2000000 / 0.85) ** (1 / 3)
     p = md.md_plan_config(md.make_config(2000000, [L2] * 3, **wca))
     rv = 2.0 ** (1 / 6) + 0.4
+    assert p["nl_build"] == "per_particle" and p["cell_factor"] == 1
+    assert p["cells"] == [int(L2 / (rv * (1 + 1e-12)))] * 3
+    p = md.md_plan_config(md.make_config(2000000, [L2] * 3, flags=md.MD_CFG_NL_TILES, **wca))
+    assert p["nl_build"] == "tiles" and p["cell_factor"] == 1
+    p = md.md_plan_config(md.make_config(2000000, [L2] * 3, cell_factor=2, **wca))
     assert p["nl_build"] == "per_particle" and p["cell_factor"] == 2
     assert p["cells"] == [int(L2 * 2 / (rv * (1 + 1e-12)))] * 3
-    p = md.md_plan_config(md.make_config(2000000, [L2] * 3, flags=md.MD_CFG_NL_TILES, **wca))
-    assert p["nl_build"] == "tiles" and p["cell_factor"] == 2
     p = md.md_plan_config(md.make_config(1048576, [L] * 3, flags=md.MD_CFG_NL_PER_PARTICLE, **lj))
-    assert p["nl_build"] == "per_particle" and p["cell_factor"] == 2
+    assert p["nl_build"] == "per_particle" and p["cell_factor"] == 1
     p = md.md_plan_config(md.make_config(1048576, [L] * 3, cell_factor=2, **lj))
     assert p["nl_build"] == "per_particle"
     # a dense box of 3 list radii: 3 full cells per side and tiles
     p = md.md_plan_config(md.make_config(1000, [8.4 * 1.0000001] * 3, **lj))
     assert p["cells"] == [3, 3, 3] and p["cell_factor"] == 1 and p["nl_build"] == "tiles"
-    # a sparse box of 4.3 list radii holds 8 half cells per side: half cells, per particle
+    # a sparse box of 4.3 list radii: 4 full cells per side, per particle
     p = md.md_plan_config(md.make_config(100, [12.0] * 3, **lj))
-    assert p["cell_factor"] == 2 and p["nl_build"] == "per_particle" and p["cells"] == [8, 8, 8]
+    assert p["cell_factor"] == 1 and p["nl_build"] == "per_particle" and p["cells"] == [4, 4, 4]
+    # a box of 2.7 list radii holds 2 full cells but 5 half cells per side
+    p = md.md_plan_config(md.make_config(20, [7.6] * 3, **lj))
+    assert p["cell_factor"] == 2 and p["nl_build"] == "per_particle" and p["cells"] == [5, 5, 5]

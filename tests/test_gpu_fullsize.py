@@ -3,9 +3,8 @@
 The 1,048,576-particle LJ fluid (FCC 64^3 with jitter, rc 2.5, skin 0.3,
 NVE) and a 2,000,000-bead Kremer-Grest melt (2,000 chains x 1,000 beads at
 density 0.85, WCA + FENE + bending 1.5, Langevin, skin 0.4) run with FP32
-pair math and the library's automatic choices.  That is the tile list build
-on cells of side rc+skin for the fluid, and the per-particle build on
-half-cutoff cells for the melt.  The FP64 oracle (linked cells, all host
+pair math and the library's automatic choices: cells of side rc+skin, with
+the tile list build for the fluid and the per-particle build for the melt.  The FP64 oracle (linked cells, all host
 threads) computes every particle's force at full size, so the check is
 element by element, not sampled:
 
