@@ -254,7 +254,7 @@ static size_t carve(const md_config* c, const Geom& g, int step_grid, uint8_t* b
         t.ccount = (int32_t*)take(sizeof(int32_t) * g.ncell);
         t.cstart = (int32_t*)take(sizeof(int32_t) * (g.ncell + 1));
     }
-    t.bsum = (int32_t*)take(sizeof(int32_t) * kScanBlocks);
+    t.bsum = (int32_t*)take(sizeof(int32_t) * kScanBlocks * kChunkPad);
     t.tmp = (int32_t*)take(sizeof(int32_t) * n);
     t.xt = (double4*)take(sizeof(double4) * n);
     t.vt = (double*)take(sizeof(double) * 3 * n);
@@ -693,7 +693,7 @@ static md_status init_core(const md_config* cfg, const double* pos, const double
     // control block and cell counters start at zero
     if (launch_zero_i32((int32_t*)h->b.ctl, sizeof(DevCtl) / 4, h->stream) != hipSuccess ||
         launch_zero_i32(h->b.ccount, g.ncell, h->stream) != hipSuccess ||
-        launch_zero_i32(h->b.bsum, kScanBlocks, h->stream) != hipSuccess ||
+        launch_zero_i32(h->b.bsum, kScanBlocks * kChunkPad, h->stream) != hipSuccess ||
         launch_zero_i32(h->b.ncount, g.n, h->stream) != hipSuccess ||
         launch_zero_i32((int32_t*)h->b.partials, 2 * kNacc * (int64_t)sg, h->stream) != hipSuccess)
         return bail(fail(nullptr, MD_ERR_HIP, "kernel launch failed during init"));

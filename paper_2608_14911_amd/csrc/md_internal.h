@@ -10,7 +10,8 @@
 namespace md {
 
 constexpr int kBlock = 256;            // threads per block of the streaming kernels
-constexpr int kScanBlocks = 1024;      // blocks of the 3-phase cell-count scan (<= 1024)
+constexpr int kScanBlocks = 1024;      // chunks (blocks) of the cell-count scan (<= 1024)
+constexpr int kChunkPad = 32;          // one 128-byte line per chunk sum (atomics on a line serialize)
 constexpr int kMaxGrid = 65535 * 16;   // cap for 1-D grids
 constexpr int kNacc = 11;              // reduced quantities per step, see Acc
 constexpr int kHistRec = 16;           // doubles per history record
@@ -101,7 +102,7 @@ struct Bufs {
     uint32_t* cellid;       // [N]
     int32_t* ccount;        // [ncell], all zero between rebuilds
     int32_t* cstart;        // [ncell + 1]
-    int32_t* bsum;          // [kScanBlocks]
+    int32_t* bsum;          // [kScanBlocks] chunk sums; one system: [kScanBlocks][kChunkPad], column 0
     int32_t* tmp;           // [N] scatter slots
     double4* xt;            // permute temporaries
     double* vt;
