@@ -455,10 +455,11 @@ static hipError_t enqueue_step(md_handle h, const EvQuad* q) {
     if (e != hipSuccess) return e;
     if (q) (void)hipEventRecord(q->e[1], h->stream);
     const double* spart = nullptr;
-    e = launch_force_stage(h, MODE_STEP, (h->cfg.flags & MD_CFG_VIRIAL_TENSOR) ? 1 : 0, nullptr, &spart);
+    const int tensor = (h->cfg.flags & MD_CFG_VIRIAL_TENSOR) ? 1 : 0;
+    e = launch_force_stage(h, MODE_STEP, tensor, nullptr, &spart);
     if (e != hipSuccess) return e;
     if (q) (void)hipEventRecord(q->e[2], h->stream);
-    e = launch_finalize(h->b, h->step_grid, MODE_STEP, spart, h->stream);
+    e = launch_finalize(h->b, h->step_grid, MODE_STEP, spart, tensor, h->stream);
     if (e != hipSuccess) return e;
     if (q) (void)hipEventRecord(q->e[3], h->stream);
     h->parity ^= 1;
@@ -757,7 +758,7 @@ md_status md_forces(md_handle h, double* f_out) {
     if (r != MD_OK) return r;
     const double* spart = nullptr;
     HIP_TRY(h, launch_force_stage(h, MODE_FORCES, 1, f_out, &spart));
-    HIP_TRY(h, launch_finalize(h->b, h->step_grid, MODE_FORCES, spart, h->stream));
+    HIP_TRY(h, launch_finalize(h->b, h->step_grid, MODE_FORCES, spart, 1, h->stream));
     return MD_OK;
 }
 
@@ -809,7 +810,7 @@ md_status md_observables(md_handle h, md_obs* out) {
     if (r != MD_OK) return r;
     const double* spart = nullptr;
     HIP_TRY(h, launch_force_stage(h, MODE_OBSERVE, 1, nullptr, &spart));
-    HIP_TRY(h, launch_finalize(h->b, h->step_grid, MODE_OBSERVE, spart, h->stream));
+    HIP_TRY(h, launch_finalize(h->b, h->step_grid, MODE_OBSERVE, spart, 1, h->stream));
     double rec[kHistRec];
     HIP_TRY(h, hipMemcpyAsync(rec, h->b.cur, sizeof(rec), hipMemcpyDeviceToHost, h->stream));
     DevCtl c;

@@ -277,7 +277,7 @@ hipError_t launch_clear_rebuild(const Bufs& b, hipStream_t s);
 hipError_t launch_step(const StepArgs& a, int fp64, int single_type, int bonded, int block,
                        hipStream_t s);
 int step_grid(int64_t n);
-hipError_t launch_finalize(const Bufs& b, int nblocks, int mode, const double* spart, hipStream_t s);
+hipError_t launch_finalize(const Bufs& b, int nblocks, int mode, const double* spart, int tensor, hipStream_t s);
 hipError_t launch_overwrite_state(const Geom& g, const Bufs& b, int parity, const double* pos,
                                   const double* vel, const int32_t* image, hipStream_t s);
 hipError_t launch_get_state(const Geom& g, const Bufs& b, int parity, double* pos, double* vel,

@@ -1416,7 +1416,9 @@ __global__ void __launch_bounds__(kBlock) k_step_ext(const StepArgs a, const flo
 // observables, and (MODE_STEP) advance the step counter and move the
 // rebuild request to the next step.
 constexpr int kFinal = 1024;
-__device__ __forceinline__ void finalize_body(const Bufs& b, int nblocks, int mode, const double* spart) {
+// nacc: the number of quantities the step kernel accumulated (the virial
+// tensor only when it was asked for); the others are zero and not read.
+__device__ __forceinline__ void finalize_body(const Bufs& b, int nblocks, int mode, const double* spart, int nacc) {
     __shared__ double red[kFinal / 64][kNacc];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     double s[kNacc];
@@ -1428,7 +1430,8 @@ __device__ __forceinline__ void finalize_body(const Bufs& b, int nblocks, int mo
         for (int r = 0; r < 4; ++r) {
             const int blk = blk0 + r * kFinal + threadIdx.x;
 #pragma unroll
-            for (int k = 0; k < kNacc; ++k) v[r][k] = blk < nblocks ? b.partials[(int64_t)k * nblocks + blk] : 0.0;
+            for (int k = 0; k < kNacc; ++k)
+                v[r][k] = (k < nacc && blk < nblocks) ? b.partials[(int64_t)k * nblocks + blk] : 0.0;
         }
 #pragma unroll
         for (int r = 0; r < 4; ++r)
@@ -1441,13 +1444,14 @@ __device__ __forceinline__ void finalize_body(const Bufs& b, int nblocks, int mo
                 if (blk >= nblocks) continue;
                 s[A_EPAIR] += spart[blk];
                 s[A_VIR] += spart[(int64_t)nblocks + blk];
-                for (int k = 0; k < 6; ++k) s[A_TXX + k] += spart[(int64_t)(2 + k) * nblocks + blk];
+                if (nacc == kNacc)
+                    for (int k = 0; k < 6; ++k) s[A_TXX + k] += spart[(int64_t)(2 + k) * nblocks + blk];
             }
         }
     }
 #pragma unroll
     for (int k = 0; k < kNacc; ++k) {
-        const double t = wave_sum(s[k]);
+        const double t = k < nacc ? wave_sum(s[k]) : 0.0;
         if (lane == 0) red[w][k] = t;
     }
     __syncthreads();
@@ -1491,8 +1495,8 @@ __device__ __forceinline__ void finalize_body(const Bufs& b, int nblocks, int mo
     }
 }
 
-__global__ void __launch_bounds__(kFinal) k_finalize(Bufs b, int nblocks, int mode, const double* spart) {
-    finalize_body(b, nblocks, mode, spart);
+__global__ void __launch_bounds__(kFinal) k_finalize(Bufs b, int nblocks, int mode, const double* spart, int nacc) {
+    finalize_body(b, nblocks, mode, spart, nacc);
 }
 
 // ------------------------------------------------------------------ batches
@@ -1633,7 +1637,7 @@ __global__ void __launch_bounds__(kBlock) k_batch_step(const SysEntry* __restric
 
 __global__ void __launch_bounds__(kFinal) k_batch_finalize(const SysEntry* __restrict__ tab, int mode) {
     const SysEntry& e = tab[blockIdx.x];
-    finalize_body(e.a.b, e.ntiles, mode, nullptr);
+    finalize_body(e.a.b, e.ntiles, mode, nullptr, kNacc);
 }
 
 __global__ void k_batch_gather_obs(const SysEntry* __restrict__ tab, int nsys, double* out) {
@@ -1754,8 +1758,8 @@ hipError_t launch_step(const StepArgs& a, int fp64, int single_type, int bonded,
     return hipGetLastError();
 }
 
-hipError_t launch_finalize(const Bufs& b, int nblocks, int mode, const double* spart, hipStream_t s) {
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kFinal), 0, s, b, nblocks, mode, spart);
+hipError_t launch_finalize(const Bufs& b, int nblocks, int mode, const double* spart, int tensor, hipStream_t s) {
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kFinal), 0, s, b, nblocks, mode, spart, tensor ? kNacc : A_VIR + 1);
     return hipGetLastError();
 }
 
