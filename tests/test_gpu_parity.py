@@ -45,6 +45,9 @@ def test_neighbor_sets_bitexact_random(seed, n, L, cf):
     ref = oracle.neighbors(pos, [L, L, L], rv)
     for i in range(n):
         assert np.array_equal(got[i], ref[i]), i
+    # the longest row, which the build keeps with one conditional atomic per
+    # wavefront, is the oracle's
+    assert s.observables()["nl_max_count"] == max(len(r) for r in ref)
     s.close()
 
 
@@ -106,6 +109,8 @@ def test_tile_list_build_equals_per_particle_build(case):
     ref = oracle.neighbors(pos, box, rc + skin)
     for i in range(n):
         assert np.array_equal(np.sort(rows[0][i]), ref[i]), i
+    for s in sys:
+        assert s.observables()["nl_max_count"] == max(len(r) for r in ref)
     for s in sys:
         s.step(40)
     st = [s.get_state() for s in sys]
