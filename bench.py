@@ -38,8 +38,8 @@ ALG_BYTES = {"lj1m": 327.0, "kg2m": 213.0, "kg1k": 213.0, "sur1m": 819.0}
 # HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE passes (scaled by a 512 MiB copy: x2.0 and x1.0), valid only for
 # the kernel source they were taken on (SHA-256 prefix of md_kernels.hip).
-TRAFFIC = {"lj1m": {"bytes": 232659.1 * 2.0 * 1024 + 75232.5 * 1024, "source": "04b4fbf1d4a75a76"},
-           "kg2m": {"bytes": 231672.3 * 2.0 * 1024 + 174643.0 * 1024, "source": "04b4fbf1d4a75a76"}}
+TRAFFIC = {"lj1m": {"bytes": 226635.5 * 2.0 * 1024 + 87480.0 * 1024, "source": "8c23e66d09ea82f3"},
+           "kg2m": {"bytes": 232674.2 * 2.0 * 1024 + 174642.0 * 1024, "source": "8c23e66d09ea82f3"}}
 
 
 def kernel_source_hash():

@@ -199,6 +199,10 @@ static md_status plan_geom(const md_config* c, Geom* g, std::string* why) {
     }
     g->nl_tile = (!per_particle && ((c->flags & MD_CFG_NL_TILES) || (dense && g->kc == 1))) ? 1 : 0;
     g->nl_cubic = (c->box[0] == c->box[1] && c->box[1] == c->box[2]) ? 1 : 0;
+    // the unbonded fast step kernel gathers 12-byte records (fewer L1 lines per
+    // gather: 4% faster on the LJ fluid); the bonded one keeps the 16-byte
+    // records, for which the extra stores cost more than the gathers save
+    g->x3_on = (c->n_bonds == 0 && c->n_angles == 0) ? 1 : 0;
     {
         // rv^2 -/+ band over ql^2 (ql = L 2^-32 exactly), rounded outwards to float
         const double ql = c->box[0] * 0x1.0p-32;
@@ -243,6 +247,8 @@ static size_t carve(const md_config* c, const Geom& g, int step_grid, uint8_t* b
     t.x[1] = (double4*)take(sizeof(double4) * n);
     t.xq[0] = (int4*)take(sizeof(int4) * n);
     t.xq[1] = (int4*)take(sizeof(int4) * n);
+    t.x3[0] = (int32_t*)take(sizeof(int32_t) * 3 * n);
+    t.x3[1] = (int32_t*)take(sizeof(int32_t) * 3 * n);
     t.v = (double*)take(sizeof(double) * 3 * n);
     t.xb = (double*)take(sizeof(double) * 3 * n);
     t.img = (int32_t*)take(sizeof(int32_t) * 3 * n);

@@ -18,6 +18,18 @@ __device__ __forceinline__ int4 quantize4(const Geom& g, double x, double y, dou
     return make_int4((int)quantize(x, g.qs[0]), (int)quantize(y, g.qs[1]), (int)quantize(z, g.qs[2]), (int)w);
 }
 
+// 12-byte fixed-point record (x, y, z): the fast step kernel gathers these,
+// 25 instead of 29 distinct 128-byte lines per 64-lane gather on the LJ
+// fluid's lists (counted on the CPU) against 16-byte records.
+struct alignas(4) Q3 {
+    int32_t x, y, z;
+};
+__device__ __forceinline__ void store_q3(int32_t* p, int64_t i, const int4& q) {
+    p[3 * i] = q.x;
+    p[3 * i + 1] = q.y;
+    p[3 * i + 2] = q.z;
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);

@@ -84,6 +84,8 @@ struct Geom {
     float rq2lo, rq2hi;     // the list band in units of (L 2^-32)^2 (cubic box)
     uint32_t r16lo, r16hi;  // a wider band in units of (L 2^-16)^2 for the 16-bit
                             // prefilter of the tile build (cubic box)
+    int32_t x3_on;          // keep the 12-byte position records (systems without bonds,
+                            // whose fast step kernel gathers them)
 };
 
 struct Bufs {
@@ -93,6 +95,7 @@ struct Bufs {
     double* cur;            // [kHistRec] observables of the last finalize
     double4* x[2];          // positions (w = type), sorted order, by step parity
     int4* xq[2];            // fixed-point positions (w = type), by step parity
+    int32_t* x3[2];         // the same x, y, z as 12-byte records, by parity (kept when Geom::x3_on)
     double* v;              // [3][N] SoA, sorted order
     double* xb;             // [3][N] positions at the last build
     int32_t* img;           // [3][N]

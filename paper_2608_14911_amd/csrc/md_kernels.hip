@@ -177,7 +177,9 @@ __global__ void __launch_bounds__(kBlock) k_overwrite_state(Geom g, Bufs b, int 
             b.v[d * n + s] = vel[3 * t + d];
         }
         b.x[parity][s] = make_double4(p[0], p[1], p[2], old.w);
-        b.xq[parity][s] = quantize4(g, p[0], p[1], p[2], old.w);
+        const int4 q = quantize4(g, p[0], p[1], p[2], old.w);
+        b.xq[parity][s] = q;
+        if (g.x3_on) store_q3(b.x3[parity], s, q);
     }
 }
 
@@ -461,7 +463,9 @@ __device__ __forceinline__ void commit_one(const Geom& g, const Bufs& b, int64_t
     {
         double4 p = b.xt[s];
         b.x[parity][s] = p;
-        b.xq[parity][s] = quantize4(g, p.x, p.y, p.z, p.w);
+        const int4 q = quantize4(g, p.x, p.y, p.z, p.w);
+        b.xq[parity][s] = q;
+        if (g.x3_on) store_q3(b.x3[parity], s, q);
         b.xb[s] = p.x;
         b.xb[n + s] = p.y;
         b.xb[2 * n + s] = p.z;
@@ -1054,7 +1058,9 @@ __device__ __forceinline__ void finish_particle(const StepArgs& a, int64_t i, co
         }
         if (d2 > g.disp2) flag_reb = true;
         b.x[a.parity ^ 1][i] = make_double4(xo[0], xo[1], xo[2], xi.w);
-        b.xq[a.parity ^ 1][i] = quantize4(g, xo[0], xo[1], xo[2], xi.w);
+        const int4 qn = quantize4(g, xo[0], xo[1], xo[2], xi.w);
+        b.xq[a.parity ^ 1][i] = qn;
+        if (g.x3_on) store_q3(b.x3[a.parity ^ 1], i, qn);
     } else if (a.mode == MODE_FORCES && a.f_out) {
         a.f_out[3 * (int64_t)tg] = F[0];
         a.f_out[3 * (int64_t)tg + 1] = F[1];
@@ -1302,7 +1308,9 @@ __device__ __forceinline__ void fast_particle(const StepArgs& a, int64_t i, doub
         cnt = cnt < g.cap ? cnt : g.cap;
         const int nslots = (cnt + 7) & ~7;
         const int32_t* __restrict__ row = b.nl + nl_base(i, g.cap);
-        const char* __restrict__ xqb = reinterpret_cast<const char*>(xq);
+        // unbonded: 12-byte records (Geom::x3_on); bonded: the 16-byte ones
+        const char* __restrict__ recb = BONDED ? reinterpret_cast<const char*>(xq)
+                                              : reinterpret_cast<const char*>(b.x3[a.parity]);
         const int last = nslots > 0 ? nslots - 1 : 0;  // loads past the row repeat its last slot
         // Indices are loaded two batches ahead of their gathers (16 loads
         // of 256 bytes in flight per wavefront) to cover HBM latency.
@@ -1315,11 +1323,16 @@ __device__ __forceinline__ void fast_particle(const StepArgs& a, int64_t i, doub
         }
         for (int k0 = 0; k0 < nslots; k0 += B) {
             int jc[B];
-            int4 q[B];
+            Q3 q[B];
 #pragma unroll
             for (int u = 0; u < B; ++u) {
                 jc[u] = jn[u];
-                q[u] = *reinterpret_cast<const int4*>(xqb + ((uint32_t)jc[u] << 4));
+                if (BONDED) {
+                    const int4 r = *reinterpret_cast<const int4*>(recb + ((uint32_t)jc[u] << 4));
+                    q[u] = Q3{r.x, r.y, r.z};
+                } else {
+                    q[u] = *reinterpret_cast<const Q3*>(recb + (uint32_t)jc[u] * 12u);
+                }
             }
 #pragma unroll
             for (int u = 0; u < B; ++u) {
