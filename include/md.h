@@ -76,8 +76,7 @@ enum { MD_FP64 = 0, MD_FP32 = 1 };       /* md_config.force_precision */
 /* md_config.flags */
 #define MD_CFG_VIRIAL_TENSOR 0x1  /* accumulate the 6-component virial every step */
 #define MD_CFG_NO_GRAPH 0x2       /* md_step launches kernels one by one, no hipGraph */
-#define MD_CFG_NL_PER_PARTICLE 0x4 /* build the Verlet list one particle per lane (half-
-                                      cutoff cells when cell_factor = 0 and they fit) */
+#define MD_CFG_NL_PER_PARTICLE 0x4 /* build the Verlet list one particle per lane */
 #define MD_CFG_NL_TILES 0x8        /* build it one wavefront per 64-particle tile.  Default:
                                       tiles when cells of side rc+skin hold >= 8 particles
                                       on average, else per particle.  Both builds give the
@@ -111,7 +110,8 @@ typedef struct md_config {
     double k_bend;             /* u = k (1 - cos theta), theta = 0 straight */
     int32_t cell_factor;       /* 1 or 2: cells of side >= (rc+skin)/cell_factor;
                                   2 is the half-cutoff sub-cell decomposition;
-                                  0 = 2 when >= 5 such cells fit per side, else 1 */
+                                  0 = 1, or 2 when fewer than 3 cells of side
+                                  rc+skin fit per side */
     int32_t nl_capacity;       /* neighbours per particle; 0 = from density */
     int32_t block_size;        /* threads per block of the force kernel; 0 = 256 */
     int32_t flags;             /* MD_CFG_* */
