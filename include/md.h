@@ -94,7 +94,7 @@ typedef struct md_pair_params {
 typedef struct md_config {
     uint32_t struct_size;      /* = sizeof(md_config); ABI version check */
     int32_t n_types;           /* 1 .. MD_MAX_TYPES */
-    int64_t n_particles;       /* >= 1 */
+    int64_t n_particles;       /* 1 .. 2^28 - 1 (32-bit byte offsets of 16-byte records) */
     double box[3];             /* periodic orthorhombic box lengths */
     double dt;                 /* > 0 */
     double skin;               /* > 0; Verlet list radius = max rc + skin */

@@ -83,7 +83,12 @@ static md_status validate(const md_config* c, std::string* why) {
     if (!c) { *why = "config is NULL"; return MD_ERR_ARG; }
     if (c->struct_size != sizeof(md_config)) { *why = "md_config.struct_size mismatch (ABI version)"; return MD_ERR_ARG; }
     if (c->n_types < 1 || c->n_types > MD_MAX_TYPES) { *why = "n_types out of range"; return MD_ERR_ARG; }
-    if (c->n_particles < 1 || c->n_particles > (int64_t)0x3fffffff) { *why = "n_particles out of range"; return MD_ERR_ARG; }
+    // the step kernels address gathered records with 32-bit byte offsets
+    // (16 bytes per particle): at most 2^28 - 1 particles per system
+    if (c->n_particles < 1 || c->n_particles > ((int64_t)1 << 28) - 1) {
+        *why = "n_particles out of range (1 .. 2^28 - 1)";
+        return MD_ERR_ARG;
+    }
     for (int d = 0; d < 3; ++d)
         if (!(c->box[d] > 0.0) || !isfinite(c->box[d])) { *why = "box must be positive and finite"; return MD_ERR_ARG; }
     if (!(c->dt > 0.0) || !isfinite(c->dt)) { *why = "dt must be > 0"; return MD_ERR_ARG; }

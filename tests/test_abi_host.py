@@ -83,6 +83,7 @@ def test_workspace_bytes_grows_with_size_and_capacity():
     (lambda c: setattr(c, "n_types", 0), md.MD_ERR_ARG),
     (lambda c: setattr(c, "n_types", 5), md.MD_ERR_ARG),
     (lambda c: setattr(c, "n_particles", 0), md.MD_ERR_ARG),
+    (lambda c: setattr(c, "n_particles", 1 << 28), md.MD_ERR_ARG),     # 32-bit record offsets
     (lambda c: setattr(c, "dt", 0.0), md.MD_ERR_ARG),
     (lambda c: setattr(c, "skin", -0.1), md.MD_ERR_ARG),
     (lambda c: setattr(c, "integrator", 7), md.MD_ERR_ARG),
