@@ -246,7 +246,7 @@ md_status md_timing_read(md_handle h, md_timing* out);
  * Learned surrogate of the non-bonded pair force.  The paper has no learned
  * model; this is an extension built on its pair-force step: a per-particle
  * radial-descriptor MLP trained by force matching against the plain
- * potential, which stays available as the fallback and as the judge of the
+ * potential, which stays available as the fallback and as the reference for the
  * surrogate's error.  FENE and bending stay plain.
  *
  *   g_k(r)   = exp(-(r - mu_k)^2 / (2 w^2)) (cos(pi r / r_d) + 1) / 2,
