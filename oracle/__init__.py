@@ -15,7 +15,9 @@ passages of the paper they follow:
                       Kremer-Grest melt.
 * ``forces``       -- F_i = -grad_i U summed over pairs inside the cutoff, by
                       brute force or the oracle's own linked cells (CellGrid,
-                      section "Software design").
+                      section "Software design"), with the energies, the
+                      virial W = sum r_ij . f_ij (computeEnergy(), pressure)
+                      and the sum of its terms' magnitudes, W's scale.
 * ``neighbors``    -- Verlet-list sets { j != i : r_ij^2 < (rc+skin)^2 }
                       (VerletList + system.skin, section "Example usage").
 * ``run``          -- VelocityVerlet with the LangevinThermostat extension
@@ -33,7 +35,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "_md_oracle.so")
 _lib = None
 
-NOBS = 10   # e_pair, e_bond, e_angle, W, Wxx, Wyy, Wzz, Wxy, Wxz, Wyz
+NOBS = 11   # e_pair, e_bond, e_angle, W, Wxx, Wyy, Wzz, Wxy, Wxz, Wyz, sum |r.f|
 NHIST = 11  # e_pair, e_bond, e_angle, e_kin, W, tensor[6]
 
 OK = 0
@@ -177,7 +179,7 @@ def forces(pos, box, pp, ntypes=1, type=None, bonds=None, angles=None, fene_K=30
     if st != OK:
         raise OracleError(st, "forces")
     out = {"e_pair": obs[0], "e_bond": obs[1], "e_angle": obs[2], "virial": obs[3],
-           "virial_tensor": obs[4:10].copy()}
+           "virial_tensor": obs[4:10].copy(), "virial_abs": obs[10]}
     if want_fscale:
         out["fscale"] = fscale
     return F, out

@@ -204,8 +204,11 @@ typedef struct {
 } orc_sys;
 
 /* obs layout (doubles): 0 e_pair, 1 e_bond, 2 e_angle, 3 virial W,
- * 4..9 virial tensor xx yy zz xy xz yz */
-#define ORC_NOBS 10
+ * 4..9 virial tensor xx yy zz xy xz yz, 10 the sum of the magnitudes of the
+ * virial's terms, sum |r_ij . f_ij| over pairs and bonds plus
+ * |r_ab . F_a| + |r_cb . F_c| per angle: the scale against which W, a sum of
+ * terms of both signs, can be compared */
+#define ORC_NOBS 11
 
 static int type_of(const orc_sys* s, int64_t i) { return s->type ? s->type[i] : 0; }
 static orc_pair pair_of(const orc_sys* s, int ti, int tj) {
@@ -242,6 +245,7 @@ static int bonded_forces(const orc_sys* s, const double* pos, double* F, double*
         for (int d = 0; d < 3; ++d) { F[3 * i + d] += f[d]; F[3 * j + d] -= f[d]; }
         obs[1] += u;
         obs[3] += fr * r2;
+        obs[10] += fabs(fr * r2);
         add_tensor(obs, 1.0, rij, f);
         if (fscale) {
             double fm = fabs(fr) * sqrt(r2);
@@ -263,8 +267,11 @@ static int bonded_forces(const orc_sys* s, const double* pos, double* F, double*
         obs[2] += u;
         /* virial: (r_a - r_b).F_a + (r_c - r_b).F_c */
         double rab[3] = {-b1[0], -b1[1], -b1[2]};
-        obs[3] += rab[0] * Fa[0] + rab[1] * Fa[1] + rab[2] * Fa[2];
-        obs[3] += b2[0] * Fc[0] + b2[1] * Fc[1] + b2[2] * Fc[2];
+        const double wa = rab[0] * Fa[0] + rab[1] * Fa[1] + rab[2] * Fa[2];
+        const double wc = b2[0] * Fc[0] + b2[1] * Fc[1] + b2[2] * Fc[2];
+        obs[3] += wa;
+        obs[3] += wc;
+        obs[10] += fabs(wa) + fabs(wc);
         add_tensor(obs, 1.0, rab, Fa);
         add_tensor(obs, 1.0, b2, Fc);
         if (fscale) {
@@ -297,6 +304,7 @@ static void pair_forces_brute(const orc_sys* s, const double* pos, double* F, do
             for (int d = 0; d < 3; ++d) { F[3 * i + d] += f[d]; F[3 * j + d] -= f[d]; }
             obs[0] += u;
             obs[3] += fr * r2;
+            obs[10] += fabs(fr * r2);
             add_tensor(obs, 1.0, rij, f);
             if (fscale) {
                 double fm = fabs(fr) * sqrt(r2);
@@ -373,11 +381,11 @@ static int pair_forces_cells(const orc_sys* s, const double* pos, double* F, dou
     }
     const double L[3] = {s->box[0], s->box[1], s->box[2]};
     const double H[3] = {0.5 * L[0], 0.5 * L[1], 0.5 * L[2]};
-    double e_pair = 0, w = 0, t0 = 0, t1 = 0, t2 = 0, t3 = 0, t4 = 0, t5 = 0;
+    double e_pair = 0, w = 0, wabs = 0, t0 = 0, t1 = 0, t2 = 0, t3 = 0, t4 = 0, t5 = 0;
 #ifdef _OPENMP
     if (nthreads <= 0) nthreads = omp_get_max_threads();
 #pragma omp parallel for schedule(dynamic, 256) num_threads(nthreads) \
-    reduction(+ : e_pair, w, t0, t1, t2, t3, t4, t5)
+    reduction(+ : e_pair, w, wabs, t0, t1, t2, t3, t4, t5)
 #endif
     for (int64_t i = 0; i < s->n; ++i) {
         int ti = type_of(s, i);
@@ -404,6 +412,7 @@ static int pair_forces_cells(const orc_sys* s, const double* pos, double* F, dou
                         fi[0] -= fr * dx; fi[1] -= fr * dy; fi[2] -= fr * dz;
                         e_pair += 0.5 * u;
                         w += 0.5 * fr * r2;
+                        wabs += 0.5 * fabs(fr * r2);
                         t0 += 0.5 * fr * dx * dx; t1 += 0.5 * fr * dy * dy; t2 += 0.5 * fr * dz * dz;
                         t3 += 0.5 * fr * dx * dy; t4 += 0.5 * fr * dx * dz; t5 += 0.5 * fr * dy * dz;
                         fs += fabs(fr) * sqrt(r2);
@@ -412,7 +421,7 @@ static int pair_forces_cells(const orc_sys* s, const double* pos, double* F, dou
         for (int d = 0; d < 3; ++d) F[3 * i + d] += fi[d];
         if (fscale) fscale[i] += fs;
     }
-    obs[0] += e_pair; obs[3] += w;
+    obs[0] += e_pair; obs[3] += w; obs[10] += wabs;
     obs[4] += t0; obs[5] += t1; obs[6] += t2; obs[7] += t3; obs[8] += t4; obs[9] += t5;
     cells_free(&c);
     return ORC_OK;

@@ -44,6 +44,40 @@ def fcc_lattice_sums(density, rc):
     return 0.5 * u.sum(), 0.5 * rf.sum(), r
 
 
+def test_virial_magnitude_sum_pins():
+    """The oracle's sum of the virial's term magnitudes, sum |r_ij . f_ij|
+    (the scale of W, whose terms have both signs): the FCC lattice value from
+    the independent enumeration; equal to W when every term is repulsive
+    (capped WCA pairs) and to -W when every term is attractive (FENE bonds with
+    the pair potential switched off); the same through cells and brute force."""
+    rho, rc = 0.8442, 2.5
+    a = (4.0 / rho) ** (1.0 / 3.0)
+    m = int(np.ceil(rc / a)) + 1
+    g = np.arange(-m, m + 1)
+    cells = np.stack(np.meshgrid(g, g, g, indexing="ij"), axis=-1).reshape(-1, 3)
+    basis = np.array([[0, 0, 0], [0.5, 0.5, 0], [0.5, 0, 0.5], [0, 0.5, 0.5]])
+    r = np.linalg.norm(((cells[:, None, :] + basis[None]).reshape(-1, 3)) * a, axis=1)
+    r = r[(r > 0) & (r < rc)]
+    _, rf = lj_numpy(r, rc=rc)
+    pos, box = inputs.fcc_lattice(8, rho, jitter=0.0)
+    n = pos.shape[0]
+    _, obs = oracle.forces(pos, box, oracle.pair_params(rc=rc))
+    assert obs["virial_abs"] / n == pytest.approx(0.5 * np.abs(rf).sum(), rel=1e-12)
+    # every lattice neighbour sits beyond the LJ minimum (a / sqrt 2 = 1.187 > 2^(1/6)): all attract
+    assert r.min() > 2.0 ** (1.0 / 6.0)
+    assert obs["virial_abs"] == pytest.approx(-obs["virial"], rel=1e-12)
+    w = inputs.random_walk_chains(10, 20, 0.6, seed=11)
+    _, o = oracle.forces(w["pos"], w["box"], oracle.pair_params(rc=WCA, caprad=0.8))
+    assert o["virial_abs"] == pytest.approx(o["virial"], rel=1e-13) and o["virial"] > 0
+    _, o = oracle.forces(w["pos"], w["box"], oracle.pair_params(eps=0.0, rc=WCA), bonds=w["bonds"])
+    assert o["virial_abs"] == -o["virial"] and o["virial"] < 0
+    kw = dict(bonds=w["bonds"], angles=w["angles"], k_bend=1.5)
+    _, ob = oracle.forces(w["pos"], w["box"], oracle.pair_params(rc=2.5, caprad=0.8), use_cells=False, **kw)
+    _, oc = oracle.forces(w["pos"], w["box"], oracle.pair_params(rc=2.5, caprad=0.8), use_cells=True, **kw)
+    assert oc["virial_abs"] == pytest.approx(ob["virial_abs"], rel=1e-11)
+    assert ob["virial_abs"] >= abs(ob["virial"])
+
+
 def test_fcc_shell_counts_and_lattice_sums():
     rho, rc, rv = 0.8442, 2.5, 2.8
     U_per, W_per, r = fcc_lattice_sums(rho, rc)
