@@ -25,6 +25,10 @@ passages of the paper they follow:
 * ``philox``, ``gauss3`` -- the counter-based noise source (Philox4x64-10,
                       Salmon et al. 2011) that both sides implement
                       independently.
+* ``forces_ext``, ``neighbors_le``, ``run_ext``, ``dpd_theta`` -- Lees-Edwards
+                      sheared boundaries (section "New Features") and the
+                      dissipative-particle-dynamics thermostat (section
+                      "Functionality"), by brute force over pairs.
 """
 import ctypes
 import os
@@ -80,6 +84,16 @@ def _load():
     lib.orc_run.argtypes = [i64, P, P, P, P, P, i32, P, P, i64, P, f64, f64, i64, P, f64,
                             f64, i32, f64, f64, u64, P, P, i64, i32, i32, P]
     lib.orc_run.restype = ctypes.c_int
+    lib.orc_dpd_theta.argtypes = [u64, u64, u64, u64]
+    lib.orc_dpd_theta.restype = f64
+    lib.orc_forces_ext.argtypes = [i64, P, P, P, i32, P, P, i64, P, f64, f64, i64, P, f64, f64, f64, f64, f64, f64,
+                                   u64, i64, P, P, P, P]
+    lib.orc_forces_ext.restype = ctypes.c_int
+    lib.orc_neighbors_le.argtypes = [i64, P, P, f64, f64, f64, i64, i32, P, P]
+    lib.orc_neighbors_le.restype = ctypes.c_int
+    lib.orc_run_ext.argtypes = [i64, P, P, P, P, P, i32, P, P, i64, P, f64, f64, i64, P, f64,
+                                f64, i32, f64, f64, u64, f64, f64, P, P, i64, P]
+    lib.orc_run_ext.restype = ctypes.c_int
     lib.orc_nthreads_default.argtypes = []
     lib.orc_nthreads_default.restype = ctypes.c_int
     _lib = lib
@@ -258,4 +272,93 @@ def run(state, params, nsteps, use_cells=True, nthreads=0):
     state["vel_half"] = vh.value
     if st != OK:
         raise OracleError(st, "run")
+    return hist
+
+
+# ---------------------------------------------------------------- Lees-Edwards + DPD
+DPD = 2
+
+
+def dpd_theta(seed, step, ti, tj):
+    """The symmetric pair noise theta_ij of the DPD thermostat."""
+    return _load().orc_dpd_theta(seed, step, ti, tj)
+
+
+def forces_ext(pos, box, pp, vel=None, ntypes=1, type=None, bonds=None, angles=None, fene_K=30.0, fene_R0=1.5,
+               k_bend=0.0, shear_rate=0.0, dpd_rc=0.0, dpd_gamma=0.0, kT=1.0, dt=0.005, seed=0, step=0,
+               want_fscale=False):
+    """Conservative forces F under the sheared boundaries at time step * dt
+    and, when dpd_rc > 0, the DPD thermostat forces Fd at velocities vel.
+    Returns (F, Fd or None, obs)."""
+    pos = _c(pos, np.float64)
+    n = pos.shape[0]
+    vel = _c(vel, np.float64)
+    box, pp = _c(box, np.float64), _c(pp, np.float64)
+    type, bonds, angles = _c(type, np.int32), _c(bonds, np.int32), _c(angles, np.int32)
+    nb = 0 if bonds is None else bonds.shape[0]
+    na = 0 if angles is None else angles.shape[0]
+    F = np.zeros((n, 3))
+    Fd = np.zeros((n, 3)) if dpd_rc > 0 else None
+    obs = np.zeros(NOBS)
+    fscale = np.zeros(n) if want_fscale else None
+    st = _load().orc_forces_ext(n, _ptr(pos), _ptr(vel), _ptr(type), ntypes, _ptr(pp), _ptr(box), nb, _ptr(bonds),
+                                fene_K, fene_R0, na, _ptr(angles), k_bend, float(shear_rate), float(dpd_rc),
+                                float(dpd_gamma), float(kT), float(dt), int(seed), int(step), _ptr(F), _ptr(Fd),
+                                _ptr(obs), _ptr(fscale))
+    if st != OK:
+        raise OracleError(st, "forces_ext")
+    out = {"e_pair": obs[0], "e_bond": obs[1], "e_angle": obs[2], "virial": obs[3],
+           "virial_tensor": obs[4:10].copy(), "virial_abs": obs[10]}
+    if want_fscale:
+        out["fscale"] = fscale
+    return F, Fd, out
+
+
+def neighbors_le(pos, box, rv, shear_rate=0.0, dt=1.0, step=0, cap=512):
+    """Verlet-list sets under the sheared minimum image at time step * dt
+    (brute force): list of sorted int arrays."""
+    pos = _c(pos, np.float64)
+    box = _c(box, np.float64)
+    n = pos.shape[0]
+    count = np.zeros(n, dtype=np.int32)
+    idx = np.zeros((n, cap), dtype=np.int32)
+    st = _load().orc_neighbors_le(n, _ptr(pos), _ptr(box), float(rv), float(shear_rate), float(dt), int(step), cap,
+                                  _ptr(count), _ptr(idx))
+    if st != OK:
+        raise OracleError(st, "neighbors_le")
+    return [np.sort(idx[k, :count[k]]) for k in range(n)]
+
+
+def run_ext(state, params, nsteps):
+    """``run`` with integrator DPD (2) and Lees-Edwards shear: params may hold
+    shear_rate and dpd_rc (DPD takes gamma and temperature as its friction and
+    kT).  Brute force over pairs."""
+    pos, vel, img = state["pos"], state["vel"], state["image"]
+    assert pos.dtype == np.float64 and pos.flags.c_contiguous
+    assert vel.dtype == np.float64 and vel.flags.c_contiguous
+    assert img.dtype == np.int32 and img.flags.c_contiguous
+    n = pos.shape[0]
+    type = _c(state.get("type"), np.int32)
+    box = _c(params["box"], np.float64)
+    pp = _c(params["pp"], np.float64)
+    mass = _c(params["mass_by_type"], np.float64)
+    bonds = _c(params.get("bonds"), np.int32)
+    angles = _c(params.get("angles"), np.int32)
+    nb = 0 if bonds is None else bonds.shape[0]
+    na = 0 if angles is None else angles.shape[0]
+    step = ctypes.c_int64(int(state["step"]))
+    vh = ctypes.c_int32(int(state["vel_half"]))
+    hist = np.zeros((nsteps, NHIST))
+    st = _load().orc_run_ext(n, _ptr(pos), _ptr(vel), _ptr(img), _ptr(type), _ptr(mass),
+                             int(params.get("ntypes", 1)), _ptr(pp), _ptr(box), nb, _ptr(bonds),
+                             float(params.get("fene_K", 30.0)), float(params.get("fene_R0", 1.5)), na,
+                             _ptr(angles), float(params.get("k_bend", 0.0)), float(params["dt"]),
+                             int(params["integrator"]), float(params.get("temperature", 0.0)),
+                             float(params.get("gamma", 0.0)), int(params.get("seed", 0)),
+                             float(params.get("shear_rate", 0.0)), float(params.get("dpd_rc", 0.0)),
+                             ctypes.byref(step), ctypes.byref(vh), nsteps, _ptr(hist))
+    state["step"] = step.value
+    state["vel_half"] = vh.value
+    if st != OK:
+        raise OracleError(st, "run_ext")
     return hist

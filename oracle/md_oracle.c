@@ -598,6 +598,306 @@ int orc_run(int64_t n, double* pos, double* vel, int32_t* image, const int32_t* 
     return status;
 }
 
+/* ------------------------------------------------------------------ */
+/* Lees-Edwards sheared boundaries and the DPD thermostat               */
+/* (section "New Features": Lees-Edwards boundary conditions; section   */
+/* "Functionality": dissipative particle dynamics).  The paper gives no */
+/* formulas; these are the textbook definitions (Lees & Edwards 1972;   */
+/* Espanol & Warren 1995; Groot & Warren 1997).                          */
+/*                                                                      */
+/* Shear: flow along x, gradient along y.  The periodic image one box   */
+/* above (y + Ly) is displaced by +delta(t) in x and moves with          */
+/* +gammadot Ly in x, delta(t) = gammadot Ly t mod Lx, t = step dt.      */
+/* Minimum image of d = r_j - r_i (fixed operation order, shared with   */
+/* the GPU): dy by compare-and-shift with s = +1 when dy > Ly/2 (j's     */
+/* nearest image lies one box below), -1 when dy < -Ly/2; dx = the x    */
+/* minimum image of x_j - x_i, then if s != 0 the x minimum image of     */
+/* dx - s delta_w, delta_w = delta folded into (-Lx/2, Lx/2]; dz as      */
+/* usual.  The image's velocity is v_j - s gammadot Ly e_x.             */
+/*                                                                      */
+/* DPD, per pair with r = |r_i - r_j| < rc_d, e = (r_i - r_j)/r,        */
+/* v_ij = v_i - v_j (image velocity), w = 1 - r/rc_d:                    */
+/*   F_i^D = -gamma w^2 (e . v_ij) e,  F_i^R = sigma w theta_ij e/sqrt(dt),*/
+/*   sigma^2 = 2 gamma kT, theta_ij = theta_ji ~ N(0,1): Philox4x64-10  */
+/*   keyed (seed, 6), counter (step, min tag, max tag, 0), Box-Muller on */
+/*   the first two uniforms.                                             */
+/* The dissipative force takes the half-step velocity v' (the velocity  */
+/* the Langevin friction also takes): Groot-Warren's modified velocity  */
+/* Verlet with lambda = 1/2.                                             */
+/* ------------------------------------------------------------------ */
+typedef struct { int on; double delta, delta_w, vjump; } orc_le;
+
+static orc_le le_at(const double box[3], double shear_rate, int64_t step, double dt) {
+    orc_le le = {shear_rate != 0.0, 0.0, 0.0, shear_rate * box[1]};
+    if (le.on) {
+        double d = fmod(shear_rate * box[1] * ((double)step * dt), box[0]);
+        if (d < 0.0) d += box[0];
+        le.delta = d;
+        le.delta_w = d > 0.5 * box[0] ? d - box[0] : d;
+    }
+    return le;
+}
+
+static void le_diff(const orc_le* le, const double L[3], const double H[3], const double* ri, const double* rj,
+                    double d[3], int* s) {
+    double dy = rj[1] - ri[1];
+    int sy = 0;
+    if (dy > H[1]) { dy -= L[1]; sy = 1; }
+    else if (dy < -H[1]) { dy += L[1]; sy = -1; }
+    double dx = min_image(rj[0] - ri[0], L[0], H[0]);
+    if (le->on && sy != 0) dx = min_image(dx - sy * le->delta_w, L[0], H[0]);
+    d[0] = dx;
+    d[1] = dy;
+    d[2] = min_image(rj[2] - ri[2], L[2], H[2]);
+    *s = le->on ? sy : 0;
+}
+
+/* theta_ij for the unordered pair {ti, tj} at this step */
+double orc_dpd_theta(uint64_t seed, uint64_t step, uint64_t ti, uint64_t tj) {
+    uint64_t ctr[4] = {step, ti < tj ? ti : tj, ti < tj ? tj : ti, 0};
+    uint64_t key[2] = {seed, 6};
+    uint64_t r[4];
+    orc_philox4x64_10(ctr, key, r);
+    const double two_pi = 6.283185307179586;
+    return sqrt(-2.0 * log(u01_open(r[0]))) * cos(two_pi * u01_open(r[1]));
+}
+
+typedef struct {
+    double shear_rate, dpd_rc, dpd_gamma, kT, dt;
+    uint64_t seed;
+    int64_t step;
+} orc_ext;
+
+/* Conservative pair forces (the LJ table) under the sheared minimum image,
+ * by brute force over all pairs, and (dpd_rc > 0) the DPD pair forces at
+ * velocities vel into Fd.  Each unordered pair once. */
+static void pair_forces_ext(const orc_sys* s, const orc_ext* x, const double* pos, const double* vel, double* F,
+                            double* Fd, double* obs, double* fscale) {
+    const double L[3] = {s->box[0], s->box[1], s->box[2]};
+    const double H[3] = {0.5 * L[0], 0.5 * L[1], 0.5 * L[2]};
+    const orc_le le = le_at(s->box, x->shear_rate, x->step, x->dt);
+    const double sigma = sqrt(2.0 * x->dpd_gamma * x->kT), isdt = 1.0 / sqrt(x->dt);
+    const double rcd2 = x->dpd_rc * x->dpd_rc;
+    for (int64_t i = 0; i < s->n; ++i) {
+        for (int64_t j = i + 1; j < s->n; ++j) {
+            double d[3];
+            int sy;
+            le_diff(&le, L, H, pos + 3 * i, pos + 3 * j, d, &sy);
+            const double r2 = (d[0] * d[0] + d[1] * d[1]) + d[2] * d[2];
+            orc_pair p = pair_of(s, type_of(s, i), type_of(s, j));
+            if (r2 < p.rc * p.rc) {
+                double u, fr;
+                lj_eval(&p, r2, &u, &fr);
+                double rij[3] = {-d[0], -d[1], -d[2]};
+                double f[3] = {fr * rij[0], fr * rij[1], fr * rij[2]};
+                for (int k = 0; k < 3; ++k) { F[3 * i + k] += f[k]; F[3 * j + k] -= f[k]; }
+                obs[0] += u;
+                obs[3] += fr * r2;
+                obs[10] += fabs(fr * r2);
+                add_tensor(obs, 1.0, rij, f);
+                if (fscale) {
+                    double fm = fabs(fr) * sqrt(r2);
+                    fscale[i] += fm; fscale[j] += fm;
+                }
+            }
+            if (Fd && r2 < rcd2) {
+                const double r = sqrt(r2);
+                const double w = 1.0 - r / x->dpd_rc;
+                const double e[3] = {-d[0] / r, -d[1] / r, -d[2] / r};          /* (r_i - r_j) / r */
+                double vij[3];
+                for (int k = 0; k < 3; ++k) vij[k] = vel[3 * i + k] - vel[3 * j + k];
+                vij[0] += sy * le.vjump;                                          /* v_i - (v_j - s vjump e_x) */
+                const double ev = (e[0] * vij[0] + e[1] * vij[1]) + e[2] * vij[2];
+                const double th = orc_dpd_theta(x->seed, (uint64_t)x->step, (uint64_t)i, (uint64_t)j);
+                const double a = -x->dpd_gamma * w * w * ev + sigma * w * th * isdt;
+                for (int k = 0; k < 3; ++k) { Fd[3 * i + k] += a * e[k]; Fd[3 * j + k] -= a * e[k]; }
+            }
+        }
+    }
+}
+
+/* Bonded forces under the sheared minimum image (the same terms as
+ * bonded_forces). */
+static int bonded_forces_ext(const orc_sys* s, const orc_ext* x, const double* pos, double* F, double* obs,
+                             double* fscale) {
+    const double L[3] = {s->box[0], s->box[1], s->box[2]};
+    const double H[3] = {0.5 * L[0], 0.5 * L[1], 0.5 * L[2]};
+    const orc_le le = le_at(s->box, x->shear_rate, x->step, x->dt);
+    int status = ORC_OK;
+    for (int64_t b = 0; b < s->nbonds; ++b) {
+        int64_t i = s->bonds[2 * b], j = s->bonds[2 * b + 1];
+        double d[3];
+        int sy;
+        le_diff(&le, L, H, pos + 3 * i, pos + 3 * j, d, &sy);
+        double rij[3] = {-d[0], -d[1], -d[2]};
+        double r2 = (rij[0] * rij[0] + rij[1] * rij[1]) + rij[2] * rij[2];
+        double u, fr;
+        if (fene_eval(s->fene_K, s->fene_R0, r2, &u, &fr) != ORC_OK) { status = ORC_ERR_BOND_BROKEN; continue; }
+        double f[3] = {fr * rij[0], fr * rij[1], fr * rij[2]};
+        for (int k = 0; k < 3; ++k) { F[3 * i + k] += f[k]; F[3 * j + k] -= f[k]; }
+        obs[1] += u;
+        obs[3] += fr * r2;
+        obs[10] += fabs(fr * r2);
+        add_tensor(obs, 1.0, rij, f);
+        if (fscale) {
+            double fm = fabs(fr) * sqrt(r2);
+            fscale[i] += fm; fscale[j] += fm;
+        }
+    }
+    for (int64_t a = 0; a < s->nangles; ++a) {
+        int64_t ia = s->angles[3 * a], ib = s->angles[3 * a + 1], ic = s->angles[3 * a + 2];
+        double b1[3], b2[3];
+        int sy;
+        le_diff(&le, L, H, pos + 3 * ia, pos + 3 * ib, b1, &sy);
+        le_diff(&le, L, H, pos + 3 * ib, pos + 3 * ic, b2, &sy);
+        double u, Fa[3], Fb[3], Fc[3];
+        bend_eval(s->k_bend, b1, b2, &u, Fa, Fb, Fc);
+        for (int k = 0; k < 3; ++k) { F[3 * ia + k] += Fa[k]; F[3 * ib + k] += Fb[k]; F[3 * ic + k] += Fc[k]; }
+        obs[2] += u;
+        double rab[3] = {-b1[0], -b1[1], -b1[2]};
+        const double wa = rab[0] * Fa[0] + rab[1] * Fa[1] + rab[2] * Fa[2];
+        const double wc = b2[0] * Fc[0] + b2[1] * Fc[1] + b2[2] * Fc[2];
+        obs[3] += wa;
+        obs[3] += wc;
+        obs[10] += fabs(wa) + fabs(wc);
+        add_tensor(obs, 1.0, rab, Fa);
+        add_tensor(obs, 1.0, b2, Fc);
+        if (fscale) {
+            fscale[ia] += sqrt(Fa[0] * Fa[0] + Fa[1] * Fa[1] + Fa[2] * Fa[2]);
+            fscale[ib] += sqrt(Fb[0] * Fb[0] + Fb[1] * Fb[1] + Fb[2] * Fb[2]);
+            fscale[ic] += sqrt(Fc[0] * Fc[0] + Fc[1] * Fc[1] + Fc[2] * Fc[2]);
+        }
+    }
+    return status;
+}
+
+/* Conservative forces F (and, with dpd_rc > 0 and Fd non-NULL, the DPD
+ * thermostat forces Fd at velocities vel) under the sheared boundaries at
+ * time step * dt.  Brute force over pairs. */
+int orc_forces_ext(int64_t n, const double* pos, const double* vel, const int32_t* type, int32_t ntypes,
+                   const double* pp, const double* box, int64_t nbonds, const int32_t* bonds, double fene_K,
+                   double fene_R0, int64_t nangles, const int32_t* angles, double k_bend, double shear_rate,
+                   double dpd_rc, double dpd_gamma, double kT, double dt, uint64_t seed, int64_t step, double* F,
+                   double* Fd, double* obs, double* fscale) {
+    if (n < 0 || ntypes < 1 || !pos || !pp || !box || !F || !obs || dt <= 0.0) return ORC_ERR_ARG;
+    if (Fd && dpd_rc > 0.0 && !vel) return ORC_ERR_ARG;
+    orc_sys s = {n, type, ntypes, pp, {box[0], box[1], box[2]}, nbonds, bonds, fene_K, fene_R0,
+                 nangles, angles, k_bend};
+    orc_ext x = {shear_rate, dpd_rc, dpd_gamma, kT, dt, seed, step};
+    memset(F, 0, sizeof(double) * 3 * n);
+    if (Fd) memset(Fd, 0, sizeof(double) * 3 * n);
+    memset(obs, 0, sizeof(double) * ORC_NOBS);
+    if (fscale) memset(fscale, 0, sizeof(double) * n);
+    pair_forces_ext(&s, &x, pos, vel, F, (dpd_rc > 0.0) ? Fd : NULL, obs, fscale);
+    int st = bonded_forces_ext(&s, &x, pos, F, obs, fscale);
+    for (int64_t i = 0; i < 3 * n; ++i)
+        if (!isfinite(F[i])) return ORC_ERR_NONFINITE;
+    return st;
+}
+
+/* Verlet-list sets under the sheared minimum image at time step * dt, by
+ * brute force (rows ascending). */
+int orc_neighbors_le(int64_t n, const double* pos, const double* box, double rv, double shear_rate, double dt,
+                     int64_t step, int32_t cap, int32_t* count, int32_t* idx) {
+    const double L[3] = {box[0], box[1], box[2]};
+    const double H[3] = {0.5 * L[0], 0.5 * L[1], 0.5 * L[2]};
+    const orc_le le = le_at(box, shear_rate, step, dt);
+    const double rv2 = rv * rv;
+    int overflow = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        int32_t c = 0;
+        for (int64_t j = 0; j < n; ++j) {
+            if (j == i) continue;
+            double d[3];
+            int sy;
+            le_diff(&le, L, H, pos + 3 * i, pos + 3 * j, d, &sy);
+            double r2 = (d[0] * d[0] + d[1] * d[1]) + d[2] * d[2];
+            if (r2 < rv2) {
+                if (c < cap) idx[i * (int64_t)cap + c] = (int32_t)j;
+                else overflow = 1;
+                ++c;
+            }
+        }
+        count[i] = c;
+    }
+    return overflow ? ORC_ERR_NL_OVERFLOW : ORC_OK;
+}
+
+/* Velocity Verlet as orc_run, extended: integrator 2 = DPD (the pair
+ * thermostat above instead of the Langevin friction and noise), and
+ * shear_rate != 0 = Lees-Edwards boundaries.  A particle leaving through
+ * y = Ly re-enters at y - Ly with x - delta(t_{n+1}) and v_x - gammadot Ly
+ * (through y = 0: the opposite shifts), before the x fold into [0, Lx).
+ * History columns as orc_run. */
+int orc_run_ext(int64_t n, double* pos, double* vel, int32_t* image, const int32_t* type,
+                const double* mass_by_type, int32_t ntypes, const double* pp, const double* box,
+                int64_t nbonds, const int32_t* bonds, double fene_K, double fene_R0, int64_t nangles,
+                const int32_t* angles, double k_bend, double dt, int32_t integrator, double temperature,
+                double gamma, uint64_t seed, double shear_rate, double dpd_rc, int64_t* step, int32_t* vel_half,
+                int64_t nsteps, double* obs_hist) {
+    if (n <= 0 || !pos || !vel || !box || !mass_by_type || dt <= 0.0) return ORC_ERR_ARG;
+    if (integrator < 0 || integrator > 2) return ORC_ERR_ARG;
+    double* F = (double*)malloc(sizeof(double) * 3 * n);
+    double* Fd = (double*)malloc(sizeof(double) * 3 * n);
+    double obs[ORC_NOBS];
+    const double L[3] = {box[0], box[1], box[2]};
+    int status = ORC_OK;
+    for (int64_t s = 0; s < nsteps; ++s) {
+        const int dpd = integrator == 2;
+        int st = orc_forces_ext(n, pos, vel, type, ntypes, pp, box, nbonds, bonds, fene_K, fene_R0, nangles, angles,
+                                k_bend, shear_rate, dpd ? dpd_rc : 0.0, gamma, temperature, dt, seed, *step, F,
+                                dpd ? Fd : NULL, obs, NULL);
+        if (st != ORC_OK) { status = st; break; }
+        const orc_le le_next = le_at(box, shear_rate, *step + 1, dt);
+        double ekin = 0.0;
+        for (int64_t i = 0; i < n; ++i) {
+            double m = mass_by_type[type ? type[i] : 0];
+            double xi[3] = {0, 0, 0};
+            double amp = 0.0;
+            if (integrator == 1) {
+                orc_gauss3(seed, 0, (uint64_t)*step, (uint64_t)i, xi);
+                amp = sqrt(2.0 * gamma * m * temperature / dt);
+            }
+            double hdt_m = 0.5 * dt / m;
+            double vv2 = 0.0, xn[3], vh[3];
+            for (int d = 0; d < 3; ++d) {
+                double vp = vel[3 * i + d];
+                double ft = F[3 * i + d];
+                if (integrator == 1) ft = (ft - gamma * m * vp) + amp * xi[d];
+                if (dpd) ft = ft + Fd[3 * i + d];
+                double von = *vel_half ? vp + hdt_m * ft : vp;
+                vh[d] = von + hdt_m * ft;
+                vv2 += von * von;
+                xn[d] = pos[3 * i + d] + dt * vh[d];
+            }
+            int img[3] = {0, 0, 0};
+            if (image) for (int d = 0; d < 3; ++d) img[d] = image[3 * i + d];
+            if (le_next.on) {
+                if (xn[1] >= L[1]) { xn[1] -= L[1]; xn[0] -= le_next.delta; vh[0] -= le_next.vjump; img[1] += 1; }
+                else if (xn[1] < 0.0) { xn[1] += L[1]; xn[0] += le_next.delta; vh[0] += le_next.vjump; img[1] -= 1; }
+            }
+            for (int d = 0; d < 3; ++d) {
+                if (xn[d] < 0.0) { xn[d] += L[d]; img[d] -= 1; }
+                if (xn[d] >= L[d]) { xn[d] -= L[d]; img[d] += 1; }
+                pos[3 * i + d] = xn[d];
+                vel[3 * i + d] = vh[d];
+                if (image) image[3 * i + d] = img[d];
+            }
+            ekin += 0.5 * m * vv2;
+        }
+        if (obs_hist) {
+            double* h = obs_hist + s * ORC_NHIST;
+            h[0] = obs[0]; h[1] = obs[1]; h[2] = obs[2]; h[3] = ekin; h[4] = obs[3];
+            for (int k = 0; k < 6; ++k) h[5 + k] = obs[4 + k];
+        }
+        *step += 1;
+        *vel_half = 1;
+    }
+    free(F);
+    free(Fd);
+    return status;
+}
+
 int orc_nthreads_default(void) {
 #ifdef _OPENMP
     return omp_get_max_threads();

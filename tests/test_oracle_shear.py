@@ -1,0 +1,199 @@
+"""Pins of the oracle's Lees-Edwards boundaries and DPD thermostat.
+
+The paper names both (section "New Features": Lees-Edwards boundary
+conditions; section "Functionality": dissipative particle dynamics) and
+prints no formula; the oracle follows the textbook definitions.  Pinned here
+by what does not retype them:
+
+* the pair noise theta_ij against numpy's own Philox4x64-10 and the
+  Box-Muller transform, and its symmetry in (i, j);
+* neighbour sets under shear against an explicit enumeration of the sheared
+  periodic images (the image n_y boxes above is displaced by n_y delta in x);
+* closed forms: a pair across the sheared boundary feels the LJ force of the
+  image distance; the dissipative force of a pair separated along the
+  gradient vanishes in the linear flow u = gammadot y e_x, also across the
+  boundary, where only the image's velocity makes it vanish;
+* shear_rate 0 reduces to the plain oracle; momentum conservation of the DPD
+  forces; Galilean invariance of the dissipative force;
+* dynamics: a DPD fluid at rest equilibrates at kT, and under Lees-Edwards
+  shear it carries the imposed linear profile <v_x>(y) = gammadot (y - y0).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2608_14911_amd import inputs
+
+
+def numpy_theta(seed, step, ti, tj):
+    c = (step | (min(ti, tj) << 64) | (max(ti, tj) << 128)) - 1
+    words = np.array([(c >> (64 * i)) & ((1 << 64) - 1) for i in range(4)], dtype=np.uint64)
+    r = np.random.Philox(key=np.array([seed, 6], dtype=np.uint64), counter=words).random_raw(4)
+    u0 = ((int(r[0]) >> 11) + 0.5) * 2.0 ** -53
+    u1 = ((int(r[1]) >> 11) + 0.5) * 2.0 ** -53
+    return math.sqrt(-2.0 * math.log(u0)) * math.cos(2.0 * math.pi * u1)
+
+
+@pytest.mark.parametrize("seed,step,ti,tj", [(1, 1, 0, 1), (77, 123456, 5, 3), (2**40 + 3, 9, 1000, 999999)])
+def test_dpd_theta_is_numpy_philox_box_muller_and_symmetric(seed, step, ti, tj):
+    t = oracle.dpd_theta(seed, step, ti, tj)
+    assert t == pytest.approx(numpy_theta(seed, step, ti, tj), rel=1e-14, abs=1e-14)
+    assert t == oracle.dpd_theta(seed, step, tj, ti)
+
+
+def image_enumeration_sets(pos, box, rv, delta):
+    """{j : min over sheared images of |r_j' - r_i| < rv}, images of j at
+    (x_j + nx Lx + ny delta, y_j + ny Ly, z_j + nz Lz)."""
+    L = np.asarray(box)
+    out = []
+    shifts = [(nx, ny, nz) for nx in (-2, -1, 0, 1, 2) for ny in (-1, 0, 1) for nz in (-1, 0, 1)]
+    for i in range(len(pos)):
+        best = np.full(len(pos), np.inf)
+        for nx, ny, nz in shifts:
+            img = pos + np.array([nx * L[0] + ny * delta, ny * L[1], nz * L[2]])
+            best = np.minimum(best, ((img - pos[i]) ** 2).sum(1))
+        best[i] = np.inf
+        out.append(np.nonzero(best < rv * rv)[0])
+    return out
+
+
+@pytest.mark.parametrize("step", [0, 7, 40, 133])
+def test_sheared_neighbor_sets_equal_image_enumeration(step):
+    L = np.array([7.3, 6.1, 6.7])
+    n, rv, rate, dt = 300, 1.6, 0.37, 0.05
+    pos = inputs.random_positions(n, L, seed=11 + step)
+    # keep every pair clear of the list radius by 1e-9 (a tie would be decided by rounding)
+    delta = math.fmod(rate * L[1] * step * dt, L[0])
+    got = oracle.neighbors_le(pos, L, rv, shear_rate=rate, dt=dt, step=step)
+    ref = image_enumeration_sets(pos, L, rv, delta)
+    same = sum(np.array_equal(a, b) for a, b in zip(got, ref))
+    assert same == n
+    # symmetric, and a shear offset really changes the sets of boundary particles
+    for i in range(n):
+        for j in got[i]:
+            assert i in got[j]
+    if step:
+        plain = oracle.neighbors_le(pos, L, rv)
+        assert any(not np.array_equal(a, b) for a, b in zip(got, plain))
+
+
+def test_pair_across_the_sheared_boundary_closed_form():
+    L = np.array([8.0, 7.0, 9.0])
+    rate, dt, step = 0.3, 0.01, 500
+    delta = math.fmod(rate * L[1] * step * dt, L[0])          # 10.5 mod 8 = 2.5
+    # j sits near the top, displaced by delta: its image below is 1.05 under i
+    pos = np.array([[1.0, 0.5, 4.0], [1.0 + delta, L[1] - 0.55, 4.0]])
+    pp = oracle.pair_params(rc=2.5)
+    F, _, o = oracle.forces_ext(pos, L, pp, shear_rate=rate, dt=dt, step=step)
+    u, f = oracle.pair_eval(pp, 1.05)
+    assert o["e_pair"] == pytest.approx(u, rel=1e-12)
+    np.testing.assert_allclose(F[0], [0.0, f, 0.0], rtol=1e-12, atol=1e-12)   # pushed up, away from the image
+    np.testing.assert_allclose(F[1], [0.0, -f, 0.0], rtol=1e-12, atol=1e-12)
+    # without the shear offset the same pair is 2.5 apart in x: no force at rc
+    F0, _, o0 = oracle.forces_ext(pos, L, pp)
+    assert o0["e_pair"] == 0.0 and np.abs(F0).max() == 0.0
+
+
+def test_shear_rate_zero_is_the_plain_oracle_and_momentum_conserved():
+    w = inputs.random_walk_chains(6, 12, 0.5, seed=3)
+    pp = oracle.pair_params(rc=2.5, caprad=0.8)
+    kw = dict(bonds=w["bonds"], angles=w["angles"], k_bend=1.5)
+    F, _, o = oracle.forces_ext(w["pos"], w["box"], pp, **kw)
+    Fp, op = oracle.forces(w["pos"], w["box"], pp, use_cells=False, **kw)
+    np.testing.assert_allclose(F, Fp, rtol=1e-12, atol=1e-10)
+    for k in ("e_pair", "e_bond", "e_angle", "virial", "virial_abs"):
+        assert o[k] == pytest.approx(op[k], rel=1e-12), k
+    vel = np.random.default_rng(2).normal(size=w["pos"].shape)
+    F, Fd, _ = oracle.forces_ext(w["pos"], w["box"], pp, vel=vel, shear_rate=0.4, dpd_rc=1.0, dpd_gamma=4.5,
+                                 dt=0.01, seed=5, step=3, **kw)
+    scale = np.abs(F).sum() + np.abs(Fd).sum()
+    assert np.abs(F.sum(0)).max() < 1e-12 * scale
+    assert np.abs(Fd.sum(0)).max() < 1e-12 * np.abs(Fd).sum()
+
+
+def test_dissipative_force_galilean_invariant_and_zero_in_linear_flow():
+    L = np.array([5.0, 5.0, 5.0])
+    pos = inputs.random_positions(375, L, seed=4)
+    vel = np.random.default_rng(5).normal(size=pos.shape)
+    pp = oracle.pair_params(eps=0.0, rc=1.0)
+    args = dict(dpd_rc=1.0, dpd_gamma=4.5, kT=0.0, dt=0.01, seed=1, step=2)   # kT = 0: dissipative part only
+    _, Fd, _ = oracle.forces_ext(pos, L, pp, vel=vel, **args)
+    _, Fd2, _ = oracle.forces_ext(pos, L, pp, vel=vel + np.array([0.7, -1.3, 2.1]), **args)
+    np.testing.assert_allclose(Fd2, Fd, rtol=1e-9, atol=1e-9 * np.abs(Fd).max())
+    assert np.abs(Fd).max() > 0.1
+    # a pair separated along y in the flow u = gammadot y e_x: no dissipation,
+    # inside the box and across the sheared boundary
+    rate, step, dt = 0.8, 250, 0.01
+    delta = math.fmod(rate * L[1] * step * dt, L[0])
+    for yi, yj, xj in ((2.0, 2.6, 1.5), (0.2, L[1] - 0.3, 1.5 + delta)):
+        p = np.array([[1.5, yi, 2.0], [xj, yj, 2.0]])
+        v = np.array([[rate * yi, 0.0, 0.0], [rate * yj, 0.0, 0.0]])
+        _, Fd, _ = oracle.forces_ext(p, L, pp, vel=v, shear_rate=rate, dpd_rc=1.0, dpd_gamma=4.5, kT=0.0, dt=dt,
+                                     step=step)
+        assert np.abs(Fd).max() < 1e-12, (yi, yj)
+    # a pair straddling the sheared boundary, moving with the flow, feels the
+    # dissipative force of the same pair (same offset, same flow velocities)
+    # in the bulk: the image of j one box above sits at x_j + delta and moves
+    # with v_j + gammadot Ly
+    bulk = np.array([[1.5, 2.0, 2.0], [1.8, 2.5, 2.0]])
+    vb = np.array([[rate * 2.0, 1.1, 0.0], [rate * 2.5, -1.2, 0.3]])
+    edge = np.array([[1.5, L[1] - 0.2, 2.0], [(1.8 - delta) % L[0], 0.3, 2.0]])
+    ve = np.array([[rate * (L[1] - 0.2), 1.1, 0.0], [rate * 0.3, -1.2, 0.3]])
+    kw = dict(shear_rate=rate, dpd_rc=1.0, dpd_gamma=4.5, kT=0.0, dt=dt, step=step)
+    _, Fb, _ = oracle.forces_ext(bulk, L, pp, vel=vb, **kw)
+    _, Fe, _ = oracle.forces_ext(edge, L, pp, vel=ve, **kw)
+    assert np.abs(Fb).max() > 0.1
+    np.testing.assert_allclose(Fe, Fb, rtol=1e-9, atol=1e-12)
+    # the same straddling pair without the shear (plain periodic image) differs
+    _, Fp, _ = oracle.forces_ext(edge, L, pp, vel=ve, dpd_rc=1.0, dpd_gamma=4.5, kT=0.0, dt=dt, step=step)
+    assert np.abs(Fp - Fb).max() > 0.1
+
+
+def dpd_fluid(L, rho, seed, rate=0.0, kT=1.0):
+    n = int(round(rho * L ** 3))
+    box = np.array([L, L, L])
+    pos = inputs.random_positions(n, box, seed=seed)
+    vel = inputs.maxwell_boltzmann(n, kT, seed=seed)
+    vel[:, 0] += rate * (pos[:, 1] - 0.5 * L)
+    st = {"pos": pos, "vel": vel, "image": np.zeros((n, 3), dtype=np.int32), "step": 0, "vel_half": 0, "type": None}
+    par = {"box": box, "pp": oracle.pair_params(eps=0.0, rc=1.0), "ntypes": 1, "mass_by_type": np.array([1.0]),
+           "dt": 0.01, "integrator": oracle.DPD, "temperature": kT, "gamma": 4.5, "seed": seed, "dpd_rc": 1.0,
+           "shear_rate": rate}
+    return st, par
+
+
+def test_dpd_fluid_equilibrates_at_kT():
+    st, par = dpd_fluid(5.0, 3.0, seed=21)
+    n = st["pos"].shape[0]
+    oracle.run_ext(st, par, 200)
+    h = oracle.run_ext(st, par, 1500)
+    T = 2.0 * h[:, 3] / (3.0 * n)
+    blk = T.reshape(10, -1).mean(1)
+    m, se = blk.mean(), blk.std(ddof=1) / math.sqrt(10)
+    assert abs(m - 1.0) <= 3.0 * se + 0.01, (m, se)
+    # momentum stays zero (pairwise forces, no boundary shear)
+    assert np.abs(st["vel"].sum(0)).max() < 1e-9 * n
+
+
+def test_lees_edwards_dpd_carries_the_linear_shear_profile():
+    rate, L = 0.4, 6.0
+    st, par = dpd_fluid(L, 3.0, seed=22, rate=rate)
+    oracle.run_ext(st, par, 500)
+    nb = 6
+    prof = np.zeros(nb)
+    cnt = np.zeros(nb)
+    for _ in range(30):
+        oracle.run_ext(st, par, 50)
+        b = np.minimum((st["pos"][:, 1] / L * nb).astype(int), nb - 1)
+        np.add.at(prof, b, st["vel"][:, 0])
+        np.add.at(cnt, b, 1)
+    prof /= cnt
+    yc = (np.arange(nb) + 0.5) * L / nb
+    slope = np.polyfit(yc, prof, 1)[0]
+    assert slope == pytest.approx(rate, rel=0.08), (slope, prof)
+    # the profile is linear: residuals small against the velocity change across the box
+    resid = prof - np.polyval(np.polyfit(yc, prof, 1), yc)
+    assert np.abs(resid).max() < 0.1 * rate * L
+    assert np.all(np.abs(st["image"][:, 1]) >= 0)
