@@ -1,23 +1,31 @@
 """Throughput of the short-range MD step on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload lj1m|kg2m|kg1k]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload default|lj1m|kg2m|batch|sur1m|kg1k]
 
-Default workload: LJ fluid of 1,048,576 particles (FCC 64^3, density 0.8442,
-uniform jitter 0.05, T = 0.72), rc = 2.5 shifted, skin 0.3, NVE dt = 0.005,
-FP32 pair math, FP64 positions / velocities / reductions.  A "step" is one
-pass of the whole hot path: gated cell sort + Verlet-list rebuild, fused
-force + velocity-Verlet kernel, FP64 energy/virial reduction.  Inputs are
-resident in HBM before the timed region.
+The headline workload is the LJ fluid of 1,048,576 particles (FCC 64^3,
+density 0.8442, uniform jitter 0.05, T = 0.72), rc = 2.5 shifted, skin 0.3,
+NVE dt = 0.005, FP32 pair math, FP64 positions / velocities / reductions.
+A "step" is one pass of the whole hot path: gated cell sort + Verlet-list
+rebuild, fused force + velocity-Verlet kernel, FP64 energy/virial reduction.
+Inputs are resident in HBM before a timed region starts.
 
-Prints one JSON line with the metric, a "roofline" object for the dominant
-(fused force+integrate) kernel, timed with HIP events on the library's
-stream over the timed region, and a "cpu_baseline" object: the FP64 oracle
-timed on this host on a bounded sample of the same workload.
+Each workload is timed twice over K steps after W warm-up steps:
+  1. the product path: md_step replaying its two-step hipGraph, no events ->
+     ``value`` and ``ms_per_step``;
+  2. an evented pass: the same K steps launched kernel by kernel with HIP
+     events on the library's stream around each stage -> the per-stage
+     breakdown and the ``roofline`` of the fused force + integrate kernel.
+The default run prints one JSON line for the LJ fluid with the other
+workloads (2M-bead melt, 256-replica batch, learned surrogate on a 1M-bead
+melt) as sub-records under "workloads", and a "cpu_baseline" object: the FP64
+oracle timed on this host on a bounded sample, with all threads and with one.
 """
 import argparse
+import hashlib
 import json
 import math
 import os
+import platform
 import sys
 import time
 
@@ -35,33 +43,37 @@ HBM_PEAK_GBS = 8000.0
 #   surrogate 1M: 2 descriptor-list passes 2 x (4 + 43.4 x 4) = 355, a_i write
 #           + read 256, positions 48, force 12, bonded 16, integration 132 -> 819
 ALG_BYTES = {"lj1m": 327.0, "kg2m": 213.0, "kg1k": 213.0, "sur1m": 819.0}
-# HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE and
-# WRITE_SIZE passes (scaled by a 512 MiB copy: x2.0 and x1.0), valid only for
-# the kernel source they were taken on (SHA-256 prefix of md_kernels.hip).
-TRAFFIC = {"lj1m": {"bytes": 226635.5 * 2.0 * 1024 + 87480.0 * 1024, "source": "8c23e66d09ea82f3"},
-           "kg2m": {"bytes": 232674.2 * 2.0 * 1024 + 174642.0 * 1024, "source": "8c23e66d09ea82f3"}}
+# HBM bytes per launch of the fused kernel from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE passes (each scaled by what the counter reads for a 512 MiB
+# copy: x2.0 and x1.0), valid only for the sources the kernel is compiled
+# from (SHA-256 prefix over KERNEL_SOURCES); null once they change.
+KERNEL_SOURCES = ("md_kernels.hip", "md_device.h", "md_internal.h", "md_api.hip")
+TRAFFIC = {}
 
 
 def kernel_source_hash():
-    import hashlib
-    p = os.path.join(ROOT, "paper_2608_14911_amd", "csrc", "md_kernels.hip")
-    with open(p, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2608_14911_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="lj1m", choices=["lj1m", "kg2m", "kg1k", "batch", "sur1m"])
+    ap.add_argument("--workload", default="default",
+                    choices=["default", "lj1m", "kg2m", "kg1k", "batch", "sur1m"],
+                    help="default: the LJ fluid with kg2m, batch and sur1m as sub-records")
     ap.add_argument("--sur-precision", default="bf16", choices=["fp32", "bf16"],
                     help="sur1m: network precision of the surrogate")
-    ap.add_argument("--no-autotune", action="store_true",
-                    help="batch: keep the sampler's skin and the library's automatic cells and list build")
-    ap.add_argument("--no-events", action="store_true",
-                    help="time with a hipGraph replay and no per-kernel events")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--batch-start", default="lattice", choices=["lattice", "pushoff"],
+                    help="batch: melt replicas laid on a lattice (no push-off) or pushed-off random walks")
+    ap.add_argument("--autotune", default="cache", choices=["cache", "tune", "none"],
+                    help="batch: the autotuner's cached choice, a fresh tuning run, or the library defaults")
+    ap.add_argument("--cpu-seconds", type=float, default=8.0, help="CPU oracle budget per leg")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quiet", action="store_true")
     ap.add_argument("--cell-factor", type=int, default=0, help="cells per list radius (1 or 2; 0 = library default)")
@@ -79,13 +91,13 @@ def log(msg, quiet=False):
         print("[bench] " + msg, file=sys.stderr, flush=True)
 
 
+# ---------------------------------------------------------------- systems
 def make_system(name, quiet, cell_factor=0, flags=0):
     from paper_2608_14911_amd import inputs
-    from paper_2608_14911_amd.system import from_workload
+    from paper_2608_14911_amd.system import from_workload, push_off
     if name == "lj1m":
         w = inputs.workload_lj(ncell=64, seed=1001)
-        s = from_workload(w, precision="fp32", cell_factor=cell_factor, flags=flags)
-        return w, s
+        return w, from_workload(w, precision="fp32", cell_factor=cell_factor, flags=flags)
     if name == "kg2m":
         w = inputs.workload_kg(2000, 1000, seed=1002)
     elif name == "sur1m":
@@ -97,12 +109,7 @@ def make_system(name, quiet, cell_factor=0, flags=0):
     # parameters of the workload.  Raw random walks overlap, so the push-off
     # list needs a large capacity; the timed system is re-created from the
     # pushed-off state with the capacity sized from the density.
-    from paper_2608_14911_amd.system import push_off
-    w0 = dict(w)
-    w0["caprad"] = 1.0
-    w0["dt"] = 0.002
-    w0["gamma"] = 1.0
-    w0["vel"] = np.zeros_like(w["pos"])
+    w0 = dict(w, caprad=1.0, dt=0.002, gamma=1.0, vel=np.zeros_like(w["pos"]))
     s = from_workload(w0, precision="fp32", cell_factor=cell_factor, nl_capacity=256, flags=flags)
     t0 = time.time()
     push_off(s, w["rc"], log=lambda m: log(m, quiet))
@@ -110,21 +117,48 @@ def make_system(name, quiet, cell_factor=0, flags=0):
     s.step(200)
     st = s.get_state()
     s.close()
-    w1 = dict(w)
-    w1["pos"], w1["vel"] = st["pos"], st["vel"]
+    w1 = dict(w, pos=st["pos"], vel=st["vel"])
     extra = {"list_cutoff": 2.5, "surrogate": True} if name == "sur1m" else {}
     s = from_workload(w1, precision="fp32", cell_factor=cell_factor, flags=flags, **extra)
     s.set_state(st)
     s.step(1)
     if s.status() != 0:
         raise RuntimeError("KG system after push-off: status %d" % s.status())
-    log("push-off done in %.1f s" % (time.time() - t0), quiet)
+    log("%s: push-off done in %.1f s" % (name, time.time() - t0), quiet)
     return w1, s
 
 
-def cpu_baseline(w, name, budget_s, quiet):
-    """The FP64 oracle (linked cells, OpenMP) on this host, on a bounded
-    number of steps of the same workload; extrapolated to atom-steps/s."""
+def free_gpu():
+    import gc
+
+    import torch
+    gc.collect()
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+
+
+# ---------------------------------------------------------------- CPU baseline
+def cpu_info():
+    model = platform.processor() or ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count()
+    return {"cpu_model": model, "nproc": os.cpu_count(), "cpus_available": avail}
+
+
+def cpu_oracle_rate(w, budget_s, nthreads, quiet, max_steps=50):
+    """The FP64 oracle (linked cells, OpenMP over particles) advancing the
+    same workload for a bounded number of steps; returns (atom-steps/s,
+    steps, seconds, threads)."""
     import oracle
     n = w["pos"].shape[0]
     st = {"pos": w["pos"].copy(), "vel": w["vel"].copy(), "image": np.zeros((n, 3), dtype=np.int32),
@@ -134,24 +168,132 @@ def cpu_baseline(w, name, budget_s, quiet):
            "integrator": oracle.LANGEVIN if w["integrator"] == "langevin" else oracle.NVE,
            "temperature": w["temperature"], "gamma": w["gamma"], "seed": w["seed"],
            "bonds": w.get("bonds"), "angles": w.get("angles"), "k_bend": w.get("k_bend", 0.0)}
-    threads = oracle.nthreads_default()
-    t0 = time.time()
-    oracle.run(st, par, 1)          # untimed: first touch
+    threads = nthreads or oracle.nthreads_default()
+    oracle.run(st, par, 1, nthreads=threads)          # untimed: first touch
     t1 = time.time()
-    oracle.run(st, par, 1)
+    oracle.run(st, par, 1, nthreads=threads)
     one = time.time() - t1
-    k = max(1, min(50, int(budget_s / max(one, 1e-6))))
+    k = max(0, min(max_steps - 1, int(budget_s / max(one, 1e-6)) - 1))
     t2 = time.time()
-    oracle.run(st, par, k)
-    el = time.time() - t2
+    if k:
+        oracle.run(st, par, k, nthreads=threads)
+    secs = (time.time() - t2) + one
     steps = k + 1
-    secs = el + one
-    log("cpu oracle: %d steps in %.2f s on %d threads (setup %.1f s)" % (steps, secs, threads, t1 - t0), quiet)
-    return {"value": n * steps / secs, "unit": "atom-steps/s", "cores": threads, "kind": "oracle",
-            "sample": "%d steps of the same %d-particle workload (FP64 linked cells, OpenMP), "
-                      "after 1 untimed step" % (steps, n)}
+    log("cpu oracle: %d steps of %d particles in %.2f s on %d threads" % (steps, n, secs, threads), quiet)
+    return n * steps / secs, steps, secs, threads
 
 
+def cpu_baseline(w, budget_s, quiet):
+    n = w["pos"].shape[0]
+    v_all, s_all, t_all, th = cpu_oracle_rate(w, budget_s, 0, quiet)
+    v_one, s_one, t_one, _ = cpu_oracle_rate(w, budget_s, 1, quiet, max_steps=10)
+    rec = {"value": v_all, "unit": "atom-steps/s", "cores": th, "kind": "oracle",
+           "sample": "%d steps (%.1f s) of the same %d-particle workload with %d OpenMP threads, and %d steps "
+                     "(%.1f s) with 1 thread; FP64 linked cells, after 1 untimed step"
+                     % (s_all, t_all, n, th, s_one, t_one),
+           "value_1thread": v_one}
+    rec.update(cpu_info())
+    return rec
+
+
+# ---------------------------------------------------------------- single systems
+def time_system(s, steps, warmup, quiet):
+    """Graph-replayed timed region, then an evented pass of the same length."""
+    import torch
+    s.step(warmup)
+    o0 = s.observables()
+    s.history()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.step(steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    o1 = s.observables()
+    hist = s.history()
+    # evented pass: kernel-by-kernel launches, events around each stage
+    s.timing(True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    s.step(steps)
+    torch.cuda.synchronize()
+    el_ev = time.perf_counter() - t1
+    tm = s.timing()
+    s.timing(False)
+    o2 = s.observables()
+    return el, el_ev, tm, o0, o1, o2, hist
+
+
+def single_record(name, a, w, s):
+    from paper_2608_14911_amd import md as md_
+    n = s.n
+    el, el_ev, tm, o0, o1, o2, hist = time_system(s, a.steps, a.warmup, a.quiet)
+    plan = md_.md_plan_config(s.cfg)
+    k_ms = tm["ms_step_kernels"] / max(tm["n_step_kernels"], 1)
+    alg = ALG_BYTES[name] * n
+    ach = alg / (k_ms * 1e-3) / 1e9
+    tr = TRAFFIC.get(name)
+    traffic = tr["bytes"] if tr and tr["source"] == kernel_source_hash() else None
+    sur = name == "sur1m"
+    rec = {
+        "metric": "atom-steps/s (1M LJ, 2M KG melt); surrogate vs plain at stated force RMSE",
+        "value": n * a.steps / el, "unit": "atom-steps/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+        "ms_per_step": 1e3 * el / a.steps, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": w["name"] + (", learned surrogate pair force (%s network)" % a.sur_precision
+                                            if sur else ""),
+                   "n_particles": n, "rc": w["rc"], "skin": w["skin"], "dt": w["dt"],
+                   "integrator": w["integrator"],
+                   "precision": "FP32 pair/bonded math, FP64 positions, velocities and reductions",
+                   "parallelism": "single GPU", "cell_factor": plan["cell_factor"],
+                   "cells_per_side": plan["cells"][0], "list_build": plan["nl_build"],
+                   "list_capacity": plan["nl_capacity"]},
+        "timing": "value and ms_per_step: md_step replaying its two-step hipGraph (no events); roofline and "
+                  "breakdown: a second pass of the same steps launched kernel by kernel with HIP events",
+        "n_rebuilds": o1["n_rebuilds"] - o0["n_rebuilds"],
+        "energy_drift_per_particle": (o1["e_total"] - o0["e_total"]) / n,
+        "nl_max_count": o1["nl_max_count"],
+        "evented_pass": {"ms_per_step": 1e3 * el_ev / a.steps, "n_rebuilds": o2["n_rebuilds"] - o1["n_rebuilds"]},
+        "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": ach / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": ("surrogate force stage (k_sur_desc, k_sur_mlp, k_sur_force, k_step_ext)" if sur else
+                                "k_step_fast_bonded (fused pair + bonded forces, velocity Verlet, reductions)"
+                                if name in ("kg2m", "kg1k") else
+                                "k_step_fast (fused pair forces, velocity Verlet, reductions)"),
+                     "kernel_ms": k_ms, "alg_bytes_per_launch": alg,
+                     "alg_bytes_per_particle": ALG_BYTES[name]},
+        "kernel_breakdown_ms_per_step": {
+            "rebuild_stage": tm["ms_rebuild"] / max(tm["n_rebuild"], 1),
+            "step_kernel" if not sur else "force_stage_and_step": k_ms,
+            "finalize": tm["ms_finalize"] / max(tm["n_finalize"], 1)},
+    }
+    if name == "kg2m" or name == "kg1k":
+        rec["kernel_breakdown_note"] = ("pair and bonded forces and the integration are fused into one kernel "
+                                        "(step_kernel); binning and the list build make up the rebuild stage")
+    return rec
+
+
+def bench_single(name, a):
+    from paper_2608_14911_amd import md as md_
+    nl_flags = {"auto": 0, "tiles": md_.MD_CFG_NL_TILES, "per-particle": md_.MD_CFG_NL_PER_PARTICLE}[a.nl_build]
+    t0 = time.time()
+    w, s = make_system(name, a.quiet, a.cell_factor, nl_flags)
+    if name == "sur1m":
+        # the surrogate replaces the WCA pair force: the network trained by
+        # surrogate_experiment.py on a 100k-bead plain-method melt
+        wpath = os.path.join(ROOT, "paper_2608_14911_amd", "data", "surrogate_kg.npz")
+        wd = np.load(wpath)
+        s.sur_set(wd["theta_" + a.sur_precision], wd["g_mean"], wd["g_istd"], a.sur_precision)
+        s.set_pair_mode("surrogate")
+    log("%s: %d particles ready in %.1f s" % (name, s.n, time.time() - t0), a.quiet)
+    rec = single_record(name, a, w, s)
+    s.close()
+    del s
+    free_gpu()
+    log("%s: %.3g atom-steps/s, %.3f ms/step" % (name, rec["value"], rec["ms_per_step"]), a.quiet)
+    return w, rec
+
+
+# ---------------------------------------------------------------- batch
 def member_alg_bytes(m, n, skin):
     """Algorithmic bytes per atom-step of one member: half Verlet list
     (int32) at its density and list radius, FP64 x / v streams, FP32 force,
@@ -163,70 +305,76 @@ def member_alg_bytes(m, n, skin):
     return 4 + 4 * half + 24 + 12 + 132 + (16 if m.get("kind") == "kg" else 0)
 
 
+def lattice_replica(r):
+    """A melt replica's chains laid on a simple cubic lattice at its own
+    density and chain length (no overlapping beads, no push-off)."""
+    from paper_2608_14911_amd import inputs
+    lc = r["chain_len"]
+    w = inputs.lattice_melt(r["pos"].shape[0] // lc, lc, r["density"], jitter=0.05, seed=r["seed"])
+    out = dict(r)
+    out.update(pos=w["pos"], box=w["box"], bonds=w["bonds"], angles=w["angles"])
+    return out
+
+
 def bench_batch(a):
     import torch
     from paper_2608_14911_amd import autotune, inputs
-    from paper_2608_14911_amd.system import Batch, System, lj_pair, nl_build_flags, prepare_replica
+    from paper_2608_14911_amd.system import Batch, prepare_replica
     t0 = time.time()
     reps = inputs.batch_replicas(256, seed=1003)
-    out = []
-    for k, r in enumerate(reps):
-        out.append(prepare_replica(r))
-        if k % 32 == 31:
-            log("replicas prepared: %d / %d (%.0f s)" % (k + 1, len(reps), time.time() - t0), a.quiet)
-    reps = out
-    if a.no_autotune:
-        choice = {"lj": (0.3, 0, "auto"), "kg": (0.4, 0, "auto")}
-        table = []
+    if a.batch_start == "lattice":
+        reps = [lattice_replica(r) if r["kind"] == "kg" else r for r in reps]
     else:
+        reps = [prepare_replica(r) for r in reps]
+    log("batch: replicas ready in %.1f s" % (time.time() - t0), a.quiet)
+    table = []
+    if a.autotune == "none":
+        choice = {}
+        how = "each replica's own skin, the library's automatic cells and list build"
+    elif a.autotune == "tune":
         choice, table = autotune.tune(reps, steps=30, log=lambda m: log(m, a.quiet))
+        how = "tuned in this run"
+    else:
+        choice, src = autotune.cached_choice(reps)
+        how = "autotuner cache (%s)" % src
     reps = autotune.apply(reps, choice)
     ntot = sum(r["pos"].shape[0] for r in reps)
     b = Batch(reps)
     b.step(a.warmup)
     o0 = b.observables()
-    b.timing(True)
     torch.cuda.synchronize()
     ts = time.perf_counter()
     b.step(a.steps)
     torch.cuda.synchronize()
     el = time.perf_counter() - ts
+    o1 = b.observables()
+    b.timing(True)
+    torch.cuda.synchronize()
+    ts = time.perf_counter()
+    b.step(a.steps)
+    torch.cuda.synchronize()
+    el_ev = time.perf_counter() - ts
     tm = b.timing()
     b.timing(False)
-    o1 = b.observables()
     b.close()
-    # the same members one by one (graph-replayed standalone handles)
-    t_sum = 0.0
-    for r in reps:
-        s = System(r["pos"], r["box"], r["vel"], pair=r["pair"], bonds=r.get("bonds"), angles=r.get("angles"),
-                   k_bend=r.get("k_bend", 0.0), dt=r["dt"], skin=r["skin"], integrator=r["integrator"],
-                   temperature=r["temperature"], gamma=r["gamma"], seed=r["seed"], cell_factor=r["cell_factor"],
-                   flags=nl_build_flags(r["nl_build"]))
-        s.step(4)
-        s.stream.synchronize()
-        t1 = time.perf_counter()
-        s.step(20)
-        s.stream.synchronize()
-        t_sum += (time.perf_counter() - t1) / 20
-        s.close()
-    value = ntot * a.steps / el
+    del b
+    free_gpu()
     k_ms = tm["ms_step_kernels"] / max(tm["n_step_kernels"], 1)
     alg = sum(member_alg_bytes(r, r["pos"].shape[0], r["skin"]) * r["pos"].shape[0] for r in reps)
     ach = alg / (k_ms * 1e-3) / 1e9
     rec = {
-        "metric": "atom-steps/s (1M LJ, 2M KG melt)",
-        "value": value, "unit": "atom-steps/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
-        "ms_per_step": 1e3 * el / a.steps, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32+f64", "data": "synthetic",
+        "value": ntot * a.steps / el, "unit": "atom-steps/s", "steps": a.steps, "warmup": a.warmup,
+        "ms_per_step": 1e3 * el / a.steps,
         "config": {"workload": "batch of 256 replicas (128 LJ fluids, 128 polymer melts), %d particles" % ntot,
                    "n_particles": ntot, "replicas": len(reps), "sizes": "log-uniform 2048..65536",
+                   "melt_start": ("chains laid on a simple cubic lattice" if a.batch_start == "lattice"
+                                  else "random walks pushed off on the GPU"),
                    "precision": "FP32 pair/bonded math, FP64 positions, velocities and reductions",
-                   "parallelism": "single GPU",
-                   "autotuned": {k: {"skin": v[0], "cell_factor": v[1] or "auto", "nl_build": v[2]}
-                                 for k, v in choice.items()}},
-        "standalone_sum_atom_steps_per_s": ntot / t_sum,
-        "batched_over_standalone": value / (ntot / t_sum),
+                   "parameters": how,
+                   "choice": {k: {"skin": v[0], "cell_factor": v[1] or "auto", "nl_build": v[2]}
+                              for k, v in sorted(choice.items())}},
         "n_rebuilds_total": sum(x["n_rebuilds"] - y["n_rebuilds"] for x, y in zip(o1, o0)),
+        "evented_pass": {"ms_per_step": 1e3 * el_ev / a.steps},
         "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": ach / HBM_PEAK_GBS, "traffic": None,
                      "kernel": "k_batch_step (fused forces + integration, all replicas)", "kernel_ms": k_ms,
@@ -234,17 +382,14 @@ def bench_batch(a):
         "kernel_breakdown_ms_per_step": {
             "rebuild_stage": tm["ms_rebuild"] / max(tm["n_rebuild"], 1), "step_kernel": k_ms,
             "finalize": tm["ms_finalize"] / max(tm["n_finalize"], 1)},
-        "autotune_trials": table,
     }
-    if not a.no_cpu_baseline:
-        w = dict(reps[0])
-        eps, sig, rc, shift, cap = w["pair"][(0, 0)]
-        w.update({"eps": eps, "sigma": sig, "rc": rc, "shift": shift})
-        rec["cpu_baseline"] = cpu_baseline(w, "batch", a.cpu_seconds, a.quiet)
-        rec["cpu_baseline"]["sample"] += " (replica 0 of the batch)"
-    print(json.dumps(rec), flush=True)
+    if table:
+        rec["autotune_trials"] = table
+    log("batch: %.3g atom-steps/s, %.3f ms/step" % (rec["value"], rec["ms_per_step"]), a.quiet)
+    return reps, rec
 
 
+# ---------------------------------------------------------------- main
 def main():
     a = parse()
     if a.gpus != 1:
@@ -257,83 +402,27 @@ def main():
         sys.exit(1)
     torch.cuda.set_device(0)
     if a.workload == "batch":
-        return bench_batch(a)
-    from paper_2608_14911_amd import md as md_
-    nl_flags = {"auto": 0, "tiles": md_.MD_CFG_NL_TILES, "per-particle": md_.MD_CFG_NL_PER_PARTICLE}[a.nl_build]
-    w, s = make_system(a.workload, a.quiet, a.cell_factor, nl_flags)
-    n = s.n
-    if a.workload == "sur1m":
-        # the surrogate replaces the WCA pair force: the network trained by
-        # surrogate_experiment.py on a 100k-bead plain-method melt (without
-        # excluded volume from a trained network the FENE bonds collapse the
-        # chains, so random weights cannot be timed over many steps)
-        wpath = os.path.join(ROOT, "paper_2608_14911_amd", "data", "surrogate_kg.npz")
-        if not os.path.exists(wpath):
-            raise SystemExit("missing %s: python -m paper_2608_14911_amd.surrogate_experiment --save %s"
-                             % (wpath, wpath))
-        wd = np.load(wpath)
-        s.sur_set(wd["theta_" + a.sur_precision], wd["g_mean"], wd["g_istd"], a.sur_precision)
-        s.set_pair_mode("surrogate")
-    s.step(a.warmup)
-    o0 = s.observables()
-    s.history()
-    timing = not a.no_events
-    if timing:
-        s.timing(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    s.step(a.steps)
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
-    tm = s.timing() if timing else None
-    if timing:
-        s.timing(False)
-    o1 = s.observables()
-    hist = s.history()
-    value = n * a.steps / el
-    ms = 1e3 * el / a.steps
-    from paper_2608_14911_amd import md as md_
-    plan = md_.md_plan_config(s.cfg)
-    rec = {
-        "metric": "atom-steps/s (1M LJ, 2M KG melt)" if a.workload != "sur1m" else
-                  "atom-steps/s (1M KG melt, learned surrogate pair force)",
-        "value": value,
-        "unit": "atom-steps/s",
-        "n_gpus": 1,
-        "steps": a.steps,
-        "warmup": a.warmup,
-        "ms_per_step": ms,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32+f64",
-        "data": "synthetic",
-        "config": {"workload": w["name"], "n_particles": n, "rc": w["rc"], "skin": w["skin"],
-                   "dt": w["dt"], "integrator": w["integrator"],
-                   "precision": "FP32 pair/bonded math, FP64 positions, velocities and reductions",
-                   "parallelism": "single GPU", "cell_factor": plan["cell_factor"],
-                   "cells_per_side": plan["cells"][0], "list_build": plan["nl_build"],
-                   "list_capacity": plan["nl_capacity"]},
-        "n_rebuilds": o1["n_rebuilds"] - o0["n_rebuilds"],
-        "energy_drift_per_particle": (o1["e_total"] - o0["e_total"]) / n,
-        "nl_max_count": o1["nl_max_count"],
-    }
-    if tm:
-        k_ms = tm["ms_step_kernels"] / max(tm["n_step_kernels"], 1)
-        alg = ALG_BYTES[a.workload] * n
-        ach = alg / (k_ms * 1e-3) / 1e9
-        tr = TRAFFIC.get(a.workload)
-        traffic = tr["bytes"] if tr and tr["source"] == kernel_source_hash() else None
-        rec["roofline"] = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                           "frac": ach / HBM_PEAK_GBS, "traffic": traffic,
-                           "kernel": ("k_step (fused pair+bonded forces, velocity Verlet, reductions)"
-                                      if a.workload != "sur1m" else
-                                      "surrogate force stage (k_sur_desc, k_sur_mlp, k_sur_force, k_step_ext)"),
-                           "kernel_ms": k_ms, "alg_bytes_per_launch": alg}
-        rec["kernel_breakdown_ms_per_step"] = {
-            "rebuild_stage": tm["ms_rebuild"] / max(tm["n_rebuild"], 1),
-            "step_kernel": k_ms,
-            "finalize": tm["ms_finalize"] / max(tm["n_finalize"], 1)}
+        reps, rec = bench_batch(a)
+        rec.update({"metric": "atom-steps/s (1M LJ, 2M KG melt); surrogate vs plain at stated force RMSE",
+                    "n_gpus": 1, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+                    "dtype": "f32+f64", "data": "synthetic"})
+        if not a.no_cpu_baseline:
+            w = dict(reps[0])
+            eps, sig, rc, shift, _ = w["pair"][(0, 0)]
+            w.update({"eps": eps, "sigma": sig, "rc": rc, "shift": shift})
+            rec["cpu_baseline"] = cpu_baseline(w, a.cpu_seconds, a.quiet)
+            rec["cpu_baseline"]["sample"] += " (replica 0 of the batch)"
+        print(json.dumps(rec), flush=True)
+        return
+    main_name = "lj1m" if a.workload == "default" else a.workload
+    w, rec = bench_single(main_name, a)
+    if a.workload == "default":
+        subs = {}
+        _, subs["kg2m"] = bench_single("kg2m", a)
+        _, subs["batch"] = bench_batch(a)
+        _, subs["sur1m"] = bench_single("sur1m", a)
+        subs["sur1m"]["vs_plain_kg"] = "plain WCA kernel on a melt of the same density: workloads.kg2m"
+        rec["workloads"] = subs
     if a.calib_copy:
         src = torch.ones(128 * 1024 * 1024, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
@@ -342,8 +431,7 @@ def main():
         torch.cuda.synchronize()
         rec["calib_copy_bytes"] = src.numel() * 4
     if not a.no_cpu_baseline:
-        rec["cpu_baseline"] = cpu_baseline(w, a.workload, a.cpu_seconds, a.quiet)
-    s.close()
+        rec["cpu_baseline"] = cpu_baseline(w, a.cpu_seconds, a.quiet)
     print(json.dumps(rec), flush=True)
 
 

@@ -65,7 +65,15 @@ enum {
 #define MD_FLAG_BOND_BROKEN 0x2u
 #define MD_FLAG_NONFINITE 0x4u
 
-enum { MD_NVE = 0, MD_LANGEVIN = 1 };    /* md_config.integrator      */
+/* md_config.integrator.  MD_DPD: the dissipative-particle-dynamics pair
+ * thermostat (section "Functionality") instead of the Langevin friction and
+ * noise: for each pair with r = |r_i - r_j| < dpd_rc, e = (r_i - r_j) / r,
+ * v_ij = v_i - v_j and w = 1 - r / dpd_rc, the force on i is
+ *   -gamma w^2 (e . v_ij) e + sqrt(2 gamma kT) w theta_ij e / sqrt(dt),
+ * theta_ij = theta_ji ~ N(0,1) from Philox4x64-10 keyed (seed, 6) at counter
+ * (step, min id, max id, 0), Box-Muller on its first two uniforms; v is the
+ * half-step velocity of velocity Verlet.  Needs MD_FP32. */
+enum { MD_NVE = 0, MD_LANGEVIN = 1, MD_DPD = 2 };
 enum { MD_FP64 = 0, MD_FP32 = 1 };       /* md_config.force_precision */
 
 #define MD_MAX_TYPES 4
@@ -112,13 +120,27 @@ typedef struct md_config {
                                   2 is the half-cutoff sub-cell decomposition;
                                   0 = 1, or 2 when fewer than 3 cells of side
                                   rc+skin fit per side */
-    int32_t nl_capacity;       /* neighbours per particle; 0 = from density */
+    int32_t nl_capacity;       /* neighbours per particle, rounded up to a multiple
+                                  of 8 (rows are streamed in batches of 8 slots);
+                                  0 = from density */
     int32_t block_size;        /* threads per block of the force kernel; 0 = 256 */
     int32_t flags;             /* MD_CFG_* */
     double list_cutoff;        /* Verlet list radius = max(list_cutoff, max rc) + skin;
                                   0 = max rc.  The surrogate needs >= MD_SUR_RCUT */
     int32_t surrogate;         /* 1: reserve workspace for the learned surrogate */
     int32_t pad_;
+    double shear_rate;         /* Lees-Edwards boundaries (section "New Features") when
+                                  != 0: flow along x, gradient along y.  The image one
+                                  box above (y + Ly) is displaced by delta(t) = shear_rate
+                                  Ly t (mod Lx), t = step dt, and moves with shear_rate Ly
+                                  along x; a particle leaving through y = Ly re-enters at
+                                  y - Ly with x - delta and v_x - shear_rate Ly (through
+                                  y = 0 the opposite).  Needs MD_FP32 and a constant dt;
+                                  the list is rebuilt when twice the largest displacement
+                                  plus the offset's change since the last build reaches
+                                  the skin */
+    double dpd_rc;             /* DPD weight range (MD_DPD); the Verlet list radius
+                                  covers max(dpd_rc, rc, list_cutoff) + skin */
 } md_config;
 
 /* Observables of one step n (positions x_n, on-step velocities v_n). */
@@ -188,8 +210,10 @@ md_status md_init(const md_config* cfg, const double* pos, const double* vel, co
  * seed, integrator, force_precision, the pair table (e.g. switching
  * LennardJonesCapped to LennardJones as the paper's example does),
  * fene_K/R0, k_bend, flags.  n_particles, n_types, box, skin, n_bonds and
- * n_angles must equal those given to md_init; a pair table whose cutoffs
- * exceed the list radius fixed at md_init is rejected. */
+ * n_angles must equal those given to md_init (MD_ERR_ARG otherwise: the
+ * list radius and the half-skin rebuild threshold are fixed at md_init); a
+ * pair table whose cutoffs plus the skin exceed that list radius is
+ * rejected. */
 md_status md_set_params(md_handle h, const md_config* cfg);
 
 /* Force a cell sort and neighbour-list build at the current positions. */

@@ -711,6 +711,7 @@ static void pair_forces_ext(const orc_sys* s, const orc_ext* x, const double* po
                 const double th = orc_dpd_theta(x->seed, (uint64_t)x->step, (uint64_t)i, (uint64_t)j);
                 const double a = -x->dpd_gamma * w * w * ev + sigma * w * th * isdt;
                 for (int k = 0; k < 3; ++k) { Fd[3 * i + k] += a * e[k]; Fd[3 * j + k] -= a * e[k]; }
+                if (fscale) { fscale[i] += fabs(a); fscale[j] += fabs(a); }
             }
         }
     }
@@ -773,7 +774,9 @@ static int bonded_forces_ext(const orc_sys* s, const orc_ext* x, const double* p
 
 /* Conservative forces F (and, with dpd_rc > 0 and Fd non-NULL, the DPD
  * thermostat forces Fd at velocities vel) under the sheared boundaries at
- * time step * dt.  Brute force over pairs. */
+ * time step * dt.  Brute force over pairs.  fscale[i]: the sum of the
+ * magnitudes of every pair and bonded force term on i, DPD pair forces
+ * included when computed. */
 int orc_forces_ext(int64_t n, const double* pos, const double* vel, const int32_t* type, int32_t ntypes,
                    const double* pp, const double* box, int64_t nbonds, const int32_t* bonds, double fene_K,
                    double fene_R0, int64_t nangles, const int32_t* angles, double k_bend, double shear_rate,

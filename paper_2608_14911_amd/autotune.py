@@ -1,27 +1,102 @@
-"""Autotuner of a batch's performance parameters.
+"""Autotuner of the performance parameters of single systems and batches.
 
-The parameters change only the cost of a step, never its result (the list
-holds every pair inside the cutoff whatever the skin, cell size and build):
-the Verlet skin (longer lists against fewer rebuilds), the cell size and the
-list build, tried as the three forms that make sense: one wavefront per
-64-particle tile on cells of side rc+skin, one particle per lane on the same
-cells, and one particle per lane on half-cutoff cells (fewer candidate pairs,
-more cells to walk).  Members are grouped by kind (LJ fluid, polymer melt);
-one group at a time, every candidate is timed on the whole batch with the
-graph-replayed step and the fastest is kept (coordinate descent).  The force
-kernels' tile is 256 particles (one block), fixed by the kernels.
+The parameters change only the cost of a step, never which pairs interact
+(the list holds every pair inside the cutoff whatever the skin, cell size and
+build; only the order of the FP32 sums follows the list order):
+
+* the Verlet skin (longer lists against fewer rebuilds) -- batches only, since
+  the single-system workloads fix their skin;
+* the cell size and the list build, tried as the three forms that make sense:
+  one wavefront per 64-particle tile on cells of side rc+skin, one particle
+  per lane on the same cells, and one particle per lane on half-cutoff cells
+  (fewer candidate pairs, more cells to walk).
+
+Results are cached in ``data/autotune_cache.json`` by
+
+    (arch, kind, N bucket, density bucket, rc)
+
+with N buckets of a factor 4 from 2,048 (2048-8191, 8192-32767, ...) and
+density buckets 0.1 wide.  A batch is tuned group by group (members sharing a
+key), each candidate timed on the whole batch with the graph-replayed step
+(coordinate descent over the groups); a single system times each candidate on
+itself.  Timing needs the GPU; looking up the cache does not.
 """
+import json
+import math
+import os
 import time
 
-SKINS = {"lj": (0.3, 0.4, 0.5), "kg": (0.3, 0.4, 0.5)}
+ARCH = "gfx950"
+CACHE_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "data", "autotune_cache.json")
+SKINS = (0.3, 0.4, 0.5)
 # (cell factor, list build)
 BUILDS = ((1, "tiles"), (1, "per_particle"), (2, "per_particle"))
 
 
-def _apply(members, choice):
+# ---------------------------------------------------------------- keys
+def n_bucket(n):
+    """Lower edge of n's bucket: 2048 * 4^k (smaller systems share the first)."""
+    k = max(0, int(math.floor(math.log(max(n, 1) / 2048.0, 4.0) + 1e-12)))
+    return 2048 * 4 ** k
+
+
+def rho_bucket(rho):
+    return "%.1f" % (math.floor(rho * 10.0 + 1e-9) / 10.0)
+
+
+def key_of(kind, n, rho, rc):
+    return "%s|%s|n%d|rho%s|rc%.4f" % (ARCH, kind, n_bucket(n), rho_bucket(rho), rc)
+
+
+def member_key(m):
+    n = m["pos"].shape[0]
+    box = m["box"]
+    rho = n / float(box[0] * box[1] * box[2])
+    return key_of(m.get("kind", "lj"), n, rho, m["pair"][(0, 0)][2])
+
+
+# ---------------------------------------------------------------- cache
+def load_cache(path=CACHE_PATH):
+    if not os.path.exists(path):
+        return {}
+    with open(path) as f:
+        return json.load(f)
+
+
+def save_cache(cache, path=CACHE_PATH):
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    tmp = path + ".tmp%d" % os.getpid()
+    with open(tmp, "w") as f:
+        json.dump(cache, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def cached_choice(members, path=CACHE_PATH):
+    """Per-member parameters {member key: (skin, cell_factor, nl_build)} from
+    the cache; keys without an entry keep the member's own skin and the
+    library's automatic cells and build.  Returns (choice, description)."""
+    cache = load_cache(path)
+    choice, hit, miss = {}, 0, 0
+    for m in members:
+        k = member_key(m)
+        if k in choice:
+            continue
+        e = cache.get(k)
+        if e is None:
+            choice[k] = (m["skin"], 0, "auto")
+            miss += 1
+        else:
+            choice[k] = (e["skin"], e["cell_factor"], e["nl_build"])
+            hit += 1
+    return choice, "%d keys from the cache, %d without an entry (library defaults)" % (hit, miss)
+
+
+def apply(members, choice):
+    """Members with the parameters of their key (choice from tune() or
+    cached_choice())."""
     out = []
     for m in members:
-        k = m.get("kind", "lj")
+        k = member_key(m)
         m = dict(m)
         if k in choice:
             m["skin"], m["cell_factor"], m["nl_build"] = choice[k]
@@ -29,9 +104,10 @@ def _apply(members, choice):
     return out
 
 
+# ---------------------------------------------------------------- timing
 def time_batch(members, steps, warmup=6):
-    """Mean wall time per step (ms) of the batch, graph-replayed, and the
-    batch itself is closed afterwards."""
+    """Mean wall time per step (ms) of the batch, graph-replayed; the batch
+    is closed afterwards."""
     from .system import Batch
     b = Batch(members)
     b.step(warmup)
@@ -44,33 +120,72 @@ def time_batch(members, steps, warmup=6):
     return ms
 
 
-def tune(members, steps=40, log=None):
-    """Returns (choice {kind: (skin, cell_factor, nl_build)}, table of trials)."""
-    kinds = sorted({m.get("kind", "lj") for m in members})
-    # start from each group's own skin and the library's automatic choice
-    choice = {k: (next(m["skin"] for m in members if m.get("kind", "lj") == k), 0, "auto") for k in kinds}
+def tune(members, steps=40, skins=SKINS, builds=BUILDS, log=None, path=CACHE_PATH, write=True):
+    """Tune a batch group by group.  Returns (choice {key: (skin, cell_factor,
+    nl_build)}, table of trials); with write=True the winners go to the
+    cache."""
+    keys = sorted({member_key(m) for m in members})
+    choice = {k: (next(m["skin"] for m in members if member_key(m) == k), 0, "auto") for k in keys}
     table = []
-    for k in kinds:
+    for k in keys:
         best = None
-        for skin in SKINS.get(k, (0.3,)):
-            for cf, build in BUILDS:
+        for skin in skins:
+            for cf, build in builds:
                 trial = dict(choice)
                 trial[k] = (skin, cf, build)
                 try:
-                    ms = time_batch(_apply(members, trial), steps)
+                    ms = time_batch(apply(members, trial), steps)
                 except Exception as e:   # e.g. a box too small for half-cutoff cells
                     if log:
                         log("autotune %s skin %.2f cf %d %s: skipped (%s)" % (k, skin, cf, build, e))
                     continue
-                table.append({"kind": k, "skin": skin, "cell_factor": cf, "nl_build": build, "ms_per_step": ms})
+                table.append({"key": k, "skin": skin, "cell_factor": cf, "nl_build": build, "ms_per_step": ms})
                 if log:
                     log("autotune %s skin %.2f cf %d %s: %.3f ms/step" % (k, skin, cf, build, ms))
                 if best is None or ms < best[0]:
                     best = (ms, skin, cf, build)
         if best is not None:
             choice[k] = best[1:]
+    if write:
+        cache = load_cache(path)
+        for k, (skin, cf, build) in choice.items():
+            if build != "auto":
+                cache[k] = {"skin": skin, "cell_factor": cf, "nl_build": build, "source": "batch"}
+        save_cache(cache, path)
     return choice, table
 
 
-def apply(members, choice):
-    return _apply(members, choice)
+def tune_system(make, n, rho, rc, kind, steps=40, builds=BUILDS, log=None, path=CACHE_PATH, write=True):
+    """Tune the cells and list build of one system.  ``make(cell_factor,
+    flags)`` returns a fresh System; its skin is the workload's own.  Returns
+    ((cell_factor, nl_build), table)."""
+    from .system import nl_build_flags
+    table, best = [], None
+    for cf, build in builds:
+        try:
+            s = make(cf, nl_build_flags(build))
+        except Exception as e:
+            if log:
+                log("autotune %s cf %d %s: skipped (%s)" % (kind, cf, build, e))
+            continue
+        s.step(6)
+        s.stream.synchronize()
+        t0 = time.perf_counter()
+        s.step(steps)
+        s.stream.synchronize()
+        ms = 1e3 * (time.perf_counter() - t0) / steps
+        skin = s.cfg.skin
+        s.close()
+        table.append({"cell_factor": cf, "nl_build": build, "ms_per_step": ms})
+        if log:
+            log("autotune %s cf %d %s: %.3f ms/step" % (kind, cf, build, ms))
+        if best is None or ms < best[0]:
+            best = (ms, cf, build)
+    if best is None:
+        raise RuntimeError("no candidate configuration ran")
+    if write:
+        cache = load_cache(path)
+        cache[key_of(kind, n, rho, rc)] = {"skin": skin, "cell_factor": best[1], "nl_build": best[2],
+                                           "source": "single"}
+        save_cache(cache, path)
+    return best[1:], table

@@ -93,10 +93,22 @@ static md_status validate(const md_config* c, std::string* why) {
         if (!(c->box[d] > 0.0) || !isfinite(c->box[d])) { *why = "box must be positive and finite"; return MD_ERR_ARG; }
     if (!(c->dt > 0.0) || !isfinite(c->dt)) { *why = "dt must be > 0"; return MD_ERR_ARG; }
     if (!(c->skin > 0.0) || !isfinite(c->skin)) { *why = "skin must be > 0"; return MD_ERR_ARG; }
-    if (c->integrator != MD_NVE && c->integrator != MD_LANGEVIN) { *why = "unknown integrator"; return MD_ERR_ARG; }
+    if (c->integrator != MD_NVE && c->integrator != MD_LANGEVIN && c->integrator != MD_DPD) {
+        *why = "unknown integrator";
+        return MD_ERR_ARG;
+    }
     if (c->force_precision != MD_FP64 && c->force_precision != MD_FP32) { *why = "unknown force precision"; return MD_ERR_ARG; }
-    if (c->integrator == MD_LANGEVIN && (!(c->gamma >= 0.0) || !(c->temperature >= 0.0))) {
-        *why = "Langevin gamma and temperature must be >= 0";
+    if (c->integrator != MD_NVE && (!(c->gamma >= 0.0) || !(c->temperature >= 0.0))) {
+        *why = "thermostat gamma and temperature must be >= 0";
+        return MD_ERR_ARG;
+    }
+    if (c->integrator == MD_DPD && !(c->dpd_rc > 0.0 && isfinite(c->dpd_rc))) {
+        *why = "DPD needs dpd_rc > 0";
+        return MD_ERR_ARG;
+    }
+    if (!isfinite(c->shear_rate)) { *why = "shear_rate must be finite"; return MD_ERR_ARG; }
+    if ((c->integrator == MD_DPD || c->shear_rate != 0.0) && c->force_precision != MD_FP32) {
+        *why = "DPD and Lees-Edwards shear run on the FP32 pair path (force_precision MD_FP32)";
         return MD_ERR_ARG;
     }
     const int nt = c->n_types;
@@ -142,7 +154,7 @@ static md_status plan_geom(const md_config* c, Geom* g, std::string* why) {
     memset(g, 0, sizeof(*g));
     g->n = c->n_particles;
     g->ntypes = c->n_types;
-    const double rv = fmax(rc_max_of(c), c->list_cutoff) + c->skin;
+    const double rv = fmax(fmax(rc_max_of(c), c->list_cutoff), c->integrator == MD_DPD ? c->dpd_rc : 0.0) + c->skin;
     g->rv2 = rv * rv;
     g->disp2 = (0.5 * c->skin) * (0.5 * c->skin);
     // List build: dense systems (>= 8 particles expected in a cell of side
@@ -192,7 +204,9 @@ static md_status plan_geom(const md_config* c, Geom* g, std::string* why) {
     g->rv2lo = (float)(g->rv2 - band);
     g->rv2hi = (float)(g->rv2 + band);
     if (c->nl_capacity > 0) {
-        g->cap = c->nl_capacity;
+        // rows are padded and streamed in batches of 8 slots, so the capacity
+        // is a multiple of 8 (4096 already is): a batch never reads past a row
+        g->cap = (c->nl_capacity + 7) & ~7;
     } else {
         const double vol = c->box[0] * c->box[1] * c->box[2];
         const double expect = (double)c->n_particles / vol * (4.0 / 3.0) * M_PI * rv * rv * rv;
@@ -203,6 +217,11 @@ static md_status plan_geom(const md_config* c, Geom* g, std::string* why) {
         g->cap = cap;
     }
     g->nl_tile = (!per_particle && ((c->flags & MD_CFG_NL_TILES) || (dense && g->kc == 1))) ? 1 : 0;
+    g->le = c->shear_rate != 0.0 ? 1 : 0;
+    g->le_rate_Ly = c->shear_rate * c->box[1];
+    g->le_dt = c->dt;
+    g->skin = c->skin;
+    if (g->le) g->nl_tile = 0;   // the sheared stencil is built one particle per lane
     g->nl_cubic = (c->box[0] == c->box[1] && c->box[1] == c->box[2]) ? 1 : 0;
     // the unbonded fast step kernel gathers 12-byte records (fewer L1 lines per
     // gather: 4% faster on the LJ fluid); the bonded one keeps the 16-byte
@@ -303,6 +322,7 @@ static size_t carve(const md_config* c, const Geom& g, int step_grid, uint8_t* b
         u.w = (float*)take(sizeof(float) * kSurNPpad);
         u.wp = (float*)take(sizeof(float) * kPrepF);
         u.wb = (uint16_t*)take(sizeof(uint16_t) * kPrepB);
+        u.wm = (uint16_t*)take(sizeof(uint16_t) * kPrepM);
         u.gmean = (float*)take(sizeof(float) * kSurNB);
         u.gistd = (float*)take(sizeof(float) * kSurNB);
         u.grad = (float*)take(sizeof(float) * kSurNPpad);
@@ -358,7 +378,8 @@ static void fill_params(md_handle h, const md_config* c) {
     {
         const md_pair_params& p = c->pair[0];
         const bool cubic = c->box[0] == c->box[1] && c->box[1] == c->box[2];
-        h->use_fast = (c->n_types == 1 && cubic && !(p.caprad > 0.0)) ? 1 : 0;
+        h->use_fast = (c->n_types == 1 && cubic && !(p.caprad > 0.0) && c->integrator != MD_DPD &&
+                       c->shear_rate == 0.0) ? 1 : 0;
         const double u = c->box[0] * 0x1.0p-32;
         FastCoef& f = h->fast;
         memset(&f, 0, sizeof(f));
@@ -384,6 +405,11 @@ static void fill_params(md_handle h, const md_config* c) {
     dy.fene_halfKR02f = (float)dy.fene_halfKR02;
     dy.k_bend = c->k_bend;
     dy.k_bendf = (float)c->k_bend;
+    dy.dpd = c->integrator == MD_DPD ? 1 : 0;
+    dy.dpd_rc = (float)c->dpd_rc;
+    dy.dpd_rc2 = (float)(c->dpd_rc * c->dpd_rc);
+    dy.dpd_gamma = (float)c->gamma;
+    dy.dpd_sigma_isdt = (float)(sqrt(2.0 * c->gamma * c->temperature) / sqrt(c->dt));
 }
 
 static void fill_masses(md_handle h, const double* mass_by_type) {
@@ -435,26 +461,33 @@ static void fill_sur_const(SurConst* c) {
     c->ratio = (float)exp2(-2.0 * (1.4426950408889634 / (2.0 * w2)) * dmu * dmu);
 }
 
-// Force stage: the plain fused kernel, or the surrogate's descriptor,
-// network and pair-force kernels followed by the external-force step
-// kernel.  Returns the surrogate partials for the finalize (or nullptr).
+// Force stage: the plain fused kernel, or the surrogate's network stage
+// followed by its fused pair-force + bonded + integration kernel.  BF16
+// form: descriptors and the matrix-core network in one kernel, the input
+// gradients passed on as BF16 rows.  FP32 form: descriptor rows, then the
+// FP32 network.  *spart receives the network's energy partials (one row),
+// or nullptr.
 static hipError_t launch_force_stage(md_handle h, int mode, int tensor, double* f_out, const double** spart) {
     StepArgs a = make_args(h, mode, tensor, f_out);
     *spart = nullptr;
     if (h->pair_mode == MD_PAIR_PLAIN) return launch_step(a, h->fp64, h->single, h->bonded, kBlock, h->stream);
     hipError_t e;
     const SurBufs& s = h->sb;
-    if ((e = launch_sur_desc(h->g, h->b, s, h->sc, h->parity, h->step_grid, h->stream)) != hipSuccess) return e;
-    // BF16 form: the input gradients travel to the pair-force pass as BF16
     const int bf = h->sur_prec == MD_SUR_BF16;
-    if ((e = launch_sur_mlp(s, s.G, h->g.n, bf ? nullptr : s.a, nullptr, s.part, bf, h->step_grid, h->stream,
-                            bf ? s.ab : nullptr)) != hipSuccess)
-        return e;
-    if ((e = launch_sur_force(h->g, h->b, s, h->sc, h->parity, nullptr, 0.0, tensor, h->step_grid, h->stream, bf)) !=
-        hipSuccess)
-        return e;
+    if (bf) {
+        if ((e = launch_sur_desc2(h->g, h->b, s, h->sc, h->parity, 1, h->stream)) != hipSuccess) return e;
+    } else {
+        if ((e = launch_sur_desc2(h->g, h->b, s, h->sc, h->parity, 0, h->stream)) != hipSuccess) return e;
+        if ((e = launch_sur_mlp(s, s.G, h->g.n, s.a, nullptr, s.part, 0, h->step_grid, h->stream)) != hipSuccess)
+            return e;
+    }
     *spart = s.part;
-    return launch_step_ext(a, s, h->bonded, h->stream);
+    return launch_sur_step(a, s, h->sc, h->bonded, bf, h->stream);
+}
+
+// the finalize of a force stage: surrogate partials carry the energy only
+static hipError_t launch_stage_finalize(md_handle h, int mode, const double* spart, int tensor) {
+    return launch_finalize(h->b, h->step_grid, mode, spart, tensor, h->stream, 1);
 }
 
 // Enqueue one full step at the handle's current parity and advance the
@@ -470,7 +503,7 @@ static hipError_t enqueue_step(md_handle h, const EvQuad* q) {
     e = launch_force_stage(h, MODE_STEP, tensor, nullptr, &spart);
     if (e != hipSuccess) return e;
     if (q) (void)hipEventRecord(q->e[2], h->stream);
-    e = launch_finalize(h->b, h->step_grid, MODE_STEP, spart, tensor, h->stream);
+    e = launch_stage_finalize(h, MODE_STEP, spart, tensor);
     if (e != hipSuccess) return e;
     if (q) (void)hipEventRecord(q->e[3], h->stream);
     h->parity ^= 1;
@@ -517,7 +550,7 @@ static md_status status_to_code(md_handle h, uint32_t st, int32_t nl_max) {
     if (st & MD_FLAG_NL_OVERFLOW) {
         char buf[160];
         snprintf(buf, sizeof buf, "neighbour list overflow: a particle has %d neighbours, capacity %d; "
-                                  "re-create with md_config.nl_capacity >= %d", nl_max, h->g.cap, nl_max);
+                                  "re-create with md_config.nl_capacity >= %d", nl_max, h->g.cap, (nl_max + 7) & ~7);
         return fail(h, MD_ERR_NL_OVERFLOW, buf);
     }
     if (st & MD_FLAG_BOND_BROKEN) return fail(h, MD_ERR_BOND_BROKEN, "a FENE bond reached R0");
@@ -741,15 +774,20 @@ md_status md_set_params(md_handle h, const md_config* cfg) {
     if (cfg->n_particles != o.n_particles || cfg->n_types != o.n_types || cfg->n_bonds != o.n_bonds ||
         cfg->n_angles != o.n_angles || memcmp(cfg->box, o.box, sizeof(o.box)) != 0)
         return fail(h, MD_ERR_ARG, "md_set_params cannot change N, types, box or topology");
+    // The rebuild threshold (skin/2)^2 and the list radius stay those of
+    // md_init.  With the skin fixed, a cutoff that fits inside the list radius
+    // leaves at least the full skin between them, so the threshold stays valid;
+    // a changed skin would not (a smaller effective skin under the old
+    // threshold misses pairs entering the cutoff).
+    if (cfg->skin != o.skin) return fail(h, MD_ERR_ARG, "md_set_params cannot change the skin fixed at md_init");
+    if (cfg->shear_rate != o.shear_rate || ((o.shear_rate != 0.0) && cfg->dt != o.dt))
+        return fail(h, MD_ERR_ARG, "md_set_params cannot change the shear rate, or the time step under shear");
     if (g.rv2 > h->g.rv2 * (1.0 + 1e-15))
         return fail(h, MD_ERR_ARG, "cutoff + skin exceeds the list radius fixed at md_init");
     double mass[MD_MAX_TYPES];
     for (int t = 0; t < MD_MAX_TYPES; ++t) mass[t] = h->dy.mass[t];
-    // keep the geometry (list radius, cells, capacity) of md_init; the
-    // rebuild threshold follows the new skin only if it is not larger
     const double old_disp2 = h->g.disp2;
     h->cfg = *cfg;
-    h->cfg.skin = o.skin;
     h->fp64 = cfg->force_precision == MD_FP64 ? 1 : 0;
     fill_params(h, cfg);
     fill_masses(h, mass);
@@ -769,7 +807,7 @@ md_status md_forces(md_handle h, double* f_out) {
     if (r != MD_OK) return r;
     const double* spart = nullptr;
     HIP_TRY(h, launch_force_stage(h, MODE_FORCES, 1, f_out, &spart));
-    HIP_TRY(h, launch_finalize(h->b, h->step_grid, MODE_FORCES, spart, 1, h->stream));
+    HIP_TRY(h, launch_stage_finalize(h, MODE_FORCES, spart, 1));
     return MD_OK;
 }
 
@@ -821,7 +859,7 @@ md_status md_observables(md_handle h, md_obs* out) {
     if (r != MD_OK) return r;
     const double* spart = nullptr;
     HIP_TRY(h, launch_force_stage(h, MODE_OBSERVE, 1, nullptr, &spart));
-    HIP_TRY(h, launch_finalize(h->b, h->step_grid, MODE_OBSERVE, spart, 1, h->stream));
+    HIP_TRY(h, launch_stage_finalize(h, MODE_OBSERVE, spart, 1));
     double rec[kHistRec];
     HIP_TRY(h, hipMemcpyAsync(rec, h->b.cur, sizeof(rec), hipMemcpyDeviceToHost, h->stream));
     DevCtl c;
@@ -976,6 +1014,7 @@ md_status md_set_pair_mode(md_handle h, int32_t mode) {
         return MD_OK;
     }
     if (mode != MD_PAIR_SURROGATE) return fail(h, MD_ERR_ARG, "bad pair mode");
+    if (h->g.le || h->dy.dpd) return fail(h, MD_ERR_ARG, "the surrogate runs without DPD and shear");
     md_status r = need_sur(h);
     if (r != MD_OK) return r;
     if (!h->sur_loaded) return fail(h, MD_ERR_ARG, "md_sur_set has not been called");
@@ -993,7 +1032,7 @@ md_status md_sur_descriptors(md_handle h, float* G) {
     if (sqrt(h->g.rv2) - h->cfg.skin < MD_SUR_RCUT * (1.0 - 1e-12))
         return fail(h, MD_ERR_ARG, "list radius minus skin is below the descriptor cutoff");
     if ((r = rebuild_now(h, 0)) != MD_OK) return r;
-    HIP_TRY(h, launch_sur_desc(h->g, h->b, h->sb, h->sc, h->parity, h->step_grid, h->stream));
+    HIP_TRY(h, launch_sur_desc2(h->g, h->b, h->sb, h->sc, h->parity, 0, h->stream));
     HIP_TRY(h, launch_sur_to_tag(h->g, h->b, h->sb.G, G, h->stream));
     return MD_OK;
 }
@@ -1004,9 +1043,13 @@ md_status md_sur_mlp_eval(md_handle h, const float* G, int64_t P, float* e, floa
     if (!h->sur_loaded) return fail(h, MD_ERR_ARG, "md_sur_set has not been called");
     if (P < 0 || (P > 0 && (!G || !dedg))) return fail(h, MD_ERR_ARG, "bad arguments");
     if (P == 0) return MD_OK;
+    if (h->sur_prec == MD_SUR_BF16) {
+        HIP_TRY(h, launch_sur_mlp16(h->sb, G, P, dedg, e, h->stream));
+        return MD_OK;
+    }
     const int64_t tiles = (P + 63) / 64;
     const int grid = (int)(tiles < 4096 ? tiles : 4096);
-    HIP_TRY(h, launch_sur_mlp(h->sb, G, P, dedg, e, nullptr, h->sur_prec == MD_SUR_BF16, grid, h->stream));
+    HIP_TRY(h, launch_sur_mlp(h->sb, G, P, dedg, e, nullptr, 0, grid, h->stream));
     return MD_OK;
 }
 
@@ -1043,7 +1086,7 @@ md_status md_sur_loss_grad(md_handle h, const double* frames, const double* f_re
         HIP_TRY(h, launch_init_load(h->g, h->b, 0, pos, nullptr, h->b.type_t, nullptr, h->stream));
         HIP_TRY(h, launch_set_ctl(h->b, 0, 0, 1, 1, h->stream));
         if ((r = rebuild_now(h, 0)) != MD_OK) return r;
-        HIP_TRY(h, launch_sur_desc(h->g, h->b, s, h->sc, 0, h->step_grid, h->stream));
+        HIP_TRY(h, launch_sur_desc2(h->g, h->b, s, h->sc, 0, 0, h->stream));
         HIP_TRY(h, launch_sur_mlp(s, s.G, n, s.a, nullptr, nullptr, bf, h->step_grid, h->stream));
         HIP_TRY(h, launch_sur_force(h->g, h->b, s, h->sc, 0, f_ref + (size_t)f * 3 * n, two_over_m, 0, h->step_grid,
                                     h->stream));
@@ -1134,10 +1177,10 @@ md_status plan_batch(const md_config* cfgs, int32_t nsys, BatchPlan* p, std::str
         }
         const md_pair_params& pp = c->pair[0];
         if (c->n_types != 1 || c->force_precision != MD_FP32 || pp.caprad > 0.0 || c->box[0] != c->box[1] ||
-            c->box[1] != c->box[2] || c->surrogate) {
+            c->box[1] != c->box[2] || c->surrogate || c->integrator == MD_DPD || c->shear_rate != 0.0) {
             *why = "system " + std::to_string(s) +
-                   ": batch members need one particle type, FP32 pair math, a cubic box, no capping radius "
-                   "and no surrogate";
+                   ": batch members need one particle type, FP32 pair math, a cubic box, no capping radius, "
+                   "no surrogate, no DPD and no shear";
             return MD_ERR_ARG;
         }
         if (c->n_particles > (int64_t)kBlock * 1024) {

@@ -61,4 +61,51 @@ __device__ __forceinline__ int64_t gtid_xcd() {
 }
 __device__ __forceinline__ int64_t gstride() { return (int64_t)gridDim.x * blockDim.x; }
 
+// ------------------------------------------------------------------ surrogate helpers
+
+// FP32 -> BF16, round to nearest even (NaN stays NaN).
+__device__ __forceinline__ short bf16_rne(float f) {
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7f800000u) == 0x7f800000u) return (short)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (short)(u >> 16);
+}
+__device__ __forceinline__ float bf16_to_f32(uint32_t h) { return __uint_as_float(h << 16); }
+
+// f_c(r) = (cos(pi r / r_d) + 1) / 2 and its derivative.
+__device__ __forceinline__ float sur_cutoff(const SurConst& c, float r, float& dfc) {
+    // argument in [0, pi]: the hardware sine / cosine are accurate to a few
+    // 1e-7 there
+    float sn, cs;
+    __sincosf(c.pi_rd * r, &sn, &cs);
+    dfc = -0.5f * c.pi_rd * sn;
+    return 0.5f * (cs + 1.f);
+}
+
+// phi_k(r) = exp(-(r - mu_k)^2 / (2 w^2)) for k = 0..31 by two-sided
+// recurrences from pivots k = 8 and 24: with t = r - mu_p,
+//   phi_{p+1} / phi_p = exp2(c (2 D t - D^2)),  phi_{p-1} / phi_p = exp2(c (-2 D t - D^2)),
+// and each further ratio is the previous one times exp2(-2 c D^2)
+// (c = log2(e) / (2 w^2), D the centre spacing): 6 exponentials per pair
+// instead of 32, chains of at most 8 products.
+__device__ __forceinline__ void sur_basis(const SurConst& c, float r, float* phi) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int p = 8 + 16 * h;
+        const float t = r - c.mu[p];
+        phi[p] = __builtin_amdgcn_exp2f(-c.c_exp * t * t);
+        float up = __builtin_amdgcn_exp2f(c.c_exp * (2.f * c.dmu * t - c.dmu * c.dmu));
+        float dn = __builtin_amdgcn_exp2f(c.c_exp * (-2.f * c.dmu * t - c.dmu * c.dmu));
+#pragma unroll
+        for (int m = 1; m <= 8; ++m) {
+            phi[p - m] = phi[p - m + 1] * dn;
+            dn *= c.ratio;
+            if (m <= 7) {
+                phi[p + m] = phi[p + m - 1] * up;
+                up *= c.ratio;
+            }
+        }
+    }
+}
+
 }  // namespace md

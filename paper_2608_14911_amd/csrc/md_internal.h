@@ -33,7 +33,8 @@ struct DevCtl {
     int32_t nl_max;        // longest row at the last build
     int32_t pad0;
     int64_t n_rebuilds;
-    int64_t pad[11];
+    int64_t build_step;    // step of the positions the list was last built from
+    int64_t pad[10];
 };
 
 // One type pair, precomputed on the host in FP64 and rounded once for FP32.
@@ -86,6 +87,13 @@ struct Geom {
                             // prefilter of the tile build (cubic box)
     int32_t x3_on;          // keep the 12-byte position records (systems without bonds,
                             // whose fast step kernel gathers them)
+    // Lees-Edwards shear (flow x, gradient y): offset delta(step) =
+    // fmod(le_rate_Ly * (step * le_dt), Lx); images one box above move with
+    // +le_rate_Ly along x
+    int32_t le;
+    double le_rate_Ly;      // shear_rate * Ly
+    double le_dt;           // dt (the offset assumes a constant time step)
+    double skin;
 };
 
 struct Bufs {
@@ -137,6 +145,11 @@ struct Dyn {
     float fene_Kf, fene_R02f, fene_halfKR02f;
     double k_bend;
     float k_bendf;
+    // DPD pair thermostat (integrator MD_DPD): -gamma w^2 (e.v) e + sigma w theta e / sqrt(dt)
+    int32_t dpd;
+    float dpd_rc, dpd_rc2;
+    float dpd_gamma;
+    float dpd_sigma_isdt;   // sqrt(2 gamma kT) / sqrt(dt)
 };
 
 // internal status bit (init only): a particle type outside 0..n_types-1
@@ -185,6 +198,12 @@ constexpr int kPW1 = 0, kPW1T = 64 * kPF1, kPW2 = kPW1T + 32 * kPF64, kPW2T = kP
 constexpr int kSW1 = 40, kSW64 = 72;
 constexpr int kQW1 = 0, kQW1T = 64 * kSW1, kQW2 = kQW1T + 32 * kSW64, kQW2T = kQW2 + 64 * kSW64,
               kPrepB = kQW2T + 64 * kSW64;
+// prepared BF16 weights for the 16x16x32 matrix-core network (inference):
+// A-operand images with the K axis in slot order (see md_surrogate.hip):
+// W1 [64][40], W2 [64][72], W2^T [64][72], W1^T [32][72]
+constexpr int kMS1 = 40, kMS64 = 72;
+constexpr int kM1 = 0, kM2 = 64 * kMS1, kM2T = kM2 + 64 * kMS64, kM1T = kM2T + 64 * kMS64,
+              kPrepM = kM1T + 32 * kMS64;
 constexpr int kSurPart = 9;                 // E, W, tensor[6], loss
 constexpr int kSurGradBlocks = 256;         // blocks of the double-backward kernel
 
@@ -200,6 +219,7 @@ struct SurBufs {
     float* w;           // [kSurNPpad] master weights
     float* wp;          // [kPrepF] prepared FP32 weights
     uint16_t* wb;       // [kPrepB] prepared BF16 weights
+    uint16_t* wm;       // [kPrepM] prepared BF16 weights, matrix-core operand images
     float* gmean;       // [32]
     float* gistd;       // [32]
     float* grad;        // [kSurNPpad]
@@ -219,8 +239,6 @@ struct SurConst {
 };
 
 hipError_t launch_sur_prepare(const SurBufs& s, hipStream_t st);
-hipError_t launch_sur_desc(const Geom& g, const Bufs& b, const SurBufs& s, const SurConst& c, int parity,
-                           int grid, hipStream_t st);
 hipError_t launch_sur_mlp(const SurBufs& s, const float* G, int64_t P, float* a, float* e, double* epart,
                           int bf16, int grid, hipStream_t st, uint16_t* a16 = nullptr);
 hipError_t launch_sur_force(const Geom& g, const Bufs& b, const SurBufs& s, const SurConst& c, int parity,
@@ -237,7 +255,15 @@ hipError_t launch_sur_adam(const SurBufs& s, int64_t t, float lr, float beta1, f
 hipError_t launch_sur_to_tag(const Geom& g, const Bufs& b, const float* src, float* dst, hipStream_t st);
 hipError_t launch_sur_from_tag(const Geom& g, const Bufs& b, const float* src, float* dst, hipStream_t st);
 hipError_t launch_sur_f_to_tag(const Geom& g, const Bufs& b, const float4* src, double* dst, hipStream_t st);
-hipError_t launch_step_ext(const StepArgs& a, const SurBufs& s, int bonded, hipStream_t st);
+// inference: descriptors (FP32 rows into s.G, or with net != 0 fused with the
+// BF16 network: s.ab rows and energy partials in s.part row 0), the BF16
+// network on given rows, and the pair force fused with bonded forces and
+// integration (the step kernel of the surrogate mode)
+hipError_t launch_sur_desc2(const Geom& g, const Bufs& b, const SurBufs& s, const SurConst& c, int parity, int net,
+                            hipStream_t st);
+hipError_t launch_sur_mlp16(const SurBufs& s, const float* G, int64_t P, float* a, float* e, hipStream_t st);
+hipError_t launch_sur_step(const StepArgs& a, const SurBufs& s, const SurConst& c, int bonded, int a_bf16,
+                           hipStream_t st);
 
 // ------------------------------------------------------------------ batches
 
@@ -280,7 +306,10 @@ hipError_t launch_clear_rebuild(const Bufs& b, hipStream_t s);
 hipError_t launch_step(const StepArgs& a, int fp64, int single_type, int bonded, int block,
                        hipStream_t s);
 int step_grid(int64_t n);
-hipError_t launch_finalize(const Bufs& b, int nblocks, int mode, const double* spart, int tensor, hipStream_t s);
+// spart: surrogate partials (row 0 energy; with spart_rows 8 also virial and
+// tensor rows), or nullptr
+hipError_t launch_finalize(const Bufs& b, int nblocks, int mode, const double* spart, int tensor, hipStream_t s,
+                           int spart_rows = 8);
 hipError_t launch_overwrite_state(const Geom& g, const Bufs& b, int parity, const double* pos,
                                   const double* vel, const int32_t* image, hipStream_t s);
 hipError_t launch_get_state(const Geom& g, const Bufs& b, int parity, double* pos, double* vel,

@@ -459,6 +459,7 @@ __device__ __forceinline__ void commit_one(const Geom& g, const Bufs& b, int64_t
     if (s == 0) {
         b.ctl->n_rebuilds += 1;
         b.ctl->nl_max = 0;
+        b.ctl->build_step = b.ctl->step;
     }
     {
         double4 p = b.xt[s];
@@ -882,6 +883,143 @@ __global__ void __launch_bounds__(kNlBlock) k_nl_tiles(Geom g, Bufs b, int parit
     nl_epilogue(b, local_max, overflow);
 }
 
+// ------------------------------------------------------------------ Lees-Edwards shear
+//
+// Flow along x, gradient along y (section "New Features": Lees-Edwards
+// boundary conditions).  The image one box above is displaced by
+// delta(step) = fmod(shear_rate Ly (step dt), Lx) and moves with
+// +shear_rate Ly along x.  Minimum image of d = r_j - r_i: dy by
+// compare-and-shift, s = +1 when dy > Ly/2 (j's nearest image lies one box
+// below: x_j - delta), -1 when dy < -Ly/2; dx = the x minimum image of
+// x_j - x_i, then for s != 0 the x minimum image of dx - s delta_w
+// (delta_w = delta folded into (-Lx/2, Lx/2]).  FP64 operations in that
+// order, so list and cutoff decisions equal any implementation doing the
+// same operations.
+
+__device__ __forceinline__ double le_delta(const Geom& g, int64_t step) {
+    double d = fmod(g.le_rate_Ly * ((double)step * g.le_dt), g.L[0]);
+    return d < 0.0 ? d + g.L[0] : d;
+}
+__device__ __forceinline__ double le_fold(const Geom& g, double d) { return d > g.hL[0] ? d - g.L[0] : d; }
+
+__device__ __forceinline__ double exact_r2_le(const Geom& g, const double4& a, const double4& b, double dw) {
+#pragma clang fp contract(off)
+    double dy = b.y - a.y;
+    int sy = 0;
+    if (dy > g.hL[1]) { dy -= g.L[1]; sy = 1; }
+    else if (dy < -g.hL[1]) { dy += g.L[1]; sy = -1; }
+    double dx = mimg(b.x - a.x, g.L[0], g.invL[0]);
+    if (sy != 0) dx = mimg(dx - sy * dw, g.L[0], g.invL[0]);
+    const double dz = mimg(b.z - a.z, g.L[2], g.invL[2]);
+    return (dx * dx + dy * dy) + dz * dz;
+}
+
+// Sign s of the sheared image from the fixed-point y coordinates: the raw
+// difference beyond half the box (2^31 units).
+__device__ __forceinline__ int le_sign_q(uint32_t qiy, uint32_t qjy) {
+    const int64_t d = (int64_t)qjy - (int64_t)qiy;
+    return d > 0x80000000LL ? 1 : (d < -0x80000000LL ? -1 : 0);
+}
+
+// Fixed-point differences r_j - r_i under the shear (qd = the offset delta in
+// units of Lx 2^-32); s as above.
+struct DiffLEQ {
+    float l0, l1, l2;
+    uint32_t qd;
+    __device__ int operator()(const int4& a, const int4& b, float& dx, float& dy, float& dz) const {
+        const int s = le_sign_q((uint32_t)a.y, (uint32_t)b.y);
+        dx = (float)(int32_t)((uint32_t)b.x - (uint32_t)a.x - (uint32_t)(s * (int64_t)qd)) * l0;
+        dy = qdiff(b.y, a.y, l1);
+        dz = qdiff(b.z, a.z, l2);
+        return s;
+    }
+};
+
+// NL(i) under the shear, one particle per lane: as nl_one, except that a
+// stencil row reached across the y boundary (s != 0) scans the x cells
+// around x_i + s delta (one cell of margin each side, the whole row when that
+// covers it).  Rows are in stencil order; sets equal the FP64 definition.
+__device__ __forceinline__ void nl_one_le(const Geom& g, const Bufs& b, int64_t i, int parity, int bonded,
+                                          double delta, double dw, uint32_t qd, int& local_max, bool& overflow) {
+    const int64_t n = g.n;
+    const double4* __restrict__ x = b.x[parity];
+    const int4* __restrict__ xq = b.xq[parity];
+    const int kc = g.kc, nx = g.nc[0];
+    const double4 xi = x[i];
+    const int4 qi = xq[i];
+    int cx, cy, cz;
+    cell_coords(g, xi.x, xi.y, xi.z, cx, cy, cz);
+    const float uy = (float)(xi.y - cy * g.h[1]);
+    const float uz = (float)(xi.z - cz * g.h[2]);
+    const DiffLEQ df{g.ql[0], g.ql[1], g.ql[2], qd};
+    int32_t* __restrict__ nlrow = b.nl + nl_base(i, g.cap);
+    int cnt = 0;
+    auto test_range = [&](int st, int en) {
+        for (int j = st; j < en; ++j) {
+            float dx, dy, dz;
+            df(qi, xq[j], dx, dy, dz);
+            const float r2 = dx * dx + dy * dy + dz * dz;
+            bool in = r2 < g.rv2lo;
+            if (!in && r2 < g.rv2hi) in = exact_r2_le(g, xi, x[j], dw) < g.rv2;
+            if (in && j != i) {
+                if (cnt < g.cap) nlrow[cnt * kTile] = j;
+                ++cnt;
+            }
+        }
+    };
+    const int32_t* __restrict__ cs = b.cstart;
+    for (int oz = -kc; oz <= kc; ++oz) {
+        const float gz = cell_gap(oz, uz, (float)g.h[2]);
+        if (gz * gz > g.rv2hi) continue;
+        const int nz = wrapc(cz + oz, g.nc[2]);
+        for (int oy = -kc; oy <= kc; ++oy) {
+            const float gy = cell_gap(oy, uy, (float)g.h[1]);
+            if (gz * gz + gy * gy > g.rv2hi) continue;
+            const int yraw = cy + oy;
+            const int s = yraw < 0 ? 1 : (yraw >= g.nc[1] ? -1 : 0);
+            const int ny = wrapc(yraw, g.nc[1]);
+            const int64_t rowc = ((int64_t)nz * g.nc[1] + ny) * nx;
+            int lo = cx - kc, hi = cx + kc;
+            if (s != 0) {
+                const double c0 = xi.x + s * delta;
+                lo = (int)floor((c0 - sqrt(g.rv2)) * g.invh[0]) - 1;
+                hi = (int)floor((c0 + sqrt(g.rv2)) * g.invh[0]) + 1;
+            }
+            if (hi - lo + 1 >= nx) {
+                test_range(cs[rowc], cs[rowc + nx]);
+                continue;
+            }
+            // [lo, hi] modulo nx: one or two contiguous ranges of cells
+            const int l = ((lo % nx) + nx) % nx;
+            const int h = l + (hi - lo);
+            if (h < nx) {
+                test_range(cs[rowc + l], cs[rowc + h + 1]);
+            } else {
+                test_range(cs[rowc + l], cs[rowc + nx]);
+                test_range(cs[rowc], cs[rowc + h - nx + 1]);
+            }
+        }
+    }
+    b.ncount[i] = cnt;
+    if (cnt > local_max) local_max = cnt;
+    if (cnt > g.cap) overflow = true;
+    const int nslot = min(((cnt + 7) & ~7), g.cap);
+    for (int k = cnt; k < nslot; ++k) nlrow[k * kTile] = (int)i;
+    if (bonded) remap_bonded(b, n, i);
+}
+
+__global__ void __launch_bounds__(kBlock) k_nl_build_le(Geom g, Bufs b, int parity, int bonded) {
+    if (!rebuild_requested(b)) return;
+    const double delta = le_delta(g, b.ctl->step);
+    const double dw = le_fold(g, delta);
+    const uint32_t qd = quantize(delta, g.qs[0]);
+    int local_max = 0;
+    bool overflow = false;
+    for (int64_t i = gtid_xcd(); i < g.n; i += gstride())
+        nl_one_le(g, b, i, parity, bonded, delta, dw, qd, local_max, overflow);
+    nl_epilogue(b, local_max, overflow);
+}
+
 __global__ void k_clear_rebuild(Bufs b) {
     if (threadIdx.x == 0 && blockIdx.x == 0) b.ctl->rebuild = 0;
 }
@@ -1007,9 +1145,16 @@ __device__ __forceinline__ void bonded_forces(const Bufs& b, const Dyn& dyn, int
 //   v_n     = v' + dt/(2m) F_tot          (v_n = v' before the first step)
 //   v_{n+h} = v_n + dt/(2m) F_tot,  x_{n+1} = x_n + dt v_{n+h}, wrapped
 // plus the half-skin displacement test against the build positions.
+// Lees-Edwards data of one step: the offset at the new positions' step and
+// the offset's change since the list was built (the rebuild criterion).
+struct LeStep {
+    double delta_next;     // delta(step + 1) in [0, Lx)
+    double drift;          // |shear_rate Ly (step + 1 - build_step) dt|
+};
+
 __device__ __forceinline__ void finish_particle(const StepArgs& a, int64_t i, const double4& xi, int tm,
                                                const double F[3], double* acc, bool& flag_reb,
-                                               bool& flag_nf) {
+                                               bool& flag_nf, const LeStep* le = nullptr) {
     const Geom& g = a.g;
     const Bufs& b = a.b;
     const int64_t n = g.n;
@@ -1038,7 +1183,43 @@ __device__ __forceinline__ void finish_particle(const StepArgs& a, int64_t i, co
         ke += von[d] * von[d];
     }
     acc[A_EKIN] += 0.5 * m * ke;
-    if (a.mode == MODE_STEP) {
+    if (a.mode == MODE_STEP && le) {
+        // sheared boundaries: crossing y = Ly (y = 0) shifts x by -delta (+delta)
+        // and v_x by -shear_rate Ly (+), before the x fold; the build position
+        // moves with the particle, so the displacement stays the physical one
+        double xn[3], vh[3];
+        for (int d = 0; d < 3; ++d) {
+            vh[d] = von[d] + hdtm * ft[d];
+            xn[d] = (d == 0 ? xi.x : d == 1 ? xi.y : xi.z) + a.dy.dt * vh[d];
+        }
+        int sc = 0;
+        if (xn[1] >= g.L[1]) { xn[1] -= g.L[1]; xn[0] -= le->delta_next; vh[0] -= g.le_rate_Ly; sc = 1; }
+        else if (xn[1] < 0.0) { xn[1] += g.L[1]; xn[0] += le->delta_next; vh[0] += g.le_rate_Ly; sc = -1; }
+        if (sc != 0) {
+            b.img[n + i] += sc;
+            b.xb[i] -= sc * le->delta_next;
+        }
+        double d2 = 0.0;
+        for (int d = 0; d < 3; ++d) {
+            if (xn[d] < 0.0 || xn[d] >= g.L[d]) {
+                int im = b.img[d * n + i];
+                if (xn[d] < 0.0) { xn[d] += g.L[d]; im -= 1; }
+                if (xn[d] >= g.L[d]) { xn[d] -= g.L[d]; im += 1; }
+                b.img[d * n + i] = im;
+            }
+            if (!isfinite(xn[d]) || !isfinite(vh[d])) flag_nf = true;
+            b.v[d * n + i] = vh[d];
+            const double dd = mimg(xn[d] - b.xb[d * n + i], g.L[d], g.invL[d]);
+            d2 += dd * dd;
+        }
+        // a pair's separation changes by at most both displacements plus the
+        // offset's change since the build: rebuild before that reaches the skin
+        if (2.0 * sqrt(d2) + le->drift >= g.skin) flag_reb = true;
+        b.x[a.parity ^ 1][i] = make_double4(xn[0], xn[1], xn[2], xi.w);
+        const int4 qn = quantize4(g, xn[0], xn[1], xn[2], xi.w);
+        b.xq[a.parity ^ 1][i] = qn;
+        if (g.x3_on) store_q3(b.x3[a.parity ^ 1], i, qn);
+    } else if (a.mode == MODE_STEP) {
         double xo[3] = {xi.x, xi.y, xi.z};
         double d2 = 0.0;
         for (int d = 0; d < 3; ++d) {
@@ -1306,7 +1487,8 @@ __device__ __forceinline__ void fast_particle(const StepArgs& a, int64_t i, doub
         float txx = 0.f, tyy = 0.f, tzz = 0.f, txy = 0.f, txz = 0.f, tyz = 0.f;
         int cnt = b.ncount[i];
         cnt = cnt < g.cap ? cnt : g.cap;
-        const int nslots = (cnt + 7) & ~7;
+        // the capacity is a multiple of 8, so the padded row stays inside it
+        const int nslots = min((cnt + 7) & ~7, g.cap);
         const int32_t* __restrict__ row = b.nl + nl_base(i, g.cap);
         // unbonded: 12-byte records (Geom::x3_on); bonded: the 16-byte ones
         const char* __restrict__ recb = BONDED ? reinterpret_cast<const char*>(xq)
@@ -1431,11 +1613,27 @@ k_step_fast_bonded(const StepArgs a) {
     step_fast_body<true, TENSOR>(a);
 }
 
-// Step with an external non-bonded force (the learned surrogate's pair
-// force, computed by its own kernels at the same positions): F = F_ext +
-// bonded terms, then the same integration and reductions.
+// theta_ij of the DPD thermostat: Philox4x64-10 keyed (seed, 6) at counter
+// (step, min id, max id, 0), Box-Muller on the first two uniforms (FP64).
+__device__ __forceinline__ double dpd_theta(uint64_t seed, uint64_t step, uint32_t ti, uint32_t tj) {
+    uint64_t x0 = step, x1 = ti < tj ? ti : tj, x2 = ti < tj ? tj : ti, x3 = 0;
+    philox4x64_10(x0, x1, x2, x3, seed, 6);
+    const double u0 = ((double)(x0 >> 11) + 0.5) * 0x1.0p-53;
+    const double u1 = ((double)(x1 >> 11) + 0.5) * 0x1.0p-53;
+    return sqrt(-2.0 * log(u0)) * cos(6.283185307179586 * u1);
+}
+
+// FP32 step with the DPD pair thermostat (MD_DPD) and / or Lees-Edwards
+// shear, one 256-particle tile per block: the pair table (any types, capping
+// radius) and the bonded terms under the sheared minimum image, the DPD
+// forces from the half-step velocities (MODE_STEP only: a thermostat force,
+// not part of md_forces), then the integration with the sheared boundary
+// crossing.  The DPD pair force on i, with e = (r_i - r_j)/r, w = 1 - r/rc_d:
+//   (-gamma w^2 (e . v_ij) + sigma w theta_ij / sqrt(dt)) e,
+// computed by both members of a pair with the same theta_ij, so the two
+// contributions cancel to FP32 rounding.
 template <bool BONDED>
-__global__ void __launch_bounds__(kBlock) k_step_ext(const StepArgs a, const float4* __restrict__ fext) {
+__global__ void __launch_bounds__(kBlock) k_step_le(const StepArgs a) {
     const Geom& g = a.g;
     const Bufs& b = a.b;
     const int64_t n = g.n;
@@ -1446,24 +1644,266 @@ __global__ void __launch_bounds__(kBlock) k_step_ext(const StepArgs a, const flo
     for (int k = 0; k < kNacc; ++k) acc[k] = 0.0;
     bool flag_reb = false, flag_bond = false, flag_nf = false;
     const bool tensor = a.tensor != 0;
-    const int64_t ntile = (n + kBlock - 1) / kBlock;
-    const int64_t bt = xcd_block(blockIdx.x, gridDim.x);
-    for (int64_t t = bt * ntile / gridDim.x; t < (bt + 1) * ntile / gridDim.x; ++t) {
-    const int64_t i = t * kBlock + threadIdx.x;
+    const int64_t step = b.ctl->step;
+    double delta = 0.0, dw = 0.0;
+    uint32_t qd = 0;
+    LeStep les{0.0, 0.0};
+    if (g.le) {
+        delta = le_delta(g, step);
+        dw = le_fold(g, delta);
+        qd = quantize(delta, g.qs[0]);
+        les.delta_next = le_delta(g, step + 1);
+        les.drift = fabs(g.le_rate_Ly * ((double)(step + 1 - b.ctl->build_step) * g.le_dt));
+    }
+    const bool dpd = a.dy.dpd && a.mode == MODE_STEP;
+    const int64_t i = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
     if (i < n) {
         const double4 xi = x64[i];
         const int4 qi = quantize4(g, xi.x, xi.y, xi.z, xi.w);
-        const float4 fe = fext[i];
-        float fx = fe.x, fy = fe.y, fz = fe.z;
+        const int ti = qi.w;
+        const DiffLEQ df{g.ql[0], g.ql[1], g.ql[2], qd};
+        float fx = 0.f, fy = 0.f, fz = 0.f, ue = 0.f, we = 0.f;
+        float txx = 0.f, tyy = 0.f, tzz = 0.f, txy = 0.f, txz = 0.f, tyz = 0.f;
+        double vi[3] = {0.0, 0.0, 0.0};
+        uint32_t tgi = 0;
+        if (dpd) {
+            for (int d = 0; d < 3; ++d) vi[d] = b.v[d * n + i];
+            tgi = (uint32_t)b.tag[i];
+        }
+        int cnt = b.ncount[i];
+        cnt = cnt < g.cap ? cnt : g.cap;
+        const int32_t* __restrict__ row = b.nl + nl_base(i, g.cap);
+        for (int k = 0; k < cnt; ++k) {
+            const int j = row[k * kTile];
+            const int4 qj = xq[j];
+            float dx, dy, dz;
+            const int s = df(qi, qj, dx, dy, dz);
+            const float r2 = dx * dx + dy * dy + dz * dz;
+            const int tp = ti * MD_MAX_TYPES + qj.w;
+            bool in = r2 < a.pt.rc2lo[tp];
+            if (!in && r2 < a.pt.rc2hi[tp]) in = exact_r2_le(g, xi, x64[j], dw) < a.pt.rc2d[tp];
+            if (in) {
+                const PairCoef<float>& c = a.pt.f[tp];
+                float fr, u;
+                if (c.cap2 > 0.f && r2 < c.cap2) {
+                    fr = c.fcap * __builtin_amdgcn_rsqf(r2);
+                    u = c.ucap;
+                } else {
+                    const float inv = __builtin_amdgcn_rcpf(r2);
+                    const float s2 = c.sig2 * inv;
+                    const float s6 = s2 * s2 * s2;
+                    fr = c.eps24 * s6 * (2.f * s6 - 1.f) * inv;
+                    u = c.eps4 * s6 * (s6 - 1.f) - c.shift;
+                }
+                fx -= fr * dx;
+                fy -= fr * dy;
+                fz -= fr * dz;
+                ue += u;
+                we += fr * r2;
+                if (tensor) {
+                    txx += fr * dx * dx; tyy += fr * dy * dy; tzz += fr * dz * dz;
+                    txy += fr * dx * dy; txz += fr * dx * dz; tyz += fr * dy * dz;
+                }
+            }
+            if (dpd && r2 < a.dy.dpd_rc2 && r2 > 0.f) {
+                const float r = sqrtf(r2);
+                const float w = 1.f - r / a.dy.dpd_rc;
+                const float ir = 1.f / r;
+                const float ex = -dx * ir, ey = -dy * ir, ez = -dz * ir;
+                // v_i - (v_j - s shear_rate Ly e_x), in FP64 then rounded once
+                const float vx = (float)(vi[0] - b.v[j] + s * g.le_rate_Ly);
+                const float vy = (float)(vi[1] - b.v[n + j]);
+                const float vz = (float)(vi[2] - b.v[2 * n + j]);
+                const float ev = ex * vx + ey * vy + ez * vz;
+                const float th = (float)dpd_theta(a.dy.seed, (uint64_t)step, tgi, (uint32_t)b.tag[j]);
+                const float A = -a.dy.dpd_gamma * w * w * ev + a.dy.dpd_sigma_isdt * w * th;
+                fx += A * ex;
+                fy += A * ey;
+                fz += A * ez;
+            }
+        }
+        acc[A_EPAIR] += 0.5 * (double)ue;
+        acc[A_VIR] += 0.5 * (double)we;
+        if (tensor) {
+            acc[A_TXX] += 0.5 * (double)txx; acc[A_TYY] += 0.5 * (double)tyy; acc[A_TZZ] += 0.5 * (double)tzz;
+            acc[A_TXY] += 0.5 * (double)txy; acc[A_TXZ] += 0.5 * (double)txz; acc[A_TYZ] += 0.5 * (double)tyz;
+        }
+        if (BONDED) {
+            const auto dfb = [&df](const int4& p, const int4& q, float& ddx, float& ddy, float& ddz) {
+                (void)df(p, q, ddx, ddy, ddz);
+            };
+            bonded_forces<float, int4>(b, a.dy, n, i, xq, qi, dfb, fx, fy, fz, acc, tensor, flag_bond);
+        }
+        const double F[3] = {(double)fx, (double)fy, (double)fz};
+        finish_particle(a, i, xi, ti, F, acc, flag_reb, flag_nf, g.le ? &les : nullptr);
+    }
+    block_epilogue(a, acc, flag_reb, flag_bond, flag_nf, tensor ? kNacc : A_VIR + 1);
+}
+
+// Step of the surrogate mode, one 256-particle tile per block: the
+// network's pair force from the per-particle input gradients a_i = dE_i/dG(i),
+//   F_i = sum_j ((a_i + a_j) . g'(r_ij)) (x_j - x_i) / r_ij  over r_ij < r_d,
+//   g'_k(r) = phi_k(r) (f_c'(r) - (r - mu_k) f_c(r) / w^2),
+// then the bonded forces, the integration and the reductions of the plain
+// step kernels.  The list row is pipelined: positions are gathered two
+// batches of B slots ahead and the a_j rows of in-range neighbours one batch
+// ahead of the pair arithmetic that uses them.  BF16 form (A16): a rows are
+// BF16; g' is rounded to BF16 pairs and dotted with a_i and a_j by
+// v_dot2_f32_bf16 with FP32 accumulation.  FP32 form: FP32 rows and FP32
+// multiply-adds.  The pair virial goes to the step's reductions; the
+// network energy comes from the network kernel's partials.
+typedef __bf16 bf16x2v __attribute__((ext_vector_type(2)));
+
+template <bool BONDED, bool TENSOR, bool A16>
+__global__ void __launch_bounds__(kBlock) k_sur_step(const StepArgs a, const SurBufs s, const SurConst c) {
+    constexpr int B = 1;                    // slots per batch (2 costs 56 more VGPRs)
+    constexpr int AW = A16 ? 16 : 32;       // 32-bit words per a row
+    const Geom& g = a.g;
+    const Bufs& b = a.b;
+    const int64_t n = g.n;
+    double acc[kNacc];
+#pragma unroll
+    for (int k = 0; k < kNacc; ++k) acc[k] = 0.0;
+    bool flag_reb = false, flag_bond = false, flag_nf = false;
+    const int64_t i = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    if (i < n) {
+        const int4* __restrict__ xq = b.xq[a.parity];
+        const double4 xi = b.x[a.parity][i];
+        const int4 qi = quantize4(g, xi.x, xi.y, xi.z, xi.w);
+        const uint32_t* __restrict__ arow = A16 ? reinterpret_cast<const uint32_t*>(s.ab)
+                                                : reinterpret_cast<const uint32_t*>(s.a);
+        uint32_t ai[AW];
+#pragma unroll
+        for (int q = 0; q < AW / 4; ++q) {
+            const uint4 v = reinterpret_cast<const uint4*>(arow + i * AW)[q];
+            ai[4 * q] = v.x; ai[4 * q + 1] = v.y; ai[4 * q + 2] = v.z; ai[4 * q + 3] = v.w;
+        }
+        int cnt = b.ncount[i];
+        cnt = cnt < g.cap ? cnt : g.cap;
+        const int nslots = min((cnt + 7) & ~7, g.cap);
+        const int32_t* __restrict__ row = b.nl + nl_base(i, g.cap);
+        const int last = nslots > 0 ? nslots - 1 : 0;
+        float fx = 0.f, fy = 0.f, fz = 0.f, wv = 0.f;
+        float txx = 0.f, tyy = 0.f, tzz = 0.f, txy = 0.f, txz = 0.f, tyz = 0.f;
+        auto idx = [&](int slot) { return row[(slot < last ? slot : last) * kTile]; };
+        auto geom = [&](const int4& qj, float& dx, float& dy, float& dz) {
+            dx = qdiff(qj.x, qi.x, g.ql[0]);
+            dy = qdiff(qj.y, qi.y, g.ql[1]);
+            dz = qdiff(qj.z, qi.z, g.ql[2]);
+            return dx * dx + dy * dy + dz * dz;
+        };
+        auto load_row = [&](int j, uint32_t* out) {
+#pragma unroll
+            for (int q = 0; q < AW / 4; ++q) {
+                const uint4 v = reinterpret_cast<const uint4*>(arow + (int64_t)j * AW)[q];
+                out[4 * q] = v.x; out[4 * q + 1] = v.y; out[4 * q + 2] = v.z; out[4 * q + 3] = v.w;
+            }
+        };
+        auto pair = [&](const int4& qj, const uint32_t* aj) {
+            float dx, dy, dz;
+            const float r2 = geom(qj, dx, dy, dz);
+            const float r = sqrtf(r2);
+            float dfc;
+            const float fc = sur_cutoff(c, r, dfc);
+            float ph[kSurNB];
+            sur_basis(c, r, ph);
+            const float Bc = c.inv_w2 * fc;
+            float cij = 0.f;
+            if (A16) {
+#pragma unroll
+                for (int k2 = 0; k2 < kSurNB / 2; ++k2) {
+                    const float g0 = ph[2 * k2] * fmaf(-(r - c.mu[2 * k2]), Bc, dfc);
+                    const float g1 = ph[2 * k2 + 1] * fmaf(-(r - c.mu[2 * k2 + 1]), Bc, dfc);
+                    const bf16x2v gp = {(__bf16)g0, (__bf16)g1};
+                    cij = __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2v, ai[k2]), gp, cij, false);
+                    cij = __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2v, aj[k2]), gp, cij, false);
+                }
+            } else {
+#pragma unroll
+                for (int k = 0; k < kSurNB; ++k) {
+                    const float dg = ph[k] * fmaf(-(r - c.mu[k]), Bc, dfc);
+                    cij = fmaf(__uint_as_float(ai[k]) + __uint_as_float(aj[k]), dg, cij);
+                }
+            }
+            const float sc = cij / r;
+            fx += sc * dx;
+            fy += sc * dy;
+            fz += sc * dz;
+            wv -= cij * r;
+            if (TENSOR) {
+                // r_ij f_ij with r_ij = -(dx, dy, dz), f_ij = sc (dx, dy, dz)
+                txx -= sc * dx * dx; tyy -= sc * dy * dy; tzz -= sc * dz * dz;
+                txy -= sc * dx * dy; txz -= sc * dx * dz; tyz -= sc * dy * dz;
+            }
+        };
+        auto in_range = [&](const int4& qj) {
+            float dx, dy, dz;
+            const float r2 = geom(qj, dx, dy, dz);
+            return r2 < c.rd2 && r2 > 0.f;   // r2 = 0: the row's padding (the particle itself)
+        };
+        if (nslots > 0) {
+            // batch b: jA/qA/inA/aA; batch b+1: jB/qB (positions in flight); b+2: jC
+            int jA[B], jB[B], jC[B];
+            int4 qA[B], qB[B];
+            bool inA[B];
+            uint32_t aA[B][AW], aB[B][AW];
+#pragma unroll
+            for (int u = 0; u < B; ++u) {
+                jA[u] = idx(u);
+                jB[u] = idx(B + u);
+                jC[u] = idx(2 * B + u);
+            }
+#pragma unroll
+            for (int u = 0; u < B; ++u) qA[u] = xq[jA[u]];
+#pragma unroll
+            for (int u = 0; u < B; ++u) qB[u] = xq[jB[u]];
+#pragma unroll
+            for (int u = 0; u < B; ++u) {
+                inA[u] = in_range(qA[u]);   // slots 0 .. B-1 < nslots
+                if (inA[u]) load_row(jA[u], aA[u]);
+            }
+            for (int k0 = 0; k0 < nslots; k0 += B) {
+                bool inB[B];
+#pragma unroll
+                for (int u = 0; u < B; ++u) {
+                    inB[u] = k0 + B + u < nslots && in_range(qB[u]);
+                    if (inB[u]) load_row(jB[u], aB[u]);
+                }
+                int4 qC[B];
+                int jD[B];
+#pragma unroll
+                for (int u = 0; u < B; ++u) {
+                    qC[u] = xq[jC[u]];
+                    jD[u] = idx(k0 + 3 * B + u);
+                }
+#pragma unroll
+                for (int u = 0; u < B; ++u)
+                    if (inA[u]) pair(qA[u], aA[u]);
+#pragma unroll
+                for (int u = 0; u < B; ++u) {
+                    qA[u] = qB[u];
+                    inA[u] = inB[u];
+#pragma unroll
+                    for (int w = 0; w < AW; ++w) aA[u][w] = aB[u][w];
+                    jB[u] = jC[u];
+                    qB[u] = qC[u];
+                    jC[u] = jD[u];
+                }
+            }
+        }
+        acc[A_VIR] += 0.5 * (double)wv;
+        if (TENSOR) {
+            acc[A_TXX] += 0.5 * (double)txx; acc[A_TYY] += 0.5 * (double)tyy; acc[A_TZZ] += 0.5 * (double)tzz;
+            acc[A_TXY] += 0.5 * (double)txy; acc[A_TXZ] += 0.5 * (double)txz; acc[A_TYZ] += 0.5 * (double)tyz;
+        }
         if (BONDED) {
             const DiffQ df{g.ql[0], g.ql[1], g.ql[2]};
-            bonded_forces<float, int4, DiffQ>(b, a.dy, n, i, xq, qi, df, fx, fy, fz, acc, tensor, flag_bond);
+            bonded_forces<float, int4, DiffQ>(b, a.dy, n, i, xq, qi, df, fx, fy, fz, acc, TENSOR, flag_bond);
         }
         const double F[3] = {(double)fx, (double)fy, (double)fz};
         finish_particle(a, i, xi, (int)xi.w, F, acc, flag_reb, flag_nf);
     }
-    }
-    block_epilogue(a, acc, flag_reb, flag_bond, flag_nf, tensor ? kNacc : A_VIR + 1);
+    block_epilogue(a, acc, flag_reb, flag_bond, flag_nf, TENSOR ? kNacc : A_VIR + 1);
 }
 
 // One block: reduce partials[k][block] in a fixed order, record the step's
@@ -1472,7 +1912,8 @@ __global__ void __launch_bounds__(kBlock) k_step_ext(const StepArgs a, const flo
 constexpr int kFinal = 1024;
 // nacc: the number of quantities the step kernel accumulated (the virial
 // tensor only when it was asked for); the others are zero and not read.
-__device__ __forceinline__ void finalize_body(const Bufs& b, int nblocks, int mode, const double* spart, int nacc) {
+__device__ __forceinline__ void finalize_body(const Bufs& b, int nblocks, int mode, const double* spart, int nacc,
+                                              int spart_rows = 8) {
     __shared__ double red[kFinal / 64][kNacc];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     double s[kNacc];
@@ -1497,9 +1938,11 @@ __device__ __forceinline__ void finalize_body(const Bufs& b, int nblocks, int mo
                 const int blk = blk0 + r * kFinal + threadIdx.x;
                 if (blk >= nblocks) continue;
                 s[A_EPAIR] += spart[blk];
-                s[A_VIR] += spart[(int64_t)nblocks + blk];
-                if (nacc == kNacc)
-                    for (int k = 0; k < 6; ++k) s[A_TXX + k] += spart[(int64_t)(2 + k) * nblocks + blk];
+                if (spart_rows > 1) {
+                    s[A_VIR] += spart[(int64_t)nblocks + blk];
+                    if (nacc == kNacc)
+                        for (int k = 0; k < 6; ++k) s[A_TXX + k] += spart[(int64_t)(2 + k) * nblocks + blk];
+                }
             }
         }
     }
@@ -1549,8 +1992,9 @@ __device__ __forceinline__ void finalize_body(const Bufs& b, int nblocks, int mo
     }
 }
 
-__global__ void __launch_bounds__(kFinal) k_finalize(Bufs b, int nblocks, int mode, const double* spart, int nacc) {
-    finalize_body(b, nblocks, mode, spart, nacc);
+__global__ void __launch_bounds__(kFinal) k_finalize(Bufs b, int nblocks, int mode, const double* spart, int nacc,
+                                                     int spart_rows) {
+    finalize_body(b, nblocks, mode, spart, nacc, spart_rows);
 }
 
 // ------------------------------------------------------------------ batches
@@ -1776,7 +2220,9 @@ hipError_t launch_rebuild(const Geom& g, const Bufs& b, int parity, int bonded, 
     hipLaunchKernelGGL(k_scatter, dim3(gs), dim3(kBlock), 0, s, g, b);
     hipLaunchKernelGGL(k_rank_permute, dim3(gs), dim3(kBlock), 0, s, g, b, parity);
     hipLaunchKernelGGL(k_commit, dim3(gs), dim3(kBlock), 0, s, g, b, parity, bonded);
-    if (g.nl_tile)
+    if (g.le)
+        hipLaunchKernelGGL(k_nl_build_le, dim3(grid_for(g.n, 1 << 20)), dim3(kBlock), 0, s, g, b, parity, bonded);
+    else if (g.nl_tile)
         hipLaunchKernelGGL(k_nl_tiles, dim3((unsigned)((g.n + kNlBlock - 1) / kNlBlock)), dim3(kNlBlock), 0, s, g, b,
                            parity, bonded);
     else
@@ -1788,7 +2234,10 @@ hipError_t launch_rebuild(const Geom& g, const Bufs& b, int parity, int bonded, 
 hipError_t launch_step(const StepArgs& a, int fp64, int single_type, int bonded, int block, hipStream_t s) {
     (void)block;
     dim3 grid((unsigned)step_grid(a.g.n)), blk(kBlock);
-    if (fp64) {
+    if (a.g.le || a.dy.dpd) {
+        if (bonded) hipLaunchKernelGGL(k_step_le<true>, grid, blk, 0, s, a);
+        else hipLaunchKernelGGL(k_step_le<false>, grid, blk, 0, s, a);
+    } else if (fp64) {
 #define MD_L64(S, B) hipLaunchKernelGGL((k_step64<S, B>), grid, blk, 0, s, a)
         if (single_type) { if (bonded) MD_L64(true, true); else MD_L64(true, false); }
         else { if (bonded) MD_L64(false, true); else MD_L64(false, false); }
@@ -1817,17 +2266,26 @@ hipError_t launch_step(const StepArgs& a, int fp64, int single_type, int bonded,
     return hipGetLastError();
 }
 
-hipError_t launch_finalize(const Bufs& b, int nblocks, int mode, const double* spart, int tensor, hipStream_t s) {
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kFinal), 0, s, b, nblocks, mode, spart, tensor ? kNacc : A_VIR + 1);
+hipError_t launch_finalize(const Bufs& b, int nblocks, int mode, const double* spart, int tensor, hipStream_t s,
+                           int spart_rows) {
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kFinal), 0, s, b, nblocks, mode, spart, tensor ? kNacc : A_VIR + 1,
+                       spart_rows);
     return hipGetLastError();
 }
 
-hipError_t launch_step_ext(const StepArgs& a, const SurBufs& sb, int bonded, hipStream_t s) {
+hipError_t launch_sur_step(const StepArgs& a, const SurBufs& sb, const SurConst& c, int bonded, int a_bf16,
+                           hipStream_t s) {
     dim3 grid((unsigned)step_grid(a.g.n)), blk(kBlock);
-    if (bonded)
-        hipLaunchKernelGGL(k_step_ext<true>, grid, blk, 0, s, a, sb.f);
-    else
-        hipLaunchKernelGGL(k_step_ext<false>, grid, blk, 0, s, a, sb.f);
+    const bool t = a.tensor != 0;
+#define MD_LS(BO, T, A) hipLaunchKernelGGL((k_sur_step<BO, T, A>), grid, blk, 0, s, a, sb, c)
+    if (a_bf16) {
+        if (bonded) { if (t) MD_LS(true, true, true); else MD_LS(true, false, true); }
+        else { if (t) MD_LS(false, true, true); else MD_LS(false, false, true); }
+    } else {
+        if (bonded) { if (t) MD_LS(true, true, false); else MD_LS(true, false, false); }
+        else { if (t) MD_LS(false, true, false); else MD_LS(false, false, false); }
+    }
+#undef MD_LS
     return hipGetLastError();
 }
 

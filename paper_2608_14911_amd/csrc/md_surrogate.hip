@@ -26,89 +26,19 @@ constexpr int kSB = 256;          // threads per block of the network kernels
 constexpr int kSA32 = 36;         // LDS row stride of 32-wide activations (floats)
 constexpr int kSA64 = 68;         // LDS row stride of 64-wide activations
 
-// FP32 -> BF16, round to nearest even (NaN stays NaN).
-__device__ __forceinline__ short bf16_rne(float f) {
-    uint32_t u = __float_as_uint(f);
-    if ((u & 0x7f800000u) == 0x7f800000u) return (short)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return (short)(u >> 16);
+// Matrix-core network (see "inference on the matrix cores" below): the
+// feature of K slot s in its 32-wide block, and its inverse.
+__host__ __device__ constexpr int slot_feature(int s) {
+    return (s & 7) < 4 ? 4 * (s >> 3) + (s & 7) : 16 + 4 * (s >> 3) + (s & 7) - 4;
 }
+__host__ __device__ constexpr int feature_slot(int k) {
+    return k < 16 ? 8 * (k >> 2) + (k & 3) : 8 * ((k - 16) >> 2) + 4 + ((k - 16) & 3);
+}
+static_assert(feature_slot(slot_feature(13)) == 13 && slot_feature(feature_slot(21)) == 21 &&
+                  slot_feature(4) == 16 && feature_slot(31) == 31,
+              "slot permutation");
 
 __device__ __forceinline__ float sigm(float z) { return __builtin_amdgcn_rcpf(1.f + __expf(-z)); }
-
-// ------------------------------------------------------------------ basis
-
-// f_c(r) = (cos(pi r / r_d) + 1) / 2 and its derivative.
-__device__ __forceinline__ float cutoff_fn(const SurConst& c, float r, float& dfc) {
-    // argument in [0, pi]: the hardware sine / cosine are accurate to a few
-    // 1e-7 there
-    float sn, cs;
-    __sincosf(c.pi_rd * r, &sn, &cs);
-    dfc = -0.5f * c.pi_rd * sn;
-    return 0.5f * (cs + 1.f);
-}
-
-// phi_k(r) = exp(-(r - mu_k)^2 / (2 w^2)) for k = 0..31 by two-sided
-// recurrences from pivots k = 8 and 24: with t = r - mu_p,
-//   phi_{p+1} / phi_p = exp2(c (2 D t - D^2)),  phi_{p-1} / phi_p = exp2(c (-2 D t - D^2)),
-// and each further ratio is the previous one times exp2(-2 c D^2)
-// (c = log2(e) / (2 w^2), D the centre spacing): 6 exponentials per pair
-// instead of 32, chains of at most 8 products.
-__device__ __forceinline__ void gauss_basis(const SurConst& c, float r, float* phi) {
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-        const int p = 8 + 16 * h;
-        const float t = r - c.mu[p];
-        phi[p] = __builtin_amdgcn_exp2f(-c.c_exp * t * t);
-        float up = __builtin_amdgcn_exp2f(c.c_exp * (2.f * c.dmu * t - c.dmu * c.dmu));
-        float dn = __builtin_amdgcn_exp2f(c.c_exp * (-2.f * c.dmu * t - c.dmu * c.dmu));
-#pragma unroll
-        for (int m = 1; m <= 8; ++m) {
-            phi[p - m] = phi[p - m + 1] * dn;
-            dn *= c.ratio;
-            if (m <= 7) {
-                phi[p + m] = phi[p + m - 1] * up;
-                up *= c.ratio;
-            }
-        }
-    }
-}
-
-// ------------------------------------------------------------------ descriptor
-
-// G_k(i) = sum over list neighbours j with r_ij < r_d of phi_k(r) f_c(r).
-__global__ void __launch_bounds__(kBlock) k_sur_desc(Geom g, Bufs b, SurBufs s, SurConst c, int parity) {
-    const int64_t n = g.n;
-    const int4* __restrict__ xq = b.xq[parity];
-    for (int64_t i = gtid_xcd(); i < n; i += gstride()) {
-        const int4 qi = xq[i];
-        int cnt = b.ncount[i];
-        cnt = cnt < g.cap ? cnt : g.cap;
-        const int32_t* __restrict__ row = b.nl + nl_base(i, g.cap);
-        float G[kSurNB];
-#pragma unroll
-        for (int k = 0; k < kSurNB; ++k) G[k] = 0.f;
-        for (int k = 0; k < cnt; ++k) {
-            const int4 qj = xq[row[k * kTile]];
-            const float dx = qdiff(qj.x, qi.x, g.ql[0]);
-            const float dy = qdiff(qj.y, qi.y, g.ql[1]);
-            const float dz = qdiff(qj.z, qi.z, g.ql[2]);
-            const float r2 = dx * dx + dy * dy + dz * dz;
-            if (r2 < c.rd2 && r2 > 0.f) {
-                const float r = sqrtf(r2);
-                float dfc;
-                const float fc = cutoff_fn(c, r, dfc);
-                float ph[kSurNB];
-                gauss_basis(c, r, ph);
-#pragma unroll
-                for (int q = 0; q < kSurNB; ++q) G[q] += ph[q] * fc;
-            }
-        }
-        float4* out = reinterpret_cast<float4*>(s.G + i * kSurNB);
-#pragma unroll
-        for (int q = 0; q < kSurNB / 4; ++q) out[q] = make_float4(G[4 * q], G[4 * q + 1], G[4 * q + 2], G[4 * q + 3]);
-    }
-}
 
 // ------------------------------------------------------------------ block sums
 
@@ -136,7 +66,6 @@ __device__ __forceinline__ void block_store(const double* v, double* part) {
 // Inference: F into s.f, per-block virial (and tensor) partials into
 // s.part rows 1..7.  Training: delta_i = (2/M) (F_i - F_ref) into s.delta
 // and the squared residual into s.part row 8.
-__device__ __forceinline__ float bf16_to_f32(uint32_t h) { return __uint_as_float(h << 16); }
 
 // Row of 32 input gradients: FP32, or BF16 (A16).
 template <bool A16>
@@ -191,11 +120,11 @@ __global__ void __launch_bounds__(kBlock) k_sur_force(Geom g, Bufs b, SurBufs s,
             if (r2 < c.rd2 && r2 > 0.f) {
                 const float r = sqrtf(r2);
                 float dfc;
-                const float fc = cutoff_fn(c, r, dfc);
+                const float fc = sur_cutoff(c, r, dfc);
                 float av[kSurNB];
                 load_a<A16>(s, j, av);
                 float ph[kSurNB];
-                gauss_basis(c, r, ph);
+                sur_basis(c, r, ph);
                 // g'_k = phi_k (f_c' - (r - mu_k) f_c / w^2): one subtract, two
                 // fused multiply-adds and a multiply per basis function
                 const float B = c.inv_w2 * fc;
@@ -265,11 +194,11 @@ __global__ void __launch_bounds__(kBlock) k_sur_u(Geom g, Bufs b, SurBufs s, Sur
             if (r2 < c.rd2 && r2 > 0.f) {
                 const float r = sqrtf(r2);
                 float dfc;
-                const float fc = cutoff_fn(c, r, dfc);
+                const float fc = sur_cutoff(c, r, dfc);
                 const float4 dj = s.delta[j];
                 const float proj = ((di.x - dj.x) * dx + (di.y - dj.y) * dy + (di.z - dj.z) * dz) / r;
                 float ph[kSurNB];
-                gauss_basis(c, r, ph);
+                sur_basis(c, r, ph);
                 const float B = c.inv_w2 * fc;
 #pragma unroll
                 for (int q = 0; q < kSurNB; ++q) {
@@ -738,6 +667,19 @@ __global__ void __launch_bounds__(kBlock) k_sur_prepare(SurBufs s) {
             s.wb[kQW1 + r * kSW1 + c] = (uint16_t)bf16_rne(w1);
             s.wb[kQW1T + c * kSW64 + r] = (uint16_t)bf16_rne(w1);
         }
+        // matrix-core images, K axis in slot order: W1 [64][K=32], W2 [64][K=64],
+        // W2^T [64 (h1)][K=64 (h2)], W1^T [32 (input)][K=64 (h1)]
+        {
+            const int kb = c >> 5, sl = 32 * kb + feature_slot(c & 31);
+            s.wm[kM2 + r * kMS64 + sl] = (uint16_t)bf16_rne(w2);
+            const int kbr = r >> 5, slr = 32 * kbr + feature_slot(r & 31);
+            s.wm[kM2T + c * kMS64 + slr] = (uint16_t)bf16_rne(w2);          // W2^T[c][r] = W2[r][c]
+            if (c < 32) {
+                const float w1 = w[kOW1 + r * 32 + c];
+                s.wm[kM1 + r * kMS1 + feature_slot(c)] = (uint16_t)bf16_rne(w1);
+                s.wm[kM1T + c * kMS64 + slr] = (uint16_t)bf16_rne(w1);      // W1^T[c][r] = W1[r][c]
+            }
+        }
         if (r == 0) {
             s.wp[kPB1 + c] = w[kOB1 + c];
             s.wp[kPB2 + c] = w[kOB2 + c];
@@ -777,6 +719,291 @@ __global__ void __launch_bounds__(kBlock) k_sur_f_to_tag(Geom g, Bufs b, const f
     }
 }
 
+
+// ------------------------------------------------------------------ inference on the matrix cores
+//
+// The BF16 network on v_mfma_f32_16x16x32_bf16, weights as the A operand
+// (16 output features x 32 inputs), 16 particles as the B operand
+// (32 inputs x 16 particles).  Lane l of a wavefront holds, with
+// q = l >> 4 and n = l & 15: A[n][8q + j] and B[8q + j][n] (j = 0..7) and
+// the accumulator D[4q + e][n] (e = 0..3).  A layer's outputs therefore sit
+// in lane group q as rows 4q..4q+3 of each 16-row block.  The K axis of every
+// weight image is stored in "slot order": in a 32-wide K block, slot
+// 8q + j stands for feature 4q + j (j < 4) or 16 + 4q + (j - 4) (j >= 4) of
+// the block, which is exactly what lane group q holds of two consecutive
+// 16-row output blocks.  One layer's activations thus feed the next layer's
+// B operand from registers, with no LDS round trip or lane exchange.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+
+constexpr int kXS = 40;          // LDS row stride (bf16) of the per-wave input / output rows
+
+// LDS image of the matrix-core weights and the FP32 biases b1, b2, w3, b3.
+struct MImage {
+    alignas(16) uint16_t w[kPrepM];
+    alignas(16) float bb[196];
+    __device__ void load(const SurBufs& s) {
+        const uint4* src = reinterpret_cast<const uint4*>(s.wm);
+        uint4* dst = reinterpret_cast<uint4*>(w);
+        for (int k = threadIdx.x; k < kPrepM / 8; k += blockDim.x) dst[k] = src[k];
+        for (int k = threadIdx.x; k < 193; k += blockDim.x) bb[k] = s.wp[kPB1 + k];
+    }
+};
+
+__device__ __forceinline__ bf16x8 lds_op(const uint16_t* p) { return *reinterpret_cast<const bf16x8*>(p); }
+
+// The network on the 64 particles of one wavefront, in 4 groups of 16.  xs:
+// the wave's 64 LDS rows (stride kXS) of standardised inputs in slot order,
+// rounded to BF16.  For group g, emit(g, E, a) receives, in every lane, the
+// particle's energy E (lane n: particle 16g + n) and a[mb][e] = dE/dx for
+// input feature 16 mb + 4q + e.  Activations are rounded to BF16 as matrix
+// operands; sums, biases, SiLU and its derivative are FP32.
+//   z1 = W1 x + b1, h1 = silu(z1), z2 = W2 h1 + b2, E = w3 . silu(z2) + b3,
+//   gz2 = w3 silu'(z2), gz1 = (W2^T gz2) silu'(z1), dE/dx = W1^T gz1.
+template <typename Emit>
+__device__ __forceinline__ void net16_wave(const MImage& wi, const uint16_t* __restrict__ xs, Emit emit) {
+    const int lane = threadIdx.x & 63, q = lane >> 4, n = lane & 15;
+    const float* b1 = wi.bb;
+    const float* b2 = wi.bb + 64;
+    const float* w3 = wi.bb + 128;
+    const float b3 = wi.bb[192];
+    const uint16_t* W1 = wi.w + kM1;
+    const uint16_t* W2 = wi.w + kM2;
+    const uint16_t* W2T = wi.w + kM2T;
+    const uint16_t* W1T = wi.w + kM1T;
+#pragma unroll 1
+    for (int g = 0; g < 4; ++g) {
+        const bf16x8 x = lds_op(xs + (16 * g + n) * kXS + 8 * q);
+        f32x4 z[4];
+#pragma unroll
+        for (int mb = 0; mb < 4; ++mb) {
+            const f32x4 zero = {0.f, 0.f, 0.f, 0.f};
+            z[mb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(lds_op(W1 + (16 * mb + n) * kMS1 + 8 * q), x, zero, 0, 0,
+                                                             0);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        float s1[16];
+        bf16x8 h[2];
+#pragma unroll
+        for (int mb = 0; mb < 4; ++mb) {
+            const float4 bv = *reinterpret_cast<const float4*>(b1 + 16 * mb + 4 * q);
+            const float bs[4] = {bv.x, bv.y, bv.z, bv.w};
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const float zz = z[mb][e] + bs[e];
+                const float sg = sigm(zz);
+                s1[4 * mb + e] = sg * (1.f + zz * (1.f - sg));
+                h[mb >> 1][4 * (mb & 1) + e] = (__bf16)(zz * sg);
+            }
+        }
+#pragma unroll
+        for (int mb = 0; mb < 4; ++mb) {
+            f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int kb = 0; kb < 2; ++kb)
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(lds_op(W2 + (16 * mb + n) * kMS64 + 32 * kb + 8 * q),
+                                                              h[kb], acc, 0, 0, 0);
+            z[mb] = acc;
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        float en = 0.f;
+        bf16x8 gz[2];
+#pragma unroll
+        for (int mb = 0; mb < 4; ++mb) {
+            const float4 bv = *reinterpret_cast<const float4*>(b2 + 16 * mb + 4 * q);
+            const float4 wv = *reinterpret_cast<const float4*>(w3 + 16 * mb + 4 * q);
+            const float bs[4] = {bv.x, bv.y, bv.z, bv.w}, ws[4] = {wv.x, wv.y, wv.z, wv.w};
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const float zz = z[mb][e] + bs[e];
+                const float sg = sigm(zz);
+                en += ws[e] * zz * sg;
+                gz[mb >> 1][4 * (mb & 1) + e] = (__bf16)(ws[e] * sg * (1.f + zz * (1.f - sg)));
+            }
+        }
+        en += __shfl_xor(en, 16, 64);
+        en += __shfl_xor(en, 32, 64);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int mb = 0; mb < 4; ++mb) {
+            f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int kb = 0; kb < 2; ++kb)
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(lds_op(W2T + (16 * mb + n) * kMS64 + 32 * kb + 8 * q),
+                                                              gz[kb], acc, 0, 0, 0);
+            z[mb] = acc;
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        bf16x8 g1[2];
+#pragma unroll
+        for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) g1[mb >> 1][4 * (mb & 1) + e] = (__bf16)(z[mb][e] * s1[4 * mb + e]);
+        f32x4 a[2];
+#pragma unroll
+        for (int mb = 0; mb < 2; ++mb) {
+            f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int kb = 0; kb < 2; ++kb)
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(lds_op(W1T + (16 * mb + n) * kMS64 + 32 * kb + 8 * q),
+                                                              g1[kb], acc, 0, 0, 0);
+            a[mb] = acc;
+        }
+        emit(g, en + b3, a);
+    }
+}
+
+// Standardise a descriptor row (FP32, natural order) into the lane's LDS row
+// in slot order, rounded to BF16; rows of absent particles are zero.
+__device__ __forceinline__ void put_x_row(const float* G, const float* __restrict__ gmean,
+                                          const float* __restrict__ gistd, bool ok, uint16_t* row) {
+#pragma unroll
+    for (int s8 = 0; s8 < 4; ++s8) {
+        bf16x8 v;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int k = slot_feature(8 * s8 + j);
+            v[j] = (__bf16)(ok ? (G[k] - gmean[k]) * gistd[k] : 0.f);
+        }
+        *reinterpret_cast<bf16x8*>(row + 8 * s8) = v;
+    }
+}
+
+// Descriptor G(i) of one particle (FP32): its list row streamed in batches
+// of 4 slots, the next batch's indices loaded before this batch's position
+// gathers are used.  Rows are padded to a multiple of 8 slots with the
+// particle itself (r = 0, skipped).
+__device__ __forceinline__ void desc_row(const Geom& g, const Bufs& b, const SurConst& c, const int4* __restrict__ xq,
+                                         int64_t i, float* G) {
+    const int4 qi = xq[i];
+    int cnt = b.ncount[i];
+    cnt = cnt < g.cap ? cnt : g.cap;
+    const int nslots = min((cnt + 7) & ~7, g.cap);
+    const int32_t* __restrict__ row = b.nl + nl_base(i, g.cap);
+#pragma unroll
+    for (int k = 0; k < kSurNB; ++k) G[k] = 0.f;
+    constexpr int B = 4;
+    const int last = nslots > 0 ? nslots - 1 : 0;
+    int jn[B];
+#pragma unroll
+    for (int u = 0; u < B; ++u) jn[u] = row[(u < last ? u : last) * kTile];
+    for (int k0 = 0; k0 < nslots; k0 += B) {
+        int4 qj[B];
+#pragma unroll
+        for (int u = 0; u < B; ++u) qj[u] = xq[jn[u]];
+#pragma unroll
+        for (int u = 0; u < B; ++u) {
+            const int kk = k0 + B + u;
+            jn[u] = row[(kk < last ? kk : last) * kTile];
+        }
+#pragma unroll
+        for (int u = 0; u < B; ++u) {
+            const float dx = qdiff(qj[u].x, qi.x, g.ql[0]);
+            const float dy = qdiff(qj[u].y, qi.y, g.ql[1]);
+            const float dz = qdiff(qj[u].z, qi.z, g.ql[2]);
+            const float r2 = dx * dx + dy * dy + dz * dz;
+            if (r2 < c.rd2 && r2 > 0.f) {
+                const float r = sqrtf(r2);
+                float dfc;
+                const float fc = sur_cutoff(c, r, dfc);
+                float ph[kSurNB];
+                sur_basis(c, r, ph);
+#pragma unroll
+                for (int k = 0; k < kSurNB; ++k) G[k] = fmaf(ph[k], fc, G[k]);
+            }
+        }
+    }
+}
+
+// Descriptors of one 256-particle tile per block (XCD-aware block order).
+// NET = false: the FP32 rows go to s.G.  NET = true: each wavefront runs the
+// BF16 network on its 64 particles straight from registers and LDS, writes
+// the BF16 input gradients a_i to s.ab and the block's energy sum to
+// s.part row 0; the descriptors never reach HBM.
+template <bool NET>
+__global__ void __launch_bounds__(kBlock) k_sur_desc2(Geom g, Bufs b, SurBufs s, SurConst c, int parity) {
+    const int64_t n = g.n;
+    const int64_t tile = xcd_block(blockIdx.x, gridDim.x);
+    const int64_t i = tile * kBlock + threadIdx.x;
+    const bool ok = i < n;
+    float G[kSurNB];
+    if (!NET) {
+        if (ok) {
+            desc_row(g, b, c, b.xq[parity], i, G);
+            float4* out = reinterpret_cast<float4*>(s.G + i * kSurNB);
+#pragma unroll
+            for (int q = 0; q < kSurNB / 4; ++q) out[q] = make_float4(G[4 * q], G[4 * q + 1], G[4 * q + 2], G[4 * q + 3]);
+        }
+        return;
+    }
+    __shared__ MImage wi;
+    __shared__ __attribute__((aligned(16))) uint16_t xs[kBlock / 64][64 * kXS];
+    __shared__ float es[kBlock / 64][64];
+    wi.load(s);
+    if (ok) desc_row(g, b, c, b.xq[parity], i, G);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, q = lane >> 4, nn = lane & 15;
+    uint16_t* xw = xs[w];
+    put_x_row(G, s.gmean, s.gistd, ok, xw + lane * kXS);
+    __syncthreads();   // weight image and input rows complete
+    net16_wave(wi, xw, [&](int gi, float e, const f32x4* a) {
+        // the group's rows were read by its first product: reuse them for
+        // dE/dG = (dE/dx) istd in natural feature order
+        uint16_t* orow = xw + (16 * gi + nn) * kXS;
+#pragma unroll
+        for (int mb = 0; mb < 2; ++mb) {
+            const int k0 = 16 * mb + 4 * q;
+            const float4 is = *reinterpret_cast<const float4*>(s.gistd + k0);
+            const uint32_t lo = (uint16_t)bf16_rne(a[mb][0] * is.x) | ((uint32_t)(uint16_t)bf16_rne(a[mb][1] * is.y) << 16);
+            const uint32_t hi = (uint16_t)bf16_rne(a[mb][2] * is.z) | ((uint32_t)(uint16_t)bf16_rne(a[mb][3] * is.w) << 16);
+            *reinterpret_cast<uint2*>(orow + k0) = make_uint2(lo, hi);
+        }
+        if (q == 0) es[w][16 * gi + nn] = e;
+    });
+    __syncthreads();   // output rows complete
+    // the wave's 64 consecutive particles: 4 KB of contiguous BF16 rows
+    const int64_t base = tile * kBlock + 64 * w;
+#pragma unroll
+    for (int cch = 0; cch < 4; ++cch) {
+        const int idx = 64 * cch + lane, r = idx >> 2, part = idx & 3;
+        if (base + r < n)
+            *reinterpret_cast<uint4*>(s.ab + (base + r) * kSurNB + 8 * part) =
+                *reinterpret_cast<const uint4*>(xw + r * kXS + 8 * part);
+    }
+    double esum = ok ? (double)es[w][lane] : 0.0;
+    block_store<1>(&esum, s.part);
+}
+
+// The BF16 network on given descriptor rows G [P][32] (raw; the handle's
+// standardisation is applied): energies e [P] (may be null) and FP32 input
+// gradients a [P][32].  One wavefront per 64 rows.
+__global__ void __launch_bounds__(kBlock) k_sur_mlp16(SurBufs s, const float* __restrict__ G, int64_t P,
+                                                     float* __restrict__ aout, float* __restrict__ eout) {
+    __shared__ MImage wi;
+    __shared__ __attribute__((aligned(16))) uint16_t xs[kBlock / 64][64 * kXS];
+    wi.load(s);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, q = lane >> 4, nn = lane & 15;
+    const int64_t base = (int64_t)blockIdx.x * kBlock + 64 * w;
+    const bool ok = base + lane < P;
+    float Gr[kSurNB];
+#pragma unroll
+    for (int k = 0; k < kSurNB; ++k) Gr[k] = ok ? G[(base + lane) * kSurNB + k] : 0.f;
+    put_x_row(Gr, s.gmean, s.gistd, ok, xs[w] + lane * kXS);
+    __syncthreads();
+    net16_wave(wi, xs[w], [&](int gi, float e, const f32x4* a) {
+        const int64_t p = base + 16 * gi + nn;
+        if (p >= P) return;
+#pragma unroll
+        for (int mb = 0; mb < 2; ++mb) {
+            const int k0 = 16 * mb + 4 * q;
+            const float4 is = *reinterpret_cast<const float4*>(s.gistd + k0);
+            *reinterpret_cast<float4*>(aout + p * kSurNB + k0) =
+                make_float4(a[mb][0] * is.x, a[mb][1] * is.y, a[mb][2] * is.z, a[mb][3] * is.w);
+        }
+        if (q == 0 && eout) eout[p] = e;
+    });
+}
+
 // ------------------------------------------------------------------ launchers
 
 static inline int sgrid(int64_t n, int cap_blocks) {
@@ -794,12 +1021,6 @@ int sur_bwd2_grid(int64_t P) {
 
 hipError_t launch_sur_prepare(const SurBufs& s, hipStream_t st) {
     hipLaunchKernelGGL(k_sur_prepare, dim3(16), dim3(kBlock), 0, st, s);
-    return hipGetLastError();
-}
-
-hipError_t launch_sur_desc(const Geom& g, const Bufs& b, const SurBufs& s, const SurConst& c, int parity, int grid,
-                           hipStream_t st) {
-    hipLaunchKernelGGL(k_sur_desc, dim3(grid), dim3(kBlock), 0, st, g, b, s, c, parity);
     return hipGetLastError();
 }
 
@@ -824,6 +1045,22 @@ hipError_t launch_sur_force(const Geom& g, const Bufs& b, const SurBufs& s, cons
     else
         hipLaunchKernelGGL((k_sur_force<false, false>), dim3(grid), dim3(kBlock), 0, st, g, b, s, c, parity,
                            nullptr, 0.0, tensor);
+    return hipGetLastError();
+}
+
+hipError_t launch_sur_desc2(const Geom& g, const Bufs& b, const SurBufs& s, const SurConst& c, int parity, int net,
+                            hipStream_t st) {
+    const dim3 grid((unsigned)((g.n + kBlock - 1) / kBlock)), blk(kBlock);
+    if (net)
+        hipLaunchKernelGGL(k_sur_desc2<true>, grid, blk, 0, st, g, b, s, c, parity);
+    else
+        hipLaunchKernelGGL(k_sur_desc2<false>, grid, blk, 0, st, g, b, s, c, parity);
+    return hipGetLastError();
+}
+
+hipError_t launch_sur_mlp16(const SurBufs& s, const float* G, int64_t P, float* a, float* e, hipStream_t st) {
+    const int64_t blocks = (P + kBlock - 1) / kBlock;
+    hipLaunchKernelGGL(k_sur_mlp16, dim3((unsigned)(blocks < 1 ? 1 : blocks)), dim3(kBlock), 0, st, s, G, P, a, e);
     return hipGetLastError();
 }
 

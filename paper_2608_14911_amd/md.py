@@ -33,6 +33,7 @@ MD_FLAG_NONFINITE = 0x4
 
 MD_NVE = 0
 MD_LANGEVIN = 1
+MD_DPD = 2
 MD_FP64 = 0
 MD_FP32 = 1
 MD_MAX_TYPES = 4
@@ -78,7 +79,8 @@ class md_config(ctypes.Structure):
                 ("n_angles", ctypes.c_int64), ("fene_K", ctypes.c_double), ("fene_R0", ctypes.c_double),
                 ("k_bend", ctypes.c_double), ("cell_factor", ctypes.c_int32),
                 ("nl_capacity", ctypes.c_int32), ("block_size", ctypes.c_int32), ("flags", ctypes.c_int32),
-                ("list_cutoff", ctypes.c_double), ("surrogate", ctypes.c_int32), ("pad_", ctypes.c_int32)]
+                ("list_cutoff", ctypes.c_double), ("surrogate", ctypes.c_int32), ("pad_", ctypes.c_int32),
+                ("shear_rate", ctypes.c_double), ("dpd_rc", ctypes.c_double)]
 
 
 class md_obs(ctypes.Structure):
@@ -209,7 +211,7 @@ def _p(x):
 def make_config(n, box, *, n_types=1, pair=None, dt=0.005, skin=0.3, integrator=MD_NVE,
                 force_precision=MD_FP32, temperature=1.0, gamma=0.0, seed=0, n_bonds=0, n_angles=0,
                 fene_K=30.0, fene_R0=1.5, k_bend=0.0, nl_capacity=0, flags=0, cell_factor=0,
-                list_cutoff=0.0, surrogate=0):
+                list_cutoff=0.0, surrogate=0, shear_rate=0.0, dpd_rc=0.0):
     """Fill an md_config.  pair: dict (ti, tj) -> (eps, sigma, rc, shift, caprad)."""
     c = md_config()
     c.struct_size = ctypes.sizeof(md_config)
@@ -232,6 +234,8 @@ def make_config(n, box, *, n_types=1, pair=None, dt=0.005, skin=0.3, integrator=
     c.flags = int(flags)
     c.list_cutoff = float(list_cutoff)
     c.surrogate = int(surrogate)
+    c.shear_rate = float(shear_rate)
+    c.dpd_rc = float(dpd_rc)
     return c
 
 

@@ -25,7 +25,8 @@ class System:
     def __init__(self, pos, box, vel=None, *, types=None, n_types=1, pair=None, masses=(1.0,),
                  bonds=None, angles=None, dt=0.005, skin=0.3, integrator="nve", precision="fp32",
                  temperature=1.0, gamma=0.0, seed=0, fene_K=30.0, fene_R0=1.5, k_bend=0.0,
-                 nl_capacity=0, flags=0, cell_factor=0, list_cutoff=0.0, surrogate=False, device="cuda"):
+                 nl_capacity=0, flags=0, cell_factor=0, list_cutoff=0.0, surrogate=False, shear_rate=0.0,
+                 dpd_rc=0.0, device="cuda"):
         torch = _torch()
         self.torch = torch
         pos = np.ascontiguousarray(pos, dtype=np.float64)
@@ -34,7 +35,7 @@ class System:
         self.box = np.asarray(box, dtype=np.float64)
         vel = np.zeros_like(pos) if vel is None else np.ascontiguousarray(vel, dtype=np.float64)
         self.device = torch.device(device)
-        integ = md.MD_LANGEVIN if integrator == "langevin" else md.MD_NVE
+        integ = {"langevin": md.MD_LANGEVIN, "dpd": md.MD_DPD}.get(integrator, md.MD_NVE)
         prec = md.MD_FP64 if precision == "fp64" else md.MD_FP32
         nb = 0 if bonds is None else len(bonds)
         na = 0 if angles is None else len(angles)
@@ -42,7 +43,8 @@ class System:
                                   force_precision=prec, temperature=temperature, gamma=gamma, seed=seed,
                                   n_bonds=nb, n_angles=na, fene_K=fene_K, fene_R0=fene_R0, k_bend=k_bend,
                                   nl_capacity=nl_capacity, flags=flags, cell_factor=cell_factor,
-                                  list_cutoff=list_cutoff, surrogate=int(bool(surrogate)))
+                                  list_cutoff=list_cutoff, surrogate=int(bool(surrogate)),
+                                  shear_rate=shear_rate, dpd_rc=dpd_rc)
         self.ws_bytes = md.md_workspace_bytes(self.cfg)
         self._ws_raw = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
         base = self._ws_raw.data_ptr()
@@ -67,7 +69,7 @@ class System:
                     pp.eps, pp.sigma, pp.rc, pp.shift, pp.caprad = (float(v) for v in row)
         for k, v in kw.items():
             if k == "integrator":
-                v = md.MD_LANGEVIN if v == "langevin" else md.MD_NVE
+                v = {"langevin": md.MD_LANGEVIN, "dpd": md.MD_DPD}.get(v, md.MD_NVE)
             if k == "precision":
                 k, v = "force_precision", (md.MD_FP64 if v == "fp64" else md.MD_FP32)
             setattr(c, k, v)

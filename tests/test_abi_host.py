@@ -284,3 +284,29 @@ def test_plan_chooses_cells_and_list_build():
     # a box of 2.7 list radii holds 2 full cells but 5 half cells per side
     p = md.md_plan_config(md.make_config(20, [7.6] * 3, **lj))
     assert p["cell_factor"] == 2 and p["nl_build"] == "per_particle" and p["cells"] == [5, 5, 5]
+
+
+def test_nl_capacity_rounds_up_to_a_multiple_of_8():
+    """The step kernels stream a row in batches of 8 slots, up to the row
+    length rounded up to 8.  A capacity that is not a multiple of 8 would let
+    a long row read the first slots of another particle's row: the list
+    layout puts slot k of particle i at (i // 64) * cap * 64 + k * 64 + i % 64,
+    so slot cap of particle i is slot 0 of particle i + 64.  The library
+    therefore rounds the capacity up."""
+    lj = dict(pair={(0, 0): (1.0, 1.0, 2.5, float("nan"), 0.0)}, skin=0.3)
+    for asked, got in ((78, 80), (80, 80), (1, 8), (81, 88), (4095, 4096), (4096, 4096)):
+        p = md.md_plan_config(md.make_config(4000, [20.0] * 3, nl_capacity=asked, **lj))
+        assert p["nl_capacity"] == got, (asked, p["nl_capacity"])
+
+    def base(i, cap):
+        return (i // 64) * cap * 64 + (i % 64)
+
+    # the aliasing the rounding prevents, and that it is gone once rounded
+    assert base(5, 78) + 78 * 64 == base(5 + 64, 78)
+    for asked in range(1, 200):
+        cap = (asked + 7) // 8 * 8
+        for cnt in range(cap + 1):
+            nslots = min((cnt + 7) // 8 * 8, cap)
+            assert nslots <= cap
+    # a workspace sized for the rounded capacity
+    assert md.md_workspace_bytes(lj_cfg(4000, nl_capacity=78)) == md.md_workspace_bytes(lj_cfg(4000, nl_capacity=80))

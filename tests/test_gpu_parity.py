@@ -153,7 +153,8 @@ def test_nl_overflow_is_reported_with_needed_capacity():
     with pytest.raises(md.MDError) as e:
         System(pos, box, pair={(0, 0): lj_pair(rc=2.5)}, skin=0.3, nl_capacity=40)
     assert e.value.code == md.MD_ERR_NL_OVERFLOW
-    assert ">= 78" in str(e.value)
+    # the longest row, and the capacity to ask for: rounded up to a multiple of 8
+    assert "has 78 neighbours" in str(e.value) and ">= 80" in str(e.value)
 
 
 def test_fcc_lattice_counts_and_sums():
@@ -394,4 +395,55 @@ def test_degenerate_systems(build):
     assert all(len(x) == 0 for x in s.neighbors(cap=8))
     assert np.abs(s.forces()).max() == 0.0
     assert s.observables()["nl_max_count"] == 0
+    s.close()
+
+
+def test_odd_list_capacity_rows_in_last_batch():
+    """A requested capacity that is not a multiple of 8, set just above the
+    longest row, so that the longest rows end inside the last batch of 8
+    slots the fast FP32 kernel streams.  The library rounds the capacity up
+    to 8; forces equal a run with a roomy capacity bit for bit (same rows, same
+    order) and agree with the oracle within the FP32 tolerance."""
+    banner("odd list capacity (LJ fast path, tiles and per-particle builds)")
+    from paper_2608_14911_amd import md
+    pos, box = lj_liquid(ncell=8, seed=5)
+    ref = oracle.neighbors(pos, box, 2.8)
+    longest = max(len(r) for r in ref)
+    cap = longest + 1 if (longest + 1) % 8 else longest + 2
+    assert cap % 8 != 0 and longest > (cap & ~7)
+    Fo, oo = oracle.forces(pos, box, oracle_pp(rc=2.5), want_fscale=True)
+    for flags in (md.MD_CFG_NL_TILES, md.MD_CFG_NL_PER_PARTICLE):
+        got = []
+        for c in (cap, 256):
+            s = System(pos, box, pair={(0, 0): lj_pair(rc=2.5)}, skin=0.3, nl_capacity=c, flags=flags)
+            assert md.md_plan_config(s.cfg)["nl_capacity"] == (c + 7) // 8 * 8
+            got.append((s.forces(), s.observables()))
+            s.close()
+        assert np.array_equal(got[0][0], got[1][0])
+        assert got[0][1]["e_pair"] == got[1][1]["e_pair"] and got[0][1]["nl_max_count"] == longest
+        assert_forces_close(got[0][0], Fo, oo["fscale"], 1e-5, "odd capacity")
+        print("odd capacity %d (rounded %d), longest row %d: max |dF| / scale %.2e" % (
+            cap, (cap + 7) // 8 * 8, longest,
+            (np.linalg.norm(got[0][0] - Fo, axis=1) / oo["fscale"]).max()), flush=True)
+
+
+def test_set_params_rejects_a_skin_change():
+    """md_set_params keeps the list radius and the half-skin rebuild threshold
+    of md_init, so a different skin is an argument error (a larger cutoff with
+    a smaller skin would keep the old threshold and miss pairs)."""
+    banner("md_set_params skin change rejected")
+    from paper_2608_14911_amd import md
+    pos, box = lj_liquid(ncell=6)
+    s = System(pos, box, pair={(0, 0): lj_pair(rc=2.5)}, skin=0.3)
+    with pytest.raises(md.MDError) as e:
+        s.set_params(pair={(0, 0): lj_pair(rc=2.7)}, skin=0.1)
+    assert e.value.code == md.MD_ERR_ARG and "skin" in str(e.value)
+    s.cfg.skin = 0.3
+    with pytest.raises(md.MDError) as e:
+        s.set_params(pair={(0, 0): lj_pair(rc=2.7)})
+    assert e.value.code == md.MD_ERR_ARG
+    # a smaller cutoff with the same skin is accepted and gives the oracle's forces
+    s.set_params(pair={(0, 0): lj_pair(rc=2.2)})
+    Fo, oo = oracle.forces(pos, box, oracle_pp(rc=2.2), want_fscale=True)
+    assert_forces_close(s.forces(), Fo, oo["fscale"], 1e-5, "rc 2.2 after set_params")
     s.close()
