@@ -206,6 +206,29 @@ md_status md_init(const md_config* cfg, const double* pos, const double* vel, co
                   const double* mass_by_type, const int32_t* bonds, const int32_t* angles,
                   void* workspace, size_t ws_bytes, void* stream, md_handle* out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture set-up, tight serving loops, harnesses that forbid hipMalloc):
+ * md_init with the workspace taken from a static device array of
+ * MD_STATIC_WORKSPACE_BYTES that the library holds on each GPU until the
+ * process ends, instead of a caller-owned one.  Same arguments, layout and
+ * errors as md_init otherwise; the handle is used and released exactly like
+ * one from md_init.
+ *   - Calls no hipMalloc / hipFree or other device-allocating routine (host
+ *     bookkeeping is allocated as for md_init); synchronises the stream once.
+ *   - The array of the calling thread's current device is used; the stream
+ *     must belong to that device.
+ *   - A configuration whose md_workspace_bytes() exceeds
+ *     MD_STATIC_WORKSPACE_BYTES is rejected with MD_ERR_WORKSPACE.
+ *   - One live handle per GPU: while a handle from md_init_static exists on a
+ *     device, a further call there returns MD_ERR_STATE; md_destroy frees
+ *     the array for the next call.  The array keeps the previous handle's
+ *     contents; md_init_static clears what must start at zero.  Work that two
+ *     threads enqueue on one GPU's array at the same time races. */
+#define MD_STATIC_WORKSPACE_BYTES (64u << 20)
+md_status md_init_static(const md_config* cfg, const double* pos, const double* vel, const int32_t* type,
+                         const double* mass_by_type, const int32_t* bonds, const int32_t* angles, void* stream,
+                         md_handle* out);
+
 /* Change run parameters without touching the state: dt, temperature, gamma,
  * seed, integrator, force_precision, the pair table (e.g. switching
  * LennardJonesCapped to LennardJones as the paper's example does),

@@ -10,6 +10,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -60,7 +61,23 @@ struct md_handle_s {
     int sur_loaded = 0;       // md_sur_set called
     int sur_prec = MD_SUR_FP32;
     int pair_mode = MD_PAIR_PLAIN;
+    // device whose static workspace this handle uses (md_init_static), or -1
+    int static_dev = -1;
 };
+
+// ------------------------------------------------------------------ static workspace
+// Workspace of md_init_static: a file-scope device array, one copy per GPU,
+// held by the code object until the process ends.  In host code its name is
+// only a stand-in; the device address comes from hipGetSymbolAddress, taken
+// once per device with that device current.
+static __device__ __align__(256) uint8_t scratch[MD_STATIC_WORKSPACE_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_static_mu;
+uint8_t* g_static_ptr[kMaxDevices];     // device address of `scratch`, per device
+md_handle g_static_owner[kMaxDevices];  // live handle on that device's array, or nullptr
+}  // namespace
 
 // ------------------------------------------------------------------ helpers
 
@@ -761,6 +778,46 @@ static md_status init_core(const md_config* cfg, const double* pos, const double
     if ((r = read_ctl(h, &c)) != MD_OK) { g_last_error = h->err; return bail(r); }
     if ((r = status_to_code(h, c.status, c.nl_max)) != MD_OK) { g_last_error = h->err; return bail(r); }
     *out = h;
+    return MD_OK;
+}
+
+md_status md_init_static(const md_config* cfg, const double* pos, const double* vel, const int32_t* type,
+                         const double* mass_by_type, const int32_t* bonds, const int32_t* angles, void* stream,
+                         md_handle* out) {
+    if (!out) return fail(nullptr, MD_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    size_t need = 0;
+    md_status st = md_workspace_bytes(cfg, &need);
+    if (st != MD_OK) return st;
+    if (need > (size_t)MD_STATIC_WORKSPACE_BYTES) {
+        char buf[200];
+        snprintf(buf, sizeof buf, "md_init_static: the system needs %zu bytes of workspace, the static workspace "
+                                  "holds %zu; use md_init with a caller-owned workspace",
+                 need, (size_t)MD_STATIC_WORKSPACE_BYTES);
+        return fail(nullptr, MD_ERR_WORKSPACE, buf);
+    }
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail(nullptr, MD_ERR_HIP, std::string("hipGetDevice: ") + hipGetErrorString(e));
+    if (dev < 0 || dev >= kMaxDevices) return fail(nullptr, MD_ERR_ARG, "device index beyond the static table");
+    std::lock_guard<std::mutex> lk(g_static_mu);
+    if (g_static_owner[dev])
+        return fail(nullptr, MD_ERR_STATE, "md_init_static: a handle on this device's static workspace is still "
+                                           "alive; md_destroy it first");
+    if (!g_static_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(nullptr, MD_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_static_ptr[dev] = (uint8_t*)p;
+    }
+    // init_core clears every counter and flag the kernels need at zero, as it
+    // does for an uninitialised caller workspace
+    st = init_core(cfg, pos, vel, type, mass_by_type, bonds, angles, g_static_ptr[dev], MD_STATIC_WORKSPACE_BYTES,
+                   stream, nullptr, out);
+    if (st != MD_OK) return st;
+    (*out)->static_dev = dev;
+    g_static_owner[dev] = *out;
     return MD_OK;
 }
 
@@ -1494,6 +1551,10 @@ md_status md_destroy(md_handle h) {
     if (!h) return MD_OK;
     (void)hipStreamSynchronize(h->stream);
     drop_graph(h);
+    if (h->static_dev >= 0) {
+        std::lock_guard<std::mutex> lk(g_static_mu);
+        if (g_static_owner[h->static_dev] == h) g_static_owner[h->static_dev] = nullptr;
+    }
     for (auto& q : h->ev_free)
         for (int k = 0; k < 4; ++k) (void)hipEventDestroy(q.e[k]);
     for (auto& q : h->ev_pending)

@@ -61,7 +61,7 @@ EXPORTED = ["md_workspace_bytes", "md_plan_config", "md_init", "md_set_params", 
             "md_set_pair_mode", "md_sur_descriptors", "md_sur_mlp_eval", "md_sur_pair_forces", "md_sur_loss_grad",
             "md_sur_adam", "md_batch_workspace_bytes", "md_batch_init", "md_batch_step",
             "md_batch_observables", "md_batch_get_state", "md_batch_destroy", "md_batch_last_error",
-            "md_batch_timing_enable", "md_batch_timing_read"]
+            "md_batch_timing_enable", "md_batch_timing_read", "md_init_static"]
 
 
 class md_pair_params(ctypes.Structure):
@@ -135,6 +135,7 @@ def lib():
         "md_workspace_bytes": [ctypes.POINTER(md_config), ctypes.POINTER(SZ)],
         "md_plan_config": [ctypes.POINTER(md_config), ctypes.POINTER(md_plan)],
         "md_init": [ctypes.POINTER(md_config), P, P, P, P, P, P, P, SZ, P, ctypes.POINTER(P)],
+        "md_init_static": [ctypes.POINTER(md_config), P, P, P, P, P, P, P, ctypes.POINTER(P)],
         "md_set_params": [P, ctypes.POINTER(md_config)],
         "md_build_neighbors": [P],
         "md_forces": [P, P],
@@ -263,6 +264,20 @@ def md_init(cfg, pos, vel, type, mass_by_type, bonds, angles, workspace, ws_byte
     code = lib().md_init(ctypes.byref(cfg), _p(pos), _p(vel), _p(type), _p(mass), _p(b), _p(a),
                          _p(workspace), ws_bytes, _p(stream), ctypes.byref(h))
     _check(code, "md_init")
+    return h
+
+
+MD_STATIC_WORKSPACE_BYTES = 64 << 20
+
+
+def md_init_static(cfg, pos, vel, type, mass_by_type, bonds, angles, stream):
+    h = ctypes.c_void_p()
+    mass = np.ascontiguousarray(mass_by_type, dtype=np.float64)
+    b = None if bonds is None else np.ascontiguousarray(bonds, dtype=np.int32)
+    a = None if angles is None else np.ascontiguousarray(angles, dtype=np.int32)
+    code = lib().md_init_static(ctypes.byref(cfg), _p(pos), _p(vel), _p(type), _p(mass), _p(b), _p(a),
+                                _p(stream), ctypes.byref(h))
+    _check(code, "md_init_static")
     return h
 
 
