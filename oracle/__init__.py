@@ -29,6 +29,10 @@ passages of the paper they follow:
                       sheared boundaries (section "New Features") and the
                       dissipative-particle-dynamics thermostat (section
                       "Functionality"), by brute force over pairs.
+* ``tables``, ``angle_tables_combine`` -- tabulated pair and angle
+                      potentials (section "Functionality") and
+                      AngularCosineSquared / TabulatedSubEnsAngular (section
+                      "New Features") for forces_ext / run_ext.
 """
 import ctypes
 import os
@@ -87,12 +91,14 @@ def _load():
     lib.orc_dpd_theta.argtypes = [u64, u64, u64, u64]
     lib.orc_dpd_theta.restype = f64
     lib.orc_forces_ext.argtypes = [i64, P, P, P, i32, P, P, i64, P, f64, f64, i64, P, f64, f64, f64, f64, f64, f64,
-                                   u64, i64, P, P, P, P]
+                                   u64, i64, P, P, P, P, P]
     lib.orc_forces_ext.restype = ctypes.c_int
     lib.orc_neighbors_le.argtypes = [i64, P, P, f64, f64, f64, i64, i32, P, P]
     lib.orc_neighbors_le.restype = ctypes.c_int
     lib.orc_run_ext.argtypes = [i64, P, P, P, P, P, i32, P, P, i64, P, f64, f64, i64, P, f64,
-                                f64, i32, f64, f64, u64, f64, f64, P, P, i64, P]
+                                f64, i32, f64, f64, u64, f64, f64, P, P, P, i64, P]
+    lib.orc_angle_tables_combine.argtypes = [i32, i32, P, P, P, P, P]
+    lib.orc_angle_tables_combine.restype = None
     lib.orc_run_ext.restype = ctypes.c_int
     lib.orc_nthreads_default.argtypes = []
     lib.orc_nthreads_default.restype = ctypes.c_int
@@ -284,9 +290,60 @@ def dpd_theta(seed, step, ti, tj):
     return _load().orc_dpd_theta(seed, step, ti, tj)
 
 
+class _Tabs(ctypes.Structure):
+    _fields_ = [("npair", ctypes.c_int32), ("pair_rmin", ctypes.c_void_p), ("pair_u", ctypes.c_void_p),
+                ("pair_f", ctypes.c_void_p), ("angle_kind", ctypes.c_int32), ("angle_K", ctypes.c_double),
+                ("angle_phi0", ctypes.c_double), ("nang", ctypes.c_int32), ("angle_u", ctypes.c_void_p),
+                ("angle_g", ctypes.c_void_p)]
+
+
+ANGLE_COSINE = 0
+ANGLE_COSINE_SQUARED = 1
+ANGLE_TABULATED = 2
+
+
+def tables(ntypes=1, pair=None, angle_kind=ANGLE_COSINE, angle_K=0.0, angle_phi0=0.0, angle_u=None, angle_g=None):
+    """Tabulated interactions for forces_ext / run_ext.  pair: dict
+    (ti, tj) -> (rmin, u[n], f[n]) on r_k = rmin + k (rc - rmin)/(n-1)
+    (symmetric; every table the same n).  Angle kinds: ANGLE_COSINE (k_bend),
+    ANGLE_COSINE_SQUARED (angle_K, angle_phi0), ANGLE_TABULATED (angle_u,
+    angle_g = du/dphi on phi_k = k pi/(n-1)).  Returns an opaque object."""
+    keep = []
+    t = _Tabs()
+    pair = pair or {}
+    n = len(next(iter(pair.values()))[1]) if pair else 0
+    rmin = np.full(ntypes * ntypes, np.nan)
+    U = np.zeros((ntypes * ntypes, max(n, 1)))
+    Fv = np.zeros((ntypes * ntypes, max(n, 1)))
+    for (a, b), (r0, u, f) in pair.items():
+        for (x, y) in ((a, b), (b, a)):
+            rmin[x * ntypes + y] = r0
+            U[x * ntypes + y, :] = u
+            Fv[x * ntypes + y, :] = f
+    keep += [rmin, U, Fv]
+    t.npair, t.pair_rmin, t.pair_u, t.pair_f = n, rmin.ctypes.data, U.ctypes.data, Fv.ctypes.data
+    t.angle_kind, t.angle_K, t.angle_phi0 = angle_kind, float(angle_K), float(angle_phi0)
+    if angle_u is not None:
+        au, ag = np.ascontiguousarray(angle_u, dtype=np.float64), np.ascontiguousarray(angle_g, dtype=np.float64)
+        keep += [au, ag]
+        t.nang, t.angle_u, t.angle_g = au.size, au.ctypes.data, ag.ctypes.data
+    t._keep = keep
+    return t
+
+
+def angle_tables_combine(u_tables, g_tables, weights):
+    """TabulatedSubEnsAngular: the table of the weighted sums of angle tables."""
+    u = np.ascontiguousarray(u_tables, dtype=np.float64)
+    g = np.ascontiguousarray(g_tables, dtype=np.float64)
+    w = np.ascontiguousarray(weights, dtype=np.float64)
+    uo, go = np.zeros(u.shape[1]), np.zeros(u.shape[1])
+    _load().orc_angle_tables_combine(u.shape[0], u.shape[1], _ptr(u), _ptr(g), _ptr(w), _ptr(uo), _ptr(go))
+    return uo, go
+
+
 def forces_ext(pos, box, pp, vel=None, ntypes=1, type=None, bonds=None, angles=None, fene_K=30.0, fene_R0=1.5,
                k_bend=0.0, shear_rate=0.0, dpd_rc=0.0, dpd_gamma=0.0, kT=1.0, dt=0.005, seed=0, step=0,
-               want_fscale=False):
+               want_fscale=False, tabs=None):
     """Conservative forces F under the sheared boundaries at time step * dt
     and, when dpd_rc > 0, the DPD thermostat forces Fd at velocities vel.
     Returns (F, Fd or None, obs)."""
@@ -303,8 +360,9 @@ def forces_ext(pos, box, pp, vel=None, ntypes=1, type=None, bonds=None, angles=N
     fscale = np.zeros(n) if want_fscale else None
     st = _load().orc_forces_ext(n, _ptr(pos), _ptr(vel), _ptr(type), ntypes, _ptr(pp), _ptr(box), nb, _ptr(bonds),
                                 fene_K, fene_R0, na, _ptr(angles), k_bend, float(shear_rate), float(dpd_rc),
-                                float(dpd_gamma), float(kT), float(dt), int(seed), int(step), _ptr(F), _ptr(Fd),
-                                _ptr(obs), _ptr(fscale))
+                                float(dpd_gamma), float(kT), float(dt), int(seed), int(step),
+                                None if tabs is None else ctypes.byref(tabs), _ptr(F), _ptr(Fd), _ptr(obs),
+                                _ptr(fscale))
     if st != OK:
         raise OracleError(st, "forces_ext")
     out = {"e_pair": obs[0], "e_bond": obs[1], "e_angle": obs[2], "virial": obs[3],
@@ -356,6 +414,7 @@ def run_ext(state, params, nsteps):
                              int(params["integrator"]), float(params.get("temperature", 0.0)),
                              float(params.get("gamma", 0.0)), int(params.get("seed", 0)),
                              float(params.get("shear_rate", 0.0)), float(params.get("dpd_rc", 0.0)),
+                             None if params.get("tabs") is None else ctypes.byref(params["tabs"]),
                              ctypes.byref(step), ctypes.byref(vh), nsteps, _ptr(hist))
     state["step"] = step.value
     state["vel_half"] = vh.value

@@ -662,11 +662,113 @@ double orc_dpd_theta(uint64_t seed, uint64_t step, uint64_t ti, uint64_t tj) {
     return sqrt(-2.0 * log(u01_open(r[0]))) * cos(two_pi * u01_open(r[1]));
 }
 
+/* Tabulated interactions (section "Functionality": tabulated potentials;
+ * section "New Features": AngularCosineSquared, TabulatedSubEnsAngular).
+ * Pair table of type pair p (when pair_rmin[p] is not NaN): npair points of
+ * u and of the radial force f = -du/dr on the uniform grid
+ * r_k = rmin + k (rc - rmin)/(npair - 1), rc the pair's cutoff; u and f are
+ * interpolated linearly in r (below rmin: the rmin values), zero from rc on.
+ * Angles, with phi the bond angle at the centre (pi for a straight chain):
+ * kind 0 the cosine bending k (1 - cos theta), theta = pi - phi; kind 1
+ * AngularCosineSquared u = K (cos phi - cos phi0)^2; kind 2 a table of u and
+ * du/dphi on the uniform grid phi_k = k pi/(nang - 1), interpolated linearly
+ * in phi, dU/dcos(phi) = -(du/dphi)/max(sin phi, 1e-8).  A weighted sum of
+ * several angle tables on one grid (TabulatedSubEnsAngular) is the table of
+ * the weighted sums (orc_angle_tables_combine). */
+typedef struct {
+    int32_t npair;
+    const double* pair_rmin;   /* [ntypes^2], NaN = Lennard-Jones */
+    const double* pair_u;      /* [ntypes^2][npair] */
+    const double* pair_f;
+    int32_t angle_kind;
+    double angle_K, angle_phi0;
+    int32_t nang;
+    const double* angle_u;     /* [nang] */
+    const double* angle_g;     /* [nang] du/dphi */
+} orc_tabs;
+
 typedef struct {
     double shear_rate, dpd_rc, dpd_gamma, kT, dt;
     uint64_t seed;
     int64_t step;
+    const orc_tabs* tabs;
 } orc_ext;
+
+static double lerp_table(const double* t, int32_t n, double x, double x0, double dx) {
+    double q = (x - x0) / dx;
+    if (q < 0.0) return t[0];
+    int64_t k = (int64_t)floor(q);
+    if (k > n - 2) k = n - 2;
+    const double a = q - (double)k;
+    return (1.0 - a) * t[k] + a * t[k + 1];
+}
+
+/* pair energy and f/r for r2 < rc^2 (tables or Lennard-Jones) */
+static void pair_eval_ext(const orc_sys* s, const orc_tabs* tb, int ti, int tj, double r2, double* u, double* fr) {
+    const int tp = ti * s->ntypes + tj;
+    orc_pair p = pair_of(s, ti, tj);
+    if (tb && tb->npair > 1 && !isnan(tb->pair_rmin[tp])) {
+        const double r = sqrt(r2);
+        const double rmin = tb->pair_rmin[tp];
+        const double dr = (p.rc - rmin) / (double)(tb->npair - 1);
+        *u = lerp_table(tb->pair_u + (int64_t)tp * tb->npair, tb->npair, r, rmin, dr);
+        *fr = lerp_table(tb->pair_f + (int64_t)tp * tb->npair, tb->npair, r, rmin, dr) / r;
+        return;
+    }
+    lj_eval(&p, r2, u, fr);
+}
+
+/* Angle energy and forces for the angle kinds above; b1 = r_b - r_a,
+ * b2 = r_c - r_b (b the centre). */
+static void angle_eval_ext(const orc_sys* s, const orc_tabs* tb, const double b1[3], const double b2[3], double* u,
+                           double Fa[3], double Fb[3], double Fc[3]) {
+    const int kind = tb ? tb->angle_kind : 0;
+    if (kind == 0) {
+        bend_eval(s->k_bend, b1, b2, u, Fa, Fb, Fc);
+        return;
+    }
+    double l1sq = b1[0] * b1[0] + b1[1] * b1[1] + b1[2] * b1[2];
+    double l2sq = b2[0] * b2[0] + b2[1] * b2[1] + b2[2] * b2[2];
+    double l1 = sqrt(l1sq), l2 = sqrt(l2sq);
+    double c = (b1[0] * b2[0] + b1[1] * b2[1] + b1[2] * b2[2]) / (l1 * l2);   /* cos theta = -cos phi */
+    const double cphi = -c;
+    double dUdc;   /* dU / d(cos theta) */
+    if (kind == 1) {
+        const double d = cphi - cos(tb->angle_phi0);
+        *u = tb->angle_K * d * d;
+        dUdc = -2.0 * tb->angle_K * d;
+    } else {
+        const double cl = cphi > 1.0 ? 1.0 : (cphi < -1.0 ? -1.0 : cphi);
+        const double phi = acos(cl);
+        const double dphi = 3.141592653589793 / (double)(tb->nang - 1);
+        *u = lerp_table(tb->angle_u, tb->nang, phi, 0.0, dphi);
+        const double g = lerp_table(tb->angle_g, tb->nang, phi, 0.0, dphi);
+        const double sn = sin(phi);
+        dUdc = g / (sn > 1e-8 ? sn : 1e-8);   /* dU/dcos(phi) = -g/sin(phi), dcos(phi)/dcos(theta) = -1 */
+    }
+    for (int d = 0; d < 3; ++d) {
+        const double dc_db1 = b2[d] / (l1 * l2) - c * b1[d] / l1sq;
+        const double dc_db2 = b1[d] / (l1 * l2) - c * b2[d] / l2sq;
+        Fa[d] = dUdc * dc_db1;        /* b1 = r_b - r_a: dc/dr_a = -dc/db1 */
+        Fc[d] = -dUdc * dc_db2;
+        Fb[d] = -(Fa[d] + Fc[d]);
+    }
+}
+
+/* TabulatedSubEnsAngular: the table of sum_m w_m (u_m, g_m) over ntab tables
+ * of n points each (rows of u and g). */
+void orc_angle_tables_combine(int32_t ntab, int32_t n, const double* u, const double* g, const double* w,
+                              double* u_out, double* g_out) {
+    for (int32_t k = 0; k < n; ++k) {
+        double su = 0.0, sg = 0.0;
+        for (int32_t m = 0; m < ntab; ++m) {
+            su += w[m] * u[(int64_t)m * n + k];
+            sg += w[m] * g[(int64_t)m * n + k];
+        }
+        u_out[k] = su;
+        g_out[k] = sg;
+    }
+}
 
 /* Conservative pair forces (the LJ table) under the sheared minimum image,
  * by brute force over all pairs, and (dpd_rc > 0) the DPD pair forces at
@@ -687,7 +789,7 @@ static void pair_forces_ext(const orc_sys* s, const orc_ext* x, const double* po
             orc_pair p = pair_of(s, type_of(s, i), type_of(s, j));
             if (r2 < p.rc * p.rc) {
                 double u, fr;
-                lj_eval(&p, r2, &u, &fr);
+                pair_eval_ext(s, x->tabs, type_of(s, i), type_of(s, j), r2, &u, &fr);
                 double rij[3] = {-d[0], -d[1], -d[2]};
                 double f[3] = {fr * rij[0], fr * rij[1], fr * rij[2]};
                 for (int k = 0; k < 3; ++k) { F[3 * i + k] += f[k]; F[3 * j + k] -= f[k]; }
@@ -752,7 +854,7 @@ static int bonded_forces_ext(const orc_sys* s, const orc_ext* x, const double* p
         le_diff(&le, L, H, pos + 3 * ia, pos + 3 * ib, b1, &sy);
         le_diff(&le, L, H, pos + 3 * ib, pos + 3 * ic, b2, &sy);
         double u, Fa[3], Fb[3], Fc[3];
-        bend_eval(s->k_bend, b1, b2, &u, Fa, Fb, Fc);
+        angle_eval_ext(s, x->tabs, b1, b2, &u, Fa, Fb, Fc);
         for (int k = 0; k < 3; ++k) { F[3 * ia + k] += Fa[k]; F[3 * ib + k] += Fb[k]; F[3 * ic + k] += Fc[k]; }
         obs[2] += u;
         double rab[3] = {-b1[0], -b1[1], -b1[2]};
@@ -780,13 +882,13 @@ static int bonded_forces_ext(const orc_sys* s, const orc_ext* x, const double* p
 int orc_forces_ext(int64_t n, const double* pos, const double* vel, const int32_t* type, int32_t ntypes,
                    const double* pp, const double* box, int64_t nbonds, const int32_t* bonds, double fene_K,
                    double fene_R0, int64_t nangles, const int32_t* angles, double k_bend, double shear_rate,
-                   double dpd_rc, double dpd_gamma, double kT, double dt, uint64_t seed, int64_t step, double* F,
-                   double* Fd, double* obs, double* fscale) {
+                   double dpd_rc, double dpd_gamma, double kT, double dt, uint64_t seed, int64_t step,
+                   const orc_tabs* tabs, double* F, double* Fd, double* obs, double* fscale) {
     if (n < 0 || ntypes < 1 || !pos || !pp || !box || !F || !obs || dt <= 0.0) return ORC_ERR_ARG;
     if (Fd && dpd_rc > 0.0 && !vel) return ORC_ERR_ARG;
     orc_sys s = {n, type, ntypes, pp, {box[0], box[1], box[2]}, nbonds, bonds, fene_K, fene_R0,
                  nangles, angles, k_bend};
-    orc_ext x = {shear_rate, dpd_rc, dpd_gamma, kT, dt, seed, step};
+    orc_ext x = {shear_rate, dpd_rc, dpd_gamma, kT, dt, seed, step, tabs};
     memset(F, 0, sizeof(double) * 3 * n);
     if (Fd) memset(Fd, 0, sizeof(double) * 3 * n);
     memset(obs, 0, sizeof(double) * ORC_NOBS);
@@ -836,8 +938,8 @@ int orc_run_ext(int64_t n, double* pos, double* vel, int32_t* image, const int32
                 const double* mass_by_type, int32_t ntypes, const double* pp, const double* box,
                 int64_t nbonds, const int32_t* bonds, double fene_K, double fene_R0, int64_t nangles,
                 const int32_t* angles, double k_bend, double dt, int32_t integrator, double temperature,
-                double gamma, uint64_t seed, double shear_rate, double dpd_rc, int64_t* step, int32_t* vel_half,
-                int64_t nsteps, double* obs_hist) {
+                double gamma, uint64_t seed, double shear_rate, double dpd_rc, const orc_tabs* tabs, int64_t* step,
+                int32_t* vel_half, int64_t nsteps, double* obs_hist) {
     if (n <= 0 || !pos || !vel || !box || !mass_by_type || dt <= 0.0) return ORC_ERR_ARG;
     if (integrator < 0 || integrator > 2) return ORC_ERR_ARG;
     double* F = (double*)malloc(sizeof(double) * 3 * n);
@@ -848,7 +950,7 @@ int orc_run_ext(int64_t n, double* pos, double* vel, int32_t* image, const int32
     for (int64_t s = 0; s < nsteps; ++s) {
         const int dpd = integrator == 2;
         int st = orc_forces_ext(n, pos, vel, type, ntypes, pp, box, nbonds, bonds, fene_K, fene_R0, nangles, angles,
-                                k_bend, shear_rate, dpd ? dpd_rc : 0.0, gamma, temperature, dt, seed, *step, F,
+                                k_bend, shear_rate, dpd ? dpd_rc : 0.0, gamma, temperature, dt, seed, *step, tabs, F,
                                 dpd ? Fd : NULL, obs, NULL);
         if (st != ORC_OK) { status = st; break; }
         const orc_le le_next = le_at(box, shear_rate, *step + 1, dt);
