@@ -29,6 +29,9 @@ passages of the paper they follow:
                       sheared boundaries (section "New Features") and the
                       dissipative-particle-dynamics thermostat (section
                       "Functionality"), by brute force over pairs.
+* ``tables(adress=..., cg=...)``, ``adress_weight`` -- AdResS force
+                      interpolation (sections "Statement of need" and
+                      "Functionality") on single-site molecules.
 * ``tables``, ``angle_tables_combine`` -- tabulated pair and angle
                       potentials (section "Functionality") and
                       AngularCosineSquared / TabulatedSubEnsAngular (section
@@ -98,6 +101,8 @@ def _load():
     lib.orc_run_ext.argtypes = [i64, P, P, P, P, P, i32, P, P, i64, P, f64, f64, i64, P, f64,
                                 f64, i32, f64, f64, u64, f64, f64, P, P, P, i64, P]
     lib.orc_angle_tables_combine.argtypes = [i32, i32, P, P, P, P, P]
+    lib.orc_adress_weight.argtypes = [f64, f64, f64, f64, f64]
+    lib.orc_adress_weight.restype = f64
     lib.orc_angle_tables_combine.restype = None
     lib.orc_run_ext.restype = ctypes.c_int
     lib.orc_nthreads_default.argtypes = []
@@ -294,7 +299,9 @@ class _Tabs(ctypes.Structure):
     _fields_ = [("npair", ctypes.c_int32), ("pair_rmin", ctypes.c_void_p), ("pair_u", ctypes.c_void_p),
                 ("pair_f", ctypes.c_void_p), ("angle_kind", ctypes.c_int32), ("angle_K", ctypes.c_double),
                 ("angle_phi0", ctypes.c_double), ("nang", ctypes.c_int32), ("angle_u", ctypes.c_void_p),
-                ("angle_g", ctypes.c_void_p)]
+                ("angle_g", ctypes.c_void_p), ("adress", ctypes.c_int32), ("ad_x0", ctypes.c_double),
+                ("ad_dat", ctypes.c_double), ("ad_dhy", ctypes.c_double), ("cg_rmin", ctypes.c_void_p),
+                ("cg_rc", ctypes.c_void_p), ("cg_u", ctypes.c_void_p), ("cg_f", ctypes.c_void_p)]
 
 
 ANGLE_COSINE = 0
@@ -302,16 +309,20 @@ ANGLE_COSINE_SQUARED = 1
 ANGLE_TABULATED = 2
 
 
-def tables(ntypes=1, pair=None, angle_kind=ANGLE_COSINE, angle_K=0.0, angle_phi0=0.0, angle_u=None, angle_g=None):
+def tables(ntypes=1, pair=None, angle_kind=ANGLE_COSINE, angle_K=0.0, angle_phi0=0.0, angle_u=None, angle_g=None,
+           adress=None, cg=None):
     """Tabulated interactions for forces_ext / run_ext.  pair: dict
     (ti, tj) -> (rmin, u[n], f[n]) on r_k = rmin + k (rc - rmin)/(n-1)
     (symmetric; every table the same n).  Angle kinds: ANGLE_COSINE (k_bend),
     ANGLE_COSINE_SQUARED (angle_K, angle_phi0), ANGLE_TABULATED (angle_u,
-    angle_g = du/dphi on phi_k = k pi/(n-1)).  Returns an opaque object."""
+    angle_g = du/dphi on phi_k = k pi/(n-1)).  AdResS: adress = (x0, d_at,
+    d_hy) and cg: dict (ti, tj) -> (rmin, rc, u[n], f[n]), the coarse-grained
+    tables (the same n as the pair tables).  Returns an opaque object."""
     keep = []
     t = _Tabs()
     pair = pair or {}
-    n = len(next(iter(pair.values()))[1]) if pair else 0
+    cg = cg or {}
+    n = len(next(iter(pair.values()))[1]) if pair else (len(next(iter(cg.values()))[2]) if cg else 0)
     rmin = np.full(ntypes * ntypes, np.nan)
     U = np.zeros((ntypes * ntypes, max(n, 1)))
     Fv = np.zeros((ntypes * ntypes, max(n, 1)))
@@ -327,8 +338,27 @@ def tables(ntypes=1, pair=None, angle_kind=ANGLE_COSINE, angle_K=0.0, angle_phi0
         au, ag = np.ascontiguousarray(angle_u, dtype=np.float64), np.ascontiguousarray(angle_g, dtype=np.float64)
         keep += [au, ag]
         t.nang, t.angle_u, t.angle_g = au.size, au.ctypes.data, ag.ctypes.data
+    cmin = np.full(ntypes * ntypes, np.nan)
+    crc = np.zeros(ntypes * ntypes)
+    CU = np.zeros((ntypes * ntypes, max(n, 1)))
+    CF = np.zeros((ntypes * ntypes, max(n, 1)))
+    for (a, b), (r0, rc, u, f) in cg.items():
+        for (x, y) in ((a, b), (b, a)):
+            cmin[x * ntypes + y], crc[x * ntypes + y] = r0, rc
+            CU[x * ntypes + y, :] = u
+            CF[x * ntypes + y, :] = f
+    keep += [cmin, crc, CU, CF]
+    t.cg_rmin, t.cg_rc, t.cg_u, t.cg_f = cmin.ctypes.data, crc.ctypes.data, CU.ctypes.data, CF.ctypes.data
+    if adress is not None:
+        t.adress = 1
+        t.ad_x0, t.ad_dat, t.ad_dhy = (float(v) for v in adress)
     t._keep = keep
     return t
+
+
+def adress_weight(x, Lx, x0, d_at, d_hy):
+    """The AdResS weight w(x) of the oracle."""
+    return _load().orc_adress_weight(float(x), float(Lx), float(x0), float(d_at), float(d_hy))
 
 
 def angle_tables_combine(u_tables, g_tables, weights):

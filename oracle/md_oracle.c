@@ -685,6 +685,20 @@ typedef struct {
     int32_t nang;
     const double* angle_u;     /* [nang] */
     const double* angle_g;     /* [nang] du/dphi */
+    /* AdResS (section "Statement of need", section "Functionality"): force
+     * interpolation between an atomistic pair force (the pair table above)
+     * and a coarse-grained one (these tables, npair points on
+     * r_k = cg_rmin + k (cg_rc - cg_rmin)/(npair - 1)), on single-site
+     * molecules: F_ij = w_i w_j F^AT_ij + (1 - w_i w_j) F^CG_ij with the
+     * weight of the position along x, d = |x - x0| (minimum image):
+     * w = 1 for d < d_at, 0 for d > d_at + d_hy, cos^2(pi (d - d_at)/(2 d_hy))
+     * between.  The reported energy is the same interpolation of u. */
+    int32_t adress;
+    double ad_x0, ad_dat, ad_dhy;
+    const double* cg_rmin;     /* [ntypes^2], NaN = no coarse-grained force */
+    const double* cg_rc;       /* [ntypes^2] */
+    const double* cg_u;        /* [ntypes^2][npair] */
+    const double* cg_f;
 } orc_tabs;
 
 typedef struct {
@@ -716,6 +730,29 @@ static void pair_eval_ext(const orc_sys* s, const orc_tabs* tb, int ti, int tj, 
         return;
     }
     lj_eval(&p, r2, u, fr);
+}
+
+/* AdResS weight of a position x along the slab axis. */
+double orc_adress_weight(double x, double Lx, double x0, double dat, double dhy) {
+    const double d = fabs(min_image(x - x0, Lx, 0.5 * Lx));
+    if (d < dat) return 1.0;
+    if (d >= dat + dhy) return 0.0;
+    const double c = cos(1.5707963267948966 * (d - dat) / dhy);
+    return c * c;
+}
+
+/* coarse-grained pair energy and f/r, zero from cg_rc on */
+static int cg_eval(const orc_sys* s, const orc_tabs* tb, int ti, int tj, double r2, double* u, double* fr) {
+    const int tp = ti * s->ntypes + tj;
+    *u = 0.0;
+    *fr = 0.0;
+    if (isnan(tb->cg_rmin[tp]) || !(r2 < tb->cg_rc[tp] * tb->cg_rc[tp])) return 0;
+    const double r = sqrt(r2);
+    const double rmin = tb->cg_rmin[tp];
+    const double dr = (tb->cg_rc[tp] - rmin) / (double)(tb->npair - 1);
+    *u = lerp_table(tb->cg_u + (int64_t)tp * tb->npair, tb->npair, r, rmin, dr);
+    *fr = lerp_table(tb->cg_f + (int64_t)tp * tb->npair, tb->npair, r, rmin, dr) / r;
+    return 1;
 }
 
 /* Angle energy and forces for the angle kinds above; b1 = r_b - r_a,
@@ -787,9 +824,20 @@ static void pair_forces_ext(const orc_sys* s, const orc_ext* x, const double* po
             le_diff(&le, L, H, pos + 3 * i, pos + 3 * j, d, &sy);
             const double r2 = (d[0] * d[0] + d[1] * d[1]) + d[2] * d[2];
             orc_pair p = pair_of(s, type_of(s, i), type_of(s, j));
-            if (r2 < p.rc * p.rc) {
-                double u, fr;
-                pair_eval_ext(s, x->tabs, type_of(s, i), type_of(s, j), r2, &u, &fr);
+            const orc_tabs* tb = x->tabs;
+            const int ad = tb && tb->adress;
+            double ucg = 0.0, frcg = 0.0;
+            const int cg_in = ad ? cg_eval(s, tb, type_of(s, i), type_of(s, j), r2, &ucg, &frcg) : 0;
+            const int at_in = r2 < p.rc * p.rc;
+            if (at_in || cg_in) {
+                double u = 0.0, fr = 0.0;
+                if (at_in) pair_eval_ext(s, tb, type_of(s, i), type_of(s, j), r2, &u, &fr);
+                if (ad) {
+                    const double lam = orc_adress_weight(pos[3 * i], L[0], tb->ad_x0, tb->ad_dat, tb->ad_dhy) *
+                                       orc_adress_weight(pos[3 * j], L[0], tb->ad_x0, tb->ad_dat, tb->ad_dhy);
+                    u = lam * u + (1.0 - lam) * ucg;
+                    fr = lam * fr + (1.0 - lam) * frcg;
+                }
                 double rij[3] = {-d[0], -d[1], -d[2]};
                 double f[3] = {fr * rij[0], fr * rij[1], fr * rij[2]};
                 for (int k = 0; k < 3; ++k) { F[3 * i + k] += f[k]; F[3 * j + k] -= f[k]; }
