@@ -72,7 +72,8 @@ def parse():
     ap.add_argument("--batch-start", default="lattice", choices=["lattice", "pushoff"],
                     help="batch: melt replicas laid on a lattice (no push-off) or pushed-off random walks")
     ap.add_argument("--autotune", default="cache", choices=["cache", "tune", "none"],
-                    help="batch: the autotuner's cached choice, a fresh tuning run, or the library defaults")
+                    help="the autotuner's cached choice (batch members; LJ 1M and KG 2M cells, list build "
+                         "and force-kernel block), a fresh tuning run, or the library defaults")
     ap.add_argument("--cpu-seconds", type=float, default=8.0, help="CPU oracle budget per leg")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quiet", action="store_true")
@@ -92,12 +93,16 @@ def log(msg, quiet=False):
 
 
 # ---------------------------------------------------------------- systems
-def make_system(name, quiet, cell_factor=0, flags=0):
+# autotuner keys of the single-system workloads: (kind, N, density, rc)
+TUNE_KEYS = {"lj1m": ("lj", 1048576, 0.8442, 2.5), "kg2m": ("kg", 2000000, 0.85, 2.0 ** (1.0 / 6.0))}
+
+
+def make_system(name, quiet, cell_factor=0, flags=0, block_size=0):
     from paper_2608_14911_amd import inputs
     from paper_2608_14911_amd.system import from_workload, push_off
     if name == "lj1m":
         w = inputs.workload_lj(ncell=64, seed=1001)
-        return w, from_workload(w, precision="fp32", cell_factor=cell_factor, flags=flags)
+        return w, from_workload(w, precision="fp32", cell_factor=cell_factor, flags=flags, block_size=block_size)
     if name == "kg2m":
         w = inputs.workload_kg(2000, 1000, seed=1002)
     elif name == "sur1m":
@@ -119,7 +124,7 @@ def make_system(name, quiet, cell_factor=0, flags=0):
     s.close()
     w1 = dict(w, pos=st["pos"], vel=st["vel"])
     extra = {"list_cutoff": 2.5, "surrogate": True} if name == "sur1m" else {}
-    s = from_workload(w1, precision="fp32", cell_factor=cell_factor, flags=flags, **extra)
+    s = from_workload(w1, precision="fp32", cell_factor=cell_factor, flags=flags, block_size=block_size, **extra)
     s.set_state(st)
     s.step(1)
     if s.status() != 0:
@@ -272,11 +277,33 @@ def single_record(name, a, w, s):
     return rec
 
 
-def bench_single(name, a):
+def single_choice(name, a):
+    """(cell_factor, list-build flags, block_size, source) of a single-system
+    workload: the command line's, the autotuner's cache entry, a fresh tuning
+    run, or the library defaults."""
+    from paper_2608_14911_amd import autotune
     from paper_2608_14911_amd import md as md_
+    from paper_2608_14911_amd.system import nl_build_flags
     nl_flags = {"auto": 0, "tiles": md_.MD_CFG_NL_TILES, "per-particle": md_.MD_CFG_NL_PER_PARTICLE}[a.nl_build]
+    if a.cell_factor or a.nl_build != "auto" or a.autotune == "none" or name not in TUNE_KEYS:
+        return a.cell_factor, nl_flags, 0, "command line / library defaults", None
+    kind, n, rho, rc = TUNE_KEYS[name]
+    if a.autotune == "tune":
+        (cf, build, bs), table = autotune.tune_system(
+            lambda cf, fl: make_system(name, True, cf, fl)[1], n, rho, rc, kind, steps=30,
+            log=lambda m: log(m, a.quiet))
+        return cf, nl_build_flags(build), bs, "autotuner (fresh run)", table
+    c = autotune.cached_system_choice(kind, n, rho, rc)
+    if c is None:
+        return 0, 0, 0, "library defaults (no autotuner cache entry)", None
+    return c[0], nl_build_flags(c[1]), c[2], "autotuner cache (%s, cell factor %d, %s, block %d)" % (
+        autotune.key_of(kind, n, rho, rc), c[0], c[1], c[2]), None
+
+
+def bench_single(name, a):
+    cf, nl_flags, bs, how, table = single_choice(name, a)
     t0 = time.time()
-    w, s = make_system(name, a.quiet, a.cell_factor, nl_flags)
+    w, s = make_system(name, a.quiet, cf, nl_flags, bs)
     if name == "sur1m":
         # the surrogate replaces the WCA pair force: the network trained by
         # surrogate_experiment.py on a 100k-bead plain-method melt
@@ -286,6 +313,10 @@ def bench_single(name, a):
         s.set_pair_mode("surrogate")
     log("%s: %d particles ready in %.1f s" % (name, s.n, time.time() - t0), a.quiet)
     rec = single_record(name, a, w, s)
+    rec["config"]["block_size"] = bs or 256
+    rec["config"]["tuning"] = how
+    if table:
+        rec["autotune_trials"] = table
     s.close()
     del s
     free_gpu()

@@ -123,7 +123,11 @@ typedef struct md_config {
     int32_t nl_capacity;       /* neighbours per particle, rounded up to a multiple
                                   of 8 (rows are streamed in batches of 8 slots);
                                   0 = from density */
-    int32_t block_size;        /* threads per block of the force kernel; 0 = 256 */
+    int32_t block_size;        /* particles (threads) per block of the FP32 fast force
+                                  kernels: 64, 128, 256 or 512; 0 = 256.  The other force
+                                  kernels and batches keep 256.  Changes cost only: every
+                                  particle's force is computed alone, and only the order
+                                  of the FP64 energy/virial block sums follows it */
     int32_t flags;             /* MD_CFG_* */
     double list_cutoff;        /* Verlet list radius = max(list_cutoff, max rc) + skin;
                                   0 = max rc.  The surrogate needs >= MD_SUR_RCUT */
@@ -141,7 +145,28 @@ typedef struct md_config {
                                   the skin */
     double dpd_rc;             /* DPD weight range (MD_DPD); the Verlet list radius
                                   covers max(dpd_rc, rc, list_cutoff) + skin */
+    int32_t table_points;      /* points per pair / angle table reserved in the
+                                  workspace (md_set_pair_table, md_set_angle_table);
+                                  0 = no tables.  Tables need MD_FP32 */
+    int32_t angle_kind;        /* MD_ANGLE_*; kinds other than MD_ANGLE_COSINE need MD_FP32 */
+    double angle_K, angle_phi0; /* MD_ANGLE_COSINE_SQUARED: u = K (cos phi - cos phi0)^2 */
+    int32_t adress;            /* 1: AdResS force interpolation (md_set_cg_table); needs
+                                  table_points > 0 and MD_FP32 */
+    int32_t pad2_;
+    double adress_x0, adress_d_at, adress_d_hy; /* slab of the atomistic zone along x */
 } md_config;
+
+/* Angle potentials (bonded interactions, section "Functionality";
+ * AngularCosineSquared and TabulatedSubEnsAngular, section "New Features"),
+ * in the bond angle phi at the centre (pi for a straight chain):
+ *   MD_ANGLE_COSINE          u = k_bend (1 + cos phi) = k_bend (1 - cos theta),
+ *                            theta = pi - phi (the Kremer-Grest bending)
+ *   MD_ANGLE_COSINE_SQUARED  u = angle_K (cos phi - cos angle_phi0)^2
+ *   MD_ANGLE_TABULATED       a table of u and du/dphi (md_set_angle_table)
+ *                            on phi_k = k pi / (n - 1), both interpolated
+ *                            linearly in phi; the force takes
+ *                            dU/dcos(phi) = -(du/dphi) / max(sin phi, 1e-8) */
+enum { MD_ANGLE_COSINE = 0, MD_ANGLE_COSINE_SQUARED = 1, MD_ANGLE_TABULATED = 2 };
 
 /* Observables of one step n (positions x_n, on-step velocities v_n). */
 typedef struct md_obs {
@@ -238,6 +263,42 @@ md_status md_init_static(const md_config* cfg, const double* pos, const double* 
  * pair table whose cutoffs plus the skin exceed that list radius is
  * rejected. */
 md_status md_set_params(md_handle h, const md_config* cfg);
+
+/* Tabulated pair potential of types (ti, tj) (section "Functionality":
+ * tabulated potentials), replacing that pair's Lennard-Jones form (its eps,
+ * sigma, shift and caprad are ignored; its rc stays the cutoff):
+ *   u, f   host FP64 [npoints]: the energy and the radial force f = -du/dr
+ *          on r_k = rmin + k (rc - rmin) / (npoints - 1)
+ * Both are interpolated linearly in r; below rmin they keep their rmin
+ * values; from rc on the pair does not interact.  Stored as FP32.
+ * npoints in 2 .. md_config.table_points; 0 <= rmin < rc.  Symmetric (sets
+ * (tj, ti) as well).  Errors: MD_ERR_ARG. */
+md_status md_set_pair_table(md_handle h, int32_t ti, int32_t tj, const double* u, const double* f, int32_t npoints,
+                            double rmin);
+/* The angle table of MD_ANGLE_TABULATED: u and du/dphi, host FP64
+ * [npoints], phi_k = k pi / (npoints - 1); npoints in 2 .. table_points. */
+md_status md_set_angle_table(md_handle h, const double* u, const double* dudphi, int32_t npoints);
+/* TabulatedSubEnsAngular: the angle table of the weighted sum of ntables
+ * tables on one grid, u and dudphi host FP64 [ntables][npoints], weights
+ * host FP64 [ntables]; sets the table sum_m w_m (u_m, du_m/dphi). */
+md_status md_set_angle_subens(md_handle h, int32_t ntables, const double* u, const double* dudphi,
+                              const double* weights, int32_t npoints);
+
+/* AdResS (adaptive resolution, sections "Statement of need" and
+ * "Functionality") on single-site molecules: with md_config.adress = 1 every
+ * pair force is interpolated between the atomistic one (the pair table, or
+ * its tabulated form) and a coarse-grained one:
+ *   F_ij = w_i w_j F^AT_ij + (1 - w_i w_j) F^CG_ij,
+ *   w(x) = 1 for d < d_at, 0 for d >= d_at + d_hy, cos^2(pi (d - d_at) / (2 d_hy))
+ *          between, d = |x - adress_x0| (minimum image along x);
+ * the reported pair energy is the same interpolation of u (force
+ * interpolation conserves no energy).  The coarse-grained potential of types
+ * (ti, tj) is a table as md_set_pair_table's: u, f host FP64 [npoints] on
+ * r_k = rmin + k (rc_cg - rmin) / (npoints - 1), zero from rc_cg on; rc_cg + skin
+ * must not exceed the list radius (set md_config.list_cutoff).  Pairs
+ * without a coarse-grained table have F^CG = 0. */
+md_status md_set_cg_table(md_handle h, int32_t ti, int32_t tj, const double* u, const double* f, int32_t npoints,
+                          double rmin, double rc_cg);
 
 /* Force a cell sort and neighbour-list build at the current positions. */
 md_status md_build_neighbors(md_handle h);
@@ -369,8 +430,9 @@ md_status md_destroy(md_handle h);
  * its own cells, list, rebuild trigger, thermostat stream and observables;
  * a member's trajectory is the one a standalone handle with the same
  * configuration computes.  Members need one particle type, FP32 pair math,
- * a cubic box, no capping radius, no surrogate, and at most 262144
- * particles.
+ * a cubic box, no capping radius, no surrogate, no DPD, no shear, no tables,
+ * the cosine angle, no AdResS, and at most 262144 particles (MD_ERR_ARG
+ * otherwise).
  * ------------------------------------------------------------------------ */
 typedef struct md_batch_s* md_batch;
 

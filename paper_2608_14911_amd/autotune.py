@@ -9,7 +9,9 @@ build; only the order of the FP32 sums follows the list order):
 * the cell size and the list build, tried as the three forms that make sense:
   one wavefront per 64-particle tile on cells of side rc+skin, one particle
   per lane on the same cells, and one particle per lane on half-cutoff cells
-  (fewer candidate pairs, more cells to walk).
+  (fewer candidate pairs, more cells to walk);
+* the tile of the force kernel: particles per block (64, 128, 256, 512) --
+  single systems only; a batch packs its members in 256-particle tiles.
 
 Results are cached in ``data/autotune_cache.json`` by
 
@@ -31,6 +33,7 @@ CACHE_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "data", "a
 SKINS = (0.3, 0.4, 0.5)
 # (cell factor, list build)
 BUILDS = ((1, "tiles"), (1, "per_particle"), (2, "per_particle"))
+BLOCKS = (64, 128, 256, 512)
 
 
 # ---------------------------------------------------------------- keys
@@ -155,10 +158,23 @@ def tune(members, steps=40, skins=SKINS, builds=BUILDS, log=None, path=CACHE_PAT
     return choice, table
 
 
-def tune_system(make, n, rho, rc, kind, steps=40, builds=BUILDS, log=None, path=CACHE_PATH, write=True):
-    """Tune the cells and list build of one system.  ``make(cell_factor,
-    flags)`` returns a fresh System; its skin is the workload's own.  Returns
-    ((cell_factor, nl_build), table)."""
+def _time_system(s, steps):
+    s.step(6)
+    s.stream.synchronize()
+    t0 = time.perf_counter()
+    s.step(steps)
+    s.stream.synchronize()
+    return 1e3 * (time.perf_counter() - t0) / steps
+
+
+def tune_system(make, n, rho, rc, kind, steps=40, builds=BUILDS, blocks=BLOCKS, log=None, path=CACHE_PATH,
+                write=True):
+    """Tune the cells, list build and force-kernel tile of one system.
+    ``make(cell_factor, flags)`` returns a fresh System; its skin is the
+    workload's own.  Cells and build are tried first at 256 particles per
+    block, then the block sizes on the winner (switched in place with
+    md_set_params, which changes cost only).  Returns ((cell_factor,
+    nl_build, block_size), table)."""
     from .system import nl_build_flags
     table, best = [], None
     for cf, build in builds:
@@ -168,24 +184,38 @@ def tune_system(make, n, rho, rc, kind, steps=40, builds=BUILDS, log=None, path=
             if log:
                 log("autotune %s cf %d %s: skipped (%s)" % (kind, cf, build, e))
             continue
-        s.step(6)
-        s.stream.synchronize()
-        t0 = time.perf_counter()
-        s.step(steps)
-        s.stream.synchronize()
-        ms = 1e3 * (time.perf_counter() - t0) / steps
+        ms = _time_system(s, steps)
         skin = s.cfg.skin
         s.close()
-        table.append({"cell_factor": cf, "nl_build": build, "ms_per_step": ms})
+        table.append({"cell_factor": cf, "nl_build": build, "block_size": 256, "ms_per_step": ms})
         if log:
-            log("autotune %s cf %d %s: %.3f ms/step" % (kind, cf, build, ms))
+            log("autotune %s cf %d %s block 256: %.3f ms/step" % (kind, cf, build, ms))
         if best is None or ms < best[0]:
-            best = (ms, cf, build)
+            best = (ms, cf, build, 256)
     if best is None:
         raise RuntimeError("no candidate configuration ran")
+    s = make(best[1], nl_build_flags(best[2]))
+    for bs in blocks:
+        s.set_params(block_size=bs)
+        ms = _time_system(s, steps)
+        table.append({"cell_factor": best[1], "nl_build": best[2], "block_size": bs, "ms_per_step": ms})
+        if log:
+            log("autotune %s cf %d %s block %d: %.3f ms/step" % (kind, best[1], best[2], bs, ms))
+        if ms < best[0]:
+            best = (ms, best[1], best[2], bs)
+    s.close()
     if write:
         cache = load_cache(path)
         cache[key_of(kind, n, rho, rc)] = {"skin": skin, "cell_factor": best[1], "nl_build": best[2],
-                                           "source": "single"}
+                                           "block_size": best[3], "source": "single"}
         save_cache(cache, path)
     return best[1:], table
+
+
+def cached_system_choice(kind, n, rho, rc, path=CACHE_PATH):
+    """(cell_factor, nl_build, block_size) of a single system from the cache,
+    or None."""
+    e = load_cache(path).get(key_of(kind, n, rho, rc))
+    if e is None or e.get("source") != "single":
+        return None
+    return e["cell_factor"], e["nl_build"], e.get("block_size", 256)

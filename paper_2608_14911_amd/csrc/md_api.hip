@@ -63,6 +63,13 @@ struct md_handle_s {
     int pair_mode = MD_PAIR_PLAIN;
     // device whose static workspace this handle uses (md_init_static), or -1
     int static_dev = -1;
+    // tables set so far (kept across md_set_params)
+    int32_t tabn[MD_MAX_TYPES * MD_MAX_TYPES] = {};
+    double tab_rmin[MD_MAX_TYPES * MD_MAX_TYPES] = {};
+    int32_t ang_n = 0;
+    int32_t cgn[MD_MAX_TYPES * MD_MAX_TYPES] = {};
+    double cg_rmin[MD_MAX_TYPES * MD_MAX_TYPES] = {};
+    double cg_rc[MD_MAX_TYPES * MD_MAX_TYPES] = {};
 };
 
 // ------------------------------------------------------------------ static workspace
@@ -115,6 +122,11 @@ static md_status validate(const md_config* c, std::string* why) {
         return MD_ERR_ARG;
     }
     if (c->force_precision != MD_FP64 && c->force_precision != MD_FP32) { *why = "unknown force precision"; return MD_ERR_ARG; }
+    if (c->block_size != 0 && c->block_size != 64 && c->block_size != 128 && c->block_size != 256 &&
+        c->block_size != 512) {
+        *why = "block_size must be 0, 64, 128, 256 or 512";
+        return MD_ERR_ARG;
+    }
     if (c->integrator != MD_NVE && (!(c->gamma >= 0.0) || !(c->temperature >= 0.0))) {
         *why = "thermostat gamma and temperature must be >= 0";
         return MD_ERR_ARG;
@@ -145,6 +157,22 @@ static md_status validate(const md_config* c, std::string* why) {
     if (c->cell_factor < 0 || c->cell_factor > 2) { *why = "cell_factor must be 0, 1 or 2"; return MD_ERR_ARG; }
     if (!(c->list_cutoff >= 0.0) || !isfinite(c->list_cutoff)) { *why = "list_cutoff must be >= 0"; return MD_ERR_ARG; }
     if (c->surrogate != 0 && c->surrogate != 1) { *why = "surrogate must be 0 or 1"; return MD_ERR_ARG; }
+    if (c->table_points < 0 || c->table_points > 65536) { *why = "table_points out of range (0 .. 65536)"; return MD_ERR_ARG; }
+    if (c->angle_kind < MD_ANGLE_COSINE || c->angle_kind > MD_ANGLE_TABULATED) { *why = "unknown angle kind"; return MD_ERR_ARG; }
+    if ((c->table_points > 0 || c->angle_kind != MD_ANGLE_COSINE) && c->force_precision != MD_FP32) {
+        *why = "tables and angle kinds other than MD_ANGLE_COSINE run on the FP32 pair path";
+        return MD_ERR_ARG;
+    }
+    if (c->adress != 0 && c->adress != 1) { *why = "adress must be 0 or 1"; return MD_ERR_ARG; }
+    if (c->adress && (c->table_points < 2 || !(c->adress_d_at >= 0.0) || !(c->adress_d_hy > 0.0) ||
+                      !isfinite(c->adress_x0))) {
+        *why = "AdResS needs table_points >= 2, d_at >= 0 and d_hy > 0";
+        return MD_ERR_ARG;
+    }
+    if (c->angle_kind == MD_ANGLE_TABULATED && c->table_points < 2) {
+        *why = "MD_ANGLE_TABULATED needs table_points >= 2";
+        return MD_ERR_ARG;
+    }
     return MD_OK;
 }
 
@@ -238,6 +266,7 @@ static md_status plan_geom(const md_config* c, Geom* g, std::string* why) {
     g->le_rate_Ly = c->shear_rate * c->box[1];
     g->le_dt = c->dt;
     g->skin = c->skin;
+    g->table_points = c->table_points;
     if (g->le) g->nl_tile = 0;   // the sheared stencil is built one particle per lane
     g->nl_cubic = (c->box[0] == c->box[1] && c->box[1] == c->box[2]) ? 1 : 0;
     // the unbonded fast step kernel gathers 12-byte records (fewer L1 lines per
@@ -265,6 +294,13 @@ static md_status plan_geom(const md_config* c, Geom* g, std::string* why) {
     return MD_OK;
 }
 
+// Partial-sum columns: one per block of the plain force kernel at its
+// smallest block (64 threads), at least one per block of the others.
+static int64_t part_cols(int64_t n) {
+    const int64_t c = (n + 63) / 64;
+    return c > (int64_t)step_grid(n) ? c : (int64_t)step_grid(n);
+}
+
 // Carve the workspace; with base == nullptr only the size is computed.
 static size_t carve(const md_config* c, const Geom& g, int step_grid, uint8_t* base, Bufs* b,
                     SurBufs* sb = nullptr, bool ext_cells = false) {
@@ -283,7 +319,7 @@ static size_t carve(const md_config* c, const Geom& g, int step_grid, uint8_t* b
     t.ctl = (DevCtl*)take(sizeof(DevCtl));
     t.cur = (double*)take(sizeof(double) * kHistRec);
     t.hist = (double*)take(sizeof(double) * kHistRec * MD_HISTORY_CAPACITY);
-    t.partials = (double*)take(sizeof(double) * kNacc * (size_t)step_grid);
+    t.partials = (double*)take(sizeof(double) * kNacc * (size_t)part_cols(n));
     t.x[0] = (double4*)take(sizeof(double4) * n);
     t.x[1] = (double4*)take(sizeof(double4) * n);
     t.xq[0] = (int4*)take(sizeof(int4) * n);
@@ -324,6 +360,7 @@ static size_t carve(const md_config* c, const Geom& g, int step_grid, uint8_t* b
     }
     t.maxb = maxb;
     t.maxa = maxa;
+    if (c->table_points > 0) t.tab = (float2*)take(sizeof(float2) * (size_t)kTableRows * c->table_points);
     if (b) *b = t;
     if (c->surrogate) {
         SurBufs u;
@@ -427,6 +464,43 @@ static void fill_params(md_handle h, const md_config* c) {
     dy.dpd_rc2 = (float)(c->dpd_rc * c->dpd_rc);
     dy.dpd_gamma = (float)c->gamma;
     dy.dpd_sigma_isdt = (float)(sqrt(2.0 * c->gamma * c->temperature) / sqrt(c->dt));
+    // tables set on the handle, against the cutoffs of this configuration
+    bool any_tab = false;
+    for (int tp = 0; tp < MD_MAX_TYPES * MD_MAX_TYPES; ++tp) {
+        pt.tabn[tp] = h->tabn[tp];
+        if (h->tabn[tp] > 1) {
+            any_tab = true;
+            pt.tab_rmin[tp] = (float)h->tab_rmin[tp];
+            pt.tab_idr[tp] = (float)((double)(h->tabn[tp] - 1) / (c->pair[tp].rc - h->tab_rmin[tp]));
+        }
+    }
+    dy.angle_kind = c->angle_kind;
+    dy.angle_K = (float)c->angle_K;
+    dy.cos_phi0 = (float)cos(c->angle_phi0);
+    dy.ang_n = h->ang_n;
+    dy.ang_idphi = h->ang_n > 1 ? (float)((double)(h->ang_n - 1) / M_PI) : 0.f;
+    dy.ang_tab = h->b.tab ? h->b.tab + (size_t)kAngleTableRow * h->g.table_points : nullptr;
+    // AdResS coarse-grained tables
+    const double Lmax = fmax(c->box[0], fmax(c->box[1], c->box[2]));
+    for (int tp = 0; tp < MD_MAX_TYPES * MD_MAX_TYPES; ++tp) {
+        pt.cgn[tp] = c->adress ? h->cgn[tp] : 0;
+        if (pt.cgn[tp] > 1) {
+            const double rc2 = h->cg_rc[tp] * h->cg_rc[tp], band = fixed_band(rc2, Lmax);
+            pt.cg_rmin[tp] = (float)h->cg_rmin[tp];
+            pt.cg_idr[tp] = (float)((double)(h->cgn[tp] - 1) / (h->cg_rc[tp] - h->cg_rmin[tp]));
+            pt.cg_rc2d[tp] = rc2;
+            pt.cg_rc2lo[tp] = (float)(rc2 - band);
+            pt.cg_rc2hi[tp] = (float)(rc2 + band);
+        }
+    }
+    dy.adress = c->adress;
+    dy.ad_x0 = (float)c->adress_x0;
+    dy.ad_dat = (float)c->adress_d_at;
+    dy.ad_dhy = (float)c->adress_d_hy;
+    dy.ad_k = c->adress ? (float)(M_PI / (2.0 * c->adress_d_hy)) : 0.f;
+    dy.gen = (c->shear_rate != 0.0 || c->integrator == MD_DPD || any_tab || c->angle_kind != MD_ANGLE_COSINE ||
+              c->adress) ? 1 : 0;
+    if (dy.gen) h->use_fast = 0;
 }
 
 static void fill_masses(md_handle h, const double* mass_by_type) {
@@ -478,6 +552,8 @@ static void fill_sur_const(SurConst* c) {
     c->ratio = (float)exp2(-2.0 * (1.4426950408889634 / (2.0 * w2)) * dmu * dmu);
 }
 
+static int block_of(md_handle h) { return h->cfg.block_size ? h->cfg.block_size : kBlock; }
+
 // Force stage: the plain fused kernel, or the surrogate's network stage
 // followed by its fused pair-force + bonded + integration kernel.  BF16
 // form: descriptors and the matrix-core network in one kernel, the input
@@ -487,7 +563,8 @@ static void fill_sur_const(SurConst* c) {
 static hipError_t launch_force_stage(md_handle h, int mode, int tensor, double* f_out, const double** spart) {
     StepArgs a = make_args(h, mode, tensor, f_out);
     *spart = nullptr;
-    if (h->pair_mode == MD_PAIR_PLAIN) return launch_step(a, h->fp64, h->single, h->bonded, kBlock, h->stream);
+    if (h->pair_mode == MD_PAIR_PLAIN)
+        return launch_step(a, h->fp64, h->single, h->bonded, block_of(h), h->stream);
     hipError_t e;
     const SurBufs& s = h->sb;
     const int bf = h->sur_prec == MD_SUR_BF16;
@@ -502,9 +579,12 @@ static hipError_t launch_force_stage(md_handle h, int mode, int tensor, double* 
     return launch_sur_step(a, s, h->sc, h->bonded, bf, h->stream);
 }
 
-// the finalize of a force stage: surrogate partials carry the energy only
+// the finalize of a force stage: surrogate partials carry the energy only;
+// the plain kernels leave one partial column per block they ran
 static hipError_t launch_stage_finalize(md_handle h, int mode, const double* spart, int tensor) {
-    return launch_finalize(h->b, h->step_grid, mode, spart, tensor, h->stream, 1);
+    int nb = h->step_grid;
+    if (h->pair_mode == MD_PAIR_PLAIN) nb = step_launch_grid(make_args(h, mode, tensor, nullptr), h->fp64, block_of(h));
+    return launch_finalize(h->b, nb, mode, spart, tensor, h->stream, 1);
 }
 
 // Enqueue one full step at the handle's current parity and advance the
@@ -600,6 +680,13 @@ static void fill_obs(md_handle h, const double* rec, md_obs* o) {
     o->n_rebuilds = (int64_t)rec[H_NREB];
     o->status_flags = (uint32_t)rec[H_STATUS];
     o->nl_max_count = (int32_t)rec[H_NLMAX];
+}
+
+// a tabulated angle kind needs its table before forces are evaluated
+static md_status need_tables(md_handle h) {
+    if (h->cfg.angle_kind == MD_ANGLE_TABULATED && h->cfg.n_angles > 0 && h->ang_n < 2)
+        return fail(h, MD_ERR_STATE, "MD_ANGLE_TABULATED: md_set_angle_table has not been called");
+    return MD_OK;
 }
 
 static md_status upload_topology(md_handle h, const int32_t* bonds, const int32_t* angles) {
@@ -757,7 +844,7 @@ static md_status init_core(const md_config* cfg, const double* pos, const double
         launch_zero_i32(h->b.ccount, g.ncell, h->stream) != hipSuccess ||
         launch_zero_i32(h->b.bsum, kScanBlocks * kChunkPad, h->stream) != hipSuccess ||
         launch_zero_i32(h->b.ncount, g.n, h->stream) != hipSuccess ||
-        launch_zero_i32((int32_t*)h->b.partials, 2 * kNacc * (int64_t)sg, h->stream) != hipSuccess)
+        launch_zero_i32((int32_t*)h->b.partials, 2 * kNacc * part_cols(g.n), h->stream) != hipSuccess)
         return bail(fail(nullptr, MD_ERR_HIP, "kernel launch failed during init"));
     if (type) {
         if (launch_copy_i32(h->b.type_t, type, g.n, h->stream) != hipSuccess)
@@ -837,6 +924,8 @@ md_status md_set_params(md_handle h, const md_config* cfg) {
     // a changed skin would not (a smaller effective skin under the old
     // threshold misses pairs entering the cutoff).
     if (cfg->skin != o.skin) return fail(h, MD_ERR_ARG, "md_set_params cannot change the skin fixed at md_init");
+    if (cfg->table_points != o.table_points)
+        return fail(h, MD_ERR_ARG, "md_set_params cannot change table_points (workspace layout)");
     if (cfg->shear_rate != o.shear_rate || ((o.shear_rate != 0.0) && cfg->dt != o.dt))
         return fail(h, MD_ERR_ARG, "md_set_params cannot change the shear rate, or the time step under shear");
     if (g.rv2 > h->g.rv2 * (1.0 + 1e-15))
@@ -853,6 +942,105 @@ md_status md_set_params(md_handle h, const md_config* cfg) {
     return MD_OK;
 }
 
+static md_status upload_table_row(md_handle h, int row, const std::vector<float2>& v) {
+    HIP_TRY(h, hipMemcpyAsync(h->b.tab + (size_t)row * h->g.table_points, v.data(), sizeof(float2) * v.size(),
+                              hipMemcpyHostToDevice, h->stream));
+    HIP_TRY(h, hipStreamSynchronize(h->stream));   // the host vector goes out of scope
+    return MD_OK;
+}
+
+md_status md_set_pair_table(md_handle h, int32_t ti, int32_t tj, const double* u, const double* f, int32_t npoints,
+                            double rmin) {
+    if (!h) return fail(nullptr, MD_ERR_ARG, "NULL handle");
+    const md_config& c = h->cfg;
+    if (ti < 0 || tj < 0 || ti >= c.n_types || tj >= c.n_types) return fail(h, MD_ERR_ARG, "type out of range");
+    if (!u || !f || npoints < 2 || npoints > c.table_points)
+        return fail(h, MD_ERR_ARG, "need u, f and 2 <= npoints <= md_config.table_points");
+    const double rc = c.pair[ti * MD_MAX_TYPES + tj].rc;
+    if (!(rmin >= 0.0 && rmin < rc)) return fail(h, MD_ERR_ARG, "need 0 <= rmin < rc");
+    std::vector<float2> v(npoints);
+    for (int k = 0; k < npoints; ++k) {
+        if (!isfinite(u[k]) || !isfinite(f[k])) return fail(h, MD_ERR_ARG, "non-finite table value");
+        v[k] = make_float2((float)u[k], (float)f[k]);
+    }
+    for (int pass = 0; pass < 2; ++pass) {
+        const int tp = pass == 0 ? ti * MD_MAX_TYPES + tj : tj * MD_MAX_TYPES + ti;
+        md_status r = upload_table_row(h, tp, v);
+        if (r != MD_OK) return r;
+        h->tabn[tp] = npoints;
+        h->tab_rmin[tp] = rmin;
+    }
+    double mass[MD_MAX_TYPES];
+    for (int t = 0; t < MD_MAX_TYPES; ++t) mass[t] = h->dy.mass[t];
+    fill_params(h, &h->cfg);
+    fill_masses(h, mass);
+    drop_graph(h);
+    return MD_OK;
+}
+
+md_status md_set_cg_table(md_handle h, int32_t ti, int32_t tj, const double* u, const double* f, int32_t npoints,
+                          double rmin, double rc_cg) {
+    if (!h) return fail(nullptr, MD_ERR_ARG, "NULL handle");
+    const md_config& c = h->cfg;
+    if (!c.adress) return fail(h, MD_ERR_ARG, "md_config.adress is 0");
+    if (ti < 0 || tj < 0 || ti >= c.n_types || tj >= c.n_types) return fail(h, MD_ERR_ARG, "type out of range");
+    if (!u || !f || npoints < 2 || npoints > c.table_points)
+        return fail(h, MD_ERR_ARG, "need u, f and 2 <= npoints <= md_config.table_points");
+    if (!(rmin >= 0.0 && rmin < rc_cg) || !isfinite(rc_cg)) return fail(h, MD_ERR_ARG, "need 0 <= rmin < rc_cg");
+    if ((rc_cg + c.skin) * (rc_cg + c.skin) > h->g.rv2 * (1.0 + 1e-12))
+        return fail(h, MD_ERR_ARG, "rc_cg + skin exceeds the list radius; raise md_config.list_cutoff");
+    std::vector<float2> v(npoints);
+    for (int k = 0; k < npoints; ++k) {
+        if (!isfinite(u[k]) || !isfinite(f[k])) return fail(h, MD_ERR_ARG, "non-finite table value");
+        v[k] = make_float2((float)u[k], (float)f[k]);
+    }
+    for (int pass = 0; pass < 2; ++pass) {
+        const int tp = pass == 0 ? ti * MD_MAX_TYPES + tj : tj * MD_MAX_TYPES + ti;
+        md_status r = upload_table_row(h, kCgTableRow + tp, v);
+        if (r != MD_OK) return r;
+        h->cgn[tp] = npoints;
+        h->cg_rmin[tp] = rmin;
+        h->cg_rc[tp] = rc_cg;
+    }
+    double mass[MD_MAX_TYPES];
+    for (int t = 0; t < MD_MAX_TYPES; ++t) mass[t] = h->dy.mass[t];
+    fill_params(h, &h->cfg);
+    fill_masses(h, mass);
+    drop_graph(h);
+    return MD_OK;
+}
+
+md_status md_set_angle_subens(md_handle h, int32_t ntables, const double* u, const double* dudphi,
+                              const double* weights, int32_t npoints) {
+    if (!h) return fail(nullptr, MD_ERR_ARG, "NULL handle");
+    if (ntables < 1 || !u || !dudphi || !weights || npoints < 2 || npoints > h->cfg.table_points)
+        return fail(h, MD_ERR_ARG, "need ntables >= 1, u, dudphi, weights and 2 <= npoints <= table_points");
+    std::vector<float2> v(npoints);
+    for (int k = 0; k < npoints; ++k) {
+        double su = 0.0, sg = 0.0;
+        for (int m = 0; m < ntables; ++m) {
+            su += weights[m] * u[(size_t)m * npoints + k];
+            sg += weights[m] * dudphi[(size_t)m * npoints + k];
+        }
+        if (!isfinite(su) || !isfinite(sg)) return fail(h, MD_ERR_ARG, "non-finite table value");
+        v[k] = make_float2((float)su, (float)sg);
+    }
+    md_status r = upload_table_row(h, kAngleTableRow, v);
+    if (r != MD_OK) return r;
+    h->ang_n = npoints;
+    double mass[MD_MAX_TYPES];
+    for (int t = 0; t < MD_MAX_TYPES; ++t) mass[t] = h->dy.mass[t];
+    fill_params(h, &h->cfg);
+    fill_masses(h, mass);
+    drop_graph(h);
+    return MD_OK;
+}
+
+md_status md_set_angle_table(md_handle h, const double* u, const double* dudphi, int32_t npoints) {
+    const double one = 1.0;
+    return md_set_angle_subens(h, 1, u, dudphi, &one, npoints);
+}
+
 md_status md_build_neighbors(md_handle h) {
     if (!h) return fail(nullptr, MD_ERR_ARG, "NULL handle");
     return rebuild_now(h, 1);
@@ -860,6 +1048,7 @@ md_status md_build_neighbors(md_handle h) {
 
 md_status md_forces(md_handle h, double* f_out) {
     if (!h) return fail(nullptr, MD_ERR_ARG, "NULL handle");
+    if (need_tables(h) != MD_OK) return MD_ERR_STATE;
     md_status r = rebuild_now(h, 0);
     if (r != MD_OK) return r;
     const double* spart = nullptr;
@@ -871,6 +1060,7 @@ md_status md_forces(md_handle h, double* f_out) {
 md_status md_step(md_handle h, int64_t nsteps) {
     if (!h) return fail(nullptr, MD_ERR_ARG, "NULL handle");
     if (nsteps < 0) return fail(h, MD_ERR_ARG, "nsteps < 0");
+    if (need_tables(h) != MD_OK) return MD_ERR_STATE;
     const bool use_graph = !(h->cfg.flags & MD_CFG_NO_GRAPH) && !h->timing && h->stream != nullptr;
     int64_t left = nsteps;
     while (left > 0) {
@@ -912,6 +1102,7 @@ md_status md_step(md_handle h, int64_t nsteps) {
 
 md_status md_observables(md_handle h, md_obs* out) {
     if (!h || !out) return fail(h, MD_ERR_ARG, "NULL handle or output");
+    if (need_tables(h) != MD_OK) return MD_ERR_STATE;
     md_status r = rebuild_now(h, 0);
     if (r != MD_OK) return r;
     const double* spart = nullptr;
@@ -1234,10 +1425,11 @@ md_status plan_batch(const md_config* cfgs, int32_t nsys, BatchPlan* p, std::str
         }
         const md_pair_params& pp = c->pair[0];
         if (c->n_types != 1 || c->force_precision != MD_FP32 || pp.caprad > 0.0 || c->box[0] != c->box[1] ||
-            c->box[1] != c->box[2] || c->surrogate || c->integrator == MD_DPD || c->shear_rate != 0.0) {
+            c->box[1] != c->box[2] || c->surrogate || c->integrator == MD_DPD || c->shear_rate != 0.0 ||
+            c->table_points != 0 || c->angle_kind != MD_ANGLE_COSINE || c->adress) {
             *why = "system " + std::to_string(s) +
                    ": batch members need one particle type, FP32 pair math, a cubic box, no capping radius, "
-                   "no surrogate, no DPD and no shear";
+                   "no surrogate, no DPD, no shear, no tables, the cosine angle and no AdResS";
             return MD_ERR_ARG;
         }
         if (c->n_particles > (int64_t)kBlock * 1024) {

@@ -58,7 +58,23 @@ struct PairTable {
     // decision is retaken in FP64 from the FP64 positions
     float rc2lo[MD_MAX_TYPES * MD_MAX_TYPES];
     float rc2hi[MD_MAX_TYPES * MD_MAX_TYPES];
+    // tabulated pairs: points (0 = Lennard-Jones), rmin and 1 / grid step;
+    // values (u, f) in Bufs::tab rows [pair][table_points]
+    int32_t tabn[MD_MAX_TYPES * MD_MAX_TYPES];
+    float tab_rmin[MD_MAX_TYPES * MD_MAX_TYPES];
+    float tab_idr[MD_MAX_TYPES * MD_MAX_TYPES];
+    // AdResS coarse-grained tables (rows kCgTableRow + pair): points (0 = none),
+    // rmin, 1 / grid step, and the cutoff (FP64, with the fixed-point band)
+    int32_t cgn[MD_MAX_TYPES * MD_MAX_TYPES];
+    float cg_rmin[MD_MAX_TYPES * MD_MAX_TYPES];
+    float cg_idr[MD_MAX_TYPES * MD_MAX_TYPES];
+    double cg_rc2d[MD_MAX_TYPES * MD_MAX_TYPES];
+    float cg_rc2lo[MD_MAX_TYPES * MD_MAX_TYPES];
+    float cg_rc2hi[MD_MAX_TYPES * MD_MAX_TYPES];
 };
+constexpr int kAngleTableRow = MD_MAX_TYPES * MD_MAX_TYPES;   // row of the angle table in Bufs::tab
+constexpr int kCgTableRow = kAngleTableRow + 1;               // first coarse-grained row
+constexpr int kTableRows = kCgTableRow + MD_MAX_TYPES * MD_MAX_TYPES;
 
 // Everything a kernel of one handle needs; passed by value.
 struct Geom {
@@ -94,6 +110,7 @@ struct Geom {
     double le_rate_Ly;      // shear_rate * Ly
     double le_dt;           // dt (the offset assumes a constant time step)
     double skin;
+    int32_t table_points;   // row length of Bufs::tab
 };
 
 struct Bufs {
@@ -130,6 +147,7 @@ struct Bufs {
     int32_t* bp_s;          // [MAXB][N]
     int2* ang_s;            // [MAXA][N]
     int32_t maxb, maxa;     // row counts actually used (<= limits)
+    float2* tab;            // [kTableRows][table_points] (u, f) or (u, du/dphi); or null
 };
 
 struct Dyn {
@@ -150,6 +168,16 @@ struct Dyn {
     float dpd_rc, dpd_rc2;
     float dpd_gamma;
     float dpd_sigma_isdt;   // sqrt(2 gamma kT) / sqrt(dt)
+    // the generic FP32 step kernel is needed (shear, DPD, tables, angle kinds)
+    int32_t gen;
+    int32_t angle_kind;     // MD_ANGLE_*
+    float angle_K, cos_phi0;
+    int32_t ang_n;          // points of the angle table
+    float ang_idphi;        // (ang_n - 1) / pi
+    const float2* ang_tab;  // the angle table (u, du/dphi), or null
+    // AdResS slab along x: weight 1 within d_at of x0, cos^2 switch over d_hy
+    int32_t adress;
+    float ad_x0, ad_dat, ad_dhy, ad_k;   // ad_k = pi / (2 d_hy)
 };
 
 // internal status bit (init only): a particle type outside 0..n_types-1
@@ -306,6 +334,9 @@ hipError_t launch_clear_rebuild(const Bufs& b, hipStream_t s);
 hipError_t launch_step(const StepArgs& a, int fp64, int single_type, int bonded, int block,
                        hipStream_t s);
 int step_grid(int64_t n);
+// blocks of the plain force kernel that launch_step runs with `block`
+// threads per block (the FP32 fast kernels take 64..512; the others 256)
+int step_launch_grid(const StepArgs& a, int fp64, int block);
 // spart: surrogate partials (row 0 energy; with spart_rows 8 also virial and
 // tensor rows), or nullptr
 hipError_t launch_finalize(const Bufs& b, int nblocks, int mode, const double* spart, int tensor, hipStream_t s,

@@ -1058,7 +1058,10 @@ __device__ __forceinline__ void add_tensor(double* acc, double s, double rx, dou
 // rows of the sorted-space topology.  Each bond is evaluated by both ends
 // (half the energy each), each angle by its three members (energy counted
 // by the centre); no atomics.
-template <typename Real, typename P, typename Diff>
+// EXT (the generic FP32 kernel): the angle kinds MD_ANGLE_COSINE_SQUARED
+// and MD_ANGLE_TABULATED besides the cosine bending, through
+// dU/dcos(theta), theta = pi - phi the angle between b1 and b2.
+template <typename Real, typename P, typename Diff, bool EXT = false>
 __device__ __forceinline__ void bonded_forces(const Bufs& b, const Dyn& dyn, int64_t n, int64_t i,
                                               const P* __restrict__ xs, const P& pi, const Diff& diff,
                                               Real& fx, Real& fy, Real& fz, double* acc, bool tensor,
@@ -1111,7 +1114,45 @@ __device__ __forceinline__ void bonded_forces(const Bufs& b, const Dyn& dyn, int
         const Real cs = (b1x * b2x + b1y * b2y + b1z * b2z) * il1l2;
         const Real i1 = rcp<Real>(l1sq), i2 = rcp<Real>(l2sq);
         Real Fx, Fy, Fz;
-        if (role == 0) {          // F_A = -k dcos/db1
+        if (EXT && dyn.angle_kind != MD_ANGLE_COSINE) {
+            // dUdc = dU/dcos(theta); cos(phi) = -cs
+            Real dUdc, ua;
+            if (dyn.angle_kind == MD_ANGLE_COSINE_SQUARED) {
+                const Real d = -cs - (Real)dyn.cos_phi0;
+                ua = (Real)dyn.angle_K * d * d;
+                dUdc = Real(-2) * (Real)dyn.angle_K * d;
+            } else {
+                const float cphi = (float)(-cs > Real(1) ? Real(1) : (-cs < Real(-1) ? Real(-1) : -cs));
+                const float phi = acosf(cphi);
+                const float q = phi * dyn.ang_idphi;
+                int k = (int)q;
+                k = k > dyn.ang_n - 2 ? dyn.ang_n - 2 : k;
+                const float al = q - (float)k;
+                const float2 t0 = dyn.ang_tab[k], t1 = dyn.ang_tab[k + 1];
+                ua = (Real)((1.f - al) * t0.x + al * t1.x);
+                const float gphi = (1.f - al) * t0.y + al * t1.y;       // du/dphi
+                const float sn = sinf(phi);
+                dUdc = (Real)(gphi / (sn > 1e-8f ? sn : 1e-8f));        // dU/dcos(theta) = -dU/dcos(phi)
+            }
+            const Real dA0 = b2x * il1l2 - cs * b1x * i1, dA1 = b2y * il1l2 - cs * b1y * i1,
+                       dA2 = b2z * il1l2 - cs * b1z * i1;          // dcos/db1
+            const Real dC0 = b1x * il1l2 - cs * b2x * i2, dC1 = b1y * il1l2 - cs * b2y * i2,
+                       dC2 = b1z * il1l2 - cs * b2z * i2;          // dcos/db2
+            if (role == 0) {
+                Fx = dUdc * dA0; Fy = dUdc * dA1; Fz = dUdc * dA2;
+                wa += -(b1x * Fx + b1y * Fy + b1z * Fz);
+                if (tensor) add_tensor(acc, 1.0, -b1x, -b1y, -b1z, Fx, Fy, Fz);
+            } else if (role == 2) {
+                Fx = -dUdc * dC0; Fy = -dUdc * dC1; Fz = -dUdc * dC2;
+                wa += b2x * Fx + b2y * Fy + b2z * Fz;
+                if (tensor) add_tensor(acc, 1.0, b2x, b2y, b2z, Fx, Fy, Fz);
+            } else {
+                Fx = -(dUdc * dA0 - dUdc * dC0);
+                Fy = -(dUdc * dA1 - dUdc * dC1);
+                Fz = -(dUdc * dA2 - dUdc * dC2);
+                ea += ua;
+            }
+        } else if (role == 0) {          // F_A = -k dcos/db1
             Fx = -kb * (b2x * il1l2 - cs * b1x * i1);
             Fy = -kb * (b2y * il1l2 - cs * b1y * i1);
             Fz = -kb * (b2z * il1l2 - cs * b1z * i1);
@@ -1250,7 +1291,9 @@ __device__ __forceinline__ void finish_particle(const StepArgs& a, int64_t i, co
 }
 
 // Flags (one store or atomic per wave) and the deterministic block
-// reduction of the per-particle sums into partials[k][block].
+// reduction of the per-particle sums into partials[k][block]; BS threads per
+// block.
+template <int BS = kBlock>
 __device__ __forceinline__ void block_epilogue(const StepArgs& a, const double* acc, bool flag_reb,
                                               bool flag_bond, bool flag_nf, int nacc, int64_t slot = -1,
                                               int64_t nslots = 0) {
@@ -1267,7 +1310,7 @@ __device__ __forceinline__ void block_epilogue(const StepArgs& a, const double* 
         if (any_bond) atomicOr(&b.ctl->status, MD_FLAG_BOND_BROKEN);
         if (any_nf) atomicOr(&b.ctl->status, MD_FLAG_NONFINITE);
     }
-    __shared__ double red[kBlock / 64][kNacc];
+    __shared__ double red[BS / 64][kNacc];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     for (int q = 0; q < nacc; ++q) {
         const double s = wave_sum(acc[q]);
@@ -1277,7 +1320,7 @@ __device__ __forceinline__ void block_epilogue(const StepArgs& a, const double* 
     if (threadIdx.x < kNacc) {
         double s = 0.0;
         if ((int)threadIdx.x < nacc)
-            for (int ww = 0; ww < kBlock / 64; ++ww) s += red[ww][threadIdx.x];
+            for (int ww = 0; ww < BS / 64; ++ww) s += red[ww][threadIdx.x];
         b.partials[(int64_t)threadIdx.x * nslots + slot] = s;
     }
 }
@@ -1394,7 +1437,19 @@ __global__ void __launch_bounds__(kBlock) k_step_q(const StepArgs a) {
             if (in) {
                 const PairCoef<float>& c = a.pt.f[tp];
                 float fr, u;
-                if (c.cap2 > 0.f && r2 < c.cap2) {
+                if (a.pt.tabn[tp] > 1) {
+                    // tabulated: u and f = -du/dr linear in r on the pair's grid
+                    const float r = sqrtf(r2);
+                    float q = (r - a.pt.tab_rmin[tp]) * a.pt.tab_idr[tp];
+                    q = q > 0.f ? q : 0.f;
+                    int kq = (int)q;
+                    kq = kq > a.pt.tabn[tp] - 2 ? a.pt.tabn[tp] - 2 : kq;
+                    const float al = q - (float)kq;
+                    const float2* trow = b.tab + (int64_t)tp * g.table_points;
+                    const float2 t0 = trow[kq], t1 = trow[kq + 1];
+                    u = (1.f - al) * t0.x + al * t1.x;
+                    fr = ((1.f - al) * t0.y + al * t1.y) / r;
+                } else if (c.cap2 > 0.f && r2 < c.cap2) {
                     fr = c.fcap * __builtin_amdgcn_rsqf(r2);
                     u = c.ucap;
                 } else {
@@ -1582,35 +1637,53 @@ __device__ __forceinline__ void fast_particle(const StepArgs& a, int64_t i, doub
     }
 }
 
-template <bool BONDED, bool TENSOR>
+// BS particles per block (64 .. 512, the block dimension the autotuner
+// picks); one block per BS-particle tile, blocks in XCD-contiguous order.
+template <bool BONDED, bool TENSOR, int BS>
 __device__ __forceinline__ void step_fast_body(const StepArgs& a) {
     const int64_t n = a.g.n;
     double acc[kNacc];
 #pragma unroll
     for (int k = 0; k < kNacc; ++k) acc[k] = 0.0;
     bool flag_reb = false, flag_bond = false, flag_nf = false;
-    const int64_t ntile = (n + kBlock - 1) / kBlock;
+    const int64_t ntile = (n + BS - 1) / BS;
     const int64_t bt = xcd_block(blockIdx.x, gridDim.x);
     for (int64_t t = bt * ntile / gridDim.x; t < (bt + 1) * ntile / gridDim.x; ++t) {
-        const int64_t i = t * kBlock + threadIdx.x;
+        const int64_t i = t * BS + threadIdx.x;
         if (i < n) fast_particle<BONDED, TENSOR>(a, i, acc, flag_reb, flag_bond, flag_nf);
     }
-    block_epilogue(a, acc, flag_reb, flag_bond, flag_nf, TENSOR ? kNacc : A_VIR + 1);
+    block_epilogue<BS>(a, acc, flag_reb, flag_bond, flag_nf, TENSOR ? kNacc : A_VIR + 1);
 }
 
-template <bool TENSOR>
-__global__ void __launch_bounds__(kBlock) k_step_fast(const StepArgs a) {
-    step_fast_body<false, TENSOR>(a);
+// The LJ form: 139-142 VGPRs, 3 wavefronts per SIMD, at every block size.
+template <bool TENSOR, int BS>
+__global__ void __launch_bounds__(BS)
+k_step_fast(const StepArgs a) {
+    step_fast_body<false, TENSOR, BS>(a);
 }
 
 // The bonded form is capped at 128 VGPRs (4 wavefronts per SIMD instead of
 // 3, a few bytes of spill): 6% faster on the 2M-bead melt, whose list is
 // short and whose bonded partners add gathers; the same cap costs the LJ
 // kernel 4%, so it keeps its 144 registers.
-template <bool TENSOR>
-__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4)))
+template <bool TENSOR, int BS>
+__global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4)))
 k_step_fast_bonded(const StepArgs a) {
-    step_fast_body<true, TENSOR>(a);
+    step_fast_body<true, TENSOR, BS>(a);
+}
+
+// AdResS weight of a position x along the slab axis: 1 within d_at of x0
+// (minimum image), cos^2(pi (d - d_at) / (2 d_hy)) over the hybrid zone, 0
+// beyond.
+__device__ __forceinline__ float adress_weight(const Dyn& dy, float x, float Lx) {
+    float d = x - dy.ad_x0;
+    if (d > 0.5f * Lx) d -= Lx;
+    else if (d < -0.5f * Lx) d += Lx;
+    d = fabsf(d);
+    if (d < dy.ad_dat) return 1.f;
+    if (d >= dy.ad_dat + dy.ad_dhy) return 0.f;
+    const float cz = cosf(dy.ad_k * (d - dy.ad_dat));
+    return cz * cz;
 }
 
 // theta_ij of the DPD thermostat: Philox4x64-10 keyed (seed, 6) at counter
@@ -1623,17 +1696,19 @@ __device__ __forceinline__ double dpd_theta(uint64_t seed, uint64_t step, uint32
     return sqrt(-2.0 * log(u0)) * cos(6.283185307179586 * u1);
 }
 
-// FP32 step with the DPD pair thermostat (MD_DPD) and / or Lees-Edwards
-// shear, one 256-particle tile per block: the pair table (any types, capping
-// radius) and the bonded terms under the sheared minimum image, the DPD
-// forces from the half-step velocities (MODE_STEP only: a thermostat force,
-// not part of md_forces), then the integration with the sheared boundary
-// crossing.  The DPD pair force on i, with e = (r_i - r_j)/r, w = 1 - r/rc_d:
+// Generic FP32 step, one 256-particle tile per block, for what the fast
+// kernels leave out: the DPD pair thermostat (MD_DPD), Lees-Edwards shear,
+// tabulated pair potentials and the angle kinds beyond the cosine bending.
+// The pair table (any types, capping radius, or a tabulated pair: u and f
+// interpolated linearly in r) and the bonded terms under the sheared minimum
+// image, the DPD forces from the half-step velocities (MODE_STEP only: a
+// thermostat force, not part of md_forces), then the integration with the
+// sheared boundary crossing.  The DPD pair force on i, with e = (r_i - r_j)/r, w = 1 - r/rc_d:
 //   (-gamma w^2 (e . v_ij) + sigma w theta_ij / sqrt(dt)) e,
 // computed by both members of a pair with the same theta_ij, so the two
 // contributions cancel to FP32 rounding.
 template <bool BONDED>
-__global__ void __launch_bounds__(kBlock) k_step_le(const StepArgs a) {
+__global__ void __launch_bounds__(kBlock) k_step_gen(const StepArgs a) {
     const Geom& g = a.g;
     const Bufs& b = a.b;
     const int64_t n = g.n;
@@ -1664,10 +1739,14 @@ __global__ void __launch_bounds__(kBlock) k_step_le(const StepArgs a) {
         const DiffLEQ df{g.ql[0], g.ql[1], g.ql[2], qd};
         float fx = 0.f, fy = 0.f, fz = 0.f, ue = 0.f, we = 0.f;
         float txx = 0.f, tyy = 0.f, tzz = 0.f, txy = 0.f, txz = 0.f, tyz = 0.f;
+        const float wi = a.dy.adress ? adress_weight(a.dy, (float)xi.x, (float)g.L[0]) : 1.f;
+        // DPD reads the half-step velocities from the snapshot in b.vt taken
+        // before this kernel (b.v is overwritten here as particles finish)
+        const double* __restrict__ vs = b.vt;
         double vi[3] = {0.0, 0.0, 0.0};
         uint32_t tgi = 0;
         if (dpd) {
-            for (int d = 0; d < 3; ++d) vi[d] = b.v[d * n + i];
+            for (int d = 0; d < 3; ++d) vi[d] = vs[d * n + i];
             tgi = (uint32_t)b.tag[i];
         }
         int cnt = b.ncount[i];
@@ -1682,10 +1761,42 @@ __global__ void __launch_bounds__(kBlock) k_step_le(const StepArgs a) {
             const int tp = ti * MD_MAX_TYPES + qj.w;
             bool in = r2 < a.pt.rc2lo[tp];
             if (!in && r2 < a.pt.rc2hi[tp]) in = exact_r2_le(g, xi, x64[j], dw) < a.pt.rc2d[tp];
-            if (in) {
+            // AdResS: the coarse-grained force of the pair, to be mixed in below
+            bool cg_in = false;
+            float ucg = 0.f, frcg = 0.f;
+            if (a.dy.adress && a.pt.cgn[tp] > 1) {
+                cg_in = r2 < a.pt.cg_rc2lo[tp];
+                if (!cg_in && r2 < a.pt.cg_rc2hi[tp]) cg_in = exact_r2_le(g, xi, x64[j], dw) < a.pt.cg_rc2d[tp];
+                if (cg_in) {
+                    const float r = sqrtf(r2);
+                    float q = (r - a.pt.cg_rmin[tp]) * a.pt.cg_idr[tp];
+                    q = q > 0.f ? q : 0.f;
+                    int kq = (int)q;
+                    kq = kq > a.pt.cgn[tp] - 2 ? a.pt.cgn[tp] - 2 : kq;
+                    const float al = q - (float)kq;
+                    const float2* trow = b.tab + (int64_t)(kCgTableRow + tp) * g.table_points;
+                    const float2 t0 = trow[kq], t1 = trow[kq + 1];
+                    ucg = (1.f - al) * t0.x + al * t1.x;
+                    frcg = ((1.f - al) * t0.y + al * t1.y) / r;
+                }
+            }
+            if (in || cg_in) {
                 const PairCoef<float>& c = a.pt.f[tp];
-                float fr, u;
-                if (c.cap2 > 0.f && r2 < c.cap2) {
+                float fr = 0.f, u = 0.f;
+                if (!in) {
+                } else if (a.pt.tabn[tp] > 1) {
+                    // tabulated: u and f = -du/dr linear in r on the pair's grid
+                    const float r = sqrtf(r2);
+                    float q = (r - a.pt.tab_rmin[tp]) * a.pt.tab_idr[tp];
+                    q = q > 0.f ? q : 0.f;
+                    int kq = (int)q;
+                    kq = kq > a.pt.tabn[tp] - 2 ? a.pt.tabn[tp] - 2 : kq;
+                    const float al = q - (float)kq;
+                    const float2* trow = b.tab + (int64_t)tp * g.table_points;
+                    const float2 t0 = trow[kq], t1 = trow[kq + 1];
+                    u = (1.f - al) * t0.x + al * t1.x;
+                    fr = ((1.f - al) * t0.y + al * t1.y) / r;
+                } else if (c.cap2 > 0.f && r2 < c.cap2) {
                     fr = c.fcap * __builtin_amdgcn_rsqf(r2);
                     u = c.ucap;
                 } else {
@@ -1694,6 +1805,12 @@ __global__ void __launch_bounds__(kBlock) k_step_le(const StepArgs a) {
                     const float s6 = s2 * s2 * s2;
                     fr = c.eps24 * s6 * (2.f * s6 - 1.f) * inv;
                     u = c.eps4 * s6 * (s6 - 1.f) - c.shift;
+                }
+                if (a.dy.adress) {
+                    // x_j from its fixed-point coordinate (positions lie in [0, L))
+                    const float lam = wi * adress_weight(a.dy, (float)(uint32_t)qj.x * g.ql[0], (float)g.L[0]);
+                    u = lam * u + (1.f - lam) * ucg;
+                    fr = lam * fr + (1.f - lam) * frcg;
                 }
                 fx -= fr * dx;
                 fy -= fr * dy;
@@ -1711,9 +1828,9 @@ __global__ void __launch_bounds__(kBlock) k_step_le(const StepArgs a) {
                 const float ir = 1.f / r;
                 const float ex = -dx * ir, ey = -dy * ir, ez = -dz * ir;
                 // v_i - (v_j - s shear_rate Ly e_x), in FP64 then rounded once
-                const float vx = (float)(vi[0] - b.v[j] + s * g.le_rate_Ly);
-                const float vy = (float)(vi[1] - b.v[n + j]);
-                const float vz = (float)(vi[2] - b.v[2 * n + j]);
+                const float vx = (float)(vi[0] - vs[j] + s * g.le_rate_Ly);
+                const float vy = (float)(vi[1] - vs[n + j]);
+                const float vz = (float)(vi[2] - vs[2 * n + j]);
                 const float ev = ex * vx + ey * vy + ez * vz;
                 const float th = (float)dpd_theta(a.dy.seed, (uint64_t)step, tgi, (uint32_t)b.tag[j]);
                 const float A = -a.dy.dpd_gamma * w * w * ev + a.dy.dpd_sigma_isdt * w * th;
@@ -1732,7 +1849,8 @@ __global__ void __launch_bounds__(kBlock) k_step_le(const StepArgs a) {
             const auto dfb = [&df](const int4& p, const int4& q, float& ddx, float& ddy, float& ddz) {
                 (void)df(p, q, ddx, ddy, ddz);
             };
-            bonded_forces<float, int4>(b, a.dy, n, i, xq, qi, dfb, fx, fy, fz, acc, tensor, flag_bond);
+            bonded_forces<float, int4, decltype(dfb), true>(b, a.dy, n, i, xq, qi, dfb, fx, fy, fz, acc, tensor,
+                                                            flag_bond);
         }
         const double F[3] = {(double)fx, (double)fy, (double)fz};
         finish_particle(a, i, xi, ti, F, acc, flag_reb, flag_nf, g.le ? &les : nullptr);
@@ -2231,12 +2349,42 @@ hipError_t launch_rebuild(const Geom& g, const Bufs& b, int parity, int bonded, 
     return hipGetLastError();
 }
 
+int step_launch_grid(const StepArgs& a, int fp64, int block) {
+    if (a.dy.gen || fp64 || !a.use_fast || block == kBlock) return step_grid(a.g.n);
+    const int64_t t = (a.g.n + block - 1) / block;
+    return (int)(t < 1 ? 1 : t);
+}
+
+template <bool BONDED, bool TENSOR>
+static void launch_fast(const StepArgs& a, int block, hipStream_t s) {
+    const dim3 grid((unsigned)step_launch_grid(a, 0, block)), blk((unsigned)block);
+#define MD_LF(BS)                                                                                  \
+    do {                                                                                           \
+        if (BONDED) hipLaunchKernelGGL((k_step_fast_bonded<TENSOR, BS>), grid, blk, 0, s, a);     \
+        else hipLaunchKernelGGL((k_step_fast<TENSOR, BS>), grid, blk, 0, s, a);                   \
+    } while (0)
+    switch (block) {
+        case 64: MD_LF(64); break;
+        case 128: MD_LF(128); break;
+        case 512: MD_LF(512); break;
+        default: MD_LF(256); break;
+    }
+#undef MD_LF
+}
+
+// Velocity snapshot for the DPD pair term: b.vt (the sort's scratch, free
+// after the rebuild stage) <- b.v, [3][N] FP64.
+__global__ void __launch_bounds__(kBlock) k_snapshot_v(const Bufs b, int64_t len) {
+    for (int64_t k = gtid(); k < len; k += gstride()) b.vt[k] = b.v[k];
+}
+
 hipError_t launch_step(const StepArgs& a, int fp64, int single_type, int bonded, int block, hipStream_t s) {
-    (void)block;
     dim3 grid((unsigned)step_grid(a.g.n)), blk(kBlock);
-    if (a.g.le || a.dy.dpd) {
-        if (bonded) hipLaunchKernelGGL(k_step_le<true>, grid, blk, 0, s, a);
-        else hipLaunchKernelGGL(k_step_le<false>, grid, blk, 0, s, a);
+    if (a.dy.gen && a.dy.dpd && a.mode == MODE_STEP)
+        hipLaunchKernelGGL(k_snapshot_v, dim3(grid_for(3 * a.g.n)), dim3(kBlock), 0, s, a.b, 3 * a.g.n);
+    if (a.dy.gen) {
+        if (bonded) hipLaunchKernelGGL(k_step_gen<true>, grid, blk, 0, s, a);
+        else hipLaunchKernelGGL(k_step_gen<false>, grid, blk, 0, s, a);
     } else if (fp64) {
 #define MD_L64(S, B) hipLaunchKernelGGL((k_step64<S, B>), grid, blk, 0, s, a)
         if (single_type) { if (bonded) MD_L64(true, true); else MD_L64(true, false); }
@@ -2245,11 +2393,11 @@ hipError_t launch_step(const StepArgs& a, int fp64, int single_type, int bonded,
     } else if (a.use_fast) {
         const bool t = a.tensor != 0;
         if (bonded) {
-            if (t) hipLaunchKernelGGL(k_step_fast_bonded<true>, grid, blk, 0, s, a);
-            else hipLaunchKernelGGL(k_step_fast_bonded<false>, grid, blk, 0, s, a);
+            if (t) launch_fast<true, true>(a, block, s);
+            else launch_fast<true, false>(a, block, s);
         } else {
-            if (t) hipLaunchKernelGGL(k_step_fast<true>, grid, blk, 0, s, a);
-            else hipLaunchKernelGGL(k_step_fast<false>, grid, blk, 0, s, a);
+            if (t) launch_fast<false, true>(a, block, s);
+            else launch_fast<false, false>(a, block, s);
         }
     } else {
 #define MD_LQ(S, B, T) hipLaunchKernelGGL((k_step_q<S, B, T>), grid, blk, 0, s, a)

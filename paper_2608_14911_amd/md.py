@@ -34,6 +34,9 @@ MD_FLAG_NONFINITE = 0x4
 MD_NVE = 0
 MD_LANGEVIN = 1
 MD_DPD = 2
+MD_ANGLE_COSINE = 0
+MD_ANGLE_COSINE_SQUARED = 1
+MD_ANGLE_TABULATED = 2
 MD_FP64 = 0
 MD_FP32 = 1
 MD_MAX_TYPES = 4
@@ -61,7 +64,8 @@ EXPORTED = ["md_workspace_bytes", "md_plan_config", "md_init", "md_set_params", 
             "md_set_pair_mode", "md_sur_descriptors", "md_sur_mlp_eval", "md_sur_pair_forces", "md_sur_loss_grad",
             "md_sur_adam", "md_batch_workspace_bytes", "md_batch_init", "md_batch_step",
             "md_batch_observables", "md_batch_get_state", "md_batch_destroy", "md_batch_last_error",
-            "md_batch_timing_enable", "md_batch_timing_read", "md_init_static"]
+            "md_batch_timing_enable", "md_batch_timing_read", "md_init_static", "md_set_pair_table",
+            "md_set_angle_table", "md_set_angle_subens", "md_set_cg_table"]
 
 
 class md_pair_params(ctypes.Structure):
@@ -80,7 +84,10 @@ class md_config(ctypes.Structure):
                 ("k_bend", ctypes.c_double), ("cell_factor", ctypes.c_int32),
                 ("nl_capacity", ctypes.c_int32), ("block_size", ctypes.c_int32), ("flags", ctypes.c_int32),
                 ("list_cutoff", ctypes.c_double), ("surrogate", ctypes.c_int32), ("pad_", ctypes.c_int32),
-                ("shear_rate", ctypes.c_double), ("dpd_rc", ctypes.c_double)]
+                ("shear_rate", ctypes.c_double), ("dpd_rc", ctypes.c_double), ("table_points", ctypes.c_int32),
+                ("angle_kind", ctypes.c_int32), ("angle_K", ctypes.c_double), ("angle_phi0", ctypes.c_double),
+                ("adress", ctypes.c_int32), ("pad2_", ctypes.c_int32), ("adress_x0", ctypes.c_double),
+                ("adress_d_at", ctypes.c_double), ("adress_d_hy", ctypes.c_double)]
 
 
 class md_obs(ctypes.Structure):
@@ -137,6 +144,10 @@ def lib():
         "md_init": [ctypes.POINTER(md_config), P, P, P, P, P, P, P, SZ, P, ctypes.POINTER(P)],
         "md_init_static": [ctypes.POINTER(md_config), P, P, P, P, P, P, P, ctypes.POINTER(P)],
         "md_set_params": [P, ctypes.POINTER(md_config)],
+        "md_set_pair_table": [P, I32, I32, P, P, I32, ctypes.c_double],
+        "md_set_angle_table": [P, P, P, I32],
+        "md_set_angle_subens": [P, I32, P, P, P, I32],
+        "md_set_cg_table": [P, I32, I32, P, P, I32, ctypes.c_double, ctypes.c_double],
         "md_build_neighbors": [P],
         "md_forces": [P, P],
         "md_step": [P, I64],
@@ -212,7 +223,8 @@ def _p(x):
 def make_config(n, box, *, n_types=1, pair=None, dt=0.005, skin=0.3, integrator=MD_NVE,
                 force_precision=MD_FP32, temperature=1.0, gamma=0.0, seed=0, n_bonds=0, n_angles=0,
                 fene_K=30.0, fene_R0=1.5, k_bend=0.0, nl_capacity=0, flags=0, cell_factor=0,
-                list_cutoff=0.0, surrogate=0, shear_rate=0.0, dpd_rc=0.0):
+                list_cutoff=0.0, surrogate=0, shear_rate=0.0, dpd_rc=0.0, table_points=0, angle_kind=0,
+                angle_K=0.0, angle_phi0=0.0, adress=None, block_size=0):
     """Fill an md_config.  pair: dict (ti, tj) -> (eps, sigma, rc, shift, caprad)."""
     c = md_config()
     c.struct_size = ctypes.sizeof(md_config)
@@ -231,12 +243,20 @@ def make_config(n, box, *, n_types=1, pair=None, dt=0.005, skin=0.3, integrator=
     c.n_bonds, c.n_angles = int(n_bonds), int(n_angles)
     c.fene_K, c.fene_R0, c.k_bend = float(fene_K), float(fene_R0), float(k_bend)
     c.nl_capacity = int(nl_capacity)
+    c.block_size = int(block_size)
     c.cell_factor = int(cell_factor)
     c.flags = int(flags)
     c.list_cutoff = float(list_cutoff)
     c.surrogate = int(surrogate)
     c.shear_rate = float(shear_rate)
     c.dpd_rc = float(dpd_rc)
+    c.table_points = int(table_points)
+    c.angle_kind = int(angle_kind)
+    c.angle_K = float(angle_K)
+    c.angle_phi0 = float(angle_phi0)
+    if adress is not None:
+        c.adress = 1
+        c.adress_x0, c.adress_d_at, c.adress_d_hy = (float(v) for v in adress)
     return c
 
 
@@ -283,6 +303,36 @@ def md_init_static(cfg, pos, vel, type, mass_by_type, bonds, angles, stream):
 
 def md_set_params(h, cfg):
     _check(lib().md_set_params(h, ctypes.byref(cfg)), "md_set_params", h)
+
+
+def md_set_pair_table(h, ti, tj, u, f, rmin):
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    assert u.shape == f.shape
+    _check(lib().md_set_pair_table(h, int(ti), int(tj), _p(u), _p(f), u.size, float(rmin)), "md_set_pair_table", h)
+
+
+def md_set_cg_table(h, ti, tj, u, f, rmin, rc_cg):
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    assert u.shape == f.shape
+    _check(lib().md_set_cg_table(h, int(ti), int(tj), _p(u), _p(f), u.size, float(rmin), float(rc_cg)),
+           "md_set_cg_table", h)
+
+
+def md_set_angle_table(h, u, dudphi):
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    g = np.ascontiguousarray(dudphi, dtype=np.float64)
+    assert u.shape == g.shape
+    _check(lib().md_set_angle_table(h, _p(u), _p(g), u.size), "md_set_angle_table", h)
+
+
+def md_set_angle_subens(h, u_tables, g_tables, weights):
+    u = np.ascontiguousarray(u_tables, dtype=np.float64)
+    g = np.ascontiguousarray(g_tables, dtype=np.float64)
+    w = np.ascontiguousarray(weights, dtype=np.float64)
+    assert u.shape == g.shape and u.shape[0] == w.size
+    _check(lib().md_set_angle_subens(h, u.shape[0], _p(u), _p(g), _p(w), u.shape[1]), "md_set_angle_subens", h)
 
 
 def md_build_neighbors(h):

@@ -26,7 +26,8 @@ class System:
                  bonds=None, angles=None, dt=0.005, skin=0.3, integrator="nve", precision="fp32",
                  temperature=1.0, gamma=0.0, seed=0, fene_K=30.0, fene_R0=1.5, k_bend=0.0,
                  nl_capacity=0, flags=0, cell_factor=0, list_cutoff=0.0, surrogate=False, shear_rate=0.0,
-                 dpd_rc=0.0, device="cuda"):
+                 dpd_rc=0.0, table_points=0, angle_kind=0, angle_K=0.0, angle_phi0=0.0, adress=None,
+                 block_size=0, device="cuda"):
         torch = _torch()
         self.torch = torch
         pos = np.ascontiguousarray(pos, dtype=np.float64)
@@ -44,7 +45,9 @@ class System:
                                   n_bonds=nb, n_angles=na, fene_K=fene_K, fene_R0=fene_R0, k_bend=k_bend,
                                   nl_capacity=nl_capacity, flags=flags, cell_factor=cell_factor,
                                   list_cutoff=list_cutoff, surrogate=int(bool(surrogate)),
-                                  shear_rate=shear_rate, dpd_rc=dpd_rc)
+                                  shear_rate=shear_rate, dpd_rc=dpd_rc, table_points=table_points,
+                                  angle_kind=angle_kind, angle_K=angle_K, angle_phi0=angle_phi0, adress=adress,
+                                  block_size=block_size)
         self.ws_bytes = md.md_workspace_bytes(self.cfg)
         self._ws_raw = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
         base = self._ws_raw.data_ptr()
@@ -74,6 +77,21 @@ class System:
                 k, v = "force_precision", (md.MD_FP64 if v == "fp64" else md.MD_FP32)
             setattr(c, k, v)
         md.md_set_params(self.h, c)
+
+    def set_pair_table(self, ti, tj, u, f, rmin):
+        """Tabulated pair potential of types (ti, tj): energies u and radial
+        forces f on the uniform grid from rmin to the pair's cutoff."""
+        md.md_set_pair_table(self.h, ti, tj, u, f, rmin)
+
+    def set_cg_table(self, ti, tj, u, f, rmin, rc_cg):
+        """AdResS: the coarse-grained pair potential of types (ti, tj)."""
+        md.md_set_cg_table(self.h, ti, tj, u, f, rmin, rc_cg)
+
+    def set_angle_table(self, u, dudphi):
+        md.md_set_angle_table(self.h, u, dudphi)
+
+    def set_angle_subens(self, u_tables, g_tables, weights):
+        md.md_set_angle_subens(self.h, u_tables, g_tables, weights)
 
     def step(self, n):
         md.md_step(self.h, n)

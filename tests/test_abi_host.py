@@ -195,7 +195,12 @@ def test_batch_workspace_and_member_validation():
            md.make_config(4000, [20.0, 20.0, 21.0]),
            md.make_config(4000, [20.0] * 3, n_types=2,
                           pair={(0, 0): (1, 1, 2.5, math.nan, 0), (0, 1): (1, 1, 2.5, math.nan, 0),
-                                (1, 1): (1, 1, 2.5, math.nan, 0)})]
+                                (1, 1): (1, 1, 2.5, math.nan, 0)}),
+           lj_cfg(4000, integrator=md.MD_DPD, dpd_rc=1.0),
+           lj_cfg(4000, shear_rate=0.1),
+           lj_cfg(4000, table_points=64),
+           lj_cfg(4000, table_points=64, adress=(10.0, 2.0, 2.0)),
+           lj_cfg(4000, angle_kind=md.MD_ANGLE_COSINE_SQUARED, angle_K=1.0, angle_phi0=2.0)]
     for c in bad:
         with pytest.raises(md.MDError):
             md.md_batch_workspace_bytes([a, c])
