@@ -93,11 +93,26 @@ def log(msg, quiet=False):
 
 
 # ---------------------------------------------------------------- systems
-# autotuner keys of the single-system workloads: (kind, N, density, rc)
-TUNE_KEYS = {"lj1m": ("lj", 1048576, 0.8442, 2.5), "kg2m": ("kg", 2000000, 0.85, 2.0 ** (1.0 / 6.0))}
+# autotuner keys of the single-system workloads: (kind, N, density, rc); the
+# surrogate's key carries its descriptor cutoff, and its skin is tuned too
+# (the descriptor list's skin is a performance choice, not part of the model)
+TUNE_KEYS = {"lj1m": ("lj", 1048576, 0.8442, 2.5), "kg2m": ("kg", 2000000, 0.85, 2.0 ** (1.0 / 6.0)),
+             "sur1m": ("sur", 1000000, 0.85, 2.5)}
+SUR_SKINS = (0.2, 0.25, 0.3, 0.4)
+_PUSHED = {}   # pushed-off melt states, reused by the tuner's trials
 
 
-def make_system(name, quiet, cell_factor=0, flags=0, block_size=0):
+def surrogate_on(s, a):
+    """The surrogate replaces the WCA pair force: the network trained by
+    surrogate_experiment.py on a 100k-bead plain-method melt."""
+    wpath = os.path.join(ROOT, "paper_2608_14911_amd", "data", "surrogate_kg.npz")
+    wd = np.load(wpath)
+    s.sur_set(wd["theta_" + a.sur_precision], wd["g_mean"], wd["g_istd"], a.sur_precision)
+    s.set_pair_mode("surrogate")
+    return s
+
+
+def make_system(name, quiet, cell_factor=0, flags=0, block_size=0, skin=None):
     from paper_2608_14911_amd import inputs
     from paper_2608_14911_amd.system import from_workload, push_off
     if name == "lj1m":
@@ -114,15 +129,19 @@ def make_system(name, quiet, cell_factor=0, flags=0, block_size=0):
     # parameters of the workload.  Raw random walks overlap, so the push-off
     # list needs a large capacity; the timed system is re-created from the
     # pushed-off state with the capacity sized from the density.
-    w0 = dict(w, caprad=1.0, dt=0.002, gamma=1.0, vel=np.zeros_like(w["pos"]))
-    s = from_workload(w0, precision="fp32", cell_factor=cell_factor, nl_capacity=256, flags=flags)
     t0 = time.time()
-    push_off(s, w["rc"], log=lambda m: log(m, quiet))
-    s.set_params(dt=w["dt"], gamma=w["gamma"])
-    s.step(200)
-    st = s.get_state()
-    s.close()
+    if name not in _PUSHED:
+        w0 = dict(w, caprad=1.0, dt=0.002, gamma=1.0, vel=np.zeros_like(w["pos"]))
+        s = from_workload(w0, precision="fp32", nl_capacity=256)
+        push_off(s, w["rc"], log=lambda m: log(m, quiet))
+        s.set_params(dt=w["dt"], gamma=w["gamma"])
+        s.step(200)
+        _PUSHED[name] = s.get_state()
+        s.close()
+    st = _PUSHED[name]
     w1 = dict(w, pos=st["pos"], vel=st["vel"])
+    if skin is not None:
+        w1["skin"] = skin
     extra = {"list_cutoff": 2.5, "surrogate": True} if name == "sur1m" else {}
     s = from_workload(w1, precision="fp32", cell_factor=cell_factor, flags=flags, block_size=block_size, **extra)
     s.set_state(st)
@@ -286,31 +305,34 @@ def single_choice(name, a):
     from paper_2608_14911_amd.system import nl_build_flags
     nl_flags = {"auto": 0, "tiles": md_.MD_CFG_NL_TILES, "per-particle": md_.MD_CFG_NL_PER_PARTICLE}[a.nl_build]
     if a.cell_factor or a.nl_build != "auto" or a.autotune == "none" or name not in TUNE_KEYS:
-        return a.cell_factor, nl_flags, 0, "command line / library defaults", None
+        return a.cell_factor, nl_flags, 0, None, "command line / library defaults", None
     kind, n, rho, rc = TUNE_KEYS[name]
+    sur = name == "sur1m"
     if a.autotune == "tune":
-        (cf, build, bs), table = autotune.tune_system(
-            lambda cf, fl: make_system(name, True, cf, fl)[1], n, rho, rc, kind, steps=30,
-            log=lambda m: log(m, a.quiet))
-        return cf, nl_build_flags(build), bs, "autotuner (fresh run)", table
+        if sur:
+            make = lambda cf, fl, sk: surrogate_on(make_system(name, True, cf, fl, 0, sk)[1], a)
+            (cf, build, bs, skin), table = autotune.tune_system(make, n, rho, rc, kind, steps=20, blocks=(),
+                                                                skins=SUR_SKINS, log=lambda m: log(m, a.quiet))
+        else:
+            make = lambda cf, fl: make_system(name, True, cf, fl)[1]
+            (cf, build, bs, skin), table = autotune.tune_system(make, n, rho, rc, kind, steps=30,
+                                                                log=lambda m: log(m, a.quiet))
+            skin = None
+        return cf, nl_build_flags(build), bs, skin, "autotuner (fresh run)", table
     c = autotune.cached_system_choice(kind, n, rho, rc)
     if c is None:
-        return 0, 0, 0, "library defaults (no autotuner cache entry)", None
-    return c[0], nl_build_flags(c[1]), c[2], "autotuner cache (%s, cell factor %d, %s, block %d)" % (
-        autotune.key_of(kind, n, rho, rc), c[0], c[1], c[2]), None
+        return 0, 0, 0, None, "library defaults (no autotuner cache entry)", None
+    return c[0], nl_build_flags(c[1]), c[2], (c[3] if sur else None), \
+        "autotuner cache (%s, cell factor %d, %s, block %d, skin %.2f)" % (
+            autotune.key_of(kind, n, rho, rc), c[0], c[1], c[2], c[3]), None
 
 
 def bench_single(name, a):
-    cf, nl_flags, bs, how, table = single_choice(name, a)
+    cf, nl_flags, bs, skin, how, table = single_choice(name, a)
     t0 = time.time()
-    w, s = make_system(name, a.quiet, cf, nl_flags, bs)
+    w, s = make_system(name, a.quiet, cf, nl_flags, bs, skin)
     if name == "sur1m":
-        # the surrogate replaces the WCA pair force: the network trained by
-        # surrogate_experiment.py on a 100k-bead plain-method melt
-        wpath = os.path.join(ROOT, "paper_2608_14911_amd", "data", "surrogate_kg.npz")
-        wd = np.load(wpath)
-        s.sur_set(wd["theta_" + a.sur_precision], wd["g_mean"], wd["g_istd"], a.sur_precision)
-        s.set_pair_mode("surrogate")
+        surrogate_on(s, a)
     log("%s: %d particles ready in %.1f s" % (name, s.n, time.time() - t0), a.quiet)
     rec = single_record(name, a, w, s)
     rec["config"]["block_size"] = bs or 256

@@ -167,55 +167,59 @@ def _time_system(s, steps):
     return 1e3 * (time.perf_counter() - t0) / steps
 
 
-def tune_system(make, n, rho, rc, kind, steps=40, builds=BUILDS, blocks=BLOCKS, log=None, path=CACHE_PATH,
-                write=True):
-    """Tune the cells, list build and force-kernel tile of one system.
-    ``make(cell_factor, flags)`` returns a fresh System; its skin is the
-    workload's own.  Cells and build are tried first at 256 particles per
-    block, then the block sizes on the winner (switched in place with
-    md_set_params, which changes cost only).  Returns ((cell_factor,
-    nl_build, block_size), table)."""
+def tune_system(make, n, rho, rc, kind, steps=40, builds=BUILDS, blocks=BLOCKS, skins=None, log=None,
+                path=CACHE_PATH, write=True):
+    """Tune the cells, list build and force-kernel tile of one system, and
+    its skin when ``skins`` is given (workloads whose skin is a performance
+    choice, such as the surrogate's descriptor list).  ``make(cell_factor,
+    flags)`` -- or ``make(cell_factor, flags, skin)`` with ``skins`` --
+    returns a fresh System.  Skins, cells and builds are tried first at 256
+    particles per block, then the block sizes on the winner (switched in
+    place with md_set_params, which changes cost only).  Returns
+    ((cell_factor, nl_build, block_size, skin), table)."""
     from .system import nl_build_flags
     table, best = [], None
-    for cf, build in builds:
-        try:
-            s = make(cf, nl_build_flags(build))
-        except Exception as e:
+    for skin_try in (skins or (None,)):
+        for cf, build in builds:
+            try:
+                s = make(cf, nl_build_flags(build)) if skin_try is None else make(cf, nl_build_flags(build), skin_try)
+            except Exception as e:
+                if log:
+                    log("autotune %s cf %d %s: skipped (%s)" % (kind, cf, build, e))
+                continue
+            ms = _time_system(s, steps)
+            skin = s.cfg.skin
+            s.close()
+            table.append({"skin": skin, "cell_factor": cf, "nl_build": build, "block_size": 256, "ms_per_step": ms})
             if log:
-                log("autotune %s cf %d %s: skipped (%s)" % (kind, cf, build, e))
-            continue
-        ms = _time_system(s, steps)
-        skin = s.cfg.skin
-        s.close()
-        table.append({"cell_factor": cf, "nl_build": build, "block_size": 256, "ms_per_step": ms})
-        if log:
-            log("autotune %s cf %d %s block 256: %.3f ms/step" % (kind, cf, build, ms))
-        if best is None or ms < best[0]:
-            best = (ms, cf, build, 256)
+                log("autotune %s skin %.2f cf %d %s block 256: %.3f ms/step" % (kind, skin, cf, build, ms))
+            if best is None or ms < best[0]:
+                best = (ms, cf, build, 256, skin)
     if best is None:
         raise RuntimeError("no candidate configuration ran")
-    s = make(best[1], nl_build_flags(best[2]))
+    s = make(best[1], nl_build_flags(best[2])) if skins is None else make(best[1], nl_build_flags(best[2]), best[4])
     for bs in blocks:
         s.set_params(block_size=bs)
         ms = _time_system(s, steps)
-        table.append({"cell_factor": best[1], "nl_build": best[2], "block_size": bs, "ms_per_step": ms})
+        table.append({"skin": best[4], "cell_factor": best[1], "nl_build": best[2], "block_size": bs,
+                      "ms_per_step": ms})
         if log:
             log("autotune %s cf %d %s block %d: %.3f ms/step" % (kind, best[1], best[2], bs, ms))
         if ms < best[0]:
-            best = (ms, best[1], best[2], bs)
+            best = (ms, best[1], best[2], bs, best[4])
     s.close()
     if write:
         cache = load_cache(path)
-        cache[key_of(kind, n, rho, rc)] = {"skin": skin, "cell_factor": best[1], "nl_build": best[2],
+        cache[key_of(kind, n, rho, rc)] = {"skin": best[4], "cell_factor": best[1], "nl_build": best[2],
                                            "block_size": best[3], "source": "single"}
         save_cache(cache, path)
     return best[1:], table
 
 
 def cached_system_choice(kind, n, rho, rc, path=CACHE_PATH):
-    """(cell_factor, nl_build, block_size) of a single system from the cache,
-    or None."""
+    """(cell_factor, nl_build, block_size, skin) of a single system from the
+    cache, or None."""
     e = load_cache(path).get(key_of(kind, n, rho, rc))
     if e is None or e.get("source") != "single":
         return None
-    return e["cell_factor"], e["nl_build"], e.get("block_size", 256)
+    return e["cell_factor"], e["nl_build"], e.get("block_size", 256), e["skin"]
