@@ -1863,9 +1863,9 @@ __global__ void __launch_bounds__(kBlock) k_step_gen(const StepArgs a) {
 //   F_i = sum_j ((a_i + a_j) . g'(r_ij)) (x_j - x_i) / r_ij  over r_ij < r_d,
 //   g'_k(r) = phi_k(r) (f_c'(r) - (r - mu_k) f_c(r) / w^2),
 // then the bonded forces, the integration and the reductions of the plain
-// step kernels.  The list row is pipelined: positions are gathered two
-// batches of B slots ahead and the a_j rows of in-range neighbours one batch
-// ahead of the pair arithmetic that uses them.  BF16 form (A16): a rows are
+// step kernels.  The list row is pipelined: positions are gathered two slots
+// ahead and the a_j rows of in-range neighbours one slot ahead of the pair
+// arithmetic that uses them.  BF16 form (A16): a rows are
 // BF16; g' is rounded to BF16 pairs and dotted with a_i and a_j by
 // v_dot2_f32_bf16 with FP32 accumulation.  FP32 form: FP32 rows and FP32
 // multiply-adds.  The pair virial goes to the step's reductions; the
@@ -1874,7 +1874,6 @@ typedef __bf16 bf16x2v __attribute__((ext_vector_type(2)));
 
 template <bool BONDED, bool TENSOR, bool A16>
 __global__ void __launch_bounds__(kBlock) k_sur_step(const StepArgs a, const SurBufs s, const SurConst c) {
-    constexpr int B = 1;                    // slots per batch (2 costs 56 more VGPRs)
     constexpr int AW = A16 ? 16 : 32;       // 32-bit words per a row
     const Geom& g = a.g;
     const Bufs& b = a.b;
@@ -1928,10 +1927,14 @@ __global__ void __launch_bounds__(kBlock) k_sur_step(const StepArgs a, const Sur
             const float Bc = c.inv_w2 * fc;
             float cij = 0.f;
             if (A16) {
+                // g'_k = phi_k (dfc - (r - mu_k) Bc) = phi_k (mu_k Bc + al): one
+                // FMA and one product per term (the FP32 cancellation of
+                // mu_k Bc against al is far below the BF16 rounding that follows)
+                const float al = fmaf(-r, Bc, dfc);
 #pragma unroll
                 for (int k2 = 0; k2 < kSurNB / 2; ++k2) {
-                    const float g0 = ph[2 * k2] * fmaf(-(r - c.mu[2 * k2]), Bc, dfc);
-                    const float g1 = ph[2 * k2 + 1] * fmaf(-(r - c.mu[2 * k2 + 1]), Bc, dfc);
+                    const float g0 = ph[2 * k2] * fmaf(c.mu[2 * k2], Bc, al);
+                    const float g1 = ph[2 * k2 + 1] * fmaf(c.mu[2 * k2 + 1], Bc, al);
                     const bf16x2v gp = {(__bf16)g0, (__bf16)g1};
                     cij = __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2v, ai[k2]), gp, cij, false);
                     cij = __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2v, aj[k2]), gp, cij, false);
@@ -1943,7 +1946,7 @@ __global__ void __launch_bounds__(kBlock) k_sur_step(const StepArgs a, const Sur
                     cij = fmaf(__uint_as_float(ai[k]) + __uint_as_float(aj[k]), dg, cij);
                 }
             }
-            const float sc = cij / r;
+            const float sc = cij * __builtin_amdgcn_rcpf(r);
             fx += sc * dx;
             fy += sc * dy;
             fz += sc * dz;
@@ -1960,53 +1963,30 @@ __global__ void __launch_bounds__(kBlock) k_sur_step(const StepArgs a, const Sur
             return r2 < c.rd2 && r2 > 0.f;   // r2 = 0: the row's padding (the particle itself)
         };
         if (nslots > 0) {
-            // batch b: jA/qA/inA/aA; batch b+1: jB/qB (positions in flight); b+2: jC
-            int jA[B], jB[B], jC[B];
-            int4 qA[B], qB[B];
-            bool inA[B];
-            uint32_t aA[B][AW], aB[B][AW];
-#pragma unroll
-            for (int u = 0; u < B; ++u) {
-                jA[u] = idx(u);
-                jB[u] = idx(B + u);
-                jC[u] = idx(2 * B + u);
-            }
-#pragma unroll
-            for (int u = 0; u < B; ++u) qA[u] = xq[jA[u]];
-#pragma unroll
-            for (int u = 0; u < B; ++u) qB[u] = xq[jB[u]];
-#pragma unroll
-            for (int u = 0; u < B; ++u) {
-                inA[u] = in_range(qA[u]);   // slots 0 .. B-1 < nslots
-                if (inA[u]) load_row(jA[u], aA[u]);
-            }
-            for (int k0 = 0; k0 < nslots; k0 += B) {
-                bool inB[B];
-#pragma unroll
-                for (int u = 0; u < B; ++u) {
-                    inB[u] = k0 + B + u < nslots && in_range(qB[u]);
-                    if (inB[u]) load_row(jB[u], aB[u]);
-                }
-                int4 qC[B];
-                int jD[B];
-#pragma unroll
-                for (int u = 0; u < B; ++u) {
-                    qC[u] = xq[jC[u]];
-                    jD[u] = idx(k0 + 3 * B + u);
-                }
-#pragma unroll
-                for (int u = 0; u < B; ++u)
-                    if (inA[u]) pair(qA[u], aA[u]);
-#pragma unroll
-                for (int u = 0; u < B; ++u) {
-                    qA[u] = qB[u];
-                    inA[u] = inB[u];
-#pragma unroll
-                    for (int w = 0; w < AW; ++w) aA[u][w] = aB[u][w];
-                    jB[u] = jC[u];
-                    qB[u] = qC[u];
-                    jC[u] = jD[u];
-                }
+            // slot k: index jA, position qA, a row aX (in range: inX); slot k+1:
+            // index jB, position qB (in flight); slot k+2: index jC.  Rows hold
+            // a multiple of 8 slots, so slots come in pairs and the a rows
+            // alternate between aX and aY without copies.
+            int jA = idx(0), jB = idx(1), jC = idx(2);
+            int4 qA = xq[jA], qB = xq[jB];
+            uint32_t aX[AW], aY[AW];
+            bool inX = in_range(qA), inY = false;
+            if (inX) load_row(jA, aX);
+            for (int k0 = 0; k0 < nslots; k0 += 2) {
+                // slot k0 (row aX); prefetch: a row of k0 + 1, position of k0 + 2
+                inY = in_range(qB);
+                if (inY) load_row(jB, aY);
+                int4 qC = xq[jC];
+                int jD = idx(k0 + 3);
+                if (inX) pair(qA, aX);
+                qA = qB; qB = qC; jA = jB; jB = jC; jC = jD;
+                // slot k0 + 1 (row aY); prefetch: a row of k0 + 2, position of k0 + 3
+                inX = k0 + 2 < nslots && in_range(qB);
+                if (inX) load_row(jB, aX);
+                qC = xq[jC];
+                jD = idx(k0 + 4);
+                if (inY) pair(qA, aY);
+                qA = qB; qB = qC; jA = jB; jB = jC; jC = jD;
             }
         }
         acc[A_VIR] += 0.5 * (double)wv;

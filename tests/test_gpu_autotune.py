@@ -122,10 +122,10 @@ def test_tune_system_caches_cells_build_and_block(tmp_path):
     def make(cf, flags):
         return System(m["pos"], m["box"], m["vel"], pair=m["pair"], dt=0.005, skin=0.3, cell_factor=cf, flags=flags)
 
-    (cf, build, bs), table = autotune.tune_system(make, n, 0.8442, 2.5, "lj", steps=8, path=path)
-    assert bs in autotune.BLOCKS and build in ("tiles", "per_particle") and cf in (1, 2)
+    (cf, build, bs, skin), table = autotune.tune_system(make, n, 0.8442, 2.5, "lj", steps=8, path=path)
+    assert bs in autotune.BLOCKS and build in ("tiles", "per_particle") and cf in (1, 2) and skin == 0.3
     assert len(table) >= 2 + len(autotune.BLOCKS)
-    assert autotune.cached_system_choice("lj", n, 0.8442, 2.5, path=path) == (cf, build, bs)
+    assert autotune.cached_system_choice("lj", n, 0.8442, 2.5, path=path) == (cf, build, bs, skin)
     # the winner and the defaults: the same trajectory up to FP32 summation order
     a, _ = run_state(System(m["pos"], m["box"], m["vel"], pair=m["pair"], dt=0.005, skin=0.3, cell_factor=cf,
                             flags=nl_build_flags(build), block_size=bs), 20)
@@ -133,3 +133,13 @@ def test_tune_system_caches_cells_build_and_block(tmp_path):
     d = np.abs(a["pos"] - b["pos"])
     d = np.minimum(d, m["box"] - d)
     assert d.max() < 1e-4
+    # a skin dimension (a workload whose skin is a performance choice)
+    path2 = str(tmp_path / "cache2.json")
+
+    def make_s(cf, flags, skin):
+        return System(m["pos"], m["box"], m["vel"], pair=m["pair"], dt=0.005, skin=skin, cell_factor=cf, flags=flags)
+
+    (cf2, build2, bs2, skin2), table2 = autotune.tune_system(make_s, n, 0.8442, 2.5, "lj", steps=6, blocks=(256,),
+                                                             skins=(0.2, 0.4), path=path2)
+    assert skin2 in (0.2, 0.4) and {t["skin"] for t in table2} == {0.2, 0.4}
+    assert autotune.cached_system_choice("lj", n, 0.8442, 2.5, path=path2) == (cf2, build2, bs2, skin2)
