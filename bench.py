@@ -42,7 +42,29 @@ HBM_PEAK_GBS = 8000.0
 #           integration 132 -> 213
 #   surrogate 1M: 2 descriptor-list passes 2 x (4 + 43.4 x 4) = 355, a_i write
 #           + read 256, positions 48, force 12, bonded 16, integration 132 -> 819
-ALG_BYTES = {"lj1m": 327.0, "kg2m": 213.0, "kg1k": 213.0, "sur1m": 819.0}
+#   DPD + shear 1M (density 3, rc_d 1, skin 0.3): NL 4 + 13.8*4 = 59,
+#           positions 24, neighbour velocities 24 and ids 4, force 12,
+#           integration 132 -> 255
+#   AdResS LJ 1M: the LJ fluid's 327 (the weights come from the positions)
+ALG_BYTES = {"lj1m": 327.0, "kg2m": 213.0, "kg1k": 213.0, "sur1m": 819.0, "dpd1m": 255.0, "adress1m": 327.0}
+STEP_KERNEL = {"lj1m": "k_step_fast (fused pair forces, velocity Verlet, reductions)",
+               "kg2m": "k_step_fast_bonded (fused pair + bonded forces, velocity Verlet, reductions)",
+               "kg1k": "k_step_fast_bonded (fused pair + bonded forces, velocity Verlet, reductions)",
+               "dpd1m": "k_step_gen (tabulated pair force, DPD pair thermostat, Lees-Edwards image and "
+                        "crossing, velocity Verlet, reductions) with its velocity snapshot",
+               "adress1m": "k_step_gen (AdResS mix of LJ and a tabulated CG pair force, velocity Verlet, "
+                           "reductions)"}
+# The surrogate's force stage is bound by vector ALU issue (counters: VALU
+# busy 95-100 % in the descriptor and pair-force kernels), so it is priced in
+# FP32 vector operations against the chip's FP32 vector peak.  Algorithmic
+# operations per bead-step, FMA = 2, over the 55.6 ordered pairs within
+# r_d = 2.5 at density 0.85: descriptors 134 per pair (32 Gaussians by
+# recurrence 70, 32 FMAs into G 64) and pair force 262 per pair (basis 70,
+# g' 64, two 32-term dot products 128): (134 + 262) x 55.6 = 22.0k.  The
+# network's 24.8k operations per bead run on the matrix cores and are left
+# out of this figure.
+SUR_VALU_FLOPS = 22.0e3
+FP32_VECTOR_PEAK_TFLOPS = 157.3
 # HBM bytes per launch of the fused kernel from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE passes (each scaled by what the counter reads for a 512 MiB
 # copy: x2.0 and x1.0), valid only for the sources the kernel is compiled
@@ -65,7 +87,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="default",
-                    choices=["default", "lj1m", "kg2m", "kg1k", "batch", "sur1m"],
+                    choices=["default", "lj1m", "kg2m", "kg1k", "batch", "sur1m", "dpd1m", "adress1m"],
                     help="default: the LJ fluid with kg2m, batch and sur1m as sub-records")
     ap.add_argument("--sur-precision", default="bf16", choices=["fp32", "bf16"],
                     help="sur1m: network precision of the surrogate")
@@ -150,6 +172,59 @@ def make_system(name, quiet, cell_factor=0, flags=0, block_size=0, skin=None):
         raise RuntimeError("KG system after push-off: status %d" % s.status())
     log("%s: push-off done in %.1f s" % (name, time.time() - t0), quiet)
     return w1, s
+
+
+def make_ext_system(name):
+    """The extended-method workloads (one GPU, 1,048,576 particles each).
+    dpd1m: a DPD fluid at density 3 (random start, Maxwell-Boltzmann
+    velocities at kT = 1 plus the imposed profile) with the soft repulsion
+    u = a (1 - r)^2 / 2, a = 25, as a 256-point pair table, DPD thermostat
+    gamma 4.5 with rc_d 1, Lees-Edwards shear rate 0.1, dt 0.01, skin 0.3.
+    adress1m: the LJ fluid of lj1m with an AdResS slab (atomistic zone
+    L/8 either side of the box centre, hybrid zones L/8 wide) and a soft CG
+    pair table u = a (1 - r / rc)^2 / 2, a = 20, rc 2.0, NVE."""
+    from paper_2608_14911_amd import inputs
+    from paper_2608_14911_amd.system import System, lj_pair
+    n = 1048576
+    if name == "dpd1m":
+        rho, rate, seed = 3.0, 0.1, 1020
+        L = (n / rho) ** (1.0 / 3.0)
+        box = np.array([L, L, L])
+        pos = inputs.random_positions(n, box, seed=seed)
+        vel = inputs.maxwell_boltzmann(n, 1.0, seed=seed)
+        vel[:, 0] += rate * (pos[:, 1] - 0.5 * L)
+        s = System(pos, box, vel, pair={(0, 0): lj_pair(rc=1.0)}, skin=0.3, dt=0.01, integrator="dpd",
+                   temperature=1.0, gamma=4.5, seed=seed, dpd_rc=1.0, shear_rate=rate, table_points=256)
+        r = np.linspace(0.0, 1.0, 256)
+        s.set_pair_table(0, 0, 12.5 * (1.0 - r) ** 2, 25.0 * (1.0 - r), 0.0)
+        w = {"name": "DPD fluid 1048576 particles, density 3, soft tabulated repulsion a = 25, gamma 4.5, "
+                     "Lees-Edwards shear rate 0.1", "rc": 1.0, "skin": 0.3, "dt": 0.01, "integrator": "dpd"}
+        return w, s
+    w = inputs.workload_lj(ncell=64, seed=1001)
+    L = w["box"][0]
+    s = System(w["pos"], w["box"], w["vel"], pair={(0, 0): lj_pair(rc=2.5)}, skin=0.3, dt=0.005, table_points=512,
+               adress=(0.5 * L, L / 8.0, L / 8.0))
+    rc_cg = 2.0
+    r = np.linspace(0.0, rc_cg, 512)
+    s.set_cg_table(0, 0, 10.0 * (1.0 - r / rc_cg) ** 2, 20.0 * (1.0 - r / rc_cg) / rc_cg, 0.0, rc_cg)
+    w2 = {"name": "LJ fluid 1048576 particles (FCC 64^3), rho 0.8442, AdResS slab: atomistic L/8 either side "
+                  "of the centre, hybrid L/8, soft tabulated CG pair (a = 20, rc 2.0)",
+          "rc": 2.5, "skin": 0.3, "dt": 0.005, "integrator": "nve"}
+    return w2, s
+
+
+def bench_ext(name, a):
+    t0 = time.time()
+    w, s = make_ext_system(name)
+    log("%s: %d particles ready in %.1f s" % (name, s.n, time.time() - t0), a.quiet)
+    rec = single_record(name, a, w, s)
+    rec["config"]["block_size"] = 256
+    rec["config"]["tuning"] = "library defaults"
+    s.close()
+    del s
+    free_gpu()
+    log("%s: %.3g atom-steps/s, %.3f ms/step" % (name, rec["value"], rec["ms_per_step"]), a.quiet)
+    return w, rec
 
 
 def free_gpu():
@@ -277,14 +352,18 @@ def single_record(name, a, w, s):
         "energy_drift_per_particle": (o1["e_total"] - o0["e_total"]) / n,
         "nl_max_count": o1["nl_max_count"],
         "evented_pass": {"ms_per_step": 1e3 * el_ev / a.steps, "n_rebuilds": o2["n_rebuilds"] - o1["n_rebuilds"]},
-        "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": ach / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": ("surrogate force stage (k_sur_desc, k_sur_mlp, k_sur_force, k_step_ext)" if sur else
-                                "k_step_fast_bonded (fused pair + bonded forces, velocity Verlet, reductions)"
-                                if name in ("kg2m", "kg1k") else
-                                "k_step_fast (fused pair forces, velocity Verlet, reductions)"),
-                     "kernel_ms": k_ms, "alg_bytes_per_launch": alg,
-                     "alg_bytes_per_particle": ALG_BYTES[name]},
+        "roofline": ({"bound": "alu", "achieved": SUR_VALU_FLOPS * n / (k_ms * 1e-3) / 1e12,
+                      "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                      "frac": SUR_VALU_FLOPS * n / (k_ms * 1e-3) / 1e12 / FP32_VECTOR_PEAK_TFLOPS,
+                      "traffic": None,
+                      "kernel": "surrogate force stage (k_sur_desc2 with the BF16 network, k_sur_step)",
+                      "kernel_ms": k_ms, "alg_flops_per_particle": SUR_VALU_FLOPS,
+                      "hbm_alg_bytes_per_particle": ALG_BYTES[name]} if sur else
+                     {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                      "frac": ach / HBM_PEAK_GBS, "traffic": traffic,
+                      "kernel": STEP_KERNEL[name],
+                      "kernel_ms": k_ms, "alg_bytes_per_launch": alg,
+                      "alg_bytes_per_particle": ALG_BYTES[name]}),
         "kernel_breakdown_ms_per_step": {
             "rebuild_stage": tm["ms_rebuild"] / max(tm["n_rebuild"], 1),
             "step_kernel" if not sur else "force_stage_and_step": k_ms,
@@ -468,13 +547,18 @@ def main():
         print(json.dumps(rec), flush=True)
         return
     main_name = "lj1m" if a.workload == "default" else a.workload
-    w, rec = bench_single(main_name, a)
+    if main_name in ("dpd1m", "adress1m"):
+        w, rec = bench_ext(main_name, a)
+    else:
+        w, rec = bench_single(main_name, a)
     if a.workload == "default":
         subs = {}
         _, subs["kg2m"] = bench_single("kg2m", a)
         _, subs["batch"] = bench_batch(a)
         _, subs["sur1m"] = bench_single("sur1m", a)
         subs["sur1m"]["vs_plain_kg"] = "plain WCA kernel on a melt of the same density: workloads.kg2m"
+        _, subs["dpd1m"] = bench_ext("dpd1m", a)
+        _, subs["adress1m"] = bench_ext("adress1m", a)
         rec["workloads"] = subs
     if a.calib_copy:
         src = torch.ones(128 * 1024 * 1024, dtype=torch.float32, device="cuda")
@@ -483,7 +567,7 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         rec["calib_copy_bytes"] = src.numel() * 4
-    if not a.no_cpu_baseline:
+    if not a.no_cpu_baseline and main_name not in ("dpd1m", "adress1m"):
         rec["cpu_baseline"] = cpu_baseline(w, a.cpu_seconds, a.quiet)
     print(json.dumps(rec), flush=True)
 
