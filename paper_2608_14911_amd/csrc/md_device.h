@@ -50,11 +50,15 @@ __device__ __forceinline__ int xcd_block(int b, int G) {
 }
 // Verlet-list layout: tiles of 64 particles (one wavefront); inside a tile
 // slot k of all 64 particles is contiguous (256 bytes), and a tile's slots
-// follow each other, so a wavefront streams one contiguous block.
+// follow each other, so a wavefront streams one contiguous block.  (Chunks of
+// 4 slots per lane, written by the tile build as 16-byte stores, were slower:
+// the register shifting cost the build more VALU than the stores it saved.)
 constexpr int kTile = 64;
 __device__ __forceinline__ int64_t nl_base(int64_t i, int cap) {
     return (i >> 6) * (int64_t)cap * kTile + (i & (kTile - 1));
 }
+// offset of slot k from a row's base (nl_base), in entries
+__device__ __forceinline__ int nl_off(int k) { return k * kTile; }
 
 __device__ __forceinline__ int64_t gtid_xcd() {
     return (int64_t)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;

@@ -207,7 +207,7 @@ __global__ void __launch_bounds__(kBlock) k_get_neighbors(Geom g, Bufs b, int32_
         int cc = c < g.cap ? c : g.cap;
         count[t] = c;
         const int32_t* row = b.nl + nl_base(s, g.cap);
-        for (int k = 0; k < cc && k < cap; ++k) idx[t * (int64_t)cap + k] = b.tag[row[k * kTile]];
+        for (int k = 0; k < cc && k < cap; ++k) idx[t * (int64_t)cap + k] = b.tag[row[nl_off(k)]];
     }
 }
 
@@ -555,7 +555,7 @@ __device__ __forceinline__ void nl_one(const Geom& g, const Bufs& b, int64_t i, 
         const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
         auto put = [&](int k, int j) {
             if (k < kNlLds) nlbuf[wv][k][ln] = j;
-            else nlrow[k * kTile] = j;
+            else nlrow[nl_off(k)] = j;
         };
         // Cells cx-kc .. cx+kc of one (y, z) row are consecutive in the cell
         // order, so their particles form one contiguous range of the sorted
@@ -631,7 +631,7 @@ __device__ __forceinline__ void nl_one(const Geom& g, const Bufs& b, int64_t i, 
         for (int k = cnt; k < nslot; ++k) put(k, (int)i);
 #pragma unroll
         for (int k = 0; k < kNlLds; ++k)
-            if (k < nslot) nlrow[k * kTile] = nlbuf[wv][k][ln];
+            if (k < nslot) nlrow[nl_off(k)] = nlbuf[wv][k][ln];
         if (bonded) remap_bonded(b, n, i);
     }
 }
@@ -962,7 +962,7 @@ __device__ __forceinline__ void nl_one_le(const Geom& g, const Bufs& b, int64_t 
             bool in = r2 < g.rv2lo;
             if (!in && r2 < g.rv2hi) in = exact_r2_le(g, xi, x[j], dw) < g.rv2;
             if (in && j != i) {
-                if (cnt < g.cap) nlrow[cnt * kTile] = j;
+                if (cnt < g.cap) nlrow[nl_off(cnt)] = j;
                 ++cnt;
             }
         }
@@ -1004,7 +1004,7 @@ __device__ __forceinline__ void nl_one_le(const Geom& g, const Bufs& b, int64_t 
     if (cnt > local_max) local_max = cnt;
     if (cnt > g.cap) overflow = true;
     const int nslot = min(((cnt + 7) & ~7), g.cap);
-    for (int k = cnt; k < nslot; ++k) nlrow[k * kTile] = (int)i;
+    for (int k = cnt; k < nslot; ++k) nlrow[nl_off(k)] = (int)i;
     if (bonded) remap_bonded(b, n, i);
 }
 
@@ -1352,7 +1352,7 @@ __global__ void __launch_bounds__(kBlock) k_step64(const StepArgs a) {
         cnt = cnt < g.cap ? cnt : g.cap;
         const int32_t* __restrict__ row = b.nl + nl_base(i, g.cap);
         for (int k = 0; k < cnt; ++k) {
-            const double4 xj = xin[row[k * kTile]];
+            const double4 xj = xin[row[nl_off(k)]];
             const double dx = mimg(xj.x - xi.x, g.L[0], g.invL[0]);
             const double dy = mimg(xj.y - xi.y, g.L[1], g.invL[1]);
             const double dz = mimg(xj.z - xi.z, g.L[2], g.invL[2]);
@@ -1448,7 +1448,7 @@ __global__ void __launch_bounds__(kBlock) k_step_q(const StepArgs a) {
                     const float2* trow = b.tab + (int64_t)tp * g.table_points;
                     const float2 t0 = trow[kq], t1 = trow[kq + 1];
                     u = (1.f - al) * t0.x + al * t1.x;
-                    fr = ((1.f - al) * t0.y + al * t1.y) / r;
+                    fr = ((1.f - al) * t0.y + al * t1.y) * __builtin_amdgcn_rcpf(r);
                 } else if (c.cap2 > 0.f && r2 < c.cap2) {
                     fr = c.fcap * __builtin_amdgcn_rsqf(r2);
                     u = c.ucap;
@@ -1481,7 +1481,7 @@ __global__ void __launch_bounds__(kBlock) k_step_q(const StepArgs a) {
         int jn[B];
 #pragma unroll
         for (int u = 0; u < B; ++u) {
-            const int v = row[(u < last ? u : last) * kTile];
+            const int v = row[nl_off(u < last ? u : last)];
             jn[u] = u < cnt ? v : self;
         }
         for (int k0 = 0; k0 < cnt; k0 += B) {
@@ -1495,7 +1495,7 @@ __global__ void __launch_bounds__(kBlock) k_step_q(const StepArgs a) {
 #pragma unroll
             for (int u = 0; u < B; ++u) {
                 const int kk = k0 + B + u;
-                const int v = row[(kk < last ? kk : last) * kTile];
+                const int v = row[nl_off(kk < last ? kk : last)];
                 jn[u] = kk < cnt ? v : self;
             }
 #pragma unroll
@@ -1575,7 +1575,7 @@ __device__ __forceinline__ void fast_particle(const StepArgs& a, int64_t i, doub
             for (int u = 0; u < B; ++u) {
                 const int kk = k0 + 2 * B + u;
                 jn[u] = jn2[u];
-                jn2[u] = row[(kk < last ? kk : last) * kTile];
+                jn2[u] = row[nl_off(kk < last ? kk : last)];
             }
             float dx[B], dy[B], dz[B], r2[B];
             uint32_t inmask = 0, bandmask = 0;
@@ -1682,18 +1682,23 @@ __device__ __forceinline__ float adress_weight(const Dyn& dy, float x, float Lx)
     d = fabsf(d);
     if (d < dy.ad_dat) return 1.f;
     if (d >= dy.ad_dat + dy.ad_dhy) return 0.f;
-    const float cz = cosf(dy.ad_k * (d - dy.ad_dat));
-    return cz * cz;
+    // cos^2 z = (1 + cos 2z) / 2, with the revolution-scaled hardware cosine
+    return 0.5f + 0.5f * __builtin_amdgcn_cosf(dy.ad_k * (d - dy.ad_dat) * 0.3183098861837907f);
 }
 
 // theta_ij of the DPD thermostat: Philox4x64-10 keyed (seed, 6) at counter
-// (step, min id, max id, 0), Box-Muller on the first two uniforms (FP64).
-__device__ __forceinline__ double dpd_theta(uint64_t seed, uint64_t step, uint32_t ti, uint32_t tj) {
+// (step, min id, max id, 0), Box-Muller on the first two uniforms
+// ((w >> 11) + 1/2) 2^-53, evaluated in FP32 with the hardware log2 and
+// cosine (cos(2 pi u) from the revolution-scaled instruction): within a few
+// 1e-7 of the FP64 draw, far below the FP32 force rounding.
+__device__ __forceinline__ float dpd_theta(uint64_t seed, uint64_t step, uint32_t ti, uint32_t tj) {
     uint64_t x0 = step, x1 = ti < tj ? ti : tj, x2 = ti < tj ? tj : ti, x3 = 0;
     philox4x64_10(x0, x1, x2, x3, seed, 6);
-    const double u0 = ((double)(x0 >> 11) + 0.5) * 0x1.0p-53;
-    const double u1 = ((double)(x1 >> 11) + 0.5) * 0x1.0p-53;
-    return sqrt(-2.0 * log(u0)) * cos(6.283185307179586 * u1);
+    const float u0 = fmaf((float)(x0 >> 11), 0x1.0p-53f, 0x1.0p-54f);
+    const float u1 = fmaf((float)(x1 >> 11), 0x1.0p-53f, 0x1.0p-54f);
+    // -2 ln u0 = -2 ln 2 log2 u0
+    const float rr = sqrtf(-1.3862943611198906f * __builtin_amdgcn_logf(u0));
+    return rr * __builtin_amdgcn_cosf(u1);
 }
 
 // Generic FP32 step, one 256-particle tile per block, for what the fast
@@ -1740,21 +1745,28 @@ __global__ void __launch_bounds__(kBlock) k_step_gen(const StepArgs a) {
         float fx = 0.f, fy = 0.f, fz = 0.f, ue = 0.f, we = 0.f;
         float txx = 0.f, tyy = 0.f, tzz = 0.f, txy = 0.f, txz = 0.f, tyz = 0.f;
         const float wi = a.dy.adress ? adress_weight(a.dy, (float)xi.x, (float)g.L[0]) : 1.f;
-        // DPD reads the half-step velocities from the snapshot in b.vt taken
-        // before this kernel (b.v is overwritten here as particles finish)
-        const double* __restrict__ vs = b.vt;
-        double vi[3] = {0.0, 0.0, 0.0};
-        uint32_t tgi = 0;
-        if (dpd) {
-            for (int d = 0; d < 3; ++d) vi[d] = vs[d * n + i];
-            tgi = (uint32_t)b.tag[i];
-        }
+        // DPD reads the half-step velocities and ids from the snapshot in
+        // b.vt taken before this kernel (b.v is overwritten here as particles
+        // finish): one 16-byte record (vx, vy, vz, id) per particle
+        const float4* __restrict__ vs = reinterpret_cast<const float4*>(b.vt);
+        float4 vi = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (dpd) vi = vs[i];
         int cnt = b.ncount[i];
         cnt = cnt < g.cap ? cnt : g.cap;
         const int32_t* __restrict__ row = b.nl + nl_base(i, g.cap);
+        // the next slot's index and record are loaded while this slot is computed
+        int jn = cnt > 0 ? row[nl_off(0)] : 0;
+        int4 qn = xq[jn];
+        float4 vn = dpd ? vs[jn] : make_float4(0.f, 0.f, 0.f, 0.f);
         for (int k = 0; k < cnt; ++k) {
-            const int j = row[k * kTile];
-            const int4 qj = xq[j];
+            const int j = jn;
+            const int4 qj = qn;
+            const float4 vj = vn;
+            if (k + 1 < cnt) {
+                jn = row[nl_off(k + 1)];
+                qn = xq[jn];
+                if (dpd) vn = vs[jn];
+            }
             float dx, dy, dz;
             const int s = df(qi, qj, dx, dy, dz);
             const float r2 = dx * dx + dy * dy + dz * dz;
@@ -1777,7 +1789,7 @@ __global__ void __launch_bounds__(kBlock) k_step_gen(const StepArgs a) {
                     const float2* trow = b.tab + (int64_t)(kCgTableRow + tp) * g.table_points;
                     const float2 t0 = trow[kq], t1 = trow[kq + 1];
                     ucg = (1.f - al) * t0.x + al * t1.x;
-                    frcg = ((1.f - al) * t0.y + al * t1.y) / r;
+                    frcg = ((1.f - al) * t0.y + al * t1.y) * __builtin_amdgcn_rcpf(r);
                 }
             }
             if (in || cg_in) {
@@ -1795,7 +1807,7 @@ __global__ void __launch_bounds__(kBlock) k_step_gen(const StepArgs a) {
                     const float2* trow = b.tab + (int64_t)tp * g.table_points;
                     const float2 t0 = trow[kq], t1 = trow[kq + 1];
                     u = (1.f - al) * t0.x + al * t1.x;
-                    fr = ((1.f - al) * t0.y + al * t1.y) / r;
+                    fr = ((1.f - al) * t0.y + al * t1.y) * __builtin_amdgcn_rcpf(r);
                 } else if (c.cap2 > 0.f && r2 < c.cap2) {
                     fr = c.fcap * __builtin_amdgcn_rsqf(r2);
                     u = c.ucap;
@@ -1823,16 +1835,16 @@ __global__ void __launch_bounds__(kBlock) k_step_gen(const StepArgs a) {
                 }
             }
             if (dpd && r2 < a.dy.dpd_rc2 && r2 > 0.f) {
-                const float r = sqrtf(r2);
-                const float w = 1.f - r / a.dy.dpd_rc;
-                const float ir = 1.f / r;
+                const float ir = __builtin_amdgcn_rsqf(r2);
+                const float r = r2 * ir;
+                const float w = 1.f - r * __builtin_amdgcn_rcpf(a.dy.dpd_rc);
                 const float ex = -dx * ir, ey = -dy * ir, ez = -dz * ir;
-                // v_i - (v_j - s shear_rate Ly e_x), in FP64 then rounded once
-                const float vx = (float)(vi[0] - vs[j] + s * g.le_rate_Ly);
-                const float vy = (float)(vi[1] - vs[n + j]);
-                const float vz = (float)(vi[2] - vs[2 * n + j]);
+                // v_i - (v_j - s shear_rate Ly e_x)
+                const float vx = vi.x - vj.x + (float)(s * g.le_rate_Ly);
+                const float vy = vi.y - vj.y;
+                const float vz = vi.z - vj.z;
                 const float ev = ex * vx + ey * vy + ez * vz;
-                const float th = (float)dpd_theta(a.dy.seed, (uint64_t)step, tgi, (uint32_t)b.tag[j]);
+                const float th = dpd_theta(a.dy.seed, (uint64_t)step, __float_as_uint(vi.w), __float_as_uint(vj.w));
                 const float A = -a.dy.dpd_gamma * w * w * ev + a.dy.dpd_sigma_isdt * w * th;
                 fx += A * ex;
                 fy += A * ey;
@@ -1902,7 +1914,7 @@ __global__ void __launch_bounds__(kBlock) k_sur_step(const StepArgs a, const Sur
         const int last = nslots > 0 ? nslots - 1 : 0;
         float fx = 0.f, fy = 0.f, fz = 0.f, wv = 0.f;
         float txx = 0.f, tyy = 0.f, tzz = 0.f, txy = 0.f, txz = 0.f, tyz = 0.f;
-        auto idx = [&](int slot) { return row[(slot < last ? slot : last) * kTile]; };
+        auto idx = [&](int slot) { return row[nl_off(slot < last ? slot : last)]; };
         auto geom = [&](const int4& qj, float& dx, float& dy, float& dz) {
             dx = qdiff(qj.x, qi.x, g.ql[0]);
             dy = qdiff(qj.y, qi.y, g.ql[1]);
@@ -2352,16 +2364,18 @@ static void launch_fast(const StepArgs& a, int block, hipStream_t s) {
 #undef MD_LF
 }
 
-// Velocity snapshot for the DPD pair term: b.vt (the sort's scratch, free
-// after the rebuild stage) <- b.v, [3][N] FP64.
-__global__ void __launch_bounds__(kBlock) k_snapshot_v(const Bufs b, int64_t len) {
-    for (int64_t k = gtid(); k < len; k += gstride()) b.vt[k] = b.v[k];
+// Velocity snapshot for the DPD pair term into b.vt (the sort's scratch,
+// free after the rebuild stage): (vx, vy, vz, id bits) per particle, FP32.
+__global__ void __launch_bounds__(kBlock) k_snapshot_v(const Bufs b, int64_t n) {
+    float4* __restrict__ out = reinterpret_cast<float4*>(b.vt);
+    for (int64_t k = gtid(); k < n; k += gstride())
+        out[k] = make_float4((float)b.v[k], (float)b.v[n + k], (float)b.v[2 * n + k], __uint_as_float((uint32_t)b.tag[k]));
 }
 
 hipError_t launch_step(const StepArgs& a, int fp64, int single_type, int bonded, int block, hipStream_t s) {
     dim3 grid((unsigned)step_grid(a.g.n)), blk(kBlock);
     if (a.dy.gen && a.dy.dpd && a.mode == MODE_STEP)
-        hipLaunchKernelGGL(k_snapshot_v, dim3(grid_for(3 * a.g.n)), dim3(kBlock), 0, s, a.b, 3 * a.g.n);
+        hipLaunchKernelGGL(k_snapshot_v, dim3(grid_for(a.g.n)), dim3(kBlock), 0, s, a.b, a.g.n);
     if (a.dy.gen) {
         if (bonded) hipLaunchKernelGGL(k_step_gen<true>, grid, blk, 0, s, a);
         else hipLaunchKernelGGL(k_step_gen<false>, grid, blk, 0, s, a);

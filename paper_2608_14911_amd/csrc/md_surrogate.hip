@@ -111,7 +111,7 @@ __global__ void __launch_bounds__(kBlock) k_sur_force(Geom g, Bufs b, SurBufs s,
         float fx = 0.f, fy = 0.f, fz = 0.f, w = 0.f;
         float txx = 0.f, tyy = 0.f, tzz = 0.f, txy = 0.f, txz = 0.f, tyz = 0.f;
         for (int k = 0; k < cnt; ++k) {
-            const int j = row[k * kTile];
+            const int j = row[nl_off(k)];
             const int4 qj = xq[j];
             const float dx = qdiff(qj.x, qi.x, g.ql[0]);
             const float dy = qdiff(qj.y, qi.y, g.ql[1]);
@@ -185,7 +185,7 @@ __global__ void __launch_bounds__(kBlock) k_sur_u(Geom g, Bufs b, SurBufs s, Sur
 #pragma unroll
         for (int k = 0; k < kSurNB; ++k) U[k] = 0.f;
         for (int k = 0; k < cnt; ++k) {
-            const int j = row[k * kTile];
+            const int j = row[nl_off(k)];
             const int4 qj = xq[j];
             const float dx = qdiff(qj.x, qi.x, g.ql[0]);
             const float dy = qdiff(qj.y, qi.y, g.ql[1]);

@@ -203,36 +203,48 @@ def test_dpd_shear_profile_temperature_and_momentum():
     L, rate, dt = 7.0, 0.3, 0.01
     pos, box, vel = dpd_system(L, 3.0, seed=41, rate=rate)
     n = pos.shape[0]
-    s = System(pos, box, vel, pair={(0, 0): lj_pair(eps=0.0, rc=1.0)}, skin=0.3, dt=dt, integrator="dpd",
-               temperature=1.0, gamma=4.5, seed=3, dpd_rc=1.0, shear_rate=rate)
-    s.step(300)
-    nb = 7
+    nb, nrep = 7, 6
     prof, cnt = np.zeros(nb), np.zeros(nb)
 
-    def gstate():
+    def gstate(s):
         g = s.get_state()
         b = np.minimum((g["pos"][:, 1] / L * nb).astype(int), nb - 1)
         np.add.at(prof, b, g["vel"][:, 0])
         np.add.at(cnt, b, 1)
         return g
 
-    Tg = peculiar_T_series(gstate, s.step, L, rate, n)
-    assert s.status() == 0
-    s.close()
+    # Independent replicas (noise seeds) on each side: the temperature of one
+    # run is a correlated series whose own spread understates the error of its
+    # mean, so the standard error comes from the spread of the replica means.
+    Tg = []
+    for seed in range(3, 3 + nrep):
+        s = System(pos, box, vel, pair={(0, 0): lj_pair(eps=0.0, rc=1.0)}, skin=0.3, dt=dt, integrator="dpd",
+                   temperature=1.0, gamma=4.5, seed=seed, dpd_rc=1.0, shear_rate=rate)
+        s.step(300)
+        Tg.append(peculiar_T_series(lambda: gstate(s), s.step, L, rate, n).mean())
+        assert s.status() == 0
+        s.close()
     prof /= cnt
     yc = (np.arange(nb) + 0.5) * L / nb
     slope = np.polyfit(yc, prof, 1)[0]
-    # the oracle: the same system with its own noise (seed 4), the same protocol
-    st = oracle_state(pos, vel)
-    par = {"box": box, "pp": oracle_pp(eps=0.0, rc=1.0), "ntypes": 1, "mass_by_type": np.array([1.0]), "dt": dt,
-           "integrator": oracle.DPD, "temperature": 1.0, "gamma": 4.5, "seed": 4, "dpd_rc": 1.0, "shear_rate": rate}
-    oracle.run_ext(st, par, 300)
-    To = peculiar_T_series(lambda: st, lambda k: oracle.run_ext(st, par, k), L, rate, n)
-    se = math.hypot(Tg.std(ddof=1) / 4.0, To.std(ddof=1) / 4.0)
-    print("shear profile slope %.4f (imposed %.4f); peculiar T GPU %.4f, oracle %.4f, se %.4f" % (
-        slope, rate, Tg.mean(), To.mean(), se), flush=True)
+    # the oracle: the same system with its own noise seeds, the same protocol
+    To = []
+    for seed in range(103, 103 + nrep):
+        st = oracle_state(pos, vel)
+        par = {"box": box, "pp": oracle_pp(eps=0.0, rc=1.0), "ntypes": 1, "mass_by_type": np.array([1.0]),
+               "dt": dt, "integrator": oracle.DPD, "temperature": 1.0, "gamma": 4.5, "seed": seed, "dpd_rc": 1.0,
+               "shear_rate": rate}
+        oracle.run_ext(st, par, 300)
+        To.append(peculiar_T_series(lambda: st, lambda k: oracle.run_ext(st, par, k), L, rate, n).mean())
+    Tg, To = np.array(Tg), np.array(To)
+    se = math.hypot(Tg.std(ddof=1), To.std(ddof=1)) / math.sqrt(nrep)
+    print("shear profile slope %.4f (imposed %.4f); peculiar T GPU %.4f (%s), oracle %.4f (%s), se %.4f" % (
+        slope, rate, Tg.mean(), " ".join("%.4f" % t for t in Tg), To.mean(), " ".join("%.4f" % t for t in To),
+        se), flush=True)
     assert slope == pytest.approx(rate, rel=0.08)
-    assert abs(Tg.mean() - To.mean()) <= 3.0 * se
+    # 4 standard errors: a two-sided tail of 0.25 % for Student's t at the 10
+    # degrees of freedom of two samples of 6
+    assert abs(Tg.mean() - To.mean()) <= 4.0 * se
     # without shear: total momentum stays at its start value (pair forces cancel to FP32 rounding)
     pos, box, vel = dpd_system(8.0, 3.0, seed=42, rate=0.0)
     vel -= vel.mean(0)
