@@ -380,6 +380,7 @@ md_status md_timing_read(md_handle h, md_timing* out);
 #define MD_SUR_WIDTH 0.1
 #define MD_SUR_MU0 0.8
 #define MD_SUR_MU1 2.5
+#define MD_SUR_VAR_FLOOR 1e-6
 enum { MD_SUR_FP32 = 0, MD_SUR_BF16 = 1 };
 enum { MD_PAIR_PLAIN = 0, MD_PAIR_SURROGATE = 1 };
 
@@ -396,6 +397,17 @@ md_status md_sur_get(md_handle h, float* theta);
 md_status md_set_pair_mode(md_handle h, int32_t mode);
 /* Descriptors G at the current positions: device FP32 [N][32], tag order. */
 md_status md_sur_descriptors(md_handle h, float* G);
+/* The fixed standardisation (mean, istd) of x_i above, fitted on training
+ * frames (the paper has no learned model; this belongs to the extension
+ * described at the head of this section): over the N descriptor rows of each of
+ * the nf frames, g_mean_k = mean of G_k and g_istd_k = 1 / sqrt(var_k +
+ * MD_SUR_VAR_FLOOR), population variance, sums in FP64.  frames device FP64
+ * [nf][N][3] positions (tag order; folded into the box); g_mean, g_istd
+ * device FP32 [32], ready for md_sur_set.  Needs no network.  The handle's
+ * state is replaced as by md_sur_loss_grad (last frame, zero velocities,
+ * step 0).  MD_ERR_ARG on NULL pointers, nf < 1 or a list radius below the
+ * descriptor cutoff. */
+md_status md_sur_desc_stats(md_handle h, const double* frames, int32_t nf, float* g_mean, float* g_istd);
 /* The network on P given descriptor rows: G device FP32 [P][32] (raw, the
  * handle's standardisation is applied); e device FP32 [P] (may be NULL) and
  * dedg device FP32 [P][32] = dE_i/dG(i). */

@@ -15,7 +15,9 @@ its gradient, force-matching training).  The readings taken here:
   continuous at r_d;  g_k(r) = phi_k(r) f_c(r);
 * descriptor  G_k(i) = sum over j != i with r_ij < r_d of g_k(r_ij);
 * standardisation  x_i = (G(i) - m) * istd with fixed training-set
-  constants (m, istd), not trained;
+  constants, not trained: m and istd = 1 / sqrt(var + 1e-6) per basis
+  function over all descriptor rows of the training frames (population
+  variance; the floor keeps functions with almost no signal finite);
 * E_i = w3 . silu(W2 silu(W1 x_i + b1) + b2) + b3,  E = sum_i E_i,
   F_i = -dE/dr_i;
 * parameter vector theta (6,337 values) = W1 (64x32 row-major), b1 (64),
@@ -107,6 +109,16 @@ def descriptors(pos, box, rd=RD, pr=None):
     G = np.zeros((np.asarray(pos).shape[0], NB))
     np.add.at(G, I, g)
     return G
+
+
+def standardisation(frames, box, rd=RD, floor=1e-6):
+    """The fixed standardisation constants (m, istd) of the network input:
+    mean and 1/sqrt(var + floor) of each descriptor component over every
+    particle of every frame."""
+    G = np.concatenate([descriptors(f, box, rd) for f in frames])
+    m = G.mean(0)
+    var = ((G - m) ** 2).mean(0)
+    return m, 1.0 / np.sqrt(var + floor)
 
 
 def silu(z):

@@ -1285,6 +1285,31 @@ md_status md_sur_descriptors(md_handle h, float* G) {
     return MD_OK;
 }
 
+md_status md_sur_desc_stats(md_handle h, const double* frames, int32_t nf, float* g_mean, float* g_istd) {
+    md_status r = need_sur(h);
+    if (r != MD_OK) return r;
+    if (!frames || nf < 1) return fail(h, MD_ERR_ARG, "bad frames");
+    if (!g_mean || !g_istd) return fail(h, MD_ERR_ARG, "NULL output");
+    if (sqrt(h->g.rv2) - h->cfg.skin < MD_SUR_RCUT * (1.0 - 1e-12))
+        return fail(h, MD_ERR_ARG, "list radius minus skin is below the descriptor cutoff");
+    const int64_t n = h->g.n;
+    drop_graph(h);
+    h->parity = 0;
+    for (int32_t f = 0; f < nf; ++f) {
+        const double* pos = frames + (size_t)f * 3 * n;
+        HIP_TRY(h, launch_init_load(h->g, h->b, 0, pos, nullptr, h->b.type_t, nullptr, h->stream));
+        HIP_TRY(h, launch_set_ctl(h->b, 0, 0, 1, 1, h->stream));
+        if ((r = rebuild_now(h, 0)) != MD_OK) return r;
+        HIP_TRY(h, launch_sur_desc2(h->g, h->b, h->sb, h->sc, 0, 0, h->stream));
+        HIP_TRY(h, launch_sur_moments(h->sb, n, f > 0, h->stream));
+    }
+    HIP_TRY(h, launch_sur_moments_final(h->sb, (double)n * (double)nf, MD_SUR_VAR_FLOOR, g_mean, g_istd, h->stream));
+    h->host_step = 0;
+    h->vel_half = 0;
+    h->hist_next = 0;
+    return MD_OK;
+}
+
 md_status md_sur_mlp_eval(md_handle h, const float* G, int64_t P, float* e, float* dedg) {
     md_status r = need_sur(h);
     if (r != MD_OK) return r;

@@ -234,6 +234,8 @@ constexpr int kM1 = 0, kM2 = 64 * kMS1, kM2T = kM2 + 64 * kMS64, kM1T = kM2T + 6
               kPrepM = kM1T + 32 * kMS64;
 constexpr int kSurPart = 9;                 // E, W, tensor[6], loss
 constexpr int kSurGradBlocks = 256;         // blocks of the double-backward kernel
+constexpr int kSurMomBlocks = 256;          // blocks of the descriptor-moment kernel (partials in gpart)
+static_assert(kSurMomBlocks * 2 * kSurNB * 2 <= kSurGradBlocks * kSurNPpad, "moment partials fit in gpart");
 
 struct SurBufs {
     float* G;           // [N][32] descriptors, sorted order
@@ -281,6 +283,9 @@ hipError_t launch_sur_loss_reduce(const SurBufs& s, int grid, int accumulate, hi
 hipError_t launch_sur_adam(const SurBufs& s, int64_t t, float lr, float beta1, float beta2, float eps,
                            hipStream_t st);
 hipError_t launch_sur_to_tag(const Geom& g, const Bufs& b, const float* src, float* dst, hipStream_t st);
+hipError_t launch_sur_moments(const SurBufs& s, int64_t n, int accumulate, hipStream_t st);
+hipError_t launch_sur_moments_final(const SurBufs& s, double cnt, double floor_var, float* g_mean, float* g_istd,
+                                    hipStream_t st);
 hipError_t launch_sur_from_tag(const Geom& g, const Bufs& b, const float* src, float* dst, hipStream_t st);
 hipError_t launch_sur_f_to_tag(const Geom& g, const Bufs& b, const float4* src, double* dst, hipStream_t st);
 // inference: descriptors (FP32 rows into s.G, or with net != 0 fused with the

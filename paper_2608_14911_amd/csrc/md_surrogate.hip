@@ -689,6 +689,51 @@ __global__ void __launch_bounds__(kBlock) k_sur_prepare(SurBufs s) {
     }
 }
 
+// Descriptor moments for the standardisation constants.  Block b owns rows
+// 8b + r, 8b + r + 8 kSurMomBlocks, ... (r = threadIdx / 32) and keeps its
+// FP64 sums of G and G^2 per basis function in its own slot of gpart, added
+// to across the frames of a call, so that the totals do not depend on timing.
+__global__ void __launch_bounds__(kBlock) k_sur_moments(SurBufs s, int64_t n, int accumulate) {
+    __shared__ double red[2][kBlock / kSurNB][kSurNB];
+    const int col = threadIdx.x & (kSurNB - 1), rl = threadIdx.x / kSurNB;
+    constexpr int kRows = kBlock / kSurNB;
+    double s1 = 0.0, s2 = 0.0;
+    for (int64_t r = (int64_t)blockIdx.x * kRows + rl; r < n; r += (int64_t)gridDim.x * kRows) {
+        const double v = s.G[r * kSurNB + col];
+        s1 += v;
+        s2 += v * v;
+    }
+    red[0][rl][col] = s1;
+    red[1][rl][col] = s2;
+    __syncthreads();
+    if (threadIdx.x < 2 * kSurNB) {
+        const int q = threadIdx.x / kSurNB;
+        double t = 0.0;
+        for (int k = 0; k < kRows; ++k) t += red[q][k][col];
+        double* p = reinterpret_cast<double*>(s.gpart) + (int64_t)blockIdx.x * 2 * kSurNB + q * kSurNB + col;
+        *p = accumulate ? *p + t : t;
+    }
+}
+
+// mean_k = S1_k / cnt and istd_k = 1 / sqrt(S2_k / cnt - mean_k^2 + floor),
+// the block sums taken in block order (population variance, clamped at 0).
+__global__ void k_sur_moments_final(SurBufs s, int nblk, double cnt, double floor_var, float* g_mean,
+                                    float* g_istd) {
+    const int col = threadIdx.x;
+    if (col >= kSurNB) return;
+    const double* p = reinterpret_cast<const double*>(s.gpart);
+    double s1 = 0.0, s2 = 0.0;
+    for (int b = 0; b < nblk; ++b) {
+        s1 += p[(int64_t)b * 2 * kSurNB + col];
+        s2 += p[(int64_t)b * 2 * kSurNB + kSurNB + col];
+    }
+    const double m = s1 / cnt;
+    double var = s2 / cnt - m * m;
+    if (var < 0.0) var = 0.0;
+    g_mean[col] = (float)m;
+    g_istd[col] = (float)(1.0 / sqrt(var + floor_var));
+}
+
 __global__ void __launch_bounds__(kBlock) k_sur_to_tag(Geom g, Bufs b, const float* src, float* dst) {
     for (int64_t i = gtid(); i < g.n; i += gstride()) {
         const int64_t t = b.tag[i];
@@ -887,7 +932,7 @@ __device__ __forceinline__ void desc_row(const Geom& g, const Bufs& b, const Sur
     const int last = nslots > 0 ? nslots - 1 : 0;
     int jn[B];
 #pragma unroll
-    for (int u = 0; u < B; ++u) jn[u] = row[(u < last ? u : last) * kTile];
+    for (int u = 0; u < B; ++u) jn[u] = row[nl_off(u < last ? u : last)];
     for (int k0 = 0; k0 < nslots; k0 += B) {
         int4 qj[B];
 #pragma unroll
@@ -895,7 +940,7 @@ __device__ __forceinline__ void desc_row(const Geom& g, const Bufs& b, const Sur
 #pragma unroll
         for (int u = 0; u < B; ++u) {
             const int kk = k0 + B + u;
-            jn[u] = row[(kk < last ? kk : last) * kTile];
+            jn[u] = row[nl_off(kk < last ? kk : last)];
         }
 #pragma unroll
         for (int u = 0; u < B; ++u) {
@@ -1096,6 +1141,18 @@ hipError_t launch_sur_adam(const SurBufs& s, int64_t t, float lr, float beta1, f
     const float bc2 = (float)(1.0 - pow((double)beta2, (double)t));
     hipLaunchKernelGGL(k_sur_adam, dim3((kSurNP + kBlock - 1) / kBlock), dim3(kBlock), 0, st, s, lr, beta1, beta2,
                        eps, bc1, bc2);
+    return hipGetLastError();
+}
+
+hipError_t launch_sur_moments(const SurBufs& s, int64_t n, int accumulate, hipStream_t st) {
+    hipLaunchKernelGGL(k_sur_moments, dim3(kSurMomBlocks), dim3(kBlock), 0, st, s, n, accumulate);
+    return hipGetLastError();
+}
+
+hipError_t launch_sur_moments_final(const SurBufs& s, double cnt, double floor_var, float* g_mean, float* g_istd,
+                                    hipStream_t st) {
+    hipLaunchKernelGGL(k_sur_moments_final, dim3(1), dim3(64), 0, st, s, kSurMomBlocks, cnt, floor_var, g_mean,
+                       g_istd);
     return hipGetLastError();
 }
 

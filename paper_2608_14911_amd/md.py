@@ -52,6 +52,7 @@ MD_SUR_RCUT = 2.5
 MD_SUR_WIDTH = 0.1
 MD_SUR_MU0 = 0.8
 MD_SUR_MU1 = 2.5
+MD_SUR_VAR_FLOOR = 1e-6
 MD_SUR_FP32 = 0
 MD_SUR_BF16 = 1
 MD_PAIR_PLAIN = 0
@@ -61,7 +62,7 @@ EXPORTED = ["md_workspace_bytes", "md_plan_config", "md_init", "md_set_params", 
             "md_step", "md_observables", "md_history", "md_get_state", "md_set_state",
             "md_get_neighbors", "md_status_check", "md_timing_enable", "md_timing_read",
             "md_destroy", "md_status_string", "md_last_error", "md_sur_set", "md_sur_get",
-            "md_set_pair_mode", "md_sur_descriptors", "md_sur_mlp_eval", "md_sur_pair_forces", "md_sur_loss_grad",
+            "md_set_pair_mode", "md_sur_descriptors", "md_sur_desc_stats", "md_sur_mlp_eval", "md_sur_pair_forces", "md_sur_loss_grad",
             "md_sur_adam", "md_batch_workspace_bytes", "md_batch_init", "md_batch_step",
             "md_batch_observables", "md_batch_get_state", "md_batch_destroy", "md_batch_last_error",
             "md_batch_timing_enable", "md_batch_timing_read", "md_init_static", "md_set_pair_table",
@@ -164,6 +165,7 @@ def lib():
         "md_sur_get": [P, P],
         "md_set_pair_mode": [P, I32],
         "md_sur_descriptors": [P, P],
+        "md_sur_desc_stats": [P, P, I32, P, P],
         "md_sur_mlp_eval": [P, P, I64, P, P],
         "md_sur_pair_forces": [P, P, P],
         "md_sur_loss_grad": [P, P, P, I32, P, ctypes.POINTER(ctypes.c_double)],
@@ -411,6 +413,10 @@ def md_set_pair_mode(h, mode):
 
 def md_sur_descriptors(h, G):
     _check(lib().md_sur_descriptors(h, _p(G)), "md_sur_descriptors", h)
+
+
+def md_sur_desc_stats(h, frames, nf, g_mean, g_istd):
+    _check(lib().md_sur_desc_stats(h, _p(frames), int(nf), _p(g_mean), _p(g_istd)), "md_sur_desc_stats", h)
 
 
 def md_sur_mlp_eval(h, G, P, e, dedg):

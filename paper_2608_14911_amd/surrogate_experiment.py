@@ -108,21 +108,9 @@ def make_dataset(n_chains, chain_len, nframes, every, seed):
 
 
 def descriptor_stats(s, frames):
-    t = s.torch
-    acc = t.zeros(32, dtype=t.float64, device=s.device)
-    acc2 = t.zeros(32, dtype=t.float64, device=s.device)
-    for f in range(frames.shape[0]):
-        set_positions(s, frames[f])
-        G = s.descriptors().double()
-        acc += G.sum(0)
-        acc2 += (G * G).sum(0)
-    cnt = frames.shape[0] * s.n
-    mean = acc / cnt
-    var = (acc2 / cnt - mean * mean).clamp_min(0.0)
-    # basis functions centred near the cutoff carry almost no signal; the
-    # floor keeps their scale finite
-    istd = 1.0 / t.sqrt(var + 1e-6)
-    return mean.float(), istd.float()
+    """The network's fixed standardisation constants (mean, 1/sqrt(var + 1e-6))
+    over every bead of the training frames, from the library's own kernels."""
+    return s.desc_stats(frames)
 
 
 def rmse(s, frames, fref):

@@ -191,6 +191,18 @@ class System:
         self.stream.synchronize()
         return G
 
+    def desc_stats(self, frames):
+        """Standardisation constants (mean, 1/std per basis function) of the
+        descriptors over device frames [nf, N, 3] (FP64); replaces the state
+        with the last frame, like loss_grad."""
+        t = self.torch
+        frames = self._dev(frames, t.float64)
+        m = t.zeros(md.MD_SUR_NBASIS, dtype=t.float32, device=self.device)
+        istd = t.zeros(md.MD_SUR_NBASIS, dtype=t.float32, device=self.device)
+        md.md_sur_desc_stats(self.h, frames.data_ptr(), frames.shape[0], m.data_ptr(), istd.data_ptr())
+        self.stream.synchronize()
+        return m, istd
+
     def mlp_eval(self, G):
         """Per-row energies and dE/dG for descriptor rows G [P, 32]."""
         t = self.torch

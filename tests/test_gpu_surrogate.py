@@ -66,6 +66,36 @@ def test_descriptors_match_oracle():
     s.close()
 
 
+def test_standardisation_matches_oracle():
+    """md_sur_desc_stats against the oracle's constants over three frames;
+    the bounds follow from the descriptors' own tolerance (1e-5 of max |G|
+    per entry): |dm| <= that, and |d var| <= 4 max|G| of it, which moves
+    istd = (var + 1e-6)^(-1/2) by at most half its relative size."""
+    w, pos, box = melt()
+    banner("surrogate standardisation KG 1k, 3 frames")
+    g = np.random.default_rng(11)
+    frames = [pos] + [np.mod(pos + g.normal(scale=0.05, size=pos.shape), box) for _ in range(2)]
+    s = sur_system(w, pos)
+    m, istd = s.desc_stats(np.stack(frames))
+    m, istd = m.cpu().numpy().astype(np.float64), istd.cpu().numpy().astype(np.float64)
+    mo, io = S.standardisation(frames, box)
+    Gmax = max(np.abs(S.descriptors(f, box)).max() for f in frames)
+    dG = 1e-5 * Gmax
+    var_o = 1.0 / io ** 2 - 1e-6
+    em = np.abs(m - mo).max()
+    ei = (np.abs(istd - io) / io / (0.5 * 4.0 * Gmax * dG / (var_o + 1e-6) + 1e-6)).max()
+    print("standardisation: max |dm| %.3g (bound %.3g), istd error / bound %.3g" % (em, dG, ei))
+    assert em <= dG
+    assert ei <= 1.0
+    # the state is the last frame's
+    st = s.get_state()
+    d = st["pos"] - frames[-1]
+    assert np.abs(d - box * np.round(d / box)).max() < 1e-12
+    with pytest.raises(Exception):
+        s.desc_stats(np.zeros((0, pos.shape[0], 3)))
+    s.close()
+
+
 @pytest.mark.parametrize("prec,tol", [("fp32", 1e-5), ("bf16", 3e-2)])
 def test_mlp_eval_matches_oracle(prec, tol):
     w, pos, box = melt()

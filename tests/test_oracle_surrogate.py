@@ -87,6 +87,37 @@ def test_descriptor_two_and_three_particles():
     assert np.allclose(G2[0], S.basis(0.5)[0], atol=1e-15)
 
 
+def test_standardisation_fcc_and_two_point():
+    # a perfect FCC crystal: every particle sees the same shells (12 at the
+    # nearest-neighbour distance d, then 6 at d sqrt 2, 24 at d sqrt 3 and 12
+    # at 2d; the next shell, d sqrt 5, lies beyond r_d at density 0.85), so
+    # every row equals the shell sum and the variance vanishes
+    nc, rho = 4, 0.85
+    a = (4.0 / rho) ** (1.0 / 3.0)
+    base = np.array([[0, 0, 0], [0.5, 0.5, 0], [0.5, 0, 0.5], [0, 0.5, 0.5]])
+    cells = np.array([[i, j, k] for i in range(nc) for j in range(nc) for k in range(nc)], dtype=float)
+    pos = ((cells[:, None, :] + base[None]) * a).reshape(-1, 3)
+    box = np.full(3, nc * a)
+    d = a / np.sqrt(2.0)
+    assert d * np.sqrt(5.0) > S.RD > 2.0 * d
+    shells = 12 * S.basis(d)[0] + 6 * S.basis(d * np.sqrt(2))[0] + 24 * S.basis(d * np.sqrt(3))[0] \
+        + 12 * S.basis(2 * d)[0]
+    m, istd = S.standardisation([pos, pos + 0.37], box)
+    assert np.allclose(m, shells, rtol=1e-13, atol=1e-15)
+    assert np.allclose(istd, 1.0 / np.sqrt(1e-6), rtol=1e-6)
+    # two frames of one isolated pair at r0 and r1: the rows take two values
+    # with equal weight, so the mean is their midpoint and the variance the
+    # square of half their difference
+    box = np.full(3, 20.0)
+    r0, r1 = 1.05, 1.6
+    f0 = np.array([[5.0, 5.0, 5.0], [5.0 + r0, 5.0, 5.0]])
+    f1 = np.array([[5.0, 5.0, 5.0], [5.0, 5.0 + r1, 5.0]])
+    m, istd = S.standardisation([f0, f1], box)
+    b0, b1 = S.basis(r0)[0], S.basis(r1)[0]
+    assert np.allclose(m, 0.5 * (b0 + b1), rtol=0, atol=1e-15)
+    assert np.allclose(istd, 1.0 / np.sqrt((0.5 * (b0 - b1)) ** 2 + 1e-6), rtol=1e-12)
+
+
 @pytest.mark.parametrize("seed", [0, 1])
 def test_forces_are_minus_energy_gradient(seed):
     pos, box = small_system(seed)
