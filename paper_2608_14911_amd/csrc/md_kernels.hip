@@ -954,16 +954,26 @@ __device__ __forceinline__ void nl_one_le(const Geom& g, const Bufs& b, int64_t 
     const DiffLEQ df{g.ql[0], g.ql[1], g.ql[2], qd};
     int32_t* __restrict__ nlrow = b.nl + nl_base(i, g.cap);
     int cnt = 0;
+    // candidates gathered four at a time, the last one repeated past the end
+    // of the range (the order of the tests, and so the row, is unchanged)
     auto test_range = [&](int st, int en) {
-        for (int j = st; j < en; ++j) {
-            float dx, dy, dz;
-            df(qi, xq[j], dx, dy, dz);
-            const float r2 = dx * dx + dy * dy + dz * dz;
-            bool in = r2 < g.rv2lo;
-            if (!in && r2 < g.rv2hi) in = exact_r2_le(g, xi, x[j], dw) < g.rv2;
-            if (in && j != i) {
-                if (cnt < g.cap) nlrow[nl_off(cnt)] = j;
-                ++cnt;
+        for (int j0 = st; j0 < en; j0 += 4) {
+            int4 qq[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) qq[u] = xq[min(j0 + u, en - 1)];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int j = j0 + u;
+                if (j >= en) break;
+                float dx, dy, dz;
+                df(qi, qq[u], dx, dy, dz);
+                const float r2 = dx * dx + dy * dy + dz * dz;
+                bool in = r2 < g.rv2lo;
+                if (!in && r2 < g.rv2hi) in = exact_r2_le(g, xi, x[j], dw) < g.rv2;
+                if (in && j != i) {
+                    if (cnt < g.cap) nlrow[nl_off(cnt)] = j;
+                    ++cnt;
+                }
             }
         }
     };
@@ -1712,13 +1722,30 @@ __device__ __forceinline__ float dpd_theta(uint64_t seed, uint64_t step, uint32_
 //   (-gamma w^2 (e . v_ij) + sigma w theta_ij / sqrt(dt)) e,
 // computed by both members of a pair with the same theta_ij, so the two
 // contributions cancel to FP32 rounding.
-template <bool BONDED>
+// SINGLE: one particle type, so the pair parameters are uniform and held in
+// scalar registers.  LDSTAB: the tables the kernel reads (the pair row of
+// type pair 0 and the AdResS coarse-grained row) are first copied into LDS,
+// [2][table_points] (u, f) pairs, so that their lookups do not wait on
+// global memory.  The neighbour row is pipelined: the index two slots ahead
+// and the record (and DPD velocity) one slot ahead of the pair arithmetic.
+template <bool BONDED, bool SINGLE, bool LDSTAB>
 __global__ void __launch_bounds__(kBlock) k_step_gen(const StepArgs a) {
+    extern __shared__ float2 stab[];
     const Geom& g = a.g;
     const Bufs& b = a.b;
     const int64_t n = g.n;
     const int4* __restrict__ xq = b.xq[a.parity];
     const double4* __restrict__ x64 = b.x[a.parity];
+    if (LDSTAB) {
+        const int np = g.table_points;
+        const float2* __restrict__ src0 = b.tab;
+        const float2* __restrict__ src1 = b.tab + (int64_t)kCgTableRow * np;
+        for (int k = threadIdx.x; k < np; k += kBlock) {
+            stab[k] = src0[k];
+            stab[np + k] = src1[k];
+        }
+        __syncthreads();
+    }
     double acc[kNacc];
 #pragma unroll
     for (int k = 0; k < kNacc; ++k) acc[k] = 0.0;
@@ -1754,23 +1781,25 @@ __global__ void __launch_bounds__(kBlock) k_step_gen(const StepArgs a) {
         int cnt = b.ncount[i];
         cnt = cnt < g.cap ? cnt : g.cap;
         const int32_t* __restrict__ row = b.nl + nl_base(i, g.cap);
-        // the next slot's index and record are loaded while this slot is computed
-        int jn = cnt > 0 ? row[nl_off(0)] : 0;
-        int4 qn = xq[jn];
-        float4 vn = dpd ? vs[jn] : make_float4(0.f, 0.f, 0.f, 0.f);
+        // slots past the end repeat the last one (every slot below cnt holds
+        // a particle index); an empty row reads the particle itself
+        const int last = cnt > 0 ? cnt - 1 : 0;
+        auto slot = [&](int k) { return cnt > 0 ? row[nl_off(k < last ? k : last)] : (int)i; };
+        int jA = slot(0), jB = slot(1);
+        int4 qA = xq[jA];
+        float4 vA = dpd ? vs[jA] : make_float4(0.f, 0.f, 0.f, 0.f);
         for (int k = 0; k < cnt; ++k) {
-            const int j = jn;
-            const int4 qj = qn;
-            const float4 vj = vn;
-            if (k + 1 < cnt) {
-                jn = row[nl_off(k + 1)];
-                qn = xq[jn];
-                if (dpd) vn = vs[jn];
-            }
+            const int j = jA;
+            const int4 qj = qA;
+            const float4 vj = vA;
+            jA = jB;
+            jB = slot(k + 2);
+            qA = xq[jA];
+            if (dpd) vA = vs[jA];
             float dx, dy, dz;
             const int s = df(qi, qj, dx, dy, dz);
             const float r2 = dx * dx + dy * dy + dz * dz;
-            const int tp = ti * MD_MAX_TYPES + qj.w;
+            const int tp = SINGLE ? 0 : ti * MD_MAX_TYPES + qj.w;
             bool in = r2 < a.pt.rc2lo[tp];
             if (!in && r2 < a.pt.rc2hi[tp]) in = exact_r2_le(g, xi, x64[j], dw) < a.pt.rc2d[tp];
             // AdResS: the coarse-grained force of the pair, to be mixed in below
@@ -1786,7 +1815,8 @@ __global__ void __launch_bounds__(kBlock) k_step_gen(const StepArgs a) {
                     int kq = (int)q;
                     kq = kq > a.pt.cgn[tp] - 2 ? a.pt.cgn[tp] - 2 : kq;
                     const float al = q - (float)kq;
-                    const float2* trow = b.tab + (int64_t)(kCgTableRow + tp) * g.table_points;
+                    const float2* trow = LDSTAB ? stab + g.table_points
+                                                : b.tab + (int64_t)(kCgTableRow + tp) * g.table_points;
                     const float2 t0 = trow[kq], t1 = trow[kq + 1];
                     ucg = (1.f - al) * t0.x + al * t1.x;
                     frcg = ((1.f - al) * t0.y + al * t1.y) * __builtin_amdgcn_rcpf(r);
@@ -1804,7 +1834,7 @@ __global__ void __launch_bounds__(kBlock) k_step_gen(const StepArgs a) {
                     int kq = (int)q;
                     kq = kq > a.pt.tabn[tp] - 2 ? a.pt.tabn[tp] - 2 : kq;
                     const float al = q - (float)kq;
-                    const float2* trow = b.tab + (int64_t)tp * g.table_points;
+                    const float2* trow = LDSTAB ? stab : b.tab + (int64_t)tp * g.table_points;
                     const float2 t0 = trow[kq], t1 = trow[kq + 1];
                     u = (1.f - al) * t0.x + al * t1.x;
                     fr = ((1.f - al) * t0.y + al * t1.y) * __builtin_amdgcn_rcpf(r);
@@ -2377,8 +2407,20 @@ hipError_t launch_step(const StepArgs& a, int fp64, int single_type, int bonded,
     if (a.dy.gen && a.dy.dpd && a.mode == MODE_STEP)
         hipLaunchKernelGGL(k_snapshot_v, dim3(grid_for(a.g.n)), dim3(kBlock), 0, s, a.b, a.g.n);
     if (a.dy.gen) {
-        if (bonded) hipLaunchKernelGGL(k_step_gen<true>, grid, blk, 0, s, a);
-        else hipLaunchKernelGGL(k_step_gen<false>, grid, blk, 0, s, a);
+        // tables in LDS for one particle type, when both rows fit in 32 KB
+        const size_t tab_lds = 2 * sizeof(float2) * (size_t)a.g.table_points;
+        const bool lds = single_type && a.b.tab && a.g.table_points >= 2 && tab_lds <= 32768;
+#define MD_LG(B, S, T) hipLaunchKernelGGL((k_step_gen<B, S, T>), grid, blk, T ? tab_lds : 0, s, a)
+        if (bonded) {
+            if (lds) MD_LG(true, true, true);
+            else if (single_type) MD_LG(true, true, false);
+            else MD_LG(true, false, false);
+        } else {
+            if (lds) MD_LG(false, true, true);
+            else if (single_type) MD_LG(false, true, false);
+            else MD_LG(false, false, false);
+        }
+#undef MD_LG
     } else if (fp64) {
 #define MD_L64(S, B) hipLaunchKernelGGL((k_step64<S, B>), grid, blk, 0, s, a)
         if (single_type) { if (bonded) MD_L64(true, true); else MD_L64(true, false); }
