@@ -70,9 +70,10 @@ enum {
  * noise: for each pair with r = |r_i - r_j| < dpd_rc, e = (r_i - r_j) / r,
  * v_ij = v_i - v_j and w = 1 - r / dpd_rc, the force on i is
  *   -gamma w^2 (e . v_ij) e + sqrt(2 gamma kT) w theta_ij e / sqrt(dt),
- * theta_ij = theta_ji ~ N(0,1) from Philox4x64-10 keyed (seed, 6) at counter
- * (step, min id, max id, 0), Box-Muller on its first two uniforms; v is the
- * half-step velocity of velocity Verlet.  Needs MD_FP32. */
+ * theta_ij = theta_ji ~ N(0,1) from Philox4x32-10 at counter (step low
+ * word, step high word, min id, max id) with key (seed low word, seed high
+ * word ^ 6), Box-Muller on its first two words as uniforms (w + 1/2) 2^-32;
+ * v is the half-step velocity of velocity Verlet.  Needs MD_FP32. */
 enum { MD_NVE = 0, MD_LANGEVIN = 1, MD_DPD = 2 };
 enum { MD_FP64 = 0, MD_FP32 = 1 };       /* md_config.force_precision */
 
@@ -190,6 +191,8 @@ typedef struct md_timing {
     double ms_rebuild;          /* summed duration of the rebuild stage (gated kernels) */
     int64_t n_finalize;
     double ms_finalize;
+    double ms_bin_sort;         /* of ms_rebuild: binning and the cell sort (the rest
+                                   is the neighbour-list build) */
 } md_timing;
 
 typedef struct md_handle_s* md_handle;

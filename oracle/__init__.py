@@ -24,7 +24,8 @@ passages of the paper they follow:
                       (section "Example usage").
 * ``philox``, ``gauss3`` -- the counter-based noise source (Philox4x64-10,
                       Salmon et al. 2011) that both sides implement
-                      independently.
+                      independently; ``philox32`` its 32-bit-word form
+                      (Philox4x32-10, same paper), the DPD pair noise.
 * ``forces_ext``, ``neighbors_le``, ``run_ext``, ``dpd_theta`` -- Lees-Edwards
                       sheared boundaries (section "New Features") and the
                       dissipative-particle-dynamics thermostat (section
@@ -74,6 +75,8 @@ def _load():
     i64, i32, f64, u64 = ctypes.c_int64, ctypes.c_int32, ctypes.c_double, ctypes.c_uint64
     lib.orc_philox4x64_10.argtypes = [P, P, P]
     lib.orc_philox4x64_10.restype = None
+    lib.orc_philox4x32_10.argtypes = [P, P, P]
+    lib.orc_philox4x32_10.restype = None
     lib.orc_gauss3.argtypes = [u64, u64, u64, u64, P]
     lib.orc_gauss3.restype = None
     lib.orc_pair_eval.argtypes = [P, f64, P, P]
@@ -124,6 +127,15 @@ def nthreads_default():
 
 
 # ---------------------------------------------------------------- RNG
+def philox32(counter, key):
+    """One Philox4x32-10 block: counter (4 x u32), key (2 x u32) -> 4 x u32."""
+    c = np.asarray(counter, dtype=np.uint32).copy()
+    k = np.asarray(key, dtype=np.uint32).copy()
+    out = np.zeros(4, dtype=np.uint32)
+    _load().orc_philox4x32_10(_ptr(c), _ptr(k), _ptr(out))
+    return out
+
+
 def philox(counter, key):
     """One Philox4x64-10 block: counter (4 x u64), key (2 x u64) -> 4 x u64."""
     c = np.asarray(counter, dtype=np.uint64).copy()

@@ -70,6 +70,31 @@ void orc_philox4x64_10(const uint64_t ctr[4], const uint64_t key[2], uint64_t ou
     out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;
 }
 
+/* Philox4x32-10 (the same paper): four 32-bit words, 10 rounds of two
+ * 32x32->64 multiplies by the published multipliers, the key bumped by the
+ * published Weyl constants between rounds. */
+static const uint32_t PHILOX32_M0 = 0xD2511F53u;
+static const uint32_t PHILOX32_M1 = 0xCD9E8D57u;
+static const uint32_t PHILOX32_W0 = 0x9E3779B9u; /* golden ratio */
+static const uint32_t PHILOX32_W1 = 0xBB67AE85u; /* sqrt(3) - 1 */
+
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
+    uint32_t x0 = ctr[0], x1 = ctr[1], x2 = ctr[2], x3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; ++round) {
+        uint64_t p0 = (uint64_t)PHILOX32_M0 * x0;
+        uint64_t p1 = (uint64_t)PHILOX32_M1 * x2;
+        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        uint32_t n0 = hi1 ^ x1 ^ k0;
+        uint32_t n2 = hi0 ^ x3 ^ k1;
+        x0 = n0; x1 = lo1; x2 = n2; x3 = lo0;
+        k0 += PHILOX32_W0;
+        k1 += PHILOX32_W1;
+    }
+    out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;
+}
+
 /* uniform in the open interval (0,1) from the top 53 bits */
 static double u01_open(uint64_t x) { return ((double)(x >> 11) + 0.5) * 0x1.0p-53; }
 
@@ -652,14 +677,19 @@ static void le_diff(const orc_le* le, const double L[3], const double H[3], cons
     *s = le->on ? sy : 0;
 }
 
-/* theta_ij for the unordered pair {ti, tj} at this step */
+/* theta_ij for the unordered pair {ti, tj} at this step: Philox4x32-10 at
+ * counter (step low word, step high word, min tag, max tag) with key (seed
+ * low word, seed high word ^ 6), Box-Muller on the first two words as
+ * uniforms (w + 1/2) 2^-32 */
 double orc_dpd_theta(uint64_t seed, uint64_t step, uint64_t ti, uint64_t tj) {
-    uint64_t ctr[4] = {step, ti < tj ? ti : tj, ti < tj ? tj : ti, 0};
-    uint64_t key[2] = {seed, 6};
-    uint64_t r[4];
-    orc_philox4x64_10(ctr, key, r);
+    const uint64_t a = ti < tj ? ti : tj, b = ti < tj ? tj : ti;
+    uint32_t ctr[4] = {(uint32_t)step, (uint32_t)(step >> 32), (uint32_t)a, (uint32_t)b};
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32) ^ 6u};
+    uint32_t r[4];
+    orc_philox4x32_10(ctr, key, r);
     const double two_pi = 6.283185307179586;
-    return sqrt(-2.0 * log(u01_open(r[0]))) * cos(two_pi * u01_open(r[1]));
+    const double u0 = ((double)r[0] + 0.5) * 0x1.0p-32, u1 = ((double)r[1] + 0.5) * 0x1.0p-32;
+    return sqrt(-2.0 * log(u0)) * cos(two_pi * u1);
 }
 
 /* Tabulated interactions (section "Functionality": tabulated potentials;

@@ -23,8 +23,11 @@ namespace {
 
 thread_local std::string g_last_error;
 
+// e[0] step start, e[4] after the cell sort, e[1] after the list build,
+// e[2] after the force stage, e[3] after the finalize
+constexpr int kStepEvents = 5;
 struct EvQuad {
-    hipEvent_t e[4];
+    hipEvent_t e[kStepEvents];
 };
 
 }  // namespace
@@ -592,7 +595,7 @@ static hipError_t launch_stage_finalize(md_handle h, int mode, const double* spa
 static hipError_t enqueue_step(md_handle h, const EvQuad* q) {
     hipError_t e;
     if (q) (void)hipEventRecord(q->e[0], h->stream);
-    e = launch_rebuild(h->g, h->b, h->parity, h->bonded, h->stream, nullptr, nullptr);
+    e = launch_rebuild(h->g, h->b, h->parity, h->bonded, h->stream, q ? q->e[4] : nullptr);
     if (e != hipSuccess) return e;
     if (q) (void)hipEventRecord(q->e[1], h->stream);
     const double* spart = nullptr;
@@ -638,7 +641,7 @@ static md_status build_graph(md_handle h) {
 
 static md_status rebuild_now(md_handle h, int force) {
     if (force) HIP_TRY(h, launch_set_ctl(h->b, -1, -1, 1, 0, h->stream));
-    HIP_TRY(h, launch_rebuild(h->g, h->b, h->parity, h->bonded, h->stream, nullptr, nullptr));
+    HIP_TRY(h, launch_rebuild(h->g, h->b, h->parity, h->bonded, h->stream));
     HIP_TRY(h, launch_clear_rebuild(h->b, h->stream));
     return MD_OK;
 }
@@ -1089,7 +1092,7 @@ md_status md_step(md_handle h, int64_t nsteps) {
                 q = h->ev_free.back();
                 h->ev_free.pop_back();
             } else {
-                for (int k = 0; k < 4; ++k) HIP_TRY(h, hipEventCreate(&q.e[k]));
+                for (int k = 0; k < kStepEvents; ++k) HIP_TRY(h, hipEventCreate(&q.e[k]));
             }
             h->ev_pending.push_back(q);
             qp = &h->ev_pending.back();
@@ -1201,12 +1204,14 @@ md_status md_timing_read(md_handle h, md_timing* out) {
     if (!h || !out) return fail(h, MD_ERR_ARG, "NULL argument");
     HIP_TRY(h, hipStreamSynchronize(h->stream));
     for (const EvQuad& q : h->ev_pending) {
-        float a = 0, b = 0, c = 0;
+        float a = 0, b = 0, c = 0, d = 0;
         HIP_TRY(h, hipEventElapsedTime(&a, q.e[0], q.e[1]));
         HIP_TRY(h, hipEventElapsedTime(&b, q.e[1], q.e[2]));
         HIP_TRY(h, hipEventElapsedTime(&c, q.e[2], q.e[3]));
+        HIP_TRY(h, hipEventElapsedTime(&d, q.e[0], q.e[4]));
         h->tacc.n_rebuild += 1;
         h->tacc.ms_rebuild += a;
+        h->tacc.ms_bin_sort += d;
         h->tacc.n_step_kernels += 1;
         h->tacc.ms_step_kernels += b;
         h->tacc.n_finalize += 1;
@@ -1506,7 +1511,8 @@ md_status bfail(md_batch b, md_status st, const std::string& msg) {
 
 hipError_t batch_enqueue_step(md_batch b, const EvQuad* q = nullptr) {
     if (q) (void)hipEventRecord(q->e[0], b->stream);
-    hipError_t e = launch_batch_rebuild(b->bc, b->tabs[0][b->parity], b->tile_sys, b->ntiles, b->parity, b->stream);
+    hipError_t e = launch_batch_rebuild(b->bc, b->tabs[0][b->parity], b->tile_sys, b->ntiles, b->parity, b->stream,
+                                        q ? q->e[4] : nullptr);
     if (e != hipSuccess) return e;
     if (q) (void)hipEventRecord(q->e[1], b->stream);
     e = launch_batch_step(b->tabs[0][b->parity], b->tile_sys, b->ntiles, b->parity, MODE_STEP, 0, b->stream);
@@ -1554,9 +1560,9 @@ md_status md_batch_destroy(md_batch b) {
     (void)hipStreamSynchronize(b->stream);
     batch_drop_graph(b);
     for (auto& q : b->ev_free)
-        for (int k = 0; k < 4; ++k) (void)hipEventDestroy(q.e[k]);
+        for (int k = 0; k < kStepEvents; ++k) (void)hipEventDestroy(q.e[k]);
     for (auto& q : b->ev_pending)
-        for (int k = 0; k < 4; ++k) (void)hipEventDestroy(q.e[k]);
+        for (int k = 0; k < kStepEvents; ++k) (void)hipEventDestroy(q.e[k]);
     for (md_handle h : b->sys) md_destroy(h);
     delete b;
     return MD_OK;
@@ -1660,7 +1666,7 @@ md_status md_batch_step(md_batch b, int64_t nsteps) {
                 q = b->ev_free.back();
                 b->ev_free.pop_back();
             } else {
-                for (int k = 0; k < 4; ++k) BHIP_TRY(b, hipEventCreate(&q.e[k]));
+                for (int k = 0; k < kStepEvents; ++k) BHIP_TRY(b, hipEventCreate(&q.e[k]));
             }
             b->ev_pending.push_back(q);
             BHIP_TRY(b, batch_enqueue_step(b, &b->ev_pending.back()));
@@ -1746,12 +1752,14 @@ md_status md_batch_timing_read(md_batch b, md_timing* out) {
     if (!b || !out) return fail(nullptr, MD_ERR_ARG, "NULL argument");
     BHIP_TRY(b, hipStreamSynchronize(b->stream));
     for (const EvQuad& q : b->ev_pending) {
-        float x = 0, y = 0, z = 0;
+        float x = 0, y = 0, z = 0, w = 0;
         BHIP_TRY(b, hipEventElapsedTime(&x, q.e[0], q.e[1]));
         BHIP_TRY(b, hipEventElapsedTime(&y, q.e[1], q.e[2]));
         BHIP_TRY(b, hipEventElapsedTime(&z, q.e[2], q.e[3]));
+        BHIP_TRY(b, hipEventElapsedTime(&w, q.e[0], q.e[4]));
         b->tacc.n_rebuild += 1;
         b->tacc.ms_rebuild += x;
+        b->tacc.ms_bin_sort += w;
         b->tacc.n_step_kernels += 1;
         b->tacc.ms_step_kernels += y;
         b->tacc.n_finalize += 1;
@@ -1773,9 +1781,9 @@ md_status md_destroy(md_handle h) {
         if (g_static_owner[h->static_dev] == h) g_static_owner[h->static_dev] = nullptr;
     }
     for (auto& q : h->ev_free)
-        for (int k = 0; k < 4; ++k) (void)hipEventDestroy(q.e[k]);
+        for (int k = 0; k < kStepEvents; ++k) (void)hipEventDestroy(q.e[k]);
     for (auto& q : h->ev_pending)
-        for (int k = 0; k < 4; ++k) (void)hipEventDestroy(q.e[k]);
+        for (int k = 0; k < kStepEvents; ++k) (void)hipEventDestroy(q.e[k]);
     delete h;
     return MD_OK;
 }

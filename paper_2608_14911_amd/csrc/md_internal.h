@@ -320,8 +320,9 @@ struct BatchCells {
     int32_t nsys;
 };
 
+// ev_sorted (or null) is recorded between the cell sort and the list build
 hipError_t launch_batch_rebuild(const BatchCells& bc, const SysEntry* tab, const int32_t* tile_sys, int64_t ntiles,
-                                int parity, hipStream_t s);
+                                int parity, hipStream_t s, hipEvent_t ev_sorted = nullptr);
 hipError_t launch_batch_step(const SysEntry* tab, const int32_t* tile_sys, int64_t ntiles, int parity, int mode,
                              int tensor, hipStream_t s);
 hipError_t launch_batch_finalize(const SysEntry* tab, int nsys, int mode, hipStream_t s);
@@ -334,7 +335,7 @@ hipError_t launch_init_load(const Geom& g, const Bufs& b, int parity, const doub
 hipError_t launch_set_ctl(const Bufs& b, int64_t step, int vel_half, int rebuild, int clear_status,
                           hipStream_t s);
 hipError_t launch_rebuild(const Geom& g, const Bufs& b, int parity, int bonded, hipStream_t s,
-                          hipEvent_t ev0, hipEvent_t ev1);
+                          hipEvent_t ev_sorted = nullptr);
 hipError_t launch_clear_rebuild(const Bufs& b, hipStream_t s);
 hipError_t launch_step(const StepArgs& a, int fp64, int single_type, int bonded, int block,
                        hipStream_t s);

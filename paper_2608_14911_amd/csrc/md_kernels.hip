@@ -72,6 +72,27 @@ __device__ __forceinline__ void philox4x64_10(uint64_t& x0, uint64_t& x1, uint64
     }
 }
 
+// Philox4x32-10 (the same paper): four 32-bit words, 10 rounds of two
+// 32x32->64 multiplies with the published multipliers, the key bumped by the
+// published Weyl constants between rounds.
+__device__ __forceinline__ void philox4x32_10(uint32_t& x0, uint32_t& x1, uint32_t& x2, uint32_t& x3,
+                                              uint32_t k0, uint32_t k1) {
+    const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t hi0 = __umulhi(M0, x0), lo0 = M0 * x0;
+        const uint32_t hi1 = __umulhi(M1, x2), lo1 = M1 * x2;
+        const uint32_t n0 = hi1 ^ x1 ^ k0;
+        const uint32_t n2 = hi0 ^ x3 ^ k1;
+        x0 = n0;
+        x1 = lo1;
+        x2 = n2;
+        x3 = lo0;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+}
+
 // Three N(0,1) draws keyed (seed, stream) at counter (step, tag, 0, 0):
 // uniforms ((w >> 11) + 1/2) 2^-53 in (0,1), Box-Muller in FP64.
 __device__ __forceinline__ void gauss3(uint64_t seed, uint64_t stream, uint64_t step, uint64_t tag,
@@ -1696,16 +1717,17 @@ __device__ __forceinline__ float adress_weight(const Dyn& dy, float x, float Lx)
     return 0.5f + 0.5f * __builtin_amdgcn_cosf(dy.ad_k * (d - dy.ad_dat) * 0.3183098861837907f);
 }
 
-// theta_ij of the DPD thermostat: Philox4x64-10 keyed (seed, 6) at counter
-// (step, min id, max id, 0), Box-Muller on the first two uniforms
-// ((w >> 11) + 1/2) 2^-53, evaluated in FP32 with the hardware log2 and
-// cosine (cos(2 pi u) from the revolution-scaled instruction): within a few
-// 1e-7 of the FP64 draw, far below the FP32 force rounding.
+// theta_ij of the DPD thermostat: Philox4x32-10 at counter (step low word,
+// step high word, min id, max id) with key (seed low word, seed high word
+// ^ 6), Box-Muller on the first two words as uniforms (w + 1/2) 2^-32,
+// evaluated in FP32 with the hardware log2 and cosine (cos(2 pi u) from the
+// revolution-scaled instruction): within a few 1e-7 of the FP64 draw, far
+// below the FP32 force rounding.
 __device__ __forceinline__ float dpd_theta(uint64_t seed, uint64_t step, uint32_t ti, uint32_t tj) {
-    uint64_t x0 = step, x1 = ti < tj ? ti : tj, x2 = ti < tj ? tj : ti, x3 = 0;
-    philox4x64_10(x0, x1, x2, x3, seed, 6);
-    const float u0 = fmaf((float)(x0 >> 11), 0x1.0p-53f, 0x1.0p-54f);
-    const float u1 = fmaf((float)(x1 >> 11), 0x1.0p-53f, 0x1.0p-54f);
+    uint32_t x0 = (uint32_t)step, x1 = (uint32_t)(step >> 32), x2 = ti < tj ? ti : tj, x3 = ti < tj ? tj : ti;
+    philox4x32_10(x0, x1, x2, x3, (uint32_t)seed, (uint32_t)(seed >> 32) ^ 6u);
+    const float u0 = fmaf((float)x0, 0x1.0p-32f, 0x1.0p-33f);
+    const float u1 = fmaf((float)x1, 0x1.0p-32f, 0x1.0p-33f);
     // -2 ln u0 = -2 ln 2 log2 u0
     const float rr = sqrtf(-1.3862943611198906f * __builtin_amdgcn_logf(u0));
     return rr * __builtin_amdgcn_cosf(u1);
@@ -2352,14 +2374,14 @@ hipError_t launch_clear_rebuild(const Bufs& b, hipStream_t s) {
 }
 
 hipError_t launch_rebuild(const Geom& g, const Bufs& b, int parity, int bonded, hipStream_t s,
-                          hipEvent_t ev0, hipEvent_t ev1) {
+                          hipEvent_t ev_sorted) {
     const int gs = grid_for(g.n, 512);
-    if (ev0) (void)hipEventRecord(ev0, s);
     hipLaunchKernelGGL(k_bin, dim3(gs), dim3(kBlock), 0, s, g, b, parity);
     hipLaunchKernelGGL(k_scan_chunks, dim3(kScanBlocks), dim3(kBlock), 0, s, g, b);
     hipLaunchKernelGGL(k_scatter, dim3(gs), dim3(kBlock), 0, s, g, b);
     hipLaunchKernelGGL(k_rank_permute, dim3(gs), dim3(kBlock), 0, s, g, b, parity);
     hipLaunchKernelGGL(k_commit, dim3(gs), dim3(kBlock), 0, s, g, b, parity, bonded);
+    if (ev_sorted) (void)hipEventRecord(ev_sorted, s);
     if (g.le)
         hipLaunchKernelGGL(k_nl_build_le, dim3(grid_for(g.n, 1 << 20)), dim3(kBlock), 0, s, g, b, parity, bonded);
     else if (g.nl_tile)
@@ -2367,7 +2389,6 @@ hipError_t launch_rebuild(const Geom& g, const Bufs& b, int parity, int bonded, 
                            parity, bonded);
     else
         hipLaunchKernelGGL(k_nl_build, dim3(grid_for(g.n, 1 << 20)), dim3(kBlock), 0, s, g, b, parity, bonded);
-    if (ev1) (void)hipEventRecord(ev1, s);
     return hipGetLastError();
 }
 
@@ -2478,7 +2499,7 @@ hipError_t launch_sur_step(const StepArgs& a, const SurBufs& sb, const SurConst&
 namespace md {
 
 hipError_t launch_batch_rebuild(const BatchCells& bc, const SysEntry* tab, const int32_t* tile_sys, int64_t ntiles,
-                                int parity, hipStream_t s) {
+                                int parity, hipStream_t s, hipEvent_t ev_sorted) {
     const dim3 tg((unsigned)ntiles), blk(kBlock);
     hipLaunchKernelGGL(k_batch_any, dim3(1), dim3(256), 0, s, bc);
     hipLaunchKernelGGL(k_batch_bin, tg, blk, 0, s, tab, tile_sys, parity);
@@ -2490,6 +2511,7 @@ hipError_t launch_batch_rebuild(const BatchCells& bc, const SysEntry* tab, const
     hipLaunchKernelGGL(k_batch_scatter, tg, blk, 0, s, tab, tile_sys);
     hipLaunchKernelGGL(k_batch_permute, tg, blk, 0, s, tab, tile_sys, parity);
     hipLaunchKernelGGL(k_batch_commit, tg, blk, 0, s, tab, tile_sys, parity);
+    if (ev_sorted) (void)hipEventRecord(ev_sorted, s);
     hipLaunchKernelGGL(k_batch_nl, tg, blk, 0, s, tab, tile_sys, parity);
     return hipGetLastError();
 }

@@ -108,7 +108,8 @@ class md_obs(ctypes.Structure):
 class md_timing(ctypes.Structure):
     _fields_ = [("n_step_kernels", ctypes.c_int64), ("ms_step_kernels", ctypes.c_double),
                 ("n_rebuild", ctypes.c_int64), ("ms_rebuild", ctypes.c_double),
-                ("n_finalize", ctypes.c_int64), ("ms_finalize", ctypes.c_double)]
+                ("n_finalize", ctypes.c_int64), ("ms_finalize", ctypes.c_double),
+                ("ms_bin_sort", ctypes.c_double)]
 
 
 class md_plan(ctypes.Structure):

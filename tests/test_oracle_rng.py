@@ -1,15 +1,17 @@
-"""Pins of the oracle's noise source.
+"""Pins of the oracle's noise sources.
 
 Philox4x64-10 (Salmon et al. 2011) is pinned against numpy's independent
 implementation of the same generator: numpy advances its 256-bit counter
 before producing a block, so the block for counter c is numpy's first block
-when it is seeded with c - 1.  The Gaussian draws are pinned by their
-moments.
+when it is seeded with c - 1.  Philox4x32-10 (the same paper; the DPD pair
+noise) is pinned against rocRAND's host implementation.  The Gaussian draws
+are pinned by their moments.
 """
 import numpy as np
 import pytest
 
 import oracle
+import rocrand_ref
 
 
 def numpy_block(counter, key):
@@ -61,3 +63,16 @@ def test_gauss3_tail_probability():
     frac = np.mean(np.abs(z) > 2.0)
     # P(|z| > 2) = 0.0455 for a standard normal
     assert abs(frac - 0.0455003) < 5 * np.sqrt(0.0455 * 0.9545 / z.size)
+
+
+def test_philox32_matches_rocrand():
+    g = np.random.default_rng(3)
+    ctrs = [[0, 0, 0, 0], [1, 0, 0, 0], [0xFFFFFFFF] * 4, [0x243F6A88, 0x85A308D3, 0x13198A2E, 0x03707344],
+            [7, 0xFFFFFFFF, 1, 0]] + [list(g.integers(0, 2**32, size=4)) for _ in range(40)]
+    keys = [[0, 0], [5, 7], [0xFFFFFFFF] * 2, [0xA4093822, 0x299F31D0], [1, 2]] + \
+        [list(g.integers(0, 2**32, size=2)) for _ in range(40)]
+    ref = rocrand_ref.blocks(ctrs, keys)
+    if ref is None:
+        pytest.skip("hipcc or the rocRAND header is not available")
+    mine = np.array([oracle.philox32(c, k) for c, k in zip(ctrs, keys)])
+    assert np.array_equal(mine, ref)

@@ -5,8 +5,8 @@ conditions; section "Functionality": dissipative particle dynamics) and
 prints no formula; the oracle follows the textbook definitions.  Pinned here
 by what does not retype them:
 
-* the pair noise theta_ij against numpy's own Philox4x64-10 and the
-  Box-Muller transform, and its symmetry in (i, j);
+* the pair noise theta_ij against rocRAND's own Philox4x32-10 and the
+  Box-Muller transform, its symmetry in (i, j), and its moments;
 * neighbour sets under shear against an explicit enumeration of the sheared
   periodic images (the image n_y boxes above is displaced by n_y delta in x);
 * closed forms: a pair across the sheared boundary feels the LJ force of the
@@ -24,23 +24,37 @@ import numpy as np
 import pytest
 
 import oracle
+import rocrand_ref
 from paper_2608_14911_amd import inputs
 
 
-def numpy_theta(seed, step, ti, tj):
-    c = (step | (min(ti, tj) << 64) | (max(ti, tj) << 128)) - 1
-    words = np.array([(c >> (64 * i)) & ((1 << 64) - 1) for i in range(4)], dtype=np.uint64)
-    r = np.random.Philox(key=np.array([seed, 6], dtype=np.uint64), counter=words).random_raw(4)
-    u0 = ((int(r[0]) >> 11) + 0.5) * 2.0 ** -53
-    u1 = ((int(r[1]) >> 11) + 0.5) * 2.0 ** -53
+def reference_theta(seed, step, ti, tj):
+    """Box-Muller on rocRAND's Philox4x32-10 block at counter (step low,
+    step high, min tag, max tag) with key (seed low, seed high ^ 6)."""
+    ctr = [step & 0xFFFFFFFF, step >> 32, min(ti, tj), max(ti, tj)]
+    key = [seed & 0xFFFFFFFF, (seed >> 32) ^ 6]
+    r = rocrand_ref.blocks([ctr], [key])
+    if r is None:
+        pytest.skip("hipcc or the rocRAND header is not available")
+    u0 = (int(r[0][0]) + 0.5) * 2.0 ** -32
+    u1 = (int(r[0][1]) + 0.5) * 2.0 ** -32
     return math.sqrt(-2.0 * math.log(u0)) * math.cos(2.0 * math.pi * u1)
 
 
-@pytest.mark.parametrize("seed,step,ti,tj", [(1, 1, 0, 1), (77, 123456, 5, 3), (2**40 + 3, 9, 1000, 999999)])
-def test_dpd_theta_is_numpy_philox_box_muller_and_symmetric(seed, step, ti, tj):
+@pytest.mark.parametrize("seed,step,ti,tj", [(1, 1, 0, 1), (77, 123456, 5, 3), (2**40 + 3, 9, 1000, 999999),
+                                             (5, 2**33 + 17, 12, 4)])
+def test_dpd_theta_is_rocrand_philox_box_muller_and_symmetric(seed, step, ti, tj):
     t = oracle.dpd_theta(seed, step, ti, tj)
-    assert t == pytest.approx(numpy_theta(seed, step, ti, tj), rel=1e-14, abs=1e-14)
+    assert t == pytest.approx(reference_theta(seed, step, ti, tj), rel=1e-14, abs=1e-14)
     assert t == oracle.dpd_theta(seed, step, tj, ti)
+
+
+def test_dpd_theta_moments():
+    n = 40000
+    th = np.array([oracle.dpd_theta(9, 1 + k // 200, k % 200, 200 + k % 37) for k in range(n)])
+    assert abs(th.mean()) < 5 / math.sqrt(n)
+    assert abs(th.var() - 1.0) < 5 * math.sqrt(2.0 / n)
+    assert abs((th ** 4).mean() - 3.0) < 5 * math.sqrt(96.0 / n)
 
 
 def image_enumeration_sets(pos, box, rv, delta):
