@@ -1337,7 +1337,12 @@ __device__ __forceinline__ void block_epilogue(const StepArgs& a, const double* 
     const bool any_bond = __any(flag_bond);
     const bool any_nf = __any(flag_nf);
     if ((threadIdx.x & 63) == 0) {
-        if (any_reb) __atomic_store_n(&b.ctl->rebuild_next, 1u, __ATOMIC_RELAXED);
+        // Stores to one address from many wavefronts serialize, and under a
+        // drifting sheared image nearly every wavefront of a step can ask for
+        // the rebuild, so a wavefront sets the flag only when it reads it
+        // clear; a stale read costs one redundant store, never a lost request.
+        if (any_reb && __hip_atomic_load(&b.ctl->rebuild_next, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u)
+            __atomic_store_n(&b.ctl->rebuild_next, 1u, __ATOMIC_RELAXED);
         if (any_bond) atomicOr(&b.ctl->status, MD_FLAG_BOND_BROKEN);
         if (any_nf) atomicOr(&b.ctl->status, MD_FLAG_NONFINITE);
     }
