@@ -975,8 +975,16 @@ __device__ __forceinline__ void nl_one_le(const Geom& g, const Bufs& b, int64_t 
     const DiffLEQ df{g.ql[0], g.ql[1], g.ql[2], qd};
     int32_t* __restrict__ nlrow = b.nl + nl_base(i, g.cap);
     int cnt = 0;
+    // the first kNlLds slots collect in LDS, [slot][lane] per wavefront, and
+    // leave in whole-wavefront stores at the end (as in the plain build)
+    __shared__ int32_t nlbuf_le[kBlock / 64][kNlLds][64];
+    const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
+    auto put = [&](int k, int j) {
+        if (k < kNlLds) nlbuf_le[wv][k][ln] = j;
+        else nlrow[nl_off(k)] = j;
+    };
     // candidates gathered four at a time, the last one repeated past the end
-    // of the range (the order of the tests, and so the row, is unchanged)
+    // of the range
     auto test_range = [&](int st, int en) {
         for (int j0 = st; j0 < en; j0 += 4) {
             int4 qq[4];
@@ -992,50 +1000,71 @@ __device__ __forceinline__ void nl_one_le(const Geom& g, const Bufs& b, int64_t 
                 bool in = r2 < g.rv2lo;
                 if (!in && r2 < g.rv2hi) in = exact_r2_le(g, xi, x[j], dw) < g.rv2;
                 if (in && j != i) {
-                    if (cnt < g.cap) nlrow[nl_off(cnt)] = j;
+                    if (cnt < g.cap) put(cnt, j);
                     ++cnt;
                 }
             }
         }
     };
+    // Piece v is the first or second contiguous range of stencil row v / 2
+    // (rows z-major; empty when the row is out of reach or does not wrap).
+    // Across the y-boundary the row's x-range is re-centred on x_i +- delta
+    // with one cell of margin each side (the whole row when that covers it).
+    // The bounds of piece v + 1 are loaded before piece v is tested.
     const int32_t* __restrict__ cs = b.cstart;
-    for (int oz = -kc; oz <= kc; ++oz) {
+    const int side = 2 * kc + 1, nv = 2 * side * side;
+    const double rv = sqrt(g.rv2);
+    auto piece = [&](int v, int& a, int& e) {
+        a = e = 0;
+        const int r = v >> 1, pc = v & 1;
+        const int oz = r / side - kc, oy = r % side - kc;
         const float gz = cell_gap(oz, uz, (float)g.h[2]);
-        if (gz * gz > g.rv2hi) continue;
+        if (gz * gz > g.rv2hi) return;
+        const float gy = cell_gap(oy, uy, (float)g.h[1]);
+        if (gz * gz + gy * gy > g.rv2hi) return;
         const int nz = wrapc(cz + oz, g.nc[2]);
-        for (int oy = -kc; oy <= kc; ++oy) {
-            const float gy = cell_gap(oy, uy, (float)g.h[1]);
-            if (gz * gz + gy * gy > g.rv2hi) continue;
-            const int yraw = cy + oy;
-            const int s = yraw < 0 ? 1 : (yraw >= g.nc[1] ? -1 : 0);
-            const int ny = wrapc(yraw, g.nc[1]);
-            const int64_t rowc = ((int64_t)nz * g.nc[1] + ny) * nx;
-            int lo = cx - kc, hi = cx + kc;
-            if (s != 0) {
-                const double c0 = xi.x + s * delta;
-                lo = (int)floor((c0 - sqrt(g.rv2)) * g.invh[0]) - 1;
-                hi = (int)floor((c0 + sqrt(g.rv2)) * g.invh[0]) + 1;
-            }
-            if (hi - lo + 1 >= nx) {
-                test_range(cs[rowc], cs[rowc + nx]);
-                continue;
-            }
-            // [lo, hi] modulo nx: one or two contiguous ranges of cells
-            const int l = ((lo % nx) + nx) % nx;
-            const int h = l + (hi - lo);
-            if (h < nx) {
-                test_range(cs[rowc + l], cs[rowc + h + 1]);
-            } else {
-                test_range(cs[rowc + l], cs[rowc + nx]);
-                test_range(cs[rowc], cs[rowc + h - nx + 1]);
-            }
+        const int yraw = cy + oy;
+        const int sh = yraw < 0 ? 1 : (yraw >= g.nc[1] ? -1 : 0);
+        const int ny = wrapc(yraw, g.nc[1]);
+        const int64_t rowc = ((int64_t)nz * g.nc[1] + ny) * nx;
+        int lo = cx - kc, hi = cx + kc;
+        if (sh != 0) {
+            const double c0 = xi.x + sh * delta;
+            lo = (int)floor((c0 - rv) * g.invh[0]) - 1;
+            hi = (int)floor((c0 + rv) * g.invh[0]) + 1;
         }
+        if (hi - lo + 1 >= nx) {
+            if (pc == 0) { a = cs[rowc]; e = cs[rowc + nx]; }
+            return;
+        }
+        // [lo, hi] modulo nx: one or two contiguous ranges of cells
+        const int l = ((lo % nx) + nx) % nx;
+        const int h = l + (hi - lo);
+        if (h < nx) {
+            if (pc == 0) { a = cs[rowc + l]; e = cs[rowc + h + 1]; }
+        } else if (pc == 0) {
+            a = cs[rowc + l]; e = cs[rowc + nx];
+        } else {
+            a = cs[rowc]; e = cs[rowc + h - nx + 1];
+        }
+    };
+    int pa, pe;
+    piece(0, pa, pe);
+    for (int v = 0; v < nv; ++v) {
+        int na = 0, ne = 0;
+        if (v + 1 < nv) piece(v + 1, na, ne);
+        test_range(pa, pe);
+        pa = na;
+        pe = ne;
     }
     b.ncount[i] = cnt;
     if (cnt > local_max) local_max = cnt;
     if (cnt > g.cap) overflow = true;
     const int nslot = min(((cnt + 7) & ~7), g.cap);
-    for (int k = cnt; k < nslot; ++k) nlrow[nl_off(k)] = (int)i;
+    for (int k = cnt; k < nslot; ++k) put(k, (int)i);
+#pragma unroll
+    for (int k = 0; k < kNlLds; ++k)
+        if (k < nslot) nlrow[nl_off(k)] = nlbuf_le[wv][k][ln];
     if (bonded) remap_bonded(b, n, i);
 }
 
