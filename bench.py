@@ -523,10 +523,40 @@ def bench_batch(a):
                      "alg_bytes_per_launch": alg},
         "kernel_breakdown_ms_per_step": breakdown(tm, "step_kernel", k_ms),
     }
+    t_one = standalone_seconds_per_step(reps)
+    free_gpu()
+    rec["vs_members_one_by_one"] = {
+        "method": "each member as its own handle (plain step kernels, graph-replayed md_step), 4 untimed "
+                  "and 20 timed steps from the same start, summed time per step",
+        "ms_per_step": 1e3 * t_one, "atom_steps_per_s": ntot / t_one,
+        "batched_over_one_by_one": rec["value"] / (ntot / t_one)}
     if table:
         rec["autotune_trials"] = table
-    log("batch: %.3g atom-steps/s, %.3f ms/step" % (rec["value"], rec["ms_per_step"]), a.quiet)
+    log("batch: %.3g atom-steps/s, %.3f ms/step (%.1fx the members one by one)" % (
+        rec["value"], rec["ms_per_step"], rec["vs_members_one_by_one"]["batched_over_one_by_one"]), a.quiet)
     return reps, rec
+
+
+def standalone_seconds_per_step(reps, steps=20, warm=4):
+    """The batch's members advanced one by one, each as its own handle with
+    the same parameters: the summed wall time per step."""
+    from paper_2608_14911_amd.system import System, nl_build_flags
+    t_sum = 0.0
+    for r in reps:
+        s = System(r["pos"], r["box"], r.get("vel"), pair=r.get("pair"), bonds=r.get("bonds"), angles=r.get("angles"),
+                   k_bend=r.get("k_bend", 0.0), dt=r.get("dt", 0.005), skin=r.get("skin", 0.3),
+                   integrator=r.get("integrator", "nve"), temperature=r.get("temperature", 1.0),
+                   gamma=r.get("gamma", 0.0), seed=r.get("seed", 0), masses=r.get("masses", (1.0,)),
+                   nl_capacity=r.get("nl_capacity", 0), cell_factor=r.get("cell_factor", 0),
+                   flags=nl_build_flags(r.get("nl_build", "auto")))
+        s.step(warm)
+        s.stream.synchronize()
+        t1 = time.perf_counter()
+        s.step(steps)
+        s.stream.synchronize()
+        t_sum += (time.perf_counter() - t1) / steps
+        s.close()
+    return t_sum
 
 
 # ---------------------------------------------------------------- main
