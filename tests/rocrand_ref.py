@@ -7,6 +7,7 @@ the counter's high half as the subsequence and to its low half as the
 block offset, and prints the block.  ``blocks()`` returns None when the
 compiler or the header is missing.
 """
+import atexit
 import os
 import shutil
 import subprocess
@@ -50,6 +51,7 @@ def _build():
     if not (os.path.exists(HIPCC) and os.path.exists(HEADER)):
         return None
     d = tempfile.mkdtemp(prefix="rocrand_ref_")
+    atexit.register(shutil.rmtree, d, True)
     src = os.path.join(d, "philox_ref.cpp")
     exe = os.path.join(d, "philox_ref")
     with open(src, "w") as f:
