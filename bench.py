@@ -1,6 +1,7 @@
 """Throughput of the short-range MD step on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload default|lj1m|kg2m|batch|sur1m|kg1k]
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+                    [--workload default|lj1m|kg2m|batch|sur1m|dpd1m|adress1m|kg1k]
 
 The headline workload is the LJ fluid of 1,048,576 particles (FCC 64^3,
 density 0.8442, uniform jitter 0.05, T = 0.72), rc = 2.5 shifted, skin 0.3,
@@ -15,10 +16,13 @@ Each workload is timed twice over K steps after W warm-up steps:
   2. an evented pass: the same K steps launched kernel by kernel with HIP
      events on the library's stream around each stage -> the per-stage
      breakdown and the ``roofline`` of the fused force + integrate kernel.
-The default run prints one JSON line for the LJ fluid with the other
-workloads (2M-bead melt, 256-replica batch, learned surrogate on a 1M-bead
-melt) as sub-records under "workloads", and a "cpu_baseline" object: the FP64
-oracle timed on this host on a bounded sample, with all threads and with one.
+The breakdown splits the rebuild stage into binning + cell sort and the
+neighbour-list build.  The default run prints one JSON line for the LJ fluid
+with the other workloads (2M-bead melt, 256-replica batch with its members
+also run one by one, learned surrogate on a 1M-bead melt, DPD fluid under
+Lees-Edwards shear, AdResS fluid) as sub-records under "workloads", and a
+"cpu_baseline" object: the FP64 oracle timed on this host on a bounded
+sample, with all threads and with one.
 """
 import argparse
 import hashlib
