@@ -345,7 +345,6 @@ static size_t carve(const md_config* c, const Geom& g, int step_grid, uint8_t* b
     t.xt = (double4*)take(sizeof(double4) * n);
     t.vt = (double*)take(sizeof(double) * 3 * n);
     t.imgt = (int32_t*)take(sizeof(int32_t) * 3 * n);
-    t.tagt = (int32_t*)take(sizeof(int32_t) * n);
     t.tsc = (int32_t*)take(sizeof(int32_t) * n);
     t.ncount = (int32_t*)take(sizeof(int32_t) * n);
     t.nl = (int32_t*)take(sizeof(int32_t) * (size_t)g.cap * (size_t)((n + 63) / 64 * 64));

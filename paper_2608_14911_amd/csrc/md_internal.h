@@ -135,7 +135,6 @@ struct Bufs {
     double4* xt;            // permute temporaries
     double* vt;
     int32_t* imgt;
-    int32_t* tagt;
     int32_t* tsc;           // [N] tags in scatter order (rank inside a cell)
     int32_t* nl;            // ELL in 64-particle tiles [N/64][cap][64], sorted indices
     int32_t* ncount;        // [N]

@@ -445,7 +445,9 @@ __global__ void __launch_bounds__(kBlock) k_scatter(Geom g, Bufs b) {
 
 // Order inside a cell by particle tag: the sorted order is then a function
 // of the positions alone, so a run resumed from a saved build snapshot
-// reproduces it exactly.  Gathers all per-particle arrays into temporaries.
+// reproduces it exactly.  Gathers the positions, velocities and images into
+// temporaries; the tags, which no thread of this pass reads, go straight to
+// their sorted slots.
 __device__ __forceinline__ void permute_one(const Geom& g, const Bufs& b, int64_t s, int parity) {
     const int64_t n = g.n;
     {
@@ -466,7 +468,7 @@ __device__ __forceinline__ void permute_one(const Geom& g, const Bufs& b, int64_
             b.vt[d * n + nw] = b.v[d * n + i];
             b.imgt[d * n + nw] = b.img[d * n + i];
         }
-        b.tagt[nw] = ti;
+        b.tag[nw] = ti;
     }
 }
 
@@ -495,10 +497,9 @@ __device__ __forceinline__ void commit_one(const Geom& g, const Bufs& b, int64_t
             b.v[d * n + s] = b.vt[d * n + s];
             b.img[d * n + s] = b.imgt[d * n + s];
         }
-        int32_t t = b.tagt[s];
-        b.tag[s] = t;
-        b.inv[t] = (int32_t)s;
-        if (bonded) b.tcnt_s[s] = b.tcnt_t[t];
+        // the inverse permutation serves only the bonded remap of the list
+        // build, which also copies the per-particle bond and angle counts
+        if (bonded) b.inv[b.tag[s]] = (int32_t)s;
     }
 }
 
@@ -530,10 +531,12 @@ __device__ __forceinline__ float cell_gap(int o, float u, float h) {
 
 __device__ __forceinline__ int wrapc(int c, int nc) { return c < 0 ? c + nc : (c >= nc ? c - nc : c); }
 
-// Bond and angle partners of sorted particle i from tags to sorted indices.
+// Bond and angle counts and partners of sorted particle i, partners from
+// tags to sorted indices.
 __device__ __forceinline__ void remap_bonded(const Bufs& b, int64_t n, int64_t i) {
     const int32_t t = b.tag[i];
     const int tc = b.tcnt_t[t];
+    b.tcnt_s[i] = tc;
     const int nb = tc & 0xff, na = tc >> 8;
     for (int k = 0; k < nb; ++k) b.bp_s[(int64_t)k * n + i] = b.inv[b.bp_t[(int64_t)k * n + t]];
     for (int k = 0; k < na; ++k) {
