@@ -554,7 +554,7 @@ __device__ __forceinline__ void remap_bonded(const Bufs& b, int64_t n, int64_t i
 // rounding, so the sets are those of the FP64 definition.  Row order:
 // stencil (z, y, x offsets), then sorted index.  Also remaps the bonded
 // topology from tags to sorted indices.
-constexpr int kNlLds = 24;  // row slots staged in LDS by the per-particle build (24 KB per block)
+constexpr int kNlLds = 24;  // row slots staged in LDS by the per-particle build (25 KB per block with the spare row)
 __device__ __forceinline__ void nl_one(const Geom& g, const Bufs& b, int64_t i, int parity, int bonded,
                                        int& local_max, bool& overflow) {
     const int64_t n = g.n;
@@ -570,12 +570,14 @@ __device__ __forceinline__ void nl_one(const Geom& g, const Bufs& b, int64_t i, 
         const float uy = (float)(xi.y - cy * g.h[1]);
         const float uz = (float)(xi.z - cz * g.h[2]);
         int cnt = 0;
+        const int self = (int)i;
         int32_t* __restrict__ nlrow = b.nl + nl_base(i, g.cap);
         // The first kNlLds slots of each row collect in LDS, [slot][lane] per
         // wavefront, and leave in whole-wavefront stores at the end: the
         // hits of the lanes fall in different iterations, so direct stores
         // would cost one partly masked store instruction per hit event.
-        __shared__ int32_t nlbuf[kBlock / 64][kNlLds][64];
+        // Row kNlLds is a spare that takes the stores of candidates that miss.
+        __shared__ int32_t nlbuf[kBlock / 64][kNlLds + 1][64];
         const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
         auto put = [&](int k, int j) {
             if (k < kNlLds) nlbuf[wv][k][ln] = j;
@@ -585,24 +587,46 @@ __device__ __forceinline__ void nl_one(const Geom& g, const Bufs& b, int64_t i, 
         // order, so their particles form one contiguous range of the sorted
         // arrays (two when the row wraps around the box).  Candidates are
         // gathered four at a time, the last one repeated past the end of the
-        // range, so a short range costs one memory round trip.
+        // range, so a short range costs one memory round trip.  The four
+        // tests become flags with one branch for the rare FP64 band, and
+        // while the row's next four slots lie in LDS every candidate is
+        // stored, a miss to the spare row: per-candidate branches cost more
+        // scalar and branch issue than the tests themselves.
         auto test_range = [&](int st, int en) {
             for (int j = st; j < en; j += 4) {
                 int4 qq[4];
 #pragma unroll
                 for (int u = 0; u < 4; ++u) qq[u] = xq[min(j + u, en - 1)];
+                bool in[4], band[4];
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
-                    if (j + u >= en) break;
                     const float dx = qdiff(qq[u].x, qi.x, g.ql[0]);
                     const float dy = qdiff(qq[u].y, qi.y, g.ql[1]);
                     const float dz = qdiff(qq[u].z, qi.z, g.ql[2]);
                     const float r2 = dx * dx + dy * dy + dz * dz;
-                    bool in = r2 < g.rv2lo;
-                    if (!in && r2 < g.rv2hi) in = exact_r2(g, xi, x[j + u]) < g.rv2;
-                    if (in && j + u != i) {
-                        if (cnt < g.cap) put(cnt, j + u);
-                        ++cnt;
+                    // bitwise, not short-circuit: no branch around the test
+                    const bool ok = (j + u < en) & (j + u != self);
+                    in[u] = ok & (r2 < g.rv2lo);
+                    band[u] = ok & (r2 >= g.rv2lo) & (r2 < g.rv2hi);
+                }
+                if (band[0] | band[1] | band[2] | band[3]) {
+#pragma unroll
+                    for (int u = 0; u < 4; ++u)
+                        if (band[u]) in[u] = exact_r2(g, xi, x[j + u]) < g.rv2;
+                }
+                if (cnt + 4 <= kNlLds) {
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        nlbuf[wv][in[u] ? cnt : kNlLds][ln] = j + u;
+                        cnt += in[u] ? 1 : 0;
+                    }
+                } else {
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        if (in[u]) {
+                            if (cnt < g.cap) put(cnt, j + u);
+                            ++cnt;
+                        }
                     }
                 }
             }
@@ -980,31 +1004,49 @@ __device__ __forceinline__ void nl_one_le(const Geom& g, const Bufs& b, int64_t 
     int cnt = 0;
     // the first kNlLds slots collect in LDS, [slot][lane] per wavefront, and
     // leave in whole-wavefront stores at the end (as in the plain build)
-    __shared__ int32_t nlbuf_le[kBlock / 64][kNlLds][64];
+    // (row kNlLds is the spare of the misses, as there)
+    __shared__ int32_t nlbuf_le[kBlock / 64][kNlLds + 1][64];
     const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
+    const int self = (int)i;
     auto put = [&](int k, int j) {
         if (k < kNlLds) nlbuf_le[wv][k][ln] = j;
         else nlrow[nl_off(k)] = j;
     };
     // candidates gathered four at a time, the last one repeated past the end
-    // of the range
+    // of the range; tests as flags and stores as in the plain build
     auto test_range = [&](int st, int en) {
         for (int j0 = st; j0 < en; j0 += 4) {
             int4 qq[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) qq[u] = xq[min(j0 + u, en - 1)];
+            bool in[4], band[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                const int j = j0 + u;
-                if (j >= en) break;
                 float dx, dy, dz;
                 df(qi, qq[u], dx, dy, dz);
                 const float r2 = dx * dx + dy * dy + dz * dz;
-                bool in = r2 < g.rv2lo;
-                if (!in && r2 < g.rv2hi) in = exact_r2_le(g, xi, x[j], dw) < g.rv2;
-                if (in && j != i) {
-                    if (cnt < g.cap) put(cnt, j);
-                    ++cnt;
+                const bool ok = (j0 + u < en) & (j0 + u != self);
+                in[u] = ok & (r2 < g.rv2lo);
+                band[u] = ok & (r2 >= g.rv2lo) & (r2 < g.rv2hi);
+            }
+            if (band[0] | band[1] | band[2] | band[3]) {
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    if (band[u]) in[u] = exact_r2_le(g, xi, x[j0 + u], dw) < g.rv2;
+            }
+            if (cnt + 4 <= kNlLds) {
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    nlbuf_le[wv][in[u] ? cnt : kNlLds][ln] = j0 + u;
+                    cnt += in[u] ? 1 : 0;
+                }
+            } else {
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    if (in[u]) {
+                        if (cnt < g.cap) put(cnt, j0 + u);
+                        ++cnt;
+                    }
                 }
             }
         }
