@@ -555,6 +555,45 @@ __device__ __forceinline__ void remap_bonded(const Bufs& b, int64_t n, int64_t i
 // stencil (z, y, x offsets), then sorted index.  Also remaps the bonded
 // topology from tags to sorted indices.
 constexpr int kNlLds = 24;  // row slots staged in LDS by the per-particle build (25 KB per block with the spare row)
+
+// Store a group of four tested candidates j0..j0+3 (hits flagged in `in`) to
+// a per-particle row: its first kNlLds slots in LDS (buf, [slot][lane] of the
+// wavefront, row kNlLds a spare), the rest in the list.  While the next four
+// slots lie in LDS every candidate is stored, a miss to the spare row, with
+// no branch; past them (LIST_PATH) one masked store per hit; otherwise, and
+// for the group that crosses from LDS to the list, the general path.  Hits
+// beyond the capacity are counted, not stored.  The list-only path pays where
+// rows run well past the LDS slots (the dense fluids of a batch); where rows
+// end near them (the sheared DPD fluid, ~28 slots) the lanes split over three
+// paths and it cost 11 % of the build, so that build leaves it out.
+template <bool LIST_PATH>
+__device__ __forceinline__ void nl_store4(int32_t (*buf)[64], int ln, int32_t* __restrict__ nlrow, int cap,
+                                          const bool (&in)[4], int j0, int& cnt) {
+    if (cnt + 4 <= kNlLds) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            buf[in[u] ? cnt : kNlLds][ln] = j0 + u;
+            cnt += in[u] ? 1 : 0;
+        }
+    } else if (LIST_PATH && cnt >= kNlLds) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            if (in[u] & (cnt < cap)) nlrow[nl_off(cnt)] = j0 + u;
+            cnt += in[u] ? 1 : 0;
+        }
+    } else {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            if (in[u]) {
+                if (cnt < cap) {
+                    if (cnt < kNlLds) buf[cnt][ln] = j0 + u;
+                    else nlrow[nl_off(cnt)] = j0 + u;
+                }
+                ++cnt;
+            }
+        }
+    }
+}
 __device__ __forceinline__ void nl_one(const Geom& g, const Bufs& b, int64_t i, int parity, int bonded,
                                        int& local_max, bool& overflow) {
     const int64_t n = g.n;
@@ -588,10 +627,10 @@ __device__ __forceinline__ void nl_one(const Geom& g, const Bufs& b, int64_t i, 
         // arrays (two when the row wraps around the box).  Candidates are
         // gathered four at a time, the last one repeated past the end of the
         // range, so a short range costs one memory round trip.  The four
-        // tests become flags with one branch for the rare FP64 band, and
-        // while the row's next four slots lie in LDS every candidate is
-        // stored, a miss to the spare row: per-candidate branches cost more
-        // scalar and branch issue than the tests themselves.
+        // tests become flags with one branch for the rare FP64 band, and the
+        // stores take as few branches as the row's position allows
+        // (nl_store4): per-candidate branches cost more scalar and branch
+        // issue than the tests themselves.
         auto test_range = [&](int st, int en) {
             for (int j = st; j < en; j += 4) {
                 int4 qq[4];
@@ -614,21 +653,7 @@ __device__ __forceinline__ void nl_one(const Geom& g, const Bufs& b, int64_t i, 
                     for (int u = 0; u < 4; ++u)
                         if (band[u]) in[u] = exact_r2(g, xi, x[j + u]) < g.rv2;
                 }
-                if (cnt + 4 <= kNlLds) {
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        nlbuf[wv][in[u] ? cnt : kNlLds][ln] = j + u;
-                        cnt += in[u] ? 1 : 0;
-                    }
-                } else {
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        if (in[u]) {
-                            if (cnt < g.cap) put(cnt, j + u);
-                            ++cnt;
-                        }
-                    }
-                }
+                nl_store4<true>(nlbuf[wv], ln, nlrow, g.cap, in, j, cnt);
             }
         };
         const int xlo = cx - kc, xhi = cx + kc;   // inclusive cell range along x
@@ -1034,21 +1059,7 @@ __device__ __forceinline__ void nl_one_le(const Geom& g, const Bufs& b, int64_t 
                 for (int u = 0; u < 4; ++u)
                     if (band[u]) in[u] = exact_r2_le(g, xi, x[j0 + u], dw) < g.rv2;
             }
-            if (cnt + 4 <= kNlLds) {
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    nlbuf_le[wv][in[u] ? cnt : kNlLds][ln] = j0 + u;
-                    cnt += in[u] ? 1 : 0;
-                }
-            } else {
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    if (in[u]) {
-                        if (cnt < g.cap) put(cnt, j0 + u);
-                        ++cnt;
-                    }
-                }
-            }
+            nl_store4<false>(nlbuf_le[wv], ln, nlrow, g.cap, in, j0, cnt);
         }
     };
     // Piece v is the first or second contiguous range of stencil row v / 2
