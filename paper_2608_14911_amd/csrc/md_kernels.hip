@@ -1188,17 +1188,37 @@ __device__ __forceinline__ void bonded_forces(const Bufs& b, const Dyn& dyn, int
     const Real K = f64 ? (Real)dyn.fene_K : (Real)dyn.fene_Kf;
     const Real R02 = f64 ? (Real)dyn.fene_R02 : (Real)dyn.fene_R02f;
     const Real hKR02 = f64 ? (Real)dyn.fene_halfKR02 : (Real)dyn.fene_halfKR02f;
+    // The first kPreB bonds and kPreA angles (all of a linear chain's) load
+    // their partner indices together and then gather the partners' records
+    // together: two memory round trips instead of two per term.  Rows past a
+    // particle's own counts hold no partner, so those gathers read the
+    // particle itself and their terms are skipped; the terms are summed in
+    // the same order as before.
+    constexpr int kPreB = 2, kPreA = 3;
+    int mb[kPreB];
+    int2 ex[kPreA];
+#pragma unroll
+    for (int q = 0; q < kPreB; ++q) mb[q] = q < b.maxb ? b.bp_s[(int64_t)q * n + i] : 0;
+#pragma unroll
+    for (int q = 0; q < kPreA; ++q) ex[q] = q < b.maxa ? b.ang_s[(int64_t)q * n + i] : make_int2(0, 0);
+    P pbq[kPreB], pa1[kPreA], pa2[kPreA];
+#pragma unroll
+    for (int q = 0; q < kPreB; ++q) pbq[q] = xs[q < nb ? mb[q] : (int)i];
+#pragma unroll
+    for (int q = 0; q < kPreA; ++q) {
+        pa1[q] = xs[q < na ? (ex[q].x & 0x3fffffff) : (int)i];
+        pa2[q] = xs[q < na ? ex[q].y : (int)i];
+    }
     Real eb = 0, wb = 0;
-    for (int q = 0; q < nb; ++q) {
-        const int m = b.bp_s[(int64_t)q * n + i];
+    auto bond = [&](const P& pm) {
         Real dx, dy, dz;
-        diff(pi, xs[m], dx, dy, dz);                 // x_m - x_i
+        diff(pi, pm, dx, dy, dz);                    // x_m - x_i
         const Real rx = -dx, ry = -dy, rz = -dz;     // r_i - r_m
         const Real r2 = rx * rx + ry * ry + rz * rz;
         const Real qq = r2 / R02;
         if (!(qq < Real(1))) {
             flag_bond = true;
-            continue;
+            return;
         }
         const Real om = Real(1) - qq;
         const Real fr = -K / om;
@@ -1208,15 +1228,17 @@ __device__ __forceinline__ void bonded_forces(const Bufs& b, const Dyn& dyn, int
         eb += -hKR02 * logr<Real>(om);
         wb += fr * r2;
         if (tensor) add_tensor(acc, 0.5, rx, ry, rz, fr * rx, fr * ry, fr * rz);
-    }
+    };
+#pragma unroll
+    for (int q = 0; q < kPreB; ++q)
+        if (q < nb) bond(pbq[q]);
+    for (int q = kPreB; q < nb; ++q) bond(xs[b.bp_s[(int64_t)q * n + i]]);
     acc[A_EBOND] += 0.5 * (double)eb;
     acc[A_VIR] += 0.5 * (double)wb;
     const Real kb = f64 ? (Real)dyn.k_bend : (Real)dyn.k_bendf;
     Real ea = 0, wa = 0;
-    for (int q = 0; q < na; ++q) {
-        const int2 e = b.ang_s[(int64_t)q * n + i];
+    auto angle = [&](const int2 e, const P& p1, const P& p2) {
         const int role = (int)((uint32_t)e.x >> 30);
-        const P p1 = xs[e.x & 0x3fffffff], p2 = xs[e.y];
         // members (A, B, C), B the centre; i is the one named by role
         const P& pa = role == 0 ? pi : p1;
         const P& pb = role == 1 ? pi : (role == 0 ? p1 : p2);
@@ -1289,6 +1311,13 @@ __device__ __forceinline__ void bonded_forces(const Bufs& b, const Dyn& dyn, int
         fx += Fx;
         fy += Fy;
         fz += Fz;
+    };
+#pragma unroll
+    for (int q = 0; q < kPreA; ++q)
+        if (q < na) angle(ex[q], pa1[q], pa2[q]);
+    for (int q = kPreA; q < na; ++q) {
+        const int2 e = b.ang_s[(int64_t)q * n + i];
+        angle(e, xs[e.x & 0x3fffffff], xs[e.y]);
     }
     acc[A_EANGLE] += (double)ea;
     acc[A_VIR] += (double)wa;
