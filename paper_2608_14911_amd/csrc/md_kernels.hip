@@ -1346,8 +1346,13 @@ __device__ __forceinline__ void finish_particle(const StepArgs& a, int64_t i, co
     const int64_t n = g.n;
     const double hdtm = a.dy.hdtm[tm];
     const double m = a.dy.mass[tm];
-    double vp[3], ft[3];
+    double vp[3], ft[3], xbv[3];
     for (int d = 0; d < 3; ++d) vp[d] = b.v[d * n + i];
+    // the build positions load with the velocities: read after the velocity
+    // stores below, each would wait on its own round trip (the compiler cannot
+    // move a load above a store it may alias)
+    if (a.mode == MODE_STEP)
+        for (int d = 0; d < 3; ++d) xbv[d] = b.xb[d * n + i];
     int32_t tg = -1;
     if (a.dy.langevin || a.mode == MODE_FORCES) tg = b.tag[i];
     if (a.dy.langevin) {
@@ -1383,7 +1388,8 @@ __device__ __forceinline__ void finish_particle(const StepArgs& a, int64_t i, co
         else if (xn[1] < 0.0) { xn[1] += g.L[1]; xn[0] += le->delta_next; vh[0] += g.le_rate_Ly; sc = -1; }
         if (sc != 0) {
             b.img[n + i] += sc;
-            b.xb[i] -= sc * le->delta_next;
+            xbv[0] -= sc * le->delta_next;
+            b.xb[i] = xbv[0];
         }
         double d2 = 0.0;
         for (int d = 0; d < 3; ++d) {
@@ -1395,7 +1401,7 @@ __device__ __forceinline__ void finish_particle(const StepArgs& a, int64_t i, co
             }
             if (!isfinite(xn[d]) || !isfinite(vh[d])) flag_nf = true;
             b.v[d * n + i] = vh[d];
-            const double dd = mimg(xn[d] - b.xb[d * n + i], g.L[d], g.invL[d]);
+            const double dd = mimg(xn[d] - xbv[d], g.L[d], g.invL[d]);
             d2 += dd * dd;
         }
         // a pair's separation changes by at most both displacements plus the
@@ -1420,7 +1426,7 @@ __device__ __forceinline__ void finish_particle(const StepArgs& a, int64_t i, co
             if (!isfinite(xn) || !isfinite(vh)) flag_nf = true;
             xo[d] = xn;
             b.v[d * n + i] = vh;
-            const double dd = mimg(xn - b.xb[d * n + i], g.L[d], g.invL[d]);
+            const double dd = mimg(xn - xbv[d], g.L[d], g.invL[d]);
             d2 += dd * dd;
         }
         if (d2 > g.disp2) flag_reb = true;
