@@ -463,10 +463,19 @@ __device__ __forceinline__ void permute_one(const Geom& g, const Bufs& b, int64_
         }
         for (; u < en; ++u) r += (b.tsc[u] < ti);
         int64_t nw = st + r;
-        b.xt[nw] = b.x[parity][i];
+        // every load before the first store: a load after a store it may
+        // alias cannot be moved above it, and would wait in turn
+        const double4 p = b.x[parity][i];
+        double vv[3];
+        int32_t im[3];
         for (int d = 0; d < 3; ++d) {
-            b.vt[d * n + nw] = b.v[d * n + i];
-            b.imgt[d * n + nw] = b.img[d * n + i];
+            vv[d] = b.v[d * n + i];
+            im[d] = b.img[d * n + i];
+        }
+        b.xt[nw] = p;
+        for (int d = 0; d < 3; ++d) {
+            b.vt[d * n + nw] = vv[d];
+            b.imgt[d * n + nw] = im[d];
         }
         b.tag[nw] = ti;
     }
@@ -485,7 +494,15 @@ __device__ __forceinline__ void commit_one(const Geom& g, const Bufs& b, int64_t
         b.ctl->build_step = b.ctl->step;
     }
     {
-        double4 p = b.xt[s];
+        // loads first, as in permute_one
+        const double4 p = b.xt[s];
+        double vv[3];
+        int32_t im[3];
+        for (int d = 0; d < 3; ++d) {
+            vv[d] = b.vt[d * n + s];
+            im[d] = b.imgt[d * n + s];
+        }
+        const int32_t t = bonded ? b.tag[s] : 0;
         b.x[parity][s] = p;
         const int4 q = quantize4(g, p.x, p.y, p.z, p.w);
         b.xq[parity][s] = q;
@@ -494,12 +511,12 @@ __device__ __forceinline__ void commit_one(const Geom& g, const Bufs& b, int64_t
         b.xb[n + s] = p.y;
         b.xb[2 * n + s] = p.z;
         for (int d = 0; d < 3; ++d) {
-            b.v[d * n + s] = b.vt[d * n + s];
-            b.img[d * n + s] = b.imgt[d * n + s];
+            b.v[d * n + s] = vv[d];
+            b.img[d * n + s] = im[d];
         }
         // the inverse permutation serves only the bonded remap of the list
         // build, which also copies the per-particle bond and angle counts
-        if (bonded) b.inv[b.tag[s]] = (int32_t)s;
+        if (bonded) b.inv[t] = (int32_t)s;
     }
 }
 
