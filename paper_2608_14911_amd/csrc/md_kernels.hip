@@ -2517,7 +2517,10 @@ hipError_t launch_clear_rebuild(const Bufs& b, hipStream_t s) {
 
 hipError_t launch_rebuild(const Geom& g, const Bufs& b, int parity, int bonded, hipStream_t s,
                           hipEvent_t ev_sorted) {
-    const int gs = grid_for(g.n, 512);
+    // the sort passes stride over the particles with at most 2048 blocks:
+    // against 512 (2M-bead melt, binning and sort per step) 62.0 -> 56.4 us,
+    // and one block per 256 particles 59.2 us
+    const int gs = grid_for(g.n, 2048);
     hipLaunchKernelGGL(k_bin, dim3(gs), dim3(kBlock), 0, s, g, b, parity);
     hipLaunchKernelGGL(k_scan_chunks, dim3(kScanBlocks), dim3(kBlock), 0, s, g, b);
     hipLaunchKernelGGL(k_scatter, dim3(gs), dim3(kBlock), 0, s, g, b);
